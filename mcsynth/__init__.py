@@ -1,0 +1,358 @@
+"""Seeded synthetic inputs for the transport problems.
+
+This module is shared by the CPU oracle wrapper and by the GPU library's
+callers.  It draws nuclide data, material compositions and problem
+descriptions from ``numpy.random.default_rng(data_seed)`` and holds none of the
+transport method's arithmetic: no grid search, no interpolation, no macroscopic
+sums, no tracking.  The transport random numbers (Philox) are *not* drawn here;
+each side implements that generator itself.
+
+The paper's real nuclear data and its reactor problems are not available, so
+every nuclide is synthetic: on its energy grid E_j the tabulated capture and
+elastic-scattering cross sections are
+
+    sigma_x(E) = a_x + b_x * sqrt(E_th / E)
+                 + sum_{r=1..10} h_{x,r} / (1 + ((E - E_r) / (Gamma_r / 2))**2)
+
+(a constant, a 1/v term and ten Lorentzian resonances; x in {c, s}), and the
+tabulated values are the data: the physics "truth" between grid points is their
+linear interpolation, as in a continuous-energy library.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+EMIN = 1.0e-5        # eV, lower end of every energy grid and the energy cutoff
+EMAX = 2.0e7         # eV, upper end of every energy grid
+E_THERMAL = 0.0253   # eV, reference energy of the 1/v term
+SOURCE_ENERGY = 2.0e6  # eV
+
+# geometry / boundary / source / tally kinds (plain integers, mirrored by each side)
+GEOM_INFINITE, GEOM_LATTICE, GEOM_SLAB = 0, 1, 2
+BC_REFLECT, BC_VACUUM = 0, 1
+SRC_POINT, SRC_BOX, SRC_BEAM = 0, 1, 2
+TALLY_ENERGY, TALLY_PIN, TALLY_MESH, TALLY_SLAB = 0, 1, 2, 3
+
+
+@dataclass
+class Nuclide:
+    E: np.ndarray        # float64, strictly increasing, eV
+    sig_c: np.ndarray    # float64 capture cross section, barns
+    sig_s: np.ndarray    # float64 elastic cross section, barns
+    awr: float           # target mass in neutron masses (A)
+
+
+@dataclass
+class Material:
+    nuclides: np.ndarray   # int32 nuclide ids, in material order
+    densities: np.ndarray  # float64 atom densities, atoms/(barn cm)
+
+
+@dataclass
+class Geometry:
+    kind: int = GEOM_INFINITE
+    material: int = 0                     # infinite medium
+    nx: int = 0                           # lattice cells along x / y
+    ny: int = 0
+    pitch: float = 0.0
+    radius: float = 0.0
+    z0: float = 0.0
+    z1: float = 0.0
+    pin_material: Optional[np.ndarray] = None   # int32 [ny*nx], -1 = no cylinder
+    moderator_material: int = 0
+    bc: tuple = (BC_REFLECT,) * 6         # x-, x+, y-, y+, z-, z+
+    x_edges: Optional[np.ndarray] = None  # slab layer edges along x
+    layer_material: Optional[np.ndarray] = None
+
+
+@dataclass
+class Source:
+    kind: int = SRC_POINT
+    position: tuple = (0.0, 0.0, 0.0)
+    box: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)  # x0, x1, y0, y1, z0, z1
+    direction: tuple = (1.0, 0.0, 0.0)
+    energy: float = SOURCE_ENERGY
+
+
+@dataclass
+class Tally:
+    kind: int = TALLY_ENERGY
+    energy_edges: Optional[np.ndarray] = None  # float64, n_bins + 1
+    mesh_dims: tuple = (1, 1, 1)
+    mesh_box: tuple = (0.0, 1.0, 0.0, 1.0, 0.0, 1.0)
+
+    def n_bins(self, geom: Geometry) -> int:
+        if self.kind == TALLY_ENERGY:
+            return len(self.energy_edges) - 1
+        if self.kind == TALLY_PIN:
+            return geom.nx * geom.ny
+        if self.kind == TALLY_MESH:
+            return int(np.prod(self.mesh_dims))
+        if self.kind == TALLY_SLAB:
+            return len(geom.x_edges) - 1
+        raise ValueError(self.kind)
+
+
+@dataclass
+class Problem:
+    name: str
+    nuclides: List[Nuclide]
+    materials: List[Material]
+    geometry: Geometry
+    source: Source
+    tally: Tally
+    energy_cutoff: float = EMIN
+    n_hash_bins: int = 8192
+    histories: int = 10_000
+    batches: int = 10
+    seed: int = 1                # transport (Philox key) seed
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_bins(self) -> int:
+        return self.tally.n_bins(self.geometry)
+
+    def data_bytes(self) -> int:
+        return int(sum(n.E.nbytes + n.sig_c.nbytes + n.sig_s.nbytes for n in self.nuclides))
+
+
+# ---------------------------------------------------------------------------
+# nuclide data
+# ---------------------------------------------------------------------------
+
+def _log_uniform(rng, lo, hi, size=None):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size))
+
+
+def log_uniform_grid(n: int) -> np.ndarray:
+    """n points uniform in ln E over [EMIN, EMAX] with both ends set exactly."""
+    g = np.exp(np.linspace(np.log(EMIN), np.log(EMAX), n))
+    g[0], g[-1] = EMIN, EMAX
+    return g
+
+
+# offsets (in widths) of the points clustered around each resonance
+_CLUSTER_T = np.array([0.0, 0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.65, 0.8, 1.0, 1.25, 1.5, 2.0,
+                       2.5, 3.0, 4.0, 5.0, 7.0, 10.0, 15.0, 25.0, 40.0])
+_CLUSTER_T = np.concatenate([-_CLUSTER_T[:0:-1], _CLUSTER_T])
+
+
+def clustered_grid(n_target: int, e_res: np.ndarray, g_res: np.ndarray) -> np.ndarray:
+    """Log-uniform base grid unioned with points clustered at E_r + Gamma_r * t."""
+    pts = (e_res[:, None] + g_res[:, None] * _CLUSTER_T[None, :]).ravel()
+    pts = pts[(pts > EMIN) & (pts < EMAX)]
+    n_base = max(16, n_target - pts.size)
+    g = np.unique(np.concatenate([log_uniform_grid(n_base), pts]))
+    assert g[0] == EMIN and g[-1] == EMAX
+    return g
+
+
+def _resonance_params(rng, n_res=10):
+    e_res = _log_uniform(rng, 1.0, 1.0e5, n_res)
+    g_res = e_res * 10.0 ** rng.uniform(-3.0, -1.5, n_res)
+    return e_res, g_res
+
+
+def _channel(E, a, b, e_res, g_res, h):
+    s = a + b * np.sqrt(E_THERMAL / E)
+    for er, gr, hr in zip(e_res, g_res, h):
+        s = s + hr / (1.0 + ((E - er) / (0.5 * gr)) ** 2)
+    return s
+
+
+def make_nuclide(rng, awr: float, n_points: int, grid: str = "loguniform",
+                 n_res: int = 10, literal_scatter: bool = False) -> Nuclide:
+    """Draw one synthetic nuclide (see module docstring for the formula).
+
+    a_c = 0; a_s ~ U[2, 20] b (potential scattering; ``literal_scatter`` sets it to 0);
+    b_c ~ logU[0.1, 100] b; b_s ~ logU[0.01, 1] b; resonance energies E_r ~ logU[1, 1e5] eV,
+    widths Gamma_r = E_r * 10**U[-3, -1.5], heights h ~ logU[10, 1e4] b, the resonance
+    positions shared by both channels and the heights drawn per channel.
+    """
+    e_res, g_res = _resonance_params(rng, n_res)
+    if grid == "loguniform":
+        E = log_uniform_grid(n_points)
+    elif grid == "clustered":
+        E = clustered_grid(n_points, e_res, g_res)
+    else:
+        raise ValueError(grid)
+    a_s = 0.0 if literal_scatter else rng.uniform(2.0, 20.0)
+    b_c = _log_uniform(rng, 0.1, 100.0)
+    b_s = _log_uniform(rng, 0.01, 1.0)
+    h_c = _log_uniform(rng, 10.0, 1.0e4, n_res)
+    h_s = _log_uniform(rng, 10.0, 1.0e4, n_res)
+    sc = _channel(E, 0.0, b_c, e_res, g_res, h_c)
+    ss = _channel(E, a_s, b_s, e_res, g_res, h_s)
+    assert np.all(np.diff(E) > 0) and np.all(sc >= 0) and np.all(ss >= 0)
+    return Nuclide(E=E.astype(np.float64), sig_c=sc.astype(np.float64),
+                   sig_s=ss.astype(np.float64), awr=float(awr))
+
+
+def constant_nuclide(sig_c: float, sig_s: float, awr: float, n_points: int = 2000) -> Nuclide:
+    """A nuclide whose tabulated cross sections are constant (closed-form tests)."""
+    E = log_uniform_grid(n_points)
+    return Nuclide(E=E, sig_c=np.full_like(E, sig_c), sig_s=np.full_like(E, sig_s), awr=float(awr))
+
+
+def _analytic_sigma_t(nuc: Nuclide, E: float) -> float:
+    # only used to scale densities: the nearest tabulated point, no interpolation
+    j = int(np.argmin(np.abs(nuc.E - E)))
+    return float(nuc.sig_c[j] + nuc.sig_s[j])
+
+
+def make_material(rng, nuclides: List[Nuclide], ids, target_sigma_t: float,
+                  density_range=(1.0e-6, 1.0e-2), fixed_fraction=None) -> Material:
+    """Densities ~ logU[density_range], rescaled so Sigma_t(2 MeV) ~= target_sigma_t (1/cm).
+
+    ``fixed_fraction`` = (position, fraction) forces the nuclide at that position of ``ids``
+    to carry the given fraction of Sigma_t(2 MeV) (a moderator's hydrogen-like nuclide).
+    """
+    ids = np.asarray(ids, dtype=np.int32)
+    dens = _log_uniform(rng, density_range[0], density_range[1], ids.size)
+    st = np.array([_analytic_sigma_t(nuclides[k], SOURCE_ENERGY) for k in ids])
+    if fixed_fraction is not None:
+        pos, frac = fixed_fraction
+        others = np.delete(np.arange(ids.size), pos)
+        rest = float(np.sum(dens[others] * st[others]))
+        dens[others] *= (1.0 - frac) * target_sigma_t / rest
+        dens[pos] = frac * target_sigma_t / st[pos]
+    else:
+        dens *= target_sigma_t / float(np.sum(dens * st))
+    return Material(nuclides=ids, densities=dens.astype(np.float64))
+
+
+def energy_edges(n_bins: int) -> np.ndarray:
+    return log_uniform_grid(n_bins + 1)
+
+
+# ---------------------------------------------------------------------------
+# problems
+# ---------------------------------------------------------------------------
+
+def c1_problem(data_seed: int = 1001, seed: int = 1, histories: int = 10_000,
+               batches: int = 10) -> Problem:
+    """Infinite homogeneous medium: one material of 4 nuclides (A = 1, 12, 56, 238), each on a
+    2,000-point log-uniform grid over [1e-5 eV, 20 MeV]; isotropic 2 MeV point source at the
+    origin; 50-bin log-energy track-length flux tally."""
+    rng = np.random.default_rng(data_seed)
+    awrs = [1.0, 12.0, 56.0, 238.0]
+    nucs = [make_nuclide(rng, a, 2000, "loguniform") for a in awrs]
+    mat = make_material(rng, nucs, [0, 1, 2, 3], 0.5, fixed_fraction=(0, 0.5))
+    return Problem(name="c1_infinite_4nuc", nuclides=nucs, materials=[mat],
+                   geometry=Geometry(kind=GEOM_INFINITE, material=0),
+                   source=Source(kind=SRC_POINT), tally=Tally(TALLY_ENERGY, energy_edges(50)),
+                   histories=histories, batches=batches, seed=seed)
+
+
+def c1_constant_problem(sig_c: float, sig_s: float, awr: float = 1.0, density: float = 0.01,
+                        seed: int = 11, histories: int = 10_000, batches: int = 10,
+                        n_bins: int = 50) -> Problem:
+    """Infinite medium of one nuclide with constant cross sections (closed-form variant)."""
+    nuc = constant_nuclide(sig_c, sig_s, awr)
+    mat = Material(nuclides=np.array([0], np.int32), densities=np.array([density]))
+    return Problem(name="c1_constant", nuclides=[nuc], materials=[mat],
+                   geometry=Geometry(kind=GEOM_INFINITE, material=0),
+                   source=Source(kind=SRC_POINT), tally=Tally(TALLY_ENERGY, energy_edges(n_bins)),
+                   histories=histories, batches=batches, seed=seed)
+
+
+PIN_R = 0.41
+PIN_PITCH = 1.26
+
+
+def _lattice_geometry(n: int, pin_mat: np.ndarray, mod_mat: int, height: float = 1.0) -> Geometry:
+    return Geometry(kind=GEOM_LATTICE, nx=n, ny=n, pitch=PIN_PITCH, radius=PIN_R, z0=0.0,
+                    z1=height, pin_material=pin_mat.astype(np.int32), moderator_material=mod_mat,
+                    bc=(BC_REFLECT,) * 6)
+
+
+def c2_problem(data_seed: int = 2002, seed: int = 2, histories: int = 1_000_000,
+               batches: int = 20, grid_range=(10_000, 60_000)) -> Problem:
+    """17x17 lattice of cylindrical pins (r 0.41 cm, pitch 1.26 cm, height 1 cm, reflective on
+    every face); materials A (30 nuclides, fuel pins), B (3 nuclides, the 25 pins at
+    (i, j) in {2,5,8,11,14}^2) and C (5 nuclides, moderator outside every cylinder; its first
+    nuclide has A = 1); 38 distinct nuclides on clustered grids of U[10k, 60k] points;
+    uniform isotropic 2 MeV source over the box; per-pin track-length flux tally."""
+    rng = np.random.default_rng(data_seed)
+    n_a, n_b, n_c = 30, 3, 5
+    awr = np.concatenate([rng.uniform(2.0, 240.0, n_a + n_b), [1.0], rng.uniform(2.0, 30.0, n_c - 1)])
+    sizes = rng.integers(grid_range[0], grid_range[1] + 1, awr.size)
+    nucs = [make_nuclide(rng, a, int(s), "clustered") for a, s in zip(awr, sizes)]
+    mat_a = make_material(rng, nucs, np.arange(0, n_a), 0.6)
+    mat_b = make_material(rng, nucs, np.arange(n_a, n_a + n_b), 0.4)
+    mat_c = make_material(rng, nucs, np.arange(n_a + n_b, n_a + n_b + n_c), 0.5,
+                          fixed_fraction=(0, 0.6))
+    n = 17
+    pin = np.zeros((n, n), np.int32)
+    for j in (2, 5, 8, 11, 14):
+        for i in (2, 5, 8, 11, 14):
+            pin[j, i] = 1
+    geom = _lattice_geometry(n, pin.ravel(), 2)
+    L = n * PIN_PITCH
+    return Problem(name="c2_pin_lattice_17x17", nuclides=nucs, materials=[mat_a, mat_b, mat_c],
+                   geometry=geom, source=Source(kind=SRC_BOX, box=(0.0, L, 0.0, L, 0.0, 1.0)),
+                   tally=Tally(TALLY_PIN), histories=histories, batches=batches, seed=seed)
+
+
+def lattice_homogeneous_problem(nuclides: List[Nuclide], material: Material, n: int = 17,
+                                seed: int = 21, histories: int = 20_000, batches: int = 10,
+                                height: float = 1.0) -> Problem:
+    """The 17x17 pin lattice with one material everywhere (closed-form variant)."""
+    geom = _lattice_geometry(n, np.zeros(n * n, np.int32), 0, height)
+    L = n * PIN_PITCH
+    return Problem(name="lattice_homogeneous", nuclides=nuclides, materials=[material],
+                   geometry=geom, source=Source(kind=SRC_BOX, box=(0.0, L, 0.0, L, 0.0, height)),
+                   tally=Tally(TALLY_PIN), histories=histories, batches=batches, seed=seed)
+
+
+def c3_problem(data_seed: int = 3003, seed: int = 3, histories: int = 20_000_000,
+               batches: int = 1, n_nuclides: int = 300, grid_range=(20_000, 150_000)) -> Problem:
+    """15x15 assemblies of 17x17 pins (a 255x255 pin lattice, 321.3 cm square, 1 cm high,
+    reflective), one material of 300 nuclides on clustered grids of U[20k, 150k] points,
+    uniform isotropic 2 MeV source, 100x100x10 mesh flux tally."""
+    rng = np.random.default_rng(data_seed)
+    awr = np.concatenate([[1.0], rng.uniform(2.0, 240.0, n_nuclides - 1)])
+    sizes = rng.integers(grid_range[0], grid_range[1] + 1, n_nuclides)
+    nucs = [make_nuclide(rng, a, int(s), "clustered") for a, s in zip(awr, sizes)]
+    mat = make_material(rng, nucs, np.arange(n_nuclides), 0.6, fixed_fraction=(0, 0.4))
+    n = 15 * 17
+    geom = _lattice_geometry(n, np.zeros(n * n, np.int32), 0)
+    L = n * PIN_PITCH
+    return Problem(name="c3_assembly_lattice_300nuc", nuclides=nucs, materials=[mat],
+                   geometry=geom, source=Source(kind=SRC_BOX, box=(0.0, L, 0.0, L, 0.0, 1.0)),
+                   tally=Tally(TALLY_MESH, mesh_dims=(100, 100, 10), mesh_box=(0.0, L, 0.0, L, 0.0, 1.0)),
+                   histories=histories, batches=batches, seed=seed)
+
+
+def slab_problem(sigma_t=(0.2, 1.5, 0.5), thickness=(60.0, 80.0, 40.0 + 20.0),
+                 scatter_ratio=(0.0, 0.0, 0.0), awr: float = 1.0, seed: int = 5,
+                 histories: int = 100_000, batches: int = 10) -> Problem:
+    """Slab of layers along x with constant cross sections, a normally incident 2 MeV beam at
+    x = 0 and vacuum on both faces (transmission = weight leaking through the far face)."""
+    nucs, mats = [], []
+    for k, (st, c) in enumerate(zip(sigma_t, scatter_ratio)):
+        nucs.append(constant_nuclide(sig_c=(1.0 - c) * st / 0.01, sig_s=c * st / 0.01, awr=awr))
+        mats.append(Material(nuclides=np.array([k], np.int32), densities=np.array([0.01])))
+    edges = np.concatenate([[0.0], np.cumsum(thickness)]).astype(np.float64)
+    geom = Geometry(kind=GEOM_SLAB, x_edges=edges, layer_material=np.arange(len(sigma_t), dtype=np.int32),
+                    bc=(BC_VACUUM, BC_VACUUM, BC_REFLECT, BC_REFLECT, BC_REFLECT, BC_REFLECT))
+    return Problem(name="slab", nuclides=nucs, materials=mats, geometry=geom,
+                   source=Source(kind=SRC_BEAM, position=(0.0, 0.0, 0.0), direction=(1.0, 0.0, 0.0)),
+                   tally=Tally(TALLY_SLAB), histories=histories, batches=batches, seed=seed)
+
+
+def lookup_energies(rng, n: int) -> np.ndarray:
+    """Energies log-uniform over [EMIN, EMAX] (the lookup benchmark's input)."""
+    return _log_uniform(rng, EMIN, EMAX, n).astype(np.float64)
+
+
+def edge_case_energies(nuc: Nuclide, rng, n_random: int = 1000) -> np.ndarray:
+    """Grid points, their neighbours one ulp away, both ends, and random log-uniform energies."""
+    E = nuc.E
+    pts = [E, np.nextafter(E, 0.0), np.nextafter(E, np.inf), [EMIN, EMAX],
+           lookup_energies(rng, n_random)]
+    out = np.concatenate(pts)
+    return out[(out >= EMIN) & (out <= EMAX)].astype(np.float64)

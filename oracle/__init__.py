@@ -1,0 +1,273 @@
+"""CPU oracle for the Monte Carlo transport hot path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The GPU library never loads it
+and shares no code with it; both read the same synthetic inputs made by
+``mcsynth``.
+
+The arithmetic lives in ``oracle.c`` (plain C, fp64, -ffp-contract=off), built
+here into ``liboracle.so`` with gcc; this module only marshals arguments and
+forms batch statistics.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# global tally slots (see oracle.c)
+G_TRACK, G_COLL_EST, G_ABSORB, G_CUTOFF, G_LEAK, G_TRACK_ABS = 0, 1, 2, 3, 4, 5
+G_NCOLL, G_NCROSS, G_LEAK_XHI, G_LEAK_XHI_UNC, N_GLOBAL = 6, 7, 8, 9, 10
+FATE_ABSORBED, FATE_CUTOFF, FATE_LEAKED, FATE_LOST = 1, 2, 3, 4
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (-O2 -fopenmp -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared",
+                               "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n_nuc", C.c_int32), ("nuc_off", C.POINTER(C.c_int64)),
+        ("E", C.POINTER(C.c_double)), ("sig_c", C.POINTER(C.c_double)),
+        ("sig_s", C.POINTER(C.c_double)), ("awr", C.POINTER(C.c_double)),
+        ("n_mat", C.c_int32), ("mat_off", C.POINTER(C.c_int32)),
+        ("mat_nuc", C.POINTER(C.c_int32)), ("mat_dens", C.POINTER(C.c_double)),
+        ("geom_kind", C.c_int32), ("inf_material", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("pitch", C.c_double), ("radius", C.c_double), ("z0", C.c_double), ("z1", C.c_double),
+        ("pin_mat", C.POINTER(C.c_int32)), ("mod_mat", C.c_int32), ("bc", C.c_int32 * 6),
+        ("n_layers", C.c_int32), ("x_edges", C.POINTER(C.c_double)),
+        ("layer_mat", C.POINTER(C.c_int32)),
+        ("src_kind", C.c_int32), ("src_pos", C.c_double * 3), ("src_box", C.c_double * 6),
+        ("src_dir", C.c_double * 3), ("src_E", C.c_double),
+        ("tally_kind", C.c_int32), ("n_ebins", C.c_int32), ("e_edges", C.POINTER(C.c_double)),
+        ("mesh_dims", C.c_int32 * 3), ("mesh_box", C.c_double * 6),
+        ("e_cut", C.c_double), ("max_events", C.c_int64),
+    ]
+
+
+class _History(C.Structure):
+    _fields_ = [("fate", C.c_int32), ("n_coll", C.c_int32), ("n_cross", C.c_int32),
+                ("pad", C.c_int32), ("n_draws", C.c_uint64), ("E_final", C.c_double),
+                ("track", C.c_double), ("weight", C.c_double)]
+
+
+HISTORY_DTYPE = np.dtype([("fate", np.int32), ("n_coll", np.int32), ("n_cross", np.int32),
+                          ("pad", np.int32), ("n_draws", np.uint64), ("E_final", np.float64),
+                          ("track", np.float64), ("weight", np.float64)])
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        D, P = C.c_double, C.POINTER
+        _lib.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        _lib.orc_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64]
+        _lib.orc_uniform.restype = D
+        _lib.orc_grid_index.argtypes = [P(D), C.c_int64, D]
+        _lib.orc_grid_index.restype = C.c_int64
+        _lib.orc_micro_xs.argtypes = [P(_Problem), C.c_int32, D, P(D), P(D), P(C.c_int64)]
+        _lib.orc_macro_xs.argtypes = [P(_Problem), C.c_int32, D, P(D), P(D)]
+        _lib.orc_elastic.argtypes = [D, D, D, P(D), P(D)]
+        _lib.orc_rotate.argtypes = [P(D), D, D]
+        _lib.orc_run.argtypes = [P(_Problem), C.c_uint64, C.c_uint64, C.c_uint64, P(D), P(D),
+                                 P(D), C.c_void_p, C.c_int]
+        _lib.orc_run.restype = C.c_int
+        _lib.orc_max_threads.restype = C.c_int
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class OracleProblem:
+    """Flattened arrays of a ``mcsynth.Problem`` held alive for the C structure."""
+
+    def __init__(self, prob, max_events: int = 10_000_000):
+        self.prob = prob
+        nucs = prob.nuclides
+        lens = np.array([n.E.size for n in nucs], np.int64)
+        self.nuc_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        self.E = np.ascontiguousarray(np.concatenate([n.E for n in nucs]), np.float64)
+        self.sc = np.ascontiguousarray(np.concatenate([n.sig_c for n in nucs]), np.float64)
+        self.ss = np.ascontiguousarray(np.concatenate([n.sig_s for n in nucs]), np.float64)
+        self.awr = np.array([n.awr for n in nucs], np.float64)
+        mats = prob.materials
+        self.mat_off = np.concatenate([[0], np.cumsum([m.nuclides.size for m in mats])]).astype(np.int32)
+        self.mat_nuc = np.ascontiguousarray(np.concatenate([m.nuclides for m in mats]), np.int32)
+        self.mat_dens = np.ascontiguousarray(np.concatenate([m.densities for m in mats]), np.float64)
+        g, s, t = prob.geometry, prob.source, prob.tally
+        self.pin_mat = np.ascontiguousarray(g.pin_material if g.pin_material is not None
+                                            else np.zeros(1, np.int32), np.int32)
+        self.x_edges = np.ascontiguousarray(g.x_edges if g.x_edges is not None
+                                            else np.zeros(2), np.float64)
+        self.layer_mat = np.ascontiguousarray(g.layer_material if g.layer_material is not None
+                                              else np.zeros(1, np.int32), np.int32)
+        self.e_edges = np.ascontiguousarray(t.energy_edges if t.energy_edges is not None
+                                            else np.zeros(2), np.float64)
+        c = _Problem()
+        c.n_nuc = len(nucs)
+        c.nuc_off = self.nuc_off.ctypes.data_as(C.POINTER(C.c_int64))
+        c.E, c.sig_c, c.sig_s, c.awr = _dptr(self.E), _dptr(self.sc), _dptr(self.ss), _dptr(self.awr)
+        c.n_mat = len(mats)
+        c.mat_off, c.mat_nuc, c.mat_dens = _iptr(self.mat_off), _iptr(self.mat_nuc), _dptr(self.mat_dens)
+        c.geom_kind, c.inf_material = g.kind, g.material
+        c.nx, c.ny, c.pitch, c.radius, c.z0, c.z1 = g.nx, g.ny, g.pitch, g.radius, g.z0, g.z1
+        c.pin_mat, c.mod_mat = _iptr(self.pin_mat), g.moderator_material
+        c.bc = (C.c_int32 * 6)(*g.bc)
+        c.n_layers = 0 if g.x_edges is None else len(g.x_edges) - 1
+        c.x_edges, c.layer_mat = _dptr(self.x_edges), _iptr(self.layer_mat)
+        c.src_kind = s.kind
+        c.src_pos = (C.c_double * 3)(*s.position)
+        c.src_box = (C.c_double * 6)(*s.box)
+        c.src_dir = (C.c_double * 3)(*s.direction)
+        c.src_E = s.energy
+        c.tally_kind = t.kind
+        c.n_ebins = 0 if t.energy_edges is None else len(t.energy_edges) - 1
+        c.e_edges = _dptr(self.e_edges)
+        c.mesh_dims = (C.c_int32 * 3)(*t.mesh_dims)
+        c.mesh_box = (C.c_double * 6)(*t.mesh_box)
+        c.e_cut = prob.energy_cutoff
+        c.max_events = max_events
+        self.c = c
+        self.n_bins = prob.n_bins
+
+    def ref(self):
+        return C.byref(self.c)
+
+
+# ------------------------------------------------------------------------
+# thin wrappers
+# ------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    L = lib()
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    L.orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def uniform(seed: int, lineage: int, pid: int, n: int) -> float:
+    return lib().orc_uniform(seed, lineage, pid, n)
+
+
+def grid_index(grid: np.ndarray, e: float) -> int:
+    g = np.ascontiguousarray(grid, np.float64)
+    return int(lib().orc_grid_index(_dptr(g), g.size, float(e)))
+
+
+def micro_xs(op: OracleProblem, nuc: int, energies):
+    L = lib()
+    energies = np.asarray(energies, np.float64)
+    sc = np.empty(energies.size)
+    ss = np.empty(energies.size)
+    idx = np.empty(energies.size, np.int64)
+    a, b, i = C.c_double(), C.c_double(), C.c_int64()
+    for k, e in enumerate(energies):
+        L.orc_micro_xs(op.ref(), nuc, float(e), C.byref(a), C.byref(b), C.byref(i))
+        sc[k], ss[k], idx[k] = a.value, b.value, i.value
+    return idx, sc, ss
+
+
+def macro_xs(op: OracleProblem, mats, energies):
+    L = lib()
+    energies = np.asarray(energies, np.float64)
+    mats = np.broadcast_to(np.asarray(mats, np.int32), energies.shape)
+    Sa = np.empty(energies.size)
+    Ss = np.empty(energies.size)
+    a, b = C.c_double(), C.c_double()
+    for k, (m, e) in enumerate(zip(mats.ravel(), energies.ravel())):
+        L.orc_macro_xs(op.ref(), int(m), float(e), C.byref(a), C.byref(b))
+        Sa[k], Ss[k] = a.value, b.value
+    return Sa, Ss
+
+
+def elastic(A: float, E: float, mu_cm: float):
+    a, b = C.c_double(), C.c_double()
+    lib().orc_elastic(A, E, mu_cm, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def rotate(d, mu: float, phi: float):
+    arr = (C.c_double * 3)(*d)
+    lib().orc_rotate(arr, mu, phi)
+    return np.array(list(arr))
+
+
+@dataclass
+class RunResult:
+    n: int
+    tl: np.ndarray       # raw track-length sums per bin
+    coll: np.ndarray     # raw collision-estimator sums per bin
+    glob: np.ndarray     # raw global sums (N_GLOBAL)
+    history: np.ndarray | None = None
+
+
+def run(op: OracleProblem, seed: int, first_pid: int, n: int, history: bool = False,
+        threads: int = 0) -> RunResult:
+    """Track histories [first_pid, first_pid + n) birth to death; raw sums."""
+    nb = op.n_bins
+    tl = np.zeros(nb)
+    coll = np.zeros(nb)
+    glob = np.zeros(N_GLOBAL)
+    hist = np.zeros(n, HISTORY_DTYPE) if history else None
+    rc = lib().orc_run(op.ref(), seed, first_pid, n, _dptr(tl), _dptr(coll), _dptr(glob),
+                       hist.ctypes.data if history else None, threads)
+    if rc != 0:
+        raise MemoryError("oracle run failed")
+    return RunResult(n=n, tl=tl, coll=coll, glob=glob, history=hist)
+
+
+@dataclass
+class BatchStats:
+    mean: dict
+    stderr: dict
+    n_batches: int
+
+
+def run_batches(op: OracleProblem, seed: int, n_batches: int, per_batch: int,
+                first_pid: int = 0, threads: int = 0) -> BatchStats:
+    """Batch statistics: each batch's per-source-particle tally T_b; mean = S1/B,
+    standard error = sqrt((S2/B - mean^2) / (B - 1))."""
+    acc = {k: [0.0, 0.0] for k in ("tl", "coll", "glob")}
+    for b in range(n_batches):
+        r = run(op, seed, first_pid + b * per_batch, per_batch, threads=threads)
+        for k in acc:
+            T = getattr(r, k) / per_batch
+            acc[k][0] = acc[k][0] + T
+            acc[k][1] = acc[k][1] + T * T
+    mean, se = {}, {}
+    B = n_batches
+    for k, (s1, s2) in acc.items():
+        m = s1 / B
+        mean[k] = m
+        se[k] = np.sqrt(np.maximum(s2 / B - m * m, 0.0) / max(B - 1, 1))
+    return BatchStats(mean=mean, stderr=se, n_batches=B)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

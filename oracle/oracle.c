@@ -1,0 +1,656 @@
+/*
+ * oracle.c -- plain, slow CPU oracle for the Monte Carlo transport hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library includes, links or
+ * calls this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg load it (through oracle/__init__.py).  It shares no code,
+ * header, table or constant with the GPU path: it reads the same synthetic
+ * input arrays and nothing else.
+ *
+ * What it computes follows the paper (Tramm et al., "Performance Portable Monte
+ * Carlo Particle Transport on Intel, NVIDIA, and AMD GPUs"):
+ *   - history-based tracking, one particle birth to death at a time, the mode
+ *     the paper uses on CPUs (section 2, paragraph "Event-Based Parallelism";
+ *     section 3);
+ *   - surface tracking (ray tracing) through the geometry, delta tracking
+ *     disabled (section 3);
+ *   - macroscopic cross sections summed over a material's nuclides, the
+ *     expensive step of the method (section 2 "Sorting"; section 4.1);
+ *   - tallies scored during active batches (section 2 "Tallying"; section 4.1).
+ * The paper gives no lower-level algorithm, so every other step is written
+ * from its plain textbook definition; each such reading is named where it is
+ * used.  Floating point is fp64 throughout, compiled with -ffp-contract=off so
+ * that every expression rounds exactly as written.
+ *
+ * Exported functions use the prefix orc_.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* problem description (mirrored by ctypes in oracle/__init__.py)           */
+/* ------------------------------------------------------------------------ */
+enum { GEOM_INFINITE = 0, GEOM_LATTICE = 1, GEOM_SLAB = 2 };
+enum { BC_REFLECT = 0, BC_VACUUM = 1 };
+enum { SRC_POINT = 0, SRC_BOX = 1, SRC_BEAM = 2 };
+enum { TALLY_ENERGY = 0, TALLY_PIN = 1, TALLY_MESH = 2, TALLY_SLAB = 3 };
+
+/* global tally slots (each a sum over histories) */
+enum {
+    G_TRACK = 0,       /* sum w*d over all flights                        */
+    G_COLL_EST = 1,    /* sum w/Sigma_t over collisions                   */
+    G_ABSORB = 2,      /* sum w over absorptions                          */
+    G_CUTOFF = 3,      /* sum w killed by the energy cutoff               */
+    G_LEAK = 4,        /* sum w leaked through any vacuum face            */
+    G_TRACK_ABS = 5,   /* sum w*d*Sigma_a (track-length absorption)       */
+    G_NCOLL = 6,       /* number of collisions                            */
+    G_NCROSS = 7,      /* number of surface crossings                     */
+    G_LEAK_XHI = 8,    /* sum w leaked through the x+ face                */
+    G_LEAK_XHI_UNC = 9,/* same, histories that never collided             */
+    N_GLOBAL = 10
+};
+
+enum { FATE_ALIVE = 0, FATE_ABSORBED = 1, FATE_CUTOFF = 2, FATE_LEAKED = 3, FATE_LOST = 4 };
+
+typedef struct {
+    /* nuclides: grid of nuclide k is E[nuc_off[k] .. nuc_off[k+1]) */
+    int32_t n_nuc;
+    const int64_t *nuc_off;
+    const double *E, *sig_c, *sig_s, *awr;
+    /* materials: nuclides mat_nuc[mat_off[m] .. mat_off[m+1]) with densities mat_dens */
+    int32_t n_mat;
+    const int32_t *mat_off, *mat_nuc;
+    const double *mat_dens;
+    /* geometry */
+    int32_t geom_kind, inf_material;
+    int32_t nx, ny;
+    double pitch, radius, z0, z1;
+    const int32_t *pin_mat;
+    int32_t mod_mat;
+    int32_t bc[6];
+    int32_t n_layers;
+    const double *x_edges;
+    const int32_t *layer_mat;
+    /* source */
+    int32_t src_kind;
+    double src_pos[3], src_box[6], src_dir[3], src_E;
+    /* tally */
+    int32_t tally_kind, n_ebins;
+    const double *e_edges;
+    int32_t mesh_dims[3];
+    double mesh_box[6];
+    /* physics */
+    double e_cut;
+    int64_t max_events;
+} orc_problem;
+
+typedef struct {
+    int32_t fate, n_coll, n_cross, pad;
+    uint64_t n_draws;
+    double E_final, track, weight;
+} orc_history;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random        */
+/* numbers: as easy as 1, 2, 3").  Written from the published definition:   */
+/* ten rounds; each round multiplies words 0 and 2 by the Philox constants,  */
+/* mixes the high halves with words 1/3 and the key, and the key is bumped   */
+/* by the Weyl constants between rounds.                                     */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Draw number n of particle (seed, lineage, pid): counter = (n/2, lineage,
+ * pid_lo, pid_hi), key = (seed_lo, seed_hi); the even draw takes output words
+ * (1:0), the odd draw words (3:2), as a 64-bit integer x; u = ((x >> 12) + 0.5)
+ * * 2^-52, exact in fp64 and strictly inside (0, 1).  (Counter layout and conversion
+ * are this build's reading; the paper does not fix them.) */
+double orc_uniform(uint64_t seed, uint32_t lineage, uint64_t pid, uint64_t n)
+{
+    uint32_t ctr[4] = {(uint32_t)(n >> 1), lineage, (uint32_t)pid, (uint32_t)(pid >> 32)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    orc_philox4x32_10(ctr, key, o);
+    uint64_t x = (n & 1) ? (((uint64_t)o[3] << 32) | o[2]) : (((uint64_t)o[1] << 32) | o[0]);
+    return ((double)(x >> 12) + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+typedef struct {
+    uint64_t seed, pid, n;
+    uint32_t lineage;
+} rng_stream;
+
+static double next_u(rng_stream *s)
+{
+    double u = orc_uniform(s->seed, s->lineage, s->pid, s->n);
+    s->n += 1;
+    return u;
+}
+
+/* ------------------------------------------------------------------------ */
+/* cross-section lookup: the plain definition (paper section 2 "Sorting" and */
+/* section 4.1 name the macroscopic lookup as the dominant cost; the hash-   */
+/* grid acceleration only speeds up reaching this same result).              */
+/* ------------------------------------------------------------------------ */
+
+/* i(E) = max{ j : E_j <= E }, clamped to [0, N-2] (a grid point itself maps to
+ * its own interval; E at or above the last point maps to N-2).  Written as a
+ * plain bisection for the first point strictly greater than E. */
+int64_t orc_grid_index(const double *grid, int64_t n, double e)
+{
+    int64_t lo = 0, hi = n; /* first index with grid[idx] > e lies in [lo, hi] */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (grid[mid] > e) hi = mid; else lo = mid + 1;
+    }
+    int64_t i = lo - 1;
+    if (i < 0) i = 0;
+    if (i > n - 2) i = n - 2;
+    return i;
+}
+
+/* Microscopic cross sections of nuclide k at E by linear interpolation:
+ * f = (E - E_i) / (E_{i+1} - E_i);  sigma = sigma_i + f * (sigma_{i+1} - sigma_i). */
+void orc_micro_xs(const orc_problem *p, int32_t k, double e, double *sc, double *ss, int64_t *idx)
+{
+    const int64_t off = p->nuc_off[k];
+    const int64_t n = p->nuc_off[k + 1] - off;
+    const double *g = p->E + off;
+    int64_t i = orc_grid_index(g, n, e);
+    double f = (e - g[i]) / (g[i + 1] - g[i]);
+    const double *c = p->sig_c + off, *s = p->sig_s + off;
+    *sc = c[i] + f * (c[i + 1] - c[i]);
+    *ss = s[i] + f * (s[i + 1] - s[i]);
+    if (idx) *idx = i;
+}
+
+/* Macroscopic capture and scattering cross sections of material m at E: the
+ * sums over the material's nuclides, in material order, of density times the
+ * microscopic value.  Sigma_t is defined as Sigma_a + Sigma_s. */
+void orc_macro_xs(const orc_problem *p, int32_t m, double e, double *Sa, double *Ss)
+{
+    double a = 0.0, s = 0.0;
+    for (int32_t q = p->mat_off[m]; q < p->mat_off[m + 1]; ++q) {
+        double sc, ss;
+        orc_micro_xs(p, p->mat_nuc[q], e, &sc, &ss, NULL);
+        a = a + p->mat_dens[q] * sc;
+        s = s + p->mat_dens[q] * ss;
+    }
+    *Sa = a;
+    *Ss = s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* collision physics (the paper's problems are restricted here to capture    */
+/* and elastic scattering, non-multiplying; the target is at rest)           */
+/* ------------------------------------------------------------------------ */
+
+/* Elastic scattering off a target of mass A at rest, isotropic in the centre
+ * of mass (two-body kinematics):
+ *   E'      = E (A^2 + 2 A mu + 1) / (A + 1)^2
+ *   mu_lab  = (1 + A mu) / sqrt(A^2 + 2 A mu + 1)                            */
+void orc_elastic(double A, double e, double mu_cm, double *e_out, double *mu_lab)
+{
+    double t = A * A + 2.0 * A * mu_cm + 1.0;
+    *e_out = e * (t / ((A + 1.0) * (A + 1.0)));
+    *mu_lab = (1.0 + A * mu_cm) / sqrt(t);
+}
+
+/* Rotate the unit direction d by polar cosine mu and azimuth phi about itself
+ * (standard direction-cosine update; a second frame is used when d is within
+ * 1e-10 of the z axis). */
+void orc_rotate(double d[3], double mu, double phi)
+{
+    double u = d[0], v = d[1], w = d[2];
+    double a = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double cp = cos(phi), sp = sin(phi);
+    double b = sqrt(fmax(0.0, 1.0 - w * w));
+    if (b > 1e-10) {
+        d[0] = mu * u + a * (u * w * cp - v * sp) / b;
+        d[1] = mu * v + a * (v * w * cp + u * sp) / b;
+        d[2] = mu * w - a * b * cp;
+    } else {
+        b = sqrt(fmax(0.0, 1.0 - v * v));
+        d[0] = mu * u + a * (u * v * cp - w * sp) / b;
+        d[1] = mu * v - a * b * cp;
+        d[2] = mu * w + a * (v * w * cp + u * sp) / b;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* geometry: surface tracking through constructive solid geometry           */
+/* ------------------------------------------------------------------------ */
+enum { S_NONE = -1, S_CYL = 0, S_XLO = 1, S_XHI = 2, S_YLO = 3, S_YHI = 4, S_ZLO = 5, S_ZHI = 6 };
+
+typedef struct {
+    double r[3], d[3];
+    double E, w;
+    int32_t mat;
+    int32_t ci, cj, inside; /* lattice cell and cylinder sense */
+    int32_t layer;          /* slab layer */
+    int32_t n_coll, n_cross;
+} particle;
+
+static int32_t lattice_material(const orc_problem *p, const particle *q)
+{
+    if (q->inside) return p->pin_mat[q->cj * p->nx + q->ci];
+    return p->mod_mat;
+}
+
+/* Locate a point: lattice cell floor(x / pitch), and inside the cell's
+ * cylinder when its squared distance to the axis is below r^2. */
+static void locate(const orc_problem *p, particle *q)
+{
+    if (p->geom_kind == GEOM_INFINITE) {
+        q->mat = p->inf_material;
+    } else if (p->geom_kind == GEOM_LATTICE) {
+        int32_t i = (int32_t)floor(q->r[0] / p->pitch), j = (int32_t)floor(q->r[1] / p->pitch);
+        if (i < 0) i = 0;
+        if (i > p->nx - 1) i = p->nx - 1;
+        if (j < 0) j = 0;
+        if (j > p->ny - 1) j = p->ny - 1;
+        q->ci = i; q->cj = j;
+        double dx = q->r[0] - ((double)i + 0.5) * p->pitch;
+        double dy = q->r[1] - ((double)j + 0.5) * p->pitch;
+        q->inside = (p->pin_mat[j * p->nx + i] >= 0) && (dx * dx + dy * dy < p->radius * p->radius);
+        q->mat = lattice_material(p, q);
+    } else {
+        int32_t l = 0;
+        while (l < p->n_layers - 1 && q->r[0] >= p->x_edges[l + 1]) ++l;
+        q->layer = l;
+        q->mat = p->layer_mat[l];
+    }
+}
+
+/* Distance along the direction to the nearest bounding surface of the current
+ * region and that surface's id.  Ties keep the first of cylinder, x, y, z. */
+static double distance_to_boundary(const orc_problem *p, const particle *q, int32_t *surf)
+{
+    const double INF = INFINITY;
+    double x = q->r[0], y = q->r[1], z = q->r[2];
+    double u = q->d[0], v = q->d[1], w = q->d[2];
+    double best = INF;
+    *surf = S_NONE;
+    if (p->geom_kind == GEOM_INFINITE) return INF;
+    if (p->geom_kind == GEOM_SLAB) {
+        double t = INF; int32_t s = S_NONE;
+        if (u > 0.0) { t = (p->x_edges[q->layer + 1] - x) / u; s = S_XHI; }
+        else if (u < 0.0) { t = (p->x_edges[q->layer] - x) / u; s = S_XLO; }
+        if (t < 0.0) t = 0.0;
+        *surf = s;
+        return t;
+    }
+    /* lattice cell (ci, cj); cylinder of radius r about the cell centre */
+    double P = p->pitch;
+    int32_t has_pin = p->pin_mat[q->cj * p->nx + q->ci] >= 0;
+    if (has_pin) {
+        double xp = x - ((double)q->ci + 0.5) * P, yp = y - ((double)q->cj + 0.5) * P;
+        double a = u * u + v * v;
+        double k = xp * u + yp * v;
+        double c = xp * xp + yp * yp - p->radius * p->radius;
+        double disc = k * k - a * c;
+        double t = INF;
+        if (a > 0.0) {
+            if (q->inside) {
+                t = (-k + sqrt(fmax(disc, 0.0))) / a;
+                if (t < 0.0) t = 0.0;
+            } else if (k < 0.0 && disc > 0.0) {
+                t = (-k - sqrt(disc)) / a;
+                if (t < 0.0) t = 0.0;
+            }
+        }
+        if (t < best) { best = t; *surf = S_CYL; }
+    }
+    if (!q->inside) {
+        if (u != 0.0) {
+            double t = (u > 0.0) ? (((double)q->ci + 1.0) * P - x) / u : ((double)q->ci * P - x) / u;
+            if (t < 0.0) t = 0.0;
+            if (t < best) { best = t; *surf = (u > 0.0) ? S_XHI : S_XLO; }
+        }
+        if (v != 0.0) {
+            double t = (v > 0.0) ? (((double)q->cj + 1.0) * P - y) / v : ((double)q->cj * P - y) / v;
+            if (t < 0.0) t = 0.0;
+            if (t < best) { best = t; *surf = (v > 0.0) ? S_YHI : S_YLO; }
+        }
+    }
+    if (w != 0.0) {
+        double t = (w > 0.0) ? (p->z1 - z) / w : (p->z0 - z) / w;
+        if (t < 0.0) t = 0.0;
+        if (t < best) { best = t; *surf = (w > 0.0) ? S_ZHI : S_ZLO; }
+    }
+    return best;
+}
+
+/* Outer face f (0..5 = x-, x+, y-, y+, z-, z+): reflect (flip the normal
+ * component, place the point exactly on the face) or leak.  Returns 1 when the
+ * particle leaked. */
+static int outer_face(const orc_problem *p, particle *q, int f, double face)
+{
+    int axis = f / 2;
+    if (p->bc[f] == BC_VACUUM) return 1;
+    q->d[axis] = -q->d[axis];
+    q->r[axis] = face;
+    return 0;
+}
+
+/* Cross surface s; returns 1 when the particle leaked. */
+static int cross_surface(const orc_problem *p, particle *q, int32_t s)
+{
+    q->n_cross += 1;
+    if (p->geom_kind == GEOM_SLAB) {
+        if (s == S_XHI) {
+            if (q->layer == p->n_layers - 1) return outer_face(p, q, 1, p->x_edges[p->n_layers]);
+            q->layer += 1;
+            q->r[0] = p->x_edges[q->layer];
+        } else {
+            if (q->layer == 0) return outer_face(p, q, 0, p->x_edges[0]);
+            q->r[0] = p->x_edges[q->layer];
+            q->layer -= 1;
+        }
+        q->mat = p->layer_mat[q->layer];
+        return 0;
+    }
+    double P = p->pitch;
+    switch (s) {
+    case S_CYL:
+        q->inside = !q->inside;
+        break;
+    case S_XHI:
+        if (q->ci == p->nx - 1) return outer_face(p, q, 1, (double)p->nx * P);
+        q->ci += 1; q->r[0] = (double)q->ci * P;
+        break;
+    case S_XLO:
+        if (q->ci == 0) return outer_face(p, q, 0, 0.0);
+        q->r[0] = (double)q->ci * P; q->ci -= 1;
+        break;
+    case S_YHI:
+        if (q->cj == p->ny - 1) return outer_face(p, q, 3, (double)p->ny * P);
+        q->cj += 1; q->r[1] = (double)q->cj * P;
+        break;
+    case S_YLO:
+        if (q->cj == 0) return outer_face(p, q, 2, 0.0);
+        q->r[1] = (double)q->cj * P; q->cj -= 1;
+        break;
+    case S_ZHI:
+        return outer_face(p, q, 5, p->z1);
+    case S_ZLO:
+        return outer_face(p, q, 4, p->z0);
+    default:
+        break;
+    }
+    q->mat = lattice_material(p, q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* tallies                                                                   */
+/* ------------------------------------------------------------------------ */
+static int64_t tally_bins(const orc_problem *p)
+{
+    switch (p->tally_kind) {
+    case TALLY_ENERGY: return p->n_ebins;
+    case TALLY_PIN: return (int64_t)p->nx * p->ny;
+    case TALLY_MESH: return (int64_t)p->mesh_dims[0] * p->mesh_dims[1] * p->mesh_dims[2];
+    case TALLY_SLAB: return p->n_layers;
+    }
+    return 0;
+}
+
+/* energy bins are [e_b, e_{b+1}); the top edge belongs to the last bin */
+static int64_t energy_bin(const orc_problem *p, double e)
+{
+    int64_t n = p->n_ebins;
+    if (e < p->e_edges[0] || e > p->e_edges[n]) return -1;
+    if (e == p->e_edges[n]) return n - 1;
+    int64_t b = 0;
+    while (b < n - 1 && e >= p->e_edges[b + 1]) ++b;
+    return b;
+}
+
+static int64_t mesh_cell(const orc_problem *p, const double r[3])
+{
+    int64_t idx[3];
+    for (int a = 0; a < 3; ++a) {
+        double lo = p->mesh_box[2 * a], hi = p->mesh_box[2 * a + 1];
+        if (r[a] < lo || r[a] > hi) return -1;
+        int64_t c = (int64_t)floor((r[a] - lo) / (hi - lo) * p->mesh_dims[a]);
+        if (c > p->mesh_dims[a] - 1) c = p->mesh_dims[a] - 1;
+        idx[a] = c;
+    }
+    return (idx[2] * p->mesh_dims[1] + idx[1]) * p->mesh_dims[0] + idx[0];
+}
+
+/* bin of a point event (collision) */
+static int64_t point_bin(const orc_problem *p, const particle *q)
+{
+    switch (p->tally_kind) {
+    case TALLY_ENERGY: return energy_bin(p, q->E);
+    case TALLY_PIN: return q->inside ? (int64_t)q->cj * p->nx + q->ci : -1;
+    case TALLY_MESH: return mesh_cell(p, q->r);
+    case TALLY_SLAB: return q->layer;
+    }
+    return -1;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Track-length score w * (length of the flight inside each bin).  For the
+ * mesh: the flight from r0 over length d is cut at every mesh plane it
+ * crosses; each piece is scored into the cell holding its midpoint. */
+static void score_flight(const orc_problem *p, const particle *q, const double r0[3], double d,
+                         double *tl)
+{
+    if (p->tally_kind != TALLY_MESH) {
+        int64_t b = point_bin(p, q);
+        if (b >= 0) tl[b] += q->w * d;
+        return;
+    }
+    double cuts[4096];
+    int nc = 0;
+    cuts[nc++] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double da = q->d[a];
+        if (da == 0.0) continue;
+        double lo = p->mesh_box[2 * a], hi = p->mesh_box[2 * a + 1];
+        double h = (hi - lo) / p->mesh_dims[a];
+        for (int32_t k = 0; k <= p->mesh_dims[a]; ++k) {
+            double t = (lo + k * h - r0[a]) / da;
+            if (t > 0.0 && t < d && nc < 4095) cuts[nc++] = t;
+        }
+    }
+    qsort(cuts, nc, sizeof(double), cmp_double);
+    cuts[nc++] = d;
+    for (int k = 0; k + 1 < nc; ++k) {
+        double len = cuts[k + 1] - cuts[k];
+        if (len <= 0.0) continue;
+        double tm = 0.5 * (cuts[k] + cuts[k + 1]);
+        double pm[3] = {r0[0] + tm * q->d[0], r0[1] + tm * q->d[1], r0[2] + tm * q->d[2]};
+        int64_t b = mesh_cell(p, pm);
+        if (b >= 0) tl[b] += q->w * len;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* one history, birth to death (paper section 2: history-based mode)        */
+/* ------------------------------------------------------------------------ */
+static void sample_source(const orc_problem *p, particle *q, rng_stream *rs)
+{
+    memset(q, 0, sizeof(*q));
+    q->E = p->src_E;
+    q->w = 1.0;
+    if (p->src_kind == SRC_BEAM) {
+        for (int a = 0; a < 3; ++a) { q->r[a] = p->src_pos[a]; q->d[a] = p->src_dir[a]; }
+    } else {
+        if (p->src_kind == SRC_BOX) {
+            for (int a = 0; a < 3; ++a) {
+                double lo = p->src_box[2 * a], hi = p->src_box[2 * a + 1];
+                q->r[a] = lo + (hi - lo) * next_u(rs);
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) q->r[a] = p->src_pos[a];
+        }
+        /* isotropic: mu = 2 xi - 1 is the z cosine, phi = 2 pi xi the azimuth */
+        double mu = 2.0 * next_u(rs) - 1.0;
+        double phi = 2.0 * M_PI * next_u(rs);
+        double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+        q->d[0] = s * cos(phi);
+        q->d[1] = s * sin(phi);
+        q->d[2] = mu;
+    }
+    locate(p, q);
+}
+
+static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, double *tl,
+                          double *coll, double *glob, orc_history *h)
+{
+    rng_stream rs = {seed, pid, 0, 0};
+    particle q;
+    sample_source(p, &q, &rs);
+    int fate = FATE_ALIVE;
+    double track = 0.0;
+    while (fate == FATE_ALIVE) {
+        if ((int64_t)q.n_coll + q.n_cross >= p->max_events) { fate = FATE_LOST; break; }
+        double Sa, Ss;
+        orc_macro_xs(p, q.mat, q.E, &Sa, &Ss);
+        double St = Sa + Ss;
+        /* distance to collision: -ln(xi) / Sigma_t */
+        double dc = -log(next_u(&rs)) / St;
+        int32_t surf;
+        double db = distance_to_boundary(p, &q, &surf);
+        double d = (db < dc) ? db : dc;
+        double r0[3] = {q.r[0], q.r[1], q.r[2]};
+        for (int a = 0; a < 3; ++a) q.r[a] = q.r[a] + d * q.d[a];
+        score_flight(p, &q, r0, d, tl);
+        glob[G_TRACK] += q.w * d;
+        glob[G_TRACK_ABS] += q.w * d * Sa;
+        track += d;
+        if (db < dc) {
+            glob[G_NCROSS] += 1.0;
+            int face_xhi = (p->geom_kind != GEOM_INFINITE) && (surf == S_XHI) &&
+                           ((p->geom_kind == GEOM_SLAB) ? (q.layer == p->n_layers - 1) : (q.ci == p->nx - 1));
+            if (cross_surface(p, &q, surf)) {
+                fate = FATE_LEAKED;
+                glob[G_LEAK] += q.w;
+                if (face_xhi) {
+                    glob[G_LEAK_XHI] += q.w;
+                    if (q.n_coll == 0) glob[G_LEAK_XHI_UNC] += q.w;
+                }
+            }
+            continue;
+        }
+        /* collision */
+        q.n_coll += 1;
+        glob[G_NCOLL] += 1.0;
+        {
+            int64_t b = point_bin(p, &q);
+            if (b >= 0) coll[b] += q.w / St;
+            glob[G_COLL_EST] += q.w / St;
+        }
+        /* analog absorption: absorbed when xi * Sigma_t < Sigma_a */
+        if (next_u(&rs) * St < Sa) {
+            glob[G_ABSORB] += q.w;
+            fate = FATE_ABSORBED;
+            break;
+        }
+        /* target nuclide: the first, in material order, whose running sum of
+         * density * sigma_s reaches xi * Sigma_s */
+        double target = next_u(&rs) * Ss;
+        double cum = 0.0;
+        int32_t nuc = -1;
+        for (int32_t qq = p->mat_off[q.mat]; qq < p->mat_off[q.mat + 1]; ++qq) {
+            double sc, ss;
+            orc_micro_xs(p, p->mat_nuc[qq], q.E, &sc, &ss, NULL);
+            double term = p->mat_dens[qq] * ss;
+            cum = cum + term;
+            if (term > 0.0) nuc = p->mat_nuc[qq];
+            if (cum >= target && term > 0.0) break;
+        }
+        double mu_cm = 2.0 * next_u(&rs) - 1.0;
+        double phi = 2.0 * M_PI * next_u(&rs);
+        double e_out, mu_lab;
+        orc_elastic(p->awr[nuc], q.E, mu_cm, &e_out, &mu_lab);
+        orc_rotate(q.d, mu_lab, phi);
+        q.E = e_out;
+        if (q.E < p->e_cut) {
+            glob[G_CUTOFF] += q.w;
+            fate = FATE_CUTOFF;
+        }
+    }
+    if (h) {
+        h->fate = fate;
+        h->n_coll = q.n_coll;
+        h->n_cross = q.n_cross;
+        h->n_draws = rs.n;
+        h->E_final = q.E;
+        h->track = track;
+        h->weight = q.w;
+    }
+}
+
+/* Run histories [first_pid, first_pid + n) and add their raw (un-normalised)
+ * scores into tl[n_bins], coll[n_bins], glob[N_GLOBAL].  The pids are split
+ * into at most 64 contiguous blocks, each tracked in pid order by one thread
+ * and summed in block order, so the result does not depend on the thread
+ * count.  hist (nullable) receives one record per pid. */
+int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *tl,
+            double *coll, double *glob, orc_history *hist, int n_threads)
+{
+    int64_t nb = tally_bins(p);
+    int64_t n_blocks = n < 64 ? (int64_t)n : 64;
+    if (n_blocks == 0) return 0;
+    int64_t stride = nb * 2 + N_GLOBAL;
+    double *part = (double *)calloc((size_t)(n_blocks * stride), sizeof(double));
+    if (!part) return -1;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t b = 0; b < n_blocks; ++b) {
+        uint64_t lo = (uint64_t)b * n / (uint64_t)n_blocks;
+        uint64_t hi = (uint64_t)(b + 1) * n / (uint64_t)n_blocks;
+        double *t = part + b * stride;
+        for (uint64_t i = lo; i < hi; ++i)
+            track_history(p, seed, first_pid + i, t, t + nb, t + 2 * nb, hist ? hist + i : NULL);
+    }
+    for (int64_t b = 0; b < n_blocks; ++b) {
+        const double *t = part + b * stride;
+        for (int64_t k = 0; k < nb; ++k) { tl[k] += t[k]; coll[k] += t[nb + k]; }
+        for (int k = 0; k < N_GLOBAL; ++k) glob[k] += t[2 * nb + k];
+    }
+    free(part);
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
