@@ -1,0 +1,304 @@
+/*
+ * mc.h -- C ABI of the MI355X Monte Carlo transport hot path (libmc.so).
+ *
+ * The library runs the event-based tracking loop of continuous-energy,
+ * fixed-source, non-multiplying neutral-particle transport (capture and
+ * elastic scattering) on one AMD Instinct MI355X (gfx950), the GPU mode of the
+ * paper "Performance Portable Monte Carlo Particle Transport on Intel, NVIDIA,
+ * and AMD GPUs" (Tramm et al.): particles in flight are processed one event
+ * type at a time over the whole bank (section 2, "Event-Based Parallelism"),
+ * the cross-section lookup queue is sorted by material and energy first
+ * (section 2, "Sorting"), the number of particles in flight is capped and
+ * refilled from the batch (section 2, "In-Flight Particles"), and tallies are
+ * scored during active batches (section 2, "Tallying"; section 4.1).
+ *
+ * Conventions for every entry point:
+ *   - Return value: MC_OK (0) or a negative mc_status.  No C++ exception
+ *     crosses the ABI.  mc_last_error() gives the reason as text.
+ *   - Host arrays passed to mc_init_* are read during the call and deep-copied
+ *     to device memory; the caller keeps ownership.
+ *   - Pointers documented as "device" must point to device memory of the
+ *     context's GPU (for example a torch tensor's data_ptr()); the library
+ *     neither frees nor retains them beyond the call.
+ *   - All GPU work is enqueued on the context's HIP stream (mc_create /
+ *     mc_set_stream).  Calls that return results to host memory synchronize
+ *     that stream; the device-output calls (mc_lookup_*, mc_sort_queue) do not.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mc_status {
+    MC_OK = 0,
+    MC_EINVAL = -1,  /* invalid argument: non-increasing grid, density <= 0, bad id, size */
+    MC_ENOMEM = -2,  /* device or host allocation failed */
+    MC_EHIP = -3,    /* a HIP runtime call failed (text in mc_last_error) */
+    MC_ELOST = -4,   /* more lost particles than mc_run_opts.max_lost */
+    MC_ESTATE = -5,  /* call order: materials before geometry before runs */
+    MC_ENODEV = -6   /* no usable gfx950 device */
+} mc_status;
+
+typedef struct mc_ctx mc_ctx; /* opaque */
+
+/* geometry, boundary, source and tally kinds */
+enum { MC_GEOM_INFINITE = 0, MC_GEOM_LATTICE = 1, MC_GEOM_SLAB = 2 };
+enum { MC_BC_REFLECT = 0, MC_BC_VACUUM = 1 };
+enum { MC_SRC_POINT = 0, MC_SRC_BOX = 1, MC_SRC_BEAM = 2 };
+enum { MC_TALLY_ENERGY = 0, MC_TALLY_PIN = 1, MC_TALLY_MESH = 2, MC_TALLY_SLAB = 3 };
+
+/* tally ids for mc_get_tallies */
+enum { MC_T_FLUX_TRACK = 0, MC_T_FLUX_COLLISION = 1, MC_T_GLOBAL = 2 };
+
+/* bins of the MC_T_GLOBAL tally (each a per-source-particle mean) */
+enum {
+    MC_G_TRACK = 0,        /* sum of w*d over every flight (total track length) */
+    MC_G_COLL_EST = 1,     /* sum of w/Sigma_t over collisions                  */
+    MC_G_ABSORB = 2,       /* weight absorbed                                   */
+    MC_G_CUTOFF = 3,       /* weight killed by the energy cutoff                */
+    MC_G_LEAK = 4,         /* weight leaked through vacuum faces                */
+    MC_G_TRACK_ABS = 5,    /* sum of w*d*Sigma_a                                */
+    MC_G_NCOLL = 6,        /* collisions                                        */
+    MC_G_NCROSS = 7,       /* surface crossings                                 */
+    MC_G_LEAK_XHI = 8,     /* weight leaked through the x+ face                 */
+    MC_G_LEAK_XHI_UNC = 9, /* the same, for particles that never collided       */
+    MC_N_GLOBAL = 10
+};
+
+/* fate codes of mc_history.fate */
+enum { MC_FATE_ABSORBED = 1, MC_FATE_CUTOFF = 2, MC_FATE_LEAKED = 3, MC_FATE_LOST = 4 };
+
+/*
+ * Problem geometry, source and tally (one struct; unused members are ignored).
+ *
+ * MC_GEOM_INFINITE: one material everywhere, no surfaces.
+ * MC_GEOM_LATTICE : nx*ny square cells of side `pitch` covering
+ *   [0, nx*pitch] x [0, ny*pitch] x [z0, z1]; cell (i, j) holds a z-cylinder
+ *   of radius `radius` (< pitch/2) about its centre filled with
+ *   pin_material[j*nx + i] (-1: no cylinder), and moderator_material outside.
+ *   A 2-level assembly lattice whose assembly pitch is a whole number of pin
+ *   pitches is described as the equivalent flat lattice.
+ * MC_GEOM_SLAB    : layers along x with edges x_edges[0..n_layers], infinite in
+ *   y and z; layer l holds layer_material[l].
+ * bc[6]           : boundary condition of the x-, x+, y-, y+, z-, z+ faces.
+ * Source: MC_SRC_POINT (isotropic at source_pos), MC_SRC_BOX (uniform in
+ *   source_box = {x0,x1,y0,y1,z0,z1}, isotropic), MC_SRC_BEAM (at source_pos
+ *   along source_dir); every source particle starts at source_energy (eV),
+ *   weight 1.
+ * Tally (binning of MC_T_FLUX_TRACK and MC_T_FLUX_COLLISION):
+ *   MC_TALLY_ENERGY: energy_edges[0..n_energy_bins] (eV, increasing; bins are
+ *     [e_b, e_{b+1}), the top edge belongs to the last bin);
+ *   MC_TALLY_PIN: one bin per lattice cell, scored inside its cylinder;
+ *   MC_TALLY_MESH: mesh_dims[0]*mesh_dims[1]*mesh_dims[2] cells over mesh_box,
+ *     x fastest; the track-length score of a flight is split over the cells
+ *     it crosses;
+ *   MC_TALLY_SLAB: one bin per layer.
+ * energy_cutoff: particles whose energy falls below it are killed (eV).
+ * All arrays are host memory, copied during mc_init_geometry.
+ */
+typedef struct mc_geometry_desc {
+    int32_t kind;
+    int32_t material;            /* MC_GEOM_INFINITE */
+    int32_t nx, ny;              /* MC_GEOM_LATTICE  */
+    double pitch, radius, z0, z1;
+    const int32_t *pin_material;
+    int32_t moderator_material;
+    int32_t bc[6];
+    int32_t n_layers;            /* MC_GEOM_SLAB     */
+    const double *x_edges;
+    const int32_t *layer_material;
+    int32_t source_kind;
+    double source_pos[3];
+    double source_box[6];
+    double source_dir[3];
+    double source_energy;
+    int32_t tally_kind;
+    int32_t n_energy_bins;
+    const double *energy_edges;
+    int32_t mesh_dims[3];
+    double mesh_box[6];
+    double energy_cutoff;
+} mc_geometry_desc;
+
+/* Options of one mc_run_batch call (all-zero = defaults). */
+typedef struct mc_run_opts {
+    uint64_t in_flight;    /* particle-bank capacity; 0: min(n, 1,048,576).  The paper
+                              caps particles in flight and refills from the batch
+                              (section 2, "In-Flight Particles"). */
+    uint64_t sort_min;     /* sort the lookup queue by (material, energy bin) when it holds
+                              at least this many particles; 0: 16,384; UINT64_MAX: never */
+    int32_t no_tally;      /* 1: inactive batch (no flux tallies scored); global tallies
+                              are still scored */
+    int32_t time_kernels;  /* 1: time every lookup launch with HIP events (mc_get_stats) */
+    int64_t max_events;    /* per-history event cap; past it the particle is killed as
+                              lost; 0: 100,000 */
+    uint64_t max_lost;     /* lost particles tolerated before MC_ELOST; 0: none tolerated */
+    void *history_log;     /* device, nullable: n mc_history records, one per pid
+                              (record k = pid first_pid + k) */
+} mc_run_opts;
+
+/* Per-history record written when mc_run_opts.history_log is set. */
+typedef struct mc_history {
+    int32_t fate, n_coll, n_cross, pad;
+    uint64_t n_draws;      /* random numbers consumed */
+    double E_final;        /* energy at death (eV) */
+    double track;          /* total path length (cm) */
+    double weight;         /* weight at death */
+} mc_history;
+
+/* Counters of the last mc_run_batch. */
+typedef struct mc_stats {
+    uint64_t iterations;        /* event-loop iterations */
+    uint64_t lookups;           /* macroscopic lookups (particles looked up) */
+    uint64_t nuclide_lookups;   /* sum over lookups of the material's nuclide count */
+    uint64_t lookup_launches;   /* lookup-kernel launches */
+    uint64_t sorted_lookups;    /* lookups done on a sorted queue */
+    uint64_t lost;              /* particles killed by the event cap */
+    uint64_t lookup_bytes;      /* algorithmic bytes of the lookups: per lookup
+                                   36 + 56 * n_nuclides */
+    double lookup_ms;           /* summed lookup-kernel time (time_kernels = 1), ms */
+    double batch_ms;            /* wall time of the batch on the stream, ms */
+} mc_stats;
+
+/* Batch statistics of one tally bin range (mc_get_tallies). */
+typedef struct mc_tally_meta {
+    uint64_t n_batches;
+    uint64_t n_bins;
+    uint64_t histories;    /* histories summed over all batches */
+} mc_tally_meta;
+
+/*
+ * Create a context on HIP device `device` (must be gfx950) that enqueues its
+ * work on `hip_stream` (a hipStream_t; NULL = the device's null stream).
+ * *out receives the context; on failure *out is NULL and the return value
+ * says why (MC_ENODEV, MC_EHIP).
+ */
+int mc_create(mc_ctx **out, int device, void *hip_stream);
+
+/* Free every device buffer of the context (synchronizes its stream). */
+void mc_destroy(mc_ctx *ctx);
+
+/* Text of the last error on this context ("" if none); owned by the context. */
+const char *mc_last_error(const mc_ctx *ctx);
+
+/* Make later calls enqueue on `hip_stream`. */
+int mc_set_stream(mc_ctx *ctx, void *hip_stream);
+
+/*
+ * Nuclide and material data (paper section 4.1: hundreds of nuclides per
+ * material, whose per-nuclide lookups and sum form the dominant cost).
+ *   n_nuc            number of nuclides (>= 1)
+ *   grid_len[k]      points of nuclide k's energy grid (>= 2)
+ *   E[k]             host, grid_len[k] fp64 energies (eV), strictly increasing
+ *   sig_c[k], sig_s[k] host, grid_len[k] fp64 capture / elastic cross sections
+ *                    (barns, >= 0) tabulated on E[k]; between points the
+ *                    library interpolates linearly
+ *   awr[k]           target mass ratio A (> 0)
+ *   n_mat            number of materials (>= 1)
+ *   mat_len[m]       nuclides in material m (>= 1)
+ *   mat_nuc          concatenated nuclide ids of all materials, in material order
+ *   mat_dens         concatenated atom densities (atoms/(barn cm), > 0)
+ *   n_hash_bins      M, bins of the logarithmic hash grid over
+ *                    [min_k E[k][0], max_k E[k][last]] (>= 1; 8192 typical)
+ * Builds the per-material hash bounds on the host.  Replaces earlier data.
+ * Errors: MC_EINVAL with the offending nuclide/material named.
+ */
+int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len,
+                      const double *const *E, const double *const *sig_c,
+                      const double *const *sig_s, const double *awr, int32_t n_mat,
+                      const int32_t *mat_len, const int32_t *mat_nuc, const double *mat_dens,
+                      int32_t n_hash_bins);
+
+/* Geometry, source and tally (see mc_geometry_desc).  Requires materials.
+ * Resets the tallies.  Errors: MC_EINVAL, MC_ESTATE. */
+int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *desc);
+
+/*
+ * Track histories with particle ids [first_pid, first_pid + n) to death and
+ * add them to the tallies as one batch.  Particle pid draws its random
+ * numbers from the Philox4x32-10 stream keyed by `seed` with counter
+ * (draw/2, lineage, pid), so a history does not depend on what else runs.
+ * opts may be NULL (defaults).  Synchronizes the stream at the end.
+ * Errors: MC_ESTATE (no geometry), MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST.
+ */
+int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n,
+                 const mc_run_opts *opts);
+
+/*
+ * Batch statistics of tally `tally_id` (MC_T_*) over every batch since the
+ * last reset: mean[b] = S1/B and stderr_[b] = sqrt((S2/B - mean^2)/(B - 1))
+ * of the per-source-particle batch values (stderr_ is 0 when B < 2).
+ * mean and stderr_ are host arrays of n_bins entries (n_bins must equal the
+ * tally's bin count: MC_N_GLOBAL for MC_T_GLOBAL); either may be NULL; meta
+ * may be NULL.
+ */
+int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_, size_t n_bins,
+                   mc_tally_meta *meta);
+
+/* Zero every tally's batch sums. */
+int mc_reset_tallies(mc_ctx *ctx);
+
+/* Counters of the last mc_run_batch (host struct). */
+int mc_get_stats(mc_ctx *ctx, mc_stats *out);
+
+/*
+ * Macroscopic cross sections of n (energy, material) pairs, the lookup step on
+ * its own (paper section 2, "Sorting": the lookup is typically the most
+ * expensive part of the simulation).
+ *   E         device, n fp64 energies (eV)
+ *   mat       device, n int32 material ids
+ *   sig_a     device, n fp64 outputs: sum over the material's nuclides of
+ *             density * capture cross section, in material order
+ *   sig_s     device, n fp64 outputs: the same for elastic scattering
+ *   sorted    1: sort the pairs by (material, hash bin) on the device first
+ *             (needs no caller memory); 0: process them in the given order
+ * Errors: MC_ESTATE (no materials), MC_EINVAL (bad material id on the host
+ * side is not checked: ids must be in [0, n_mat)).
+ */
+int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *sig_a,
+                    double *sig_s, int32_t sorted);
+
+/*
+ * Per-nuclide results of the same lookup for n pairs that all use material
+ * `mat` (n_k = its nuclide count):
+ *   E        device, n fp64 energies
+ *   idx      device, n*n_k int32: grid index i(E) = max{j : E_j <= E} clamped
+ *            to [0, N-2], for nuclide q of the material at [p*n_k + q]
+ *   sig_c, sig_s device, n*n_k fp64 interpolated microscopic cross sections
+ * Any output pointer may be NULL.
+ */
+int mc_lookup_nuclides(mc_ctx *ctx, int32_t mat, size_t n, const double *E, int32_t *idx,
+                       double *sig_c, double *sig_s);
+
+/*
+ * The sort step on its own (paper section 2, "Sorting"): key[p] = mat[p] * M +
+ * b(E[p]) with b the hash bin, then perm receives 0..n-1 ordered by key
+ * (order among equal keys unspecified) and keys_sorted the keys in that order.
+ *   E, mat      device inputs (n each)
+ *   perm        device, n uint32 outputs
+ *   keys_sorted device, n uint32 outputs (nullable)
+ */
+int mc_sort_queue(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, uint32_t *perm,
+                  uint32_t *keys_sorted);
+
+/*
+ * Host-only helper (no device needed): the hash bounds the library builds for
+ * one grid.  lo[b] = i(E_b) for b = 0..M-1, E_b = emin * exp(b * ln(emax/emin)/M),
+ * and lo[M] = N-2, where i() is the grid index of mc_lookup_nuclides.  lo is a
+ * host array of M + 1 entries.
+ */
+int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t M, int32_t *lo);
+
+/* Library version string. */
+const char *mc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MC_H */

@@ -91,6 +91,8 @@ def lib():
                                  P(D), C.c_void_p, C.c_int]
         _lib.orc_run.restype = C.c_int
         _lib.orc_max_threads.restype = C.c_int
+        _lib.orc_micro_xs_many.argtypes = [P(_Problem), C.c_int32, C.c_int64, P(D), P(C.c_int64), P(D), P(D)]
+        _lib.orc_macro_xs_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D), P(D)]
     return _lib
 
 
@@ -181,28 +183,23 @@ def grid_index(grid: np.ndarray, e: float) -> int:
 
 
 def micro_xs(op: OracleProblem, nuc: int, energies):
-    L = lib()
-    energies = np.asarray(energies, np.float64)
-    sc = np.empty(energies.size)
-    ss = np.empty(energies.size)
-    idx = np.empty(energies.size, np.int64)
-    a, b, i = C.c_double(), C.c_double(), C.c_int64()
-    for k, e in enumerate(energies):
-        L.orc_micro_xs(op.ref(), nuc, float(e), C.byref(a), C.byref(b), C.byref(i))
-        sc[k], ss[k], idx[k] = a.value, b.value, i.value
+    """(grid index, sigma_c, sigma_s) of nuclide ``nuc`` at each energy."""
+    e = np.ascontiguousarray(energies, np.float64).ravel()
+    sc = np.empty(e.size)
+    ss = np.empty(e.size)
+    idx = np.empty(e.size, np.int64)
+    lib().orc_micro_xs_many(op.ref(), nuc, e.size, _dptr(e), idx.ctypes.data_as(C.POINTER(C.c_int64)),
+                            _dptr(sc), _dptr(ss))
     return idx, sc, ss
 
 
 def macro_xs(op: OracleProblem, mats, energies):
-    L = lib()
-    energies = np.asarray(energies, np.float64)
-    mats = np.broadcast_to(np.asarray(mats, np.int32), energies.shape)
-    Sa = np.empty(energies.size)
-    Ss = np.empty(energies.size)
-    a, b = C.c_double(), C.c_double()
-    for k, (m, e) in enumerate(zip(mats.ravel(), energies.ravel())):
-        L.orc_macro_xs(op.ref(), int(m), float(e), C.byref(a), C.byref(b))
-        Sa[k], Ss[k] = a.value, b.value
+    """(Sigma_a, Sigma_s) of each (material, energy) pair."""
+    e = np.ascontiguousarray(energies, np.float64).ravel()
+    m = np.ascontiguousarray(np.broadcast_to(np.asarray(mats, np.int32), np.shape(energies)), np.int32).ravel()
+    Sa = np.empty(e.size)
+    Ss = np.empty(e.size)
+    lib().orc_macro_xs_many(op.ref(), e.size, _iptr(m), _dptr(e), _dptr(Sa), _dptr(Ss))
     return Sa, Ss
 
 

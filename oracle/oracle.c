@@ -654,3 +654,19 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* Vector forms of the two lookups above, for the tests (plain loops). */
+void orc_micro_xs_many(const orc_problem *p, int32_t k, int64_t n, const double *e, int64_t *idx,
+                       double *sc, double *ss)
+{
+    for (int64_t i = 0; i < n; ++i) orc_micro_xs(p, k, e[i], sc + i, ss + i, idx + i);
+}
+
+void orc_macro_xs_many(const orc_problem *p, int64_t n, const int32_t *mat, const double *e, double *Sa,
+                       double *Ss)
+{
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) orc_macro_xs(p, mat[i], e[i], Sa + i, Ss + i);
+}

@@ -1,0 +1,353 @@
+// mc_device.h -- device-side data layout and per-particle primitives of the
+// gfx950 transport path.  Every expression here is compiled with fp
+// contraction off (see the pragma below and -ffp-contract=off on the hipcc
+// line) so that interpolation, macroscopic sums and kinematics round exactly
+// as written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace mc {
+
+constexpr int WG = 256;          // threads per workgroup of every event kernel
+constexpr int WAVES = WG / 64;   // wave64
+constexpr int TILE_ITEMS = 16;   // items per thread in the queue-building kernels
+constexpr int TILE = WG * TILE_ITEMS;
+constexpr int MAX_LDS_BINS = 1024;  // tallies with more bins use the mesh path
+
+// particle flags
+constexpr uint8_t F_ALIVE = 1, F_LOOKUP = 2;
+// event codes written by the advance kernel
+enum : uint8_t { EV_COLLIDE = 0, EV_CYL = 1, EV_XLO = 2, EV_XHI = 3, EV_YLO = 4, EV_YHI = 5,
+                 EV_ZLO = 6, EV_ZHI = 7 };
+enum { GEOM_INFINITE = 0, GEOM_LATTICE = 1, GEOM_SLAB = 2 };
+enum { BC_REFLECT = 0, BC_VACUUM = 1 };
+enum { SRC_POINT = 0, SRC_BOX = 1, SRC_BEAM = 2 };
+enum { TALLY_ENERGY = 0, TALLY_PIN = 1, TALLY_MESH = 2, TALLY_SLAB = 3 };
+enum { G_TRACK = 0, G_COLL_EST = 1, G_ABSORB = 2, G_CUTOFF = 3, G_LEAK = 4, G_TRACK_ABS = 5,
+       G_NCOLL = 6, G_NCROSS = 7, G_LEAK_XHI = 8, G_LEAK_XHI_UNC = 9, N_GLOBAL = 10 };
+enum { FATE_ABSORBED = 1, FATE_CUTOFF = 2, FATE_LEAKED = 3, FATE_LOST = 4 };
+
+// One nuclide entry of a material, in material order: where its grid lives
+// in the concatenated tables, how long it is, and its atom density.
+struct MatNuc {
+    uint32_t off;   // first point of the nuclide's grid in Eg / xs
+    uint32_t len;   // number of grid points
+    double dens;    // atoms / (barn cm)
+};
+
+// Cross-section tables in HBM.
+//   Eg[p]      fp64 grid energies of every nuclide, concatenated
+//   xs[p]      {sigma_c, sigma_s} at the same point (16 B, one load per point)
+//   hash       per material m: (M + 1) rows of n_k uint32 bounds, row b holding
+//              i_q(E_b) for the material's nuclides q (bin-major so that one
+//              particle's bounds for all its nuclides are contiguous)
+struct XsDev {
+    const double *Eg;
+    const double2 *xs;
+    const double *awr;         // per nuclide
+    const int32_t *mat_off;    // [n_mat + 1] into mat_nuc / mnuc
+    const int32_t *mat_nuc;    // nuclide ids in material order
+    const MatNuc *mnuc;        // per (material, position)
+    const uint32_t *hash;
+    const uint64_t *hash_off;  // [n_mat] start of material m's rows
+    int32_t n_mat;
+    int32_t M;                 // hash bins
+    double ln_emin, inv_delta; // bin b = floor((ln E - ln emin) * inv_delta)
+};
+
+struct GeomDev {
+    int32_t kind, inf_mat;
+    int32_t nx, ny;
+    double pitch, radius, z0, z1;
+    const int32_t *pin_mat;
+    int32_t mod_mat;
+    int32_t bc[6];
+    int32_t n_layers;
+    const double *x_edges;
+    const int32_t *layer_mat;
+    int32_t src_kind;
+    double src_pos[3], src_box[6], src_dir[3], src_E;
+    int32_t tally_kind, n_bins, n_ebins;
+    const double *e_edges;
+    int32_t mesh_dims[3];
+    double mesh_lo[3], mesh_hi[3];
+    double e_cut;
+};
+
+// Structure-of-arrays particle bank (capacity C slots) and its queues.
+struct BankDev {
+    double *x, *y, *z, *u, *v, *w, *E, *wt, *Sa, *Ss, *track;
+    int32_t *mat, *cell, *ncoll, *ncross;
+    uint8_t *flags, *inside, *event;
+    uint64_t *pid;
+    uint32_t *ndraw, *lineage;
+    uint32_t *A, *L, *Ls, *Lkey, *Qc, *Qx;   // alive, lookup, sorted lookup, keys, collide, cross
+    uint32_t *tile_cnt;                       // per-tile counts of the queue kernels
+    uint32_t C;
+};
+
+// Queue sizes of one event-loop iteration (a ring of two, by iteration parity).
+struct Counters {
+    uint64_t issued;   // histories started so far in this batch
+    uint32_t nA, nL;   // alive and lookup queue lengths
+    uint32_t nC, nX;   // collide and cross queue lengths
+    uint32_t n_new, pad;
+};
+
+// Per-workgroup tally rows: workgroup g of an event kernel adds its partial
+// sums into row g, and only that workgroup writes the row, so no atomics and
+// a fixed summation order.
+struct TallyDev {
+    double *tl;     // [rows][n_bins] track-length flux (lattice / energy / slab)
+    double *coll;   // [rows][n_bins] collision estimator
+    double *glob;   // [rows][N_GLOBAL]
+    double *mesh_tl, *mesh_coll;  // [n_bins] mesh tallies (atomic accumulation)
+    int32_t n_bins, rows;
+    int32_t enabled;  // 0: inactive batch, binned flux tallies off
+};
+
+struct HistLog {
+    int32_t fate, n_coll, n_cross, pad;
+    uint64_t n_draws;
+    double E_final, track, weight;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies, a swap-and-xor of the halves with the key, key bumped by the
+// golden-ratio / sqrt(3)-1 Weyl increments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a0 = 0xD2511F53u * c.x, h0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t a1 = 0xCD9E8D57u * c.z, h1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(h1 ^ c.y ^ k.x, a1, h0 ^ c.w ^ k.y, a0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// The stream of one particle: draw n uses counter (n/2, lineage, pid) under
+// key seed; even draws take output words (y:x), odd draws (w:z); the top 52
+// bits give u = (m + 1/2) 2^-52 in (0, 1).
+struct Rng {
+    uint64_t seed, pid;
+    uint32_t lineage, n;
+    uint4 blk;
+    bool have;
+
+    __device__ __forceinline__ Rng(uint64_t s, uint64_t p, uint32_t lin, uint32_t n0)
+        : seed(s), pid(p), lineage(lin), n(n0), blk(make_uint4(0, 0, 0, 0)), have(false) {}
+
+    __device__ __forceinline__ double next()
+    {
+        if (!have || (n & 1u) == 0u) {
+            blk = philox4x32_10(make_uint4(n >> 1, lineage, (uint32_t)pid, (uint32_t)(pid >> 32)),
+                                make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+            have = true;
+        }
+        const uint64_t bits = (n & 1u) ? (((uint64_t)blk.w << 32) | blk.z)
+                                       : (((uint64_t)blk.y << 32) | blk.x);
+        n += 1;
+        return ((double)(bits >> 12) + 0.5) * 0x1p-52;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// cross-section lookup
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t hash_bin(const XsDev &xs, double e)
+{
+    const double t = (log(e) - xs.ln_emin) * xs.inv_delta;
+    int32_t b = (t > 0.0) ? (int32_t)t : 0;
+    return b < xs.M - 1 ? b : xs.M - 1;
+}
+
+// Grid index i(E) = max{j : E_j <= E} clamped to [0, N-2].  [lo, hi] is the
+// hash bracket of E's bin; the bisection finds the largest j in it with
+// E_j <= E and the two walks then correct for a bin computed one off (the
+// device logarithm may round differently from the host's at a bin edge).
+__device__ __forceinline__ uint32_t grid_find(const double *__restrict__ g, uint32_t n, uint32_t lo,
+                                              uint32_t hi, double e)
+{
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1u) >> 1;
+        if (g[mid] <= e) lo = mid; else hi = mid - 1u;
+    }
+    uint32_t i = lo;
+    while (i > 0u && e < g[i]) --i;
+    while (i + 2u < n && e >= g[i + 1u]) ++i;
+    return i;
+}
+
+// Micro cross sections of one nuclide at E from interval i (linear in E).
+__device__ __forceinline__ void lerp_xs(const XsDev &xs, uint32_t off, uint32_t i, double e,
+                                        double &sc, double &ss)
+{
+    const double e0 = xs.Eg[off + i], e1 = xs.Eg[off + i + 1u];
+    const double2 x0 = xs.xs[off + i], x1 = xs.xs[off + i + 1u];
+    const double f = (e - e0) / (e1 - e0);
+    sc = x0.x + f * (x1.x - x0.x);
+    ss = x0.y + f * (x1.y - x0.y);
+}
+
+// Hash row pointer of bin b of material m (global memory).
+__device__ __forceinline__ const uint32_t *hash_row(const XsDev &xs, int32_t m, int32_t b, int32_t nk)
+{
+    return xs.hash + xs.hash_off[m] + (uint64_t)b * (uint64_t)nk;
+}
+
+// sigma_s of nuclide position q of material m at E (collision kernel re-gather).
+__device__ __forceinline__ double micro_scatter(const XsDev &xs, int32_t m, int32_t q, int32_t nk,
+                                                int32_t b, double e)
+{
+    const MatNuc mn = xs.mnuc[xs.mat_off[m] + q];
+    const uint32_t *h = hash_row(xs, m, b, nk);
+    const uint32_t i = grid_find(xs.Eg + mn.off, mn.len, h[q], h[nk + q], e);
+    double sc, ss;
+    lerp_xs(xs, mn.off, i, e, sc, ss);
+    return ss;
+}
+
+// ---------------------------------------------------------------------------
+// kinematics
+// ---------------------------------------------------------------------------
+// Elastic scattering off a target of mass ratio A at rest, isotropic in the
+// centre-of-mass frame with cosine mu: E' = E (A^2 + 2 A mu + 1)/(A + 1)^2 and
+// lab cosine (1 + A mu)/sqrt(A^2 + 2 A mu + 1).
+__device__ __forceinline__ void elastic_at_rest(double A, double e, double mu, double &e_out,
+                                                double &mu_lab)
+{
+    const double q = A * A + 2.0 * A * mu + 1.0;
+    e_out = e * (q / ((A + 1.0) * (A + 1.0)));
+    mu_lab = (1.0 + A * mu) / sqrt(q);
+}
+
+// Turn direction (u, v, w) through polar cosine mu and azimuth phi.
+__device__ __forceinline__ void turn(double &u, double &v, double &w, double mu, double phi)
+{
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    double den = sqrt(fmax(0.0, 1.0 - w * w));
+    double nu, nv, nw;
+    if (den > 1e-10) {
+        nu = mu * u + st * (u * w * cp - v * sp) / den;
+        nv = mu * v + st * (v * w * cp + u * sp) / den;
+        nw = mu * w - st * den * cp;
+    } else {
+        den = sqrt(fmax(0.0, 1.0 - v * v));
+        nu = mu * u + st * (u * v * cp - w * sp) / den;
+        nv = mu * v - st * den * cp;
+        nw = mu * w + st * (v * w * cp + u * sp) / den;
+    }
+    u = nu; v = nv; w = nw;
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t region_material(const GeomDev &g, int32_t cell, bool inside)
+{
+    if (g.kind == GEOM_LATTICE) return inside ? g.pin_mat[cell] : g.mod_mat;
+    if (g.kind == GEOM_SLAB) return g.layer_mat[cell];
+    return g.inf_mat;
+}
+
+// Cell and cylinder sense of a point (lattice) or its layer (slab).
+__device__ __forceinline__ void locate_point(const GeomDev &g, double x, double y, int32_t &cell,
+                                             bool &inside)
+{
+    inside = false;
+    cell = 0;
+    if (g.kind == GEOM_LATTICE) {
+        int32_t i = (int32_t)floor(x / g.pitch), j = (int32_t)floor(y / g.pitch);
+        i = i < 0 ? 0 : (i > g.nx - 1 ? g.nx - 1 : i);
+        j = j < 0 ? 0 : (j > g.ny - 1 ? g.ny - 1 : j);
+        cell = j * g.nx + i;
+        const double dx = x - ((double)i + 0.5) * g.pitch, dy = y - ((double)j + 0.5) * g.pitch;
+        inside = g.pin_mat[cell] >= 0 && (dx * dx + dy * dy < g.radius * g.radius);
+    } else if (g.kind == GEOM_SLAB) {
+        int32_t l = 0;
+        while (l < g.n_layers - 1 && x >= g.x_edges[l + 1]) ++l;
+        cell = l;
+    }
+}
+
+// Distance to the nearest surface bounding the particle's region and which
+// one (ties resolved in the order cylinder, x, y, z).
+__device__ __forceinline__ double surface_distance(const GeomDev &g, double x, double y, double z,
+                                                   double u, double v, double w, int32_t cell,
+                                                   bool inside, uint8_t &ev)
+{
+    ev = EV_COLLIDE;
+    double best = INFINITY;
+    if (g.kind == GEOM_INFINITE) return best;
+    if (g.kind == GEOM_SLAB) {
+        if (u > 0.0) { best = (g.x_edges[cell + 1] - x) / u; ev = EV_XHI; }
+        else if (u < 0.0) { best = (g.x_edges[cell] - x) / u; ev = EV_XLO; }
+        return best < 0.0 ? 0.0 : best;
+    }
+    const int32_t ci = cell % g.nx, cj = cell / g.nx;
+    const double P = g.pitch;
+    if (g.pin_mat[cell] >= 0) {
+        const double xr = x - ((double)ci + 0.5) * P, yr = y - ((double)cj + 0.5) * P;
+        const double a = u * u + v * v;
+        const double k = xr * u + yr * v;
+        const double c = xr * xr + yr * yr - g.radius * g.radius;
+        const double disc = k * k - a * c;
+        double t = INFINITY;
+        if (a > 0.0) {
+            if (inside) t = fmax((-k + sqrt(fmax(disc, 0.0))) / a, 0.0);
+            else if (k < 0.0 && disc > 0.0) t = fmax((-k - sqrt(disc)) / a, 0.0);
+        }
+        if (t < best) { best = t; ev = EV_CYL; }
+    }
+    if (!inside) {
+        if (u != 0.0) {
+            const double t = fmax((u > 0.0 ? ((double)ci + 1.0) * P - x : (double)ci * P - x) / u, 0.0);
+            if (t < best) { best = t; ev = u > 0.0 ? EV_XHI : EV_XLO; }
+        }
+        if (v != 0.0) {
+            const double t = fmax((v > 0.0 ? ((double)cj + 1.0) * P - y : (double)cj * P - y) / v, 0.0);
+            if (t < best) { best = t; ev = v > 0.0 ? EV_YHI : EV_YLO; }
+        }
+    }
+    if (w != 0.0) {
+        const double t = fmax((w > 0.0 ? g.z1 - z : g.z0 - z) / w, 0.0);
+        if (t < best) { best = t; ev = w > 0.0 ? EV_ZHI : EV_ZLO; }
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// wave / block helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Butterfly sum over the wave: every lane ends with the same bits, because at
+// each stage partners add the same two values (commutativity).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = v + __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+}  // namespace mc

@@ -1,0 +1,50 @@
+// mc_internal.h -- launch wrappers shared by the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mc_device.h"
+
+namespace mc {
+
+struct LookupLaunch {
+    XsDev xs;
+    const uint32_t *list = nullptr;
+    const uint32_t *keys = nullptr;
+    const uint32_t *n_ptr = nullptr;
+    uint32_t n_bound = 0;
+    const double *E = nullptr;
+    const int32_t *mat = nullptr;
+    double *Sa = nullptr, *Ss = nullptr;
+    uint8_t *flags = nullptr;
+    int32_t *idx_out = nullptr;
+    double *sc_out = nullptr, *ss_out = nullptr;
+    unsigned long long *nuc_count = nullptr;
+};
+
+hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
+hipError_t launch_slots_count(const BankDev &b, hipStream_t st);
+hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, Counters *ctr, int cur,
+                              uint64_t first_pid, uint64_t n_hist, uint64_t seed, hipStream_t st);
+hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_ptr, uint32_t n_bound,
+                       const double *E, const int32_t *mat, uint32_t *keys_tmp, uint32_t *hist,
+                       uint32_t *offs, uint32_t n_keys, uint32_t *out_list, uint32_t *out_keys,
+                       hipStream_t st);
+hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st);
+hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+                          uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on,
+                          hipStream_t st);
+hipError_t launch_split(const BankDev &b, Counters *ctr, uint32_t n_bound, hipStream_t st);
+hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+                        uint32_t n_bound, HistLog *log, uint64_t first_pid, unsigned long long *lost,
+                        hipStream_t st);
+hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t,
+                          const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
+                          uint64_t first_pid, hipStream_t st);
+hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols, const double *direct,
+                              double *partial, double inv_n, double *S1, double *S2, hipStream_t st);
+
+}  // namespace mc

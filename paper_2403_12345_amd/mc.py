@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libmc.so (declarations in include/mc.h).
+
+Every function here has the name of the C entry point it calls and only
+marshals arguments: numpy arrays for host inputs, torch tensors (or raw
+integers) for device pointers, torch's current HIP stream for the stream.
+Every step of the transport path runs in the library's HIP kernels; there is
+no Python or CPU fallback.  Loading fails loudly when libmc.so is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmc.so")
+
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST, MC_ESTATE, MC_ENODEV = 0, -1, -2, -3, -4, -5, -6
+MC_GEOM_INFINITE, MC_GEOM_LATTICE, MC_GEOM_SLAB = 0, 1, 2
+MC_TALLY_ENERGY, MC_TALLY_PIN, MC_TALLY_MESH, MC_TALLY_SLAB = 0, 1, 2, 3
+MC_T_FLUX_TRACK, MC_T_FLUX_COLLISION, MC_T_GLOBAL = 0, 1, 2
+(MC_G_TRACK, MC_G_COLL_EST, MC_G_ABSORB, MC_G_CUTOFF, MC_G_LEAK, MC_G_TRACK_ABS, MC_G_NCOLL,
+ MC_G_NCROSS, MC_G_LEAK_XHI, MC_G_LEAK_XHI_UNC, MC_N_GLOBAL) = range(11)
+MC_FATE_ABSORBED, MC_FATE_CUTOFF, MC_FATE_LEAKED, MC_FATE_LOST = 1, 2, 3, 4
+
+_STATUS = {MC_EINVAL: "MC_EINVAL", MC_ENOMEM: "MC_ENOMEM", MC_EHIP: "MC_EHIP", MC_ELOST: "MC_ELOST",
+           MC_ESTATE: "MC_ESTATE", MC_ENODEV: "MC_ENODEV"}
+
+
+class MCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mc_geometry_desc(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("material", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("pitch", C.c_double), ("radius", C.c_double), ("z0", C.c_double), ("z1", C.c_double),
+        ("pin_material", C.POINTER(C.c_int32)), ("moderator_material", C.c_int32),
+        ("bc", C.c_int32 * 6), ("n_layers", C.c_int32), ("x_edges", C.POINTER(C.c_double)),
+        ("layer_material", C.POINTER(C.c_int32)), ("source_kind", C.c_int32),
+        ("source_pos", C.c_double * 3), ("source_box", C.c_double * 6),
+        ("source_dir", C.c_double * 3), ("source_energy", C.c_double),
+        ("tally_kind", C.c_int32), ("n_energy_bins", C.c_int32),
+        ("energy_edges", C.POINTER(C.c_double)), ("mesh_dims", C.c_int32 * 3),
+        ("mesh_box", C.c_double * 6), ("energy_cutoff", C.c_double),
+    ]
+
+
+class mc_run_opts(C.Structure):
+    _fields_ = [("in_flight", C.c_uint64), ("sort_min", C.c_uint64), ("no_tally", C.c_int32),
+                ("time_kernels", C.c_int32), ("max_events", C.c_int64), ("max_lost", C.c_uint64),
+                ("history_log", C.c_void_p)]
+
+
+class mc_stats(C.Structure):
+    _fields_ = [("iterations", C.c_uint64), ("lookups", C.c_uint64), ("nuclide_lookups", C.c_uint64),
+                ("lookup_launches", C.c_uint64), ("sorted_lookups", C.c_uint64), ("lost", C.c_uint64),
+                ("lookup_bytes", C.c_uint64), ("lookup_ms", C.c_double), ("batch_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mc_tally_meta(C.Structure):
+    _fields_ = [("n_batches", C.c_uint64), ("n_bins", C.c_uint64), ("histories", C.c_uint64)]
+
+
+HISTORY_DTYPE = np.dtype([("fate", np.int32), ("n_coll", np.int32), ("n_cross", np.int32),
+                          ("pad", np.int32), ("n_draws", np.uint64), ("E_final", np.float64),
+                          ("track", np.float64), ("weight", np.float64)])
+
+_lib = None
+
+
+def load():
+    """Load libmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; "
+                          f"g.build()') -- there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    P, V, D, I32, U64, SZ = C.POINTER, C.c_void_p, C.c_double, C.c_int32, C.c_uint64, C.c_size_t
+    sig = {
+        "mc_version": ([], C.c_char_p),
+        "mc_create": ([P(V), C.c_int, V], C.c_int),
+        "mc_destroy": ([V], None),
+        "mc_last_error": ([V], C.c_char_p),
+        "mc_set_stream": ([V, V], C.c_int),
+        "mc_init_materials": ([V, I32, P(I32), P(P(D)), P(P(D)), P(P(D)), P(D), I32, P(I32), P(I32),
+                               P(D), I32], C.c_int),
+        "mc_init_geometry": ([V, P(mc_geometry_desc)], C.c_int),
+        "mc_run_batch": ([V, U64, U64, U64, P(mc_run_opts)], C.c_int),
+        "mc_get_tallies": ([V, I32, P(D), P(D), SZ, P(mc_tally_meta)], C.c_int),
+        "mc_reset_tallies": ([V], C.c_int),
+        "mc_get_stats": ([V, P(mc_stats)], C.c_int),
+        "mc_lookup_macro": ([V, SZ, V, V, V, V, I32], C.c_int),
+        "mc_lookup_nuclides": ([V, I32, SZ, V, V, V, V], C.c_int),
+        "mc_sort_queue": ([V, SZ, V, V, V, V], C.c_int),
+        "mc_hash_bounds": ([P(D), I32, D, D, I32, P(I32)], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(ctx, rc):
+    if rc != MC_OK:
+        msg = load().mc_last_error(ctx).decode() if ctx else ""
+        raise MCError(rc, msg)
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor (or an integer / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def mc_version() -> str:
+    return load().mc_version().decode()
+
+
+def mc_create(device: int = 0, stream=None):
+    ctx = C.c_void_p()
+    rc = load().mc_create(C.byref(ctx), device, _stream_handle(stream))
+    _check(None, rc)
+    return ctx
+
+
+def mc_destroy(ctx):
+    load().mc_destroy(ctx)
+
+
+def mc_last_error(ctx) -> str:
+    return load().mc_last_error(ctx).decode()
+
+
+def mc_set_stream(ctx, stream=None):
+    _check(ctx, load().mc_set_stream(ctx, _stream_handle(stream)))
+
+
+def mc_init_materials(ctx, E, sig_c, sig_s, awr, mat_nuclides, mat_densities, n_hash_bins=8192):
+    """E, sig_c, sig_s: lists of 1-D float64 arrays (one per nuclide); awr: per
+    nuclide; mat_nuclides / mat_densities: lists (one per material)."""
+    n_nuc = len(E)
+    E = [np.ascontiguousarray(e, np.float64) for e in E]
+    sc = [np.ascontiguousarray(s, np.float64) for s in sig_c]
+    ss = [np.ascontiguousarray(s, np.float64) for s in sig_s]
+    grid_len = np.array([e.size for e in E], np.int32)
+    PD = C.POINTER(C.c_double)
+    pe = (PD * n_nuc)(*[_dp(a) for a in E])
+    pc = (PD * n_nuc)(*[_dp(a) for a in sc])
+    ps = (PD * n_nuc)(*[_dp(a) for a in ss])
+    awr = np.ascontiguousarray(awr, np.float64)
+    mat_len = np.array([len(m) for m in mat_nuclides], np.int32)
+    mat_nuc = np.ascontiguousarray(np.concatenate([np.asarray(m, np.int32) for m in mat_nuclides]), np.int32)
+    mat_dens = np.ascontiguousarray(np.concatenate([np.asarray(d, np.float64) for d in mat_densities]))
+    rc = load().mc_init_materials(ctx, n_nuc, _ip(grid_len), pe, pc, ps, _dp(awr), len(mat_len),
+                                  _ip(mat_len), _ip(mat_nuc), _dp(mat_dens), int(n_hash_bins))
+    _check(ctx, rc)
+
+
+def mc_init_geometry(ctx, desc: mc_geometry_desc):
+    _check(ctx, load().mc_init_geometry(ctx, C.byref(desc)))
+
+
+def mc_run_batch(ctx, seed: int, first_pid: int, n: int, opts: mc_run_opts | None = None):
+    rc = load().mc_run_batch(ctx, seed, first_pid, n, C.byref(opts) if opts is not None else None)
+    _check(ctx, rc)
+
+
+def mc_get_tallies(ctx, tally_id: int, n_bins: int):
+    mean = np.zeros(n_bins)
+    se = np.zeros(n_bins)
+    meta = mc_tally_meta()
+    _check(ctx, load().mc_get_tallies(ctx, tally_id, _dp(mean), _dp(se), n_bins, C.byref(meta)))
+    return mean, se, meta
+
+
+def mc_reset_tallies(ctx):
+    _check(ctx, load().mc_reset_tallies(ctx))
+
+
+def mc_get_stats(ctx) -> mc_stats:
+    s = mc_stats()
+    _check(ctx, load().mc_get_stats(ctx, C.byref(s)))
+    return s
+
+
+def mc_lookup_macro(ctx, E, mat, sig_a, sig_s, sorted_: bool = False):
+    n = E.numel() if hasattr(E, "numel") else int(E)
+    _check(ctx, load().mc_lookup_macro(ctx, n, _ptr(E), _ptr(mat), _ptr(sig_a), _ptr(sig_s),
+                                       1 if sorted_ else 0))
+
+
+def mc_lookup_nuclides(ctx, mat: int, E, idx=None, sig_c=None, sig_s=None):
+    _check(ctx, load().mc_lookup_nuclides(ctx, mat, E.numel(), _ptr(E), _ptr(idx), _ptr(sig_c),
+                                          _ptr(sig_s)))
+
+
+def mc_sort_queue(ctx, E, mat, perm, keys_sorted=None):
+    _check(ctx, load().mc_sort_queue(ctx, E.numel(), _ptr(E), _ptr(mat), _ptr(perm),
+                                     _ptr(keys_sorted)))
+
+
+def mc_hash_bounds(E, emin: float, emax: float, M: int) -> np.ndarray:
+    E = np.ascontiguousarray(E, np.float64)
+    lo = np.zeros(M + 1, np.int32)
+    rc = load().mc_hash_bounds(_dp(E), E.size, emin, emax, M, _ip(lo))
+    _check(None, rc)
+    return lo

@@ -1,0 +1,108 @@
+"""Marshalling of a problem description (an object with the attributes of
+``mcsynth.Problem``: nuclides, materials, geometry, source, tally,
+energy_cutoff, n_hash_bins) into the C ABI, and a small context wrapper.
+
+Nothing here computes any part of the transport path; it only fills the
+library's structs and forwards calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import mc
+
+
+def geometry_desc(prob):
+    """Fill an mc_geometry_desc; returns (desc, keep-alive arrays)."""
+    g, s, t = prob.geometry, prob.source, prob.tally
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a
+
+    d = mc.mc_geometry_desc()
+    d.kind, d.material = g.kind, g.material
+    d.nx, d.ny, d.pitch, d.radius, d.z0, d.z1 = g.nx, g.ny, g.pitch, g.radius, g.z0, g.z1
+    if g.pin_material is not None:
+        d.pin_material = arr(g.pin_material, np.int32).ctypes.data_as(C.POINTER(C.c_int32))
+    d.moderator_material = g.moderator_material
+    d.bc = (C.c_int32 * 6)(*g.bc)
+    if g.x_edges is not None:
+        d.n_layers = len(g.x_edges) - 1
+        d.x_edges = arr(g.x_edges, np.float64).ctypes.data_as(C.POINTER(C.c_double))
+        d.layer_material = arr(g.layer_material, np.int32).ctypes.data_as(C.POINTER(C.c_int32))
+    d.source_kind = s.kind
+    d.source_pos = (C.c_double * 3)(*s.position)
+    d.source_box = (C.c_double * 6)(*s.box)
+    d.source_dir = (C.c_double * 3)(*s.direction)
+    d.source_energy = s.energy
+    d.tally_kind = t.kind
+    if t.energy_edges is not None:
+        d.n_energy_bins = len(t.energy_edges) - 1
+        d.energy_edges = arr(t.energy_edges, np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    d.mesh_dims = (C.c_int32 * 3)(*t.mesh_dims)
+    d.mesh_box = (C.c_double * 6)(*t.mesh_box)
+    d.energy_cutoff = prob.energy_cutoff
+    return d, keep
+
+
+def run_opts(in_flight=0, sort_min=0, no_tally=False, time_kernels=False, max_events=0, max_lost=0,
+             history_log=None):
+    o = mc.mc_run_opts()
+    o.in_flight = int(in_flight)
+    o.sort_min = int(sort_min)
+    o.no_tally = 1 if no_tally else 0
+    o.time_kernels = 1 if time_kernels else 0
+    o.max_events = int(max_events)
+    o.max_lost = int(max_lost)
+    o.history_log = mc._ptr(history_log)
+    return o
+
+
+class Transport:
+    """One library context holding one problem."""
+
+    def __init__(self, prob, device: int = 0, stream=None):
+        self.prob = prob
+        self.ctx = mc.mc_create(device, stream)
+        try:
+            mc.mc_init_materials(self.ctx, [n.E for n in prob.nuclides], [n.sig_c for n in prob.nuclides],
+                                 [n.sig_s for n in prob.nuclides], [n.awr for n in prob.nuclides],
+                                 [m.nuclides for m in prob.materials], [m.densities for m in prob.materials],
+                                 prob.n_hash_bins)
+            desc, keep = geometry_desc(prob)
+            mc.mc_init_geometry(self.ctx, desc)
+            del keep
+        except Exception:
+            mc.mc_destroy(self.ctx)
+            raise
+        self.n_bins = prob.n_bins
+
+    def run_batch(self, seed, first_pid, n, **opts):
+        mc.mc_run_batch(self.ctx, seed, first_pid, n, run_opts(**opts))
+
+    def tallies(self, tally_id):
+        nb = mc.MC_N_GLOBAL if tally_id == mc.MC_T_GLOBAL else self.n_bins
+        mean, se, meta = mc.mc_get_tallies(self.ctx, tally_id, nb)
+        return mean, se, meta
+
+    def reset(self):
+        mc.mc_reset_tallies(self.ctx)
+
+    def stats(self) -> dict:
+        return mc.mc_get_stats(self.ctx).as_dict()
+
+    def close(self):
+        if self.ctx is not None:
+            mc.mc_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

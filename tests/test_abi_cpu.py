@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/mc.h declares, reports no device here, and builds
+hash bounds that bracket every energy of their bin."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mcsynth
+from paper_2403_12345_amd import mc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "mc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mc_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mc.load()
+    names = declared_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert mc.mc_version().startswith("mc355")
+
+
+def test_struct_sizes_match_header_layout():
+    # mc_history is 48 bytes (4 int32, 1 uint64, 3 double); the run options 48
+    assert mc.HISTORY_DTYPE.itemsize == 48
+    assert ctypes.sizeof(mc.mc_run_opts) == 48
+    assert ctypes.sizeof(mc.mc_stats) == 8 * 9
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(mc.MCError) as e:
+        mc.mc_create(0, 0)
+    assert e.value.code == mc.MC_ENODEV
+
+
+@pytest.mark.parametrize("M", [1, 7, 64, 8192])
+def test_hash_bounds_bracket_every_grid_point(M):
+    rng = np.random.default_rng(M)
+    for n in (2, 3, 50, 2000):
+        nuc = mcsynth.make_nuclide(rng, 12.0, n, "loguniform")
+        E = nuc.E
+        lo = mc.mc_hash_bounds(E, mcsynth.EMIN, mcsynth.EMAX, M)
+        assert lo.shape == (M + 1,)
+        assert lo[M] == n - 2 and lo[0] == 0
+        assert np.all(np.diff(lo) >= 0) and np.all(lo >= 0) and np.all(lo <= n - 2)
+        delta = np.log(mcsynth.EMAX / mcsynth.EMIN) / M
+        edges = mcsynth.EMIN * np.exp(np.arange(M + 1) * delta)
+        # every grid point (and points between) lies in the bracket of its bin
+        q = np.concatenate([E, np.sqrt(E[:-1] * E[1:]), mcsynth.lookup_energies(rng, 500)])
+        q = q[(q >= mcsynth.EMIN) & (q < mcsynth.EMAX)]
+        b = np.clip(np.searchsorted(edges, q, side="right") - 1, 0, M - 1)
+        i = np.clip(np.searchsorted(E, q, side="right") - 1, 0, n - 2)
+        assert np.all(lo[b] <= i) and np.all(i <= lo[b + 1])
+
+
+def test_hash_bounds_rejects_bad_arguments():
+    with pytest.raises(mc.MCError):
+        mc.mc_hash_bounds(np.array([1.0]), 1e-5, 2e7, 8)
+    with pytest.raises(mc.MCError):
+        mc.mc_hash_bounds(np.array([1.0, 2.0]), 1e-5, 2e7, 0)
