@@ -68,6 +68,60 @@ def cpu_baseline(prob, seed: int, target_s: float = 12.0):
                       f"history-based OpenMP over {threads} threads, {t2:.1f} s"}
 
 
+def lookup_microbench(n: int = 10_000_000, reps: int = 3):
+    """Stand-alone lookup of n (energy, material) pairs on the 300-nuclide
+    material (grids of 20k-150k points, ~0.6 GB of tables, far above the
+    on-chip caches): the lookup-bound case, unsorted and sorted."""
+    import numpy as np
+    import torch
+
+    import mcsynth
+    from paper_2403_12345_amd import mc
+    from paper_2403_12345_amd.transport import Transport
+
+    prob = mcsynth.c3_problem()
+    rng = np.random.default_rng(12345)
+    E = torch.from_numpy(mcsynth.lookup_energies(rng, n)).cuda()
+    M = torch.zeros(n, dtype=torch.int32, device="cuda")
+    Sa = torch.empty(n, dtype=torch.float64, device="cuda")
+    Ss = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = {"workload": "macroscopic lookups of 1e7 log-uniform energies in [1e-5, 2e7] eV on one material "
+                       "of 300 synthetic nuclides (clustered grids of 20k-150k points)",
+           "n": n, "xs_bytes": prob.data_bytes(), "bytes_per_lookup": 36 + 56 * 300}
+    with Transport(prob, device=0) as t:
+        for name, srt in (("unsorted", False), ("sorted", True)):
+            mc.mc_lookup_macro(t.ctx, E, M, Sa, Ss, srt)  # warm-up
+            mc.mc_set_timing(t.ctx, True)
+            for _ in range(reps):
+                mc.mc_lookup_macro(t.ctx, E, M, Sa, Ss, srt)
+            s = t.stats()
+            mc.mc_set_timing(t.ctx, False)
+            sec = s["lookup_ms"] / 1e3
+            gbs = s["lookup_bytes"] / sec / 1e9
+            out[name] = {"lookups_per_s": s["lookups"] / sec, "achieved_GBs": gbs,
+                         "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                         "avg_launch_ms": s["lookup_ms"] / s["lookup_launches"]}
+    return out
+
+
+def copy_calibration(n_doubles: int = 1 << 28, reps: int = 5):
+    """A plain device copy of known size (2 GiB read + 2 GiB written per launch),
+    the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(n_doubles, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / reps
+    return {"bytes_read_per_launch": n_doubles * 8, "bytes_written_per_launch": n_doubles * 8,
+            "copy_GBs": 2 * n_doubles * 8 / sec / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +129,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-inactive", action="store_true", help="skip the tally-off contrast batch")
+    ap.add_argument("--no-lookup-bench", action="store_true", help="skip the 300-nuclide lookup benchmark")
+    ap.add_argument("--mode", choices=("full", "lookup", "copy"), default="full",
+                    help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
@@ -87,6 +144,12 @@ def main():
     from paper_2403_12345_amd.transport import Transport
 
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        print(json.dumps({"copy_calibration": copy_calibration()}), flush=True)
+        return
+    if args.mode == "lookup":
+        print(json.dumps({"lookup_microbench": lookup_microbench()}), flush=True)
+        return
     prob = mcsynth.c2_problem()
     n = prob.histories
     seed = prob.seed
@@ -160,6 +223,8 @@ def main():
         "iterations_per_step": tot["iterations"] / args.steps,
         "inactive_particles_per_s": inactive,
     }
+    if not args.no_lookup_bench:
+        line["lookup_microbench"] = lookup_microbench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, seed)
     print(json.dumps(line), flush=True)

@@ -244,8 +244,18 @@ int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_,
 /* Zero every tally's batch sums. */
 int mc_reset_tallies(mc_ctx *ctx);
 
-/* Counters of the last mc_run_batch (host struct). */
+/* Counters of the last mc_run_batch, or of the stand-alone lookups since
+ * mc_set_timing (host struct). */
 int mc_get_stats(mc_ctx *ctx, mc_stats *out);
+
+/*
+ * on = 1: zero the counters of mc_get_stats and, from then on, time every
+ * lookup kernel that mc_lookup_macro launches with HIP events on the context's
+ * stream and add it to those counters (lookups, nuclide_lookups,
+ * lookup_launches, lookup_bytes, lookup_ms; each timed call synchronizes the
+ * stream).  on = 0: stop timing the stand-alone calls.
+ */
+int mc_set_timing(mc_ctx *ctx, int32_t on);
 
 /*
  * Macroscopic cross sections of n (energy, material) pairs, the lookup step on

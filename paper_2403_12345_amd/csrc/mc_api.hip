@@ -78,6 +78,7 @@ struct mc_ctx {
     std::vector<hipEvent_t> ev_a, ev_b;
     hipEvent_t ev_batch0 = nullptr, ev_batch1 = nullptr;
     mc_stats stats{};
+    bool timing = false;  // time the stand-alone lookups (mc_set_timing)
 };
 
 static int fail(mc_ctx *c, int code, const std::string &msg)
@@ -741,6 +742,14 @@ int mc_get_stats(mc_ctx *ctx, mc_stats *out)
     return MC_OK;
 }
 
+int mc_set_timing(mc_ctx *ctx, int32_t on)
+{
+    if (!ctx) return MC_EINVAL;
+    ctx->timing = on != 0;
+    if (on) ctx->stats = mc_stats{};
+    return MC_OK;
+}
+
 int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *sig_a, double *sig_s,
                     int32_t sorted)
 {
@@ -764,7 +773,29 @@ int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, 
         l.list = ctx->s_perm;
         l.keys = ctx->s_keys;
     }
+    if (!ctx->timing) {
+        HIPCHK(launch_lookup(l, ctx->stream));
+        return MC_OK;
+    }
+    int rc = timing_event_pair(ctx, 0);
+    if (rc) return rc;
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->dstat), 2, 0u, ctx->stream));
+    l.nuc_count = ctx->dstat;
+    HIPCHK(hipEventRecord(ctx->ev_a[0], ctx->stream));
     HIPCHK(launch_lookup(l, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev_b[0], ctx->stream));
+    unsigned long long nuc = 0;
+    HIPCHK(hipMemcpyAsync(&nuc, ctx->dstat, sizeof(nuc), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_a[0], ctx->ev_b[0]));
+    mc_stats &s = ctx->stats;
+    s.lookups += n;
+    s.nuclide_lookups += nuc;
+    s.lookup_launches += 1;
+    s.sorted_lookups += sorted ? n : 0;
+    s.lookup_bytes += 36ull * n + 56ull * nuc;
+    s.lookup_ms += ms;
     return MC_OK;
 }
 

@@ -102,6 +102,7 @@ def load():
         "mc_lookup_nuclides": ([V, I32, SZ, V, V, V, V], C.c_int),
         "mc_sort_queue": ([V, SZ, V, V, V, V], C.c_int),
         "mc_hash_bounds": ([P(D), I32, D, D, I32, P(I32)], C.c_int),
+        "mc_set_timing": ([V, I32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -232,6 +233,10 @@ def mc_lookup_nuclides(ctx, mat: int, E, idx=None, sig_c=None, sig_s=None):
 def mc_sort_queue(ctx, E, mat, perm, keys_sorted=None):
     _check(ctx, load().mc_sort_queue(ctx, E.numel(), _ptr(E), _ptr(mat), _ptr(perm),
                                      _ptr(keys_sorted)))
+
+
+def mc_set_timing(ctx, on: bool):
+    _check(ctx, load().mc_set_timing(ctx, 1 if on else 0))
 
 
 def mc_hash_bounds(E, emin: float, emax: float, M: int) -> np.ndarray:
