@@ -164,6 +164,8 @@ typedef struct mc_stats {
                                    36 + 56 * n_nuclides */
     double lookup_ms;           /* summed lookup-kernel time (time_kernels = 1), ms */
     double batch_ms;            /* wall time of the batch on the stream, ms */
+    uint64_t tail_particles;    /* particles finished by the one-launch tail (their
+                                   later lookups are not in the counters above) */
 } mc_stats;
 
 /* Batch statistics of one tally bin range (mc_get_tallies). */
@@ -289,7 +291,8 @@ int mc_lookup_nuclides(mc_ctx *ctx, int32_t mat, size_t n, const double *E, int3
 /*
  * The sort step on its own (paper section 2, "Sorting"): key[p] = mat[p] * M +
  * b(E[p]) with b the hash bin, then perm receives 0..n-1 ordered by key
- * (order among equal keys unspecified) and keys_sorted the keys in that order.
+ * (stable: equal keys keep their input order) and keys_sorted the keys in that
+ * order.
  *   E, mat      device inputs (n each)
  *   perm        device, n uint32 outputs
  *   keys_sorted device, n uint32 outputs (nullable)
@@ -304,6 +307,28 @@ int mc_sort_queue(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, ui
  * host array of M + 1 entries.
  */
 int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t M, int32_t *lo);
+
+/*
+ * Launch-shape parameters of the kernels (the autotuner's search space).
+ * Zero fields keep the library default.  They change speed only: every
+ * setting gives the same results bit for bit.
+ *   lookup_ilp    nuclides each lane looks up in lockstep in the lookup
+ *                 kernel (1, 2 or 4; default 2)
+ *   tail_particles when no history remains to start and at most this many
+ *                 particles are in flight, the remaining histories are
+ *                 finished by one kernel launch in which each lane runs its
+ *                 particle to the end (0: default 32,768; -1: never)
+ */
+typedef struct mc_tuning {
+    int32_t lookup_ilp;
+    int32_t tail_particles;
+    int32_t reserved[6];
+} mc_tuning;
+
+/* Set (mc_set_tuning) or read (mc_get_tuning) the context's launch shapes.
+ * Errors: MC_EINVAL for a value outside the ranges above. */
+int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t);
+int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
 
 /* Library version string. */
 const char *mc_version(void);

@@ -13,6 +13,7 @@
 #include "../../include/mc.h"
 #include "mc_device.h"
 #include "mc_internal.h"
+#include "mc_physics.h"
 
 using namespace mc;
 
@@ -21,6 +22,7 @@ namespace {
 constexpr uint64_t kDefaultInFlight = 1ull << 20;
 constexpr uint64_t kDefaultSortMin = 16384;
 constexpr int64_t kDefaultMaxEvents = 100000;
+constexpr int64_t kDefaultTailParticles = 32768;
 
 struct Buffers {
     std::vector<void *> ptrs;
@@ -44,8 +46,7 @@ struct mc_ctx {
     XsDev xs{};
     int32_t n_nuc = 0, n_mat = 0;
     std::vector<int32_t> mat_len;
-    uint32_t *hist = nullptr, *offs = nullptr;  // sort scratch, n_mat * M keys
-    uint32_t n_keys = 0;
+    uint32_t n_keys = 0;  // n_mat * M sort keys
 
     // geometry and tallies
     bool have_geom = false;
@@ -58,6 +59,7 @@ struct mc_ctx {
     // particle bank and per-workgroup tally rows
     Buffers bank_bufs;
     BankDev bank{};
+    SortBufs bank_sort{};
     TallyDev tal{};
     double *partial = nullptr;
     uint32_t cap = 0;
@@ -72,14 +74,22 @@ struct mc_ctx {
     // scratch of the stand-alone lookup / sort entry points
     Buffers scratch_bufs;
     size_t scratch_n = 0;
-    uint32_t *s_perm = nullptr, *s_keys = nullptr, *s_keys_tmp = nullptr;
+    uint32_t *s_perm = nullptr, *s_keys = nullptr;
     int32_t *s_mat = nullptr;
+    SortBufs s_sort{};
 
     std::vector<hipEvent_t> ev_a, ev_b;
     hipEvent_t ev_batch0 = nullptr, ev_batch1 = nullptr;
     mc_stats stats{};
     bool timing = false;  // time the stand-alone lookups (mc_set_timing)
+    mc_tuning tune{};      // launch shapes (0 = default)
 };
+
+static int lookup_ilp(const mc_ctx *ctx) { return ctx->tune.lookup_ilp ? ctx->tune.lookup_ilp : DEFAULT_LOOKUP_ILP; }
+static int64_t tail_particles(const mc_ctx *ctx)
+{
+    return ctx->tune.tail_particles == 0 ? kDefaultTailParticles : (int64_t)ctx->tune.tail_particles;
+}
 
 static int fail(mc_ctx *c, int code, const std::string &msg)
 {
@@ -306,13 +316,10 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_hash, hash.data(), hash.size());
     if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_hoff, hoff.data(), hoff.size());
     ctx->n_keys = (uint32_t)((uint64_t)n_mat * (uint64_t)M);
-    if (!rc) rc = dalloc(ctx, ctx->mat_bufs, &ctx->hist, ctx->n_keys);
-    if (!rc) rc = dalloc(ctx, ctx->mat_bufs, &ctx->offs, ctx->n_keys);
     if (rc) {
         ctx->mat_bufs.release();
         return rc;
     }
-    HIPCHK(hipMemset(ctx->hist, 0, (size_t)ctx->n_keys * sizeof(uint32_t)));
     x.Eg = d_Eg;
     x.xs = d_xs;
     x.awr = d_awr;
@@ -493,6 +500,21 @@ int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
     return reset_tallies(ctx);
 }
 
+// Radix-sort scratch for up to n items (chunk totals start at zero).
+static int alloc_sort(mc_ctx *ctx, Buffers &B, SortBufs &sb, size_t n)
+{
+    int rc = dalloc(ctx, B, &sb.kA, n);
+    if (!rc) rc = dalloc(ctx, B, &sb.kB, n);
+    if (!rc) rc = dalloc(ctx, B, &sb.vA, n);
+    if (!rc) rc = dalloc(ctx, B, &sb.vB, n);
+    const size_t tiles = sort_tile_count(n), chunks = sort_chunk_count(n);
+    if (!rc) rc = dalloc(ctx, B, &sb.tile_hist, tiles * 256);
+    if (!rc) rc = dalloc(ctx, B, &sb.chunk_total, chunks * 256);
+    if (!rc) rc = dalloc(ctx, B, &sb.chunk_off, chunks * 256);
+    if (!rc) HIPCHK(hipMemset(sb.chunk_total, 0, chunks * 256 * sizeof(uint32_t)));
+    return rc;
+}
+
 // Particle bank of capacity cap and the tally rows of its workgroups.
 static int ensure_bank(mc_ctx *ctx, uint32_t cap)
 {
@@ -532,11 +554,14 @@ static int ensure_bank(mc_ctx *ctx, uint32_t cap)
     if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins);
     if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins);
     if (!rc) rc = dalloc(ctx, B, &ctx->partial, (size_t)64 * std::max<size_t>(ctx->n_bins, N_GLOBAL));
+    SortBufs sb{};
+    if (!rc) rc = alloc_sort(ctx, B, sb, cap);
     if (rc) {
         B.release();
         return rc;
     }
     ctx->bank = b;
+    ctx->bank_sort = sb;
     ctx->tal = t;
     ctx->cap = cap;
     ctx->bank_bins = ctx->n_bins;
@@ -551,8 +576,8 @@ static int ensure_scratch(mc_ctx *ctx, size_t n)
     ctx->scratch_n = 0;
     int rc = dalloc(ctx, ctx->scratch_bufs, &ctx->s_perm, n);
     if (!rc) rc = dalloc(ctx, ctx->scratch_bufs, &ctx->s_keys, n);
-    if (!rc) rc = dalloc(ctx, ctx->scratch_bufs, &ctx->s_keys_tmp, n);
     if (!rc) rc = dalloc(ctx, ctx->scratch_bufs, &ctx->s_mat, n);
+    if (!rc) rc = alloc_sort(ctx, ctx->scratch_bufs, ctx->s_sort, n);
     if (rc) {
         ctx->scratch_bufs.release();
         return rc;
@@ -630,6 +655,14 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
             break;
         }
         Counters *dc = ctx->ctr + cur;
+        const int64_t tail = tail_particles(ctx);
+        if (tail > 0 && c.issued == n && (int64_t)c.nA <= tail) {
+            // every history has started and few remain: finish them in one launch
+            HIPCHK(launch_tail(b, ctx->xs, g, tal, dc, c.nA, seed, max_events, log, first_pid, ctx->dstat + 1, st));
+            s.tail_particles = c.nA;
+            ++it;
+            break;
+        }
         if (c.nL > 0) {
             LookupLaunch l;
             l.xs = ctx->xs;
@@ -641,10 +674,11 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
             l.Ss = b.Ss;
             l.flags = b.flags;
             l.nuc_count = ctx->dstat;
+            l.ilp = lookup_ilp(ctx);
             const bool sort = (uint64_t)c.nL >= sort_min && sort_min != UINT64_MAX;
             if (sort) {
-                HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, c.nL, b.E, b.mat, b.Qc, ctx->hist, ctx->offs,
-                                   ctx->n_keys, b.Ls, b.Lkey, st));
+                HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, c.nL, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls,
+                                   b.Lkey, st));
                 l.list = b.Ls;
                 l.keys = b.Lkey;
                 s.sorted_lookups += c.nL;
@@ -742,6 +776,25 @@ int mc_get_stats(mc_ctx *ctx, mc_stats *out)
     return MC_OK;
 }
 
+int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t)
+{
+    if (!ctx || !t) return MC_EINVAL;
+    if (t->lookup_ilp != 0 && t->lookup_ilp != 1 && t->lookup_ilp != 2 && t->lookup_ilp != 4)
+        return fail(ctx, MC_EINVAL, "lookup_ilp must be 0, 1, 2 or 4");
+    if (t->tail_particles < -1) return fail(ctx, MC_EINVAL, "tail_particles must be >= -1");
+    ctx->tune = *t;
+    return MC_OK;
+}
+
+int mc_get_tuning(mc_ctx *ctx, mc_tuning *t)
+{
+    if (!ctx || !t) return MC_EINVAL;
+    *t = ctx->tune;
+    t->lookup_ilp = lookup_ilp(ctx);
+    t->tail_particles = (int32_t)tail_particles(ctx);
+    return MC_OK;
+}
+
 int mc_set_timing(mc_ctx *ctx, int32_t on)
 {
     if (!ctx) return MC_EINVAL;
@@ -765,11 +818,12 @@ int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, 
     l.mat = mat;
     l.Sa = sig_a;
     l.Ss = sig_s;
+    l.ilp = lookup_ilp(ctx);
     if (sorted) {
         int rc = ensure_scratch(ctx, n);
         if (rc) return rc;
-        HIPCHK(launch_sort(ctx->xs, nullptr, nullptr, (uint32_t)n, E, mat, ctx->s_keys_tmp, ctx->hist, ctx->offs,
-                           ctx->n_keys, ctx->s_perm, ctx->s_keys, ctx->stream));
+        HIPCHK(launch_sort(ctx->xs, nullptr, nullptr, (uint32_t)n, E, mat, ctx->s_sort, ctx->n_keys, ctx->s_perm,
+                           ctx->s_keys, ctx->stream));
         l.list = ctx->s_perm;
         l.keys = ctx->s_keys;
     }
@@ -819,6 +873,7 @@ int mc_lookup_nuclides(mc_ctx *ctx, int32_t mat, size_t n, const double *E, int3
     l.idx_out = idx;
     l.sc_out = sig_c;
     l.ss_out = sig_s;
+    l.ilp = lookup_ilp(ctx);
     HIPCHK(launch_lookup(l, ctx->stream));
     return MC_OK;
 }
@@ -833,8 +888,8 @@ int mc_sort_queue(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, ui
     HIPCHK(hipSetDevice(ctx->device));
     int rc = ensure_scratch(ctx, n);
     if (rc) return rc;
-    HIPCHK(launch_sort(ctx->xs, nullptr, nullptr, (uint32_t)n, E, mat, ctx->s_keys_tmp, ctx->hist, ctx->offs,
-                       ctx->n_keys, perm, keys_sorted, ctx->stream));
+    HIPCHK(launch_sort(ctx->xs, nullptr, nullptr, (uint32_t)n, E, mat, ctx->s_sort, ctx->n_keys, perm,
+                       keys_sorted ? keys_sorted : ctx->s_keys, ctx->stream));
     return MC_OK;
 }
 

@@ -198,6 +198,86 @@ __device__ __forceinline__ void lerp_xs(const XsDev &xs, uint32_t off, uint32_t 
     ss = x0.y + f * (x1.y - x0.y);
 }
 
+// Micro cross sections of up to ILP nuclides (positions q .. q+cnt-1 of a
+// material whose entries start at mnuc, hash brackets h[q], h[nk + q]) at E.
+// The bisections run in lockstep with their probe loads issued together, so a
+// wave keeps ILP independent gathers in flight per step instead of one.  The
+// interval found is checked against the energies loaded for the
+// interpolation; only when the hash bin was computed one off (device and host
+// logarithms rounding differently at a bin edge) does a lane walk to the
+// defined index and reload.  Each nuclide's result is exactly that of
+// grid_find + lerp_xs.
+template <int ILP>
+__device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__restrict__ mnuc,
+                                            const uint32_t *h, int32_t nk, int32_t q, int32_t cnt, double e,
+                                            double (&dens)[ILP], uint32_t (&ix)[ILP], double (&sc)[ILP],
+                                            double (&ss)[ILP])
+{
+    uint32_t lo[ILP], hi[ILP], off[ILP], len[ILP];
+#pragma unroll
+    for (int k = 0; k < ILP; ++k) {
+        const bool act = k < cnt;
+        const int32_t qk = q + (act ? k : 0);  // inactive slots repeat nuclide q, in bounds
+        const MatNuc mn = mnuc[qk];
+        const uint32_t a = h[qk], b = h[nk + qk];
+        off[k] = mn.off;
+        len[k] = mn.len;
+        dens[k] = act ? mn.dens : 0.0;
+        lo[k] = a;
+        hi[k] = act ? b : a;
+    }
+    // lockstep bisection: largest j in [lo, hi] with E_j <= E
+    for (;;) {
+        bool more = false;
+        uint32_t mid[ILP];
+        double v[ILP];
+#pragma unroll
+        for (int k = 0; k < ILP; ++k) {
+            mid[k] = lo[k] < hi[k] ? (lo[k] + hi[k] + 1u) >> 1 : lo[k];
+            v[k] = xs.Eg[off[k] + mid[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < ILP; ++k) {
+            if (lo[k] < hi[k]) {
+                if (v[k] <= e) lo[k] = mid[k]; else hi[k] = mid[k] - 1u;
+                more = more || lo[k] < hi[k];
+            }
+        }
+        if (!more) break;
+    }
+    double e0[ILP], e1[ILP];
+    double2 x0[ILP], x1[ILP];
+#pragma unroll
+    for (int k = 0; k < ILP; ++k) {
+        e0[k] = xs.Eg[off[k] + lo[k]];
+        e1[k] = xs.Eg[off[k] + lo[k] + 1u];
+        x0[k] = xs.xs[off[k] + lo[k]];
+        x1[k] = xs.xs[off[k] + lo[k] + 1u];
+    }
+#pragma unroll
+    for (int k = 0; k < ILP; ++k) {
+        uint32_t i = lo[k];
+        const bool below = e < e0[k] && i > 0u;
+        const bool above = e >= e1[k] && i + 2u < len[k];
+        if (k < cnt && (below || above)) {
+            const double *g = xs.Eg + off[k];
+            while (i > 0u && e < g[i]) --i;
+            while (i + 2u < len[k] && e >= g[i + 1u]) ++i;
+            e0[k] = g[i];
+            e1[k] = g[i + 1u];
+            x0[k] = xs.xs[off[k] + i];
+            x1[k] = xs.xs[off[k] + i + 1u];
+        }
+        ix[k] = i;
+    }
+#pragma unroll
+    for (int k = 0; k < ILP; ++k) {
+        const double f = (e - e0[k]) / (e1[k] - e0[k]);
+        sc[k] = x0[k].x + f * (x1[k].x - x0[k].x);
+        ss[k] = x0[k].y + f * (x1[k].y - x0[k].y);
+    }
+}
+
 // Hash row pointer of bin b of material m (global memory).
 __device__ __forceinline__ const uint32_t *hash_row(const XsDev &xs, int32_t m, int32_t b, int32_t nk)
 {

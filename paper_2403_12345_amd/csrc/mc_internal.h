@@ -21,6 +21,7 @@ struct LookupLaunch {
     int32_t *idx_out = nullptr;
     double *sc_out = nullptr, *ss_out = nullptr;
     unsigned long long *nuc_count = nullptr;
+    int32_t ilp = 4;  // nuclides looked up in lockstep per lane (1, 2 or 4)
 };
 
 hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);
@@ -29,10 +30,20 @@ hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 hipError_t launch_slots_count(const BankDev &b, hipStream_t st);
 hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, Counters *ctr, int cur,
                               uint64_t first_pid, uint64_t n_hist, uint64_t seed, hipStream_t st);
+// Scratch of the radix sort of up to `cap` items.
+struct SortBufs {
+    uint32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr;
+    uint32_t *tile_hist = nullptr;    // [tiles][256]
+    uint32_t *chunk_total = nullptr;  // [chunks][256], kept zero between sorts
+    uint32_t *chunk_off = nullptr;    // [chunks][256]
+};
+size_t sort_tile_count(size_t n);
+size_t sort_chunk_count(size_t n);
+// Stable sort of the n (<= n_bound) items list[i] (or i) by key = mat * M + hash bin of E;
+// out_list receives the items, out_keys the keys (both required).
 hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_ptr, uint32_t n_bound,
-                       const double *E, const int32_t *mat, uint32_t *keys_tmp, uint32_t *hist,
-                       uint32_t *offs, uint32_t n_keys, uint32_t *out_list, uint32_t *out_keys,
-                       hipStream_t st);
+                       const double *E, const int32_t *mat, const SortBufs &sb, uint32_t n_keys,
+                       uint32_t *out_list, uint32_t *out_keys, hipStream_t st);
 hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st);
 hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
                           uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on,
@@ -44,6 +55,9 @@ hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, c
 hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t,
                           const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
                           uint64_t first_pid, hipStream_t st);
+hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+                       uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                       unsigned long long *lost, hipStream_t st);
 hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols, const double *direct,
                               double *partial, double inv_n, double *S1, double *S2, hipStream_t st);
 

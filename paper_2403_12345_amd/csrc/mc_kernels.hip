@@ -18,6 +18,7 @@
 // the same run to run.
 #include "mc_device.h"
 #include "mc_internal.h"
+#include "mc_physics.h"
 
 #pragma clang fp contract(off)
 
@@ -227,63 +228,151 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
 }
 
 // ---------------------------------------------------------------------------
-// sort of the lookup queue by key = material * M + hash bin (counting sort:
-// histogram, exclusive scan, scatter).  Equal keys may land in any order;
-// every lookup writes only its own particle, so results do not depend on it.
+// sort of a queue by key = material * M + hash bin of E: a stable LSD radix
+// sort, 8 bits per pass.  Per pass: count the digits of each 4096-item tile
+// (wave multi-split, one LDS add per distinct digit of a wave), scan the
+// per-chunk digit totals, and scatter each tile in item order to
+//   chunk offset + earlier tiles of the chunk + earlier waves + lane rank.
+// Ranks come from ballots, not atomics, so the order is stable and the same
+// run to run.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_sort_hist(XsDev xs, const uint32_t *list, const uint32_t *n_ptr,
-                                                  uint32_t n_fixed, const double *E, const int32_t *mat,
-                                                  uint32_t *keys, uint32_t *hist)
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = WG * RS_ITEMS;  // 4096 items per tile
+constexpr int RS_CHUNK = 16;            // tiles per chunk of the offset scan
+
+// Lanes of the wave holding the same 8-bit digit (0 for an invalid lane).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid)
 {
-    const uint32_t n = n_ptr ? *n_ptr : n_fixed;
-    const uint32_t i = blockIdx.x * WG + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t p = list ? list[i] : i;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return valid ? m : 0ull;
+}
+
+__device__ __forceinline__ uint32_t sort_key(const XsDev &xs, const double *E, const int32_t *mat, uint32_t p)
+{
     int32_t m = mat[p];
     m = m < 0 ? 0 : (m >= xs.n_mat ? xs.n_mat - 1 : m);  // ids are validated by the caller; stay in bounds
-    const uint32_t key = (uint32_t)m * (uint32_t)xs.M + (uint32_t)hash_bin(xs, E[p]);
-    keys[i] = key;
-    atomicAdd(hist + key, 1u);
+    return (uint32_t)m * (uint32_t)xs.M + (uint32_t)hash_bin(xs, E[p]);
 }
 
-// Exclusive scan of the histogram into offsets, zeroing the histogram for the
-// next use (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *hist, uint32_t *offs, uint32_t n_keys)
+struct SortPassArgs {
+    XsDev xs;
+    const double *E;
+    const int32_t *mat;
+    const uint32_t *n_ptr;
+    uint32_t n_fixed;
+    int32_t shift;
+    const uint32_t *keys_in;   // null on the first pass: keys computed from (E, mat) of vals_in
+    uint32_t *keys_first;      // first pass: where the computed keys go
+    const uint32_t *vals_in;   // null: identity
+    uint32_t *keys_out, *vals_out;
+    uint32_t *tile_hist;       // [tiles][256]
+    uint32_t *chunk_total;     // [chunks][256], zero on entry of a count
+    const uint32_t *chunk_off; // [chunks][256]
+};
+
+__global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
 {
-    __shared__ uint32_t part[1024];
-    const uint32_t per = (n_keys + 1023u) / 1024u;
-    const uint32_t lo = threadIdx.x * per;
-    const uint32_t hi = lo + per < n_keys ? lo + per : n_keys;
-    uint32_t s = 0;
-    for (uint32_t k = lo; k < hi; ++k) s += hist[k];
-    part[threadIdx.x] = s;
+    __shared__ uint32_t h[256];
+    const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
+    const uint32_t base = blockIdx.x * (uint32_t)RS_TILE;
+    if (base >= n) return;
+    h[threadIdx.x] = 0u;
     __syncthreads();
-    for (uint32_t o = 1; o < 1024; o <<= 1) {
-        const uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const uint32_t i = base + r * WG + threadIdx.x;
+        const bool valid = i < n;
+        uint32_t key = 0;
+        if (valid) {
+            if (a.keys_in) {
+                key = a.keys_in[i];
+            } else {
+                key = sort_key(a.xs, a.E, a.mat, a.vals_in ? a.vals_in[i] : i);
+                a.keys_first[i] = key;
+            }
+        }
+        const uint32_t d = (key >> a.shift) & 255u;
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && lane_id() == __ffsll((long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
-    uint32_t run = part[threadIdx.x] - s;
-    for (uint32_t k = lo; k < hi; ++k) {
-        const uint32_t c = hist[k];
-        offs[k] = run;
-        run += c;
-        hist[k] = 0u;
-    }
+    __syncthreads();
+    const uint32_t c = h[threadIdx.x];
+    a.tile_hist[blockIdx.x * 256 + threadIdx.x] = c;
+    if (c) atomicAdd(&a.chunk_total[(blockIdx.x / RS_CHUNK) * 256 + threadIdx.x], c);
 }
 
-__global__ void __launch_bounds__(WG) k_sort_scatter(const uint32_t *list, const uint32_t *n_ptr,
-                                                     uint32_t n_fixed, const uint32_t *keys, uint32_t *offs,
-                                                     uint32_t *out_list, uint32_t *out_keys)
+// chunk_off[c][d] = (items with digit < d) + (items of digit d in chunks < c);
+// resets chunk_total for the next pass.  One workgroup, thread = digit.
+__global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32_t *chunk_off, uint32_t n_chunks)
 {
-    const uint32_t n = n_ptr ? *n_ptr : n_fixed;
-    const uint32_t i = blockIdx.x * WG + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t key = keys[i];
-    const uint32_t pos = atomicAdd(offs + key, 1u);
-    out_list[pos] = list ? list[i] : i;
-    if (out_keys) out_keys[pos] = key;
+    __shared__ uint32_t tot[256];
+    const uint32_t d = threadIdx.x;
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < n_chunks; ++c) {
+        const uint32_t v = chunk_total[c * 256 + d];
+        chunk_off[c * 256 + d] = run;
+        chunk_total[c * 256 + d] = 0u;
+        run += v;
+    }
+    tot[d] = run;
+    __syncthreads();
+    // exclusive scan over the 256 digit totals (Hillis-Steele)
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        const uint32_t v = d >= o ? tot[d - o] : 0u;
+        __syncthreads();
+        tot[d] += v;
+        __syncthreads();
+    }
+    const uint32_t base = tot[d] - run;
+    for (uint32_t c = 0; c < n_chunks; ++c) chunk_off[c * 256 + d] += base;
+}
+
+__global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
+{
+    __shared__ uint32_t off[256];
+    __shared__ uint32_t wc[WAVES * 256];
+    const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
+    const uint32_t base = blockIdx.x * (uint32_t)RS_TILE;
+    if (base >= n) return;
+    const uint32_t t = blockIdx.x, c0 = (t / RS_CHUNK) * RS_CHUNK;
+    {
+        uint32_t o = a.chunk_off[(t / RS_CHUNK) * 256 + threadIdx.x];
+        for (uint32_t u = c0; u < t; ++u) o += a.tile_hist[u * 256 + threadIdx.x];
+        off[threadIdx.x] = o;
+    }
+    const int wave = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t *keys_in = a.keys_in ? a.keys_in : a.keys_first;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) wc[w * 256 + threadIdx.x] = 0u;
+        __syncthreads();
+        const uint32_t i = base + r * WG + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const uint32_t val = valid ? (a.vals_in ? a.vals_in[i] : i) : 0u;
+        const uint32_t d = (key >> a.shift) & 255u;
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && lane_id() == __ffsll((long long)peers) - 1) wc[wave * 256 + d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = off[d] + (uint32_t)__popcll(peers & lt);
+            for (int w = 0; w < wave; ++w) pos += wc[w * 256 + d];
+            a.keys_out[pos] = key;
+            a.vals_out[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) add += wc[w * 256 + threadIdx.x];
+        off[threadIdx.x] += add;
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -311,6 +400,7 @@ struct LookupArgs {
 
 constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
 
+template <int ILP>
 __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 {
     __shared__ uint32_t sh[LDS_HASH_WORDS];
@@ -368,21 +458,30 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     if (m >= 0) {
     const int32_t q0 = xs.mat_off[m];
     const int32_t nk = xs.mat_off[m + 1] - q0;
-    const uint32_t *h0;
-    if (staged) h0 = sh + (b - s_info[2]) * nk;
-    else h0 = hash_row(xs, m, b, nk);
     double sa = 0.0, ss = 0.0;
-    for (int32_t q = 0; q < nk; ++q) {
-        const MatNuc mn = xs.mnuc[q0 + q];
-        const uint32_t ix = grid_find(xs.Eg + mn.off, mn.len, h0[q], h0[nk + q], e);
-        double c, s;
-        lerp_xs(xs, mn.off, ix, e, c, s);
-        sa = sa + mn.dens * c;
-        ss = ss + mn.dens * s;
-        if (a.idx_out) a.idx_out[(size_t)p * nk + q] = (int32_t)ix;
-        if (a.sc_out) a.sc_out[(size_t)p * nk + q] = c;
-        if (a.ss_out) a.ss_out[(size_t)p * nk + q] = s;
-    }
+    const MatNuc *mnuc = xs.mnuc + q0;
+    // the nuclide loop, once with the brackets in LDS and once in global memory
+    auto nuclides = [&](const uint32_t *h0) {
+        for (int32_t q = 0; q < nk; q += ILP) {
+            const int32_t cnt = nk - q < ILP ? nk - q : ILP;
+            double dens[ILP], c[ILP], s[ILP];
+            uint32_t ix[ILP];
+            micro_group<ILP>(xs, mnuc, h0, nk, q, cnt, e, dens, ix, c, s);
+            // the sum runs in material order, one nuclide after the other
+#pragma unroll
+            for (int k = 0; k < ILP; ++k) {
+                if (k < cnt) {
+                    sa = sa + dens[k] * c[k];
+                    ss = ss + dens[k] * s[k];
+                    if (a.idx_out) a.idx_out[(size_t)p * nk + q + k] = (int32_t)ix[k];
+                    if (a.sc_out) a.sc_out[(size_t)p * nk + q + k] = c[k];
+                    if (a.ss_out) a.ss_out[(size_t)p * nk + q + k] = s[k];
+                }
+            }
+        }
+    };
+    if (staged) nuclides(sh + (b - s_info[2]) * nk);
+    else nuclides(hash_row(xs, m, b, nk));
     if (a.Sa) a.Sa[p] = sa;
     if (a.Ss) a.Ss[p] = ss;
     if (a.flags) a.flags[p] = F_ALIVE;
@@ -396,186 +495,35 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// tallies: deterministic per-workgroup accumulation
-// ---------------------------------------------------------------------------
-// Adds val into bin `bin` (< 0: nothing) of the workgroup's row.  Each wave
-// peels off one distinct bin at a time: the lanes holding it are summed by the
-// butterfly and the first of them adds the sum into the wave's LDS slab; the
-// four slabs are then added in wave order into the workgroup's row.
-__device__ void wg_bin_add(int32_t bin, double val, double *slab, int32_t nbins, double *row)
-{
-    for (int32_t t = threadIdx.x; t < WAVES * nbins; t += WG) slab[t] = 0.0;
-    __syncthreads();
-    const int wave = threadIdx.x >> 6;
-    bool active = bin >= 0;
-    uint64_t mask = __ballot(active);
-    while (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        const int32_t B = __shfl(bin, leader, 64);
-        const bool mine = active && bin == B;
-        const double s = wave_sum(mine ? val : 0.0);
-        if (lane_id() == leader) slab[wave * nbins + B] += s;
-        active = active && !mine;
-        mask = __ballot(active);
-    }
-    __syncthreads();
-    for (int32_t t = threadIdx.x; t < nbins; t += WG) {
-        double s = 0.0;
-        for (int w = 0; w < WAVES; ++w) s = s + slab[w * nbins + t];
-        if (s != 0.0) row[t] = row[t] + s;
-    }
-    __syncthreads();
-}
-
-// Adds NG per-thread values into the workgroup's global-tally row.
-template <int NG>
-__device__ void wg_glob_add(const int32_t (&slot)[NG], const double (&val)[NG], double *lds, double *row)
-{
-    const int wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NG; ++k) {
-        const double s = wave_sum(val[k]);
-        if (lane_id() == 0) lds[k * WAVES + wave] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NG) {
-        double s = 0.0;
-        for (int w = 0; w < WAVES; ++w) s = s + lds[threadIdx.x * WAVES + w];
-        if (s != 0.0) row[slot[threadIdx.x]] = row[slot[threadIdx.x]] + s;
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ int32_t energy_bin(const GeomDev &g, double e)
-{
-    const int32_t n = g.n_ebins;
-    if (!(e >= g.e_edges[0]) || e > g.e_edges[n]) return -1;
-    int32_t lo = 0, hi = n - 1;  // largest b in [0, n-1] with edge[b] <= e
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (g.e_edges[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int32_t mesh_index(const GeomDev &g, double x, double y, double z)
-{
-    const double r[3] = {x, y, z};
-    int32_t c[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (r[k] < g.mesh_lo[k] || r[k] > g.mesh_hi[k]) return -1;
-        int32_t v = (int32_t)floor((r[k] - g.mesh_lo[k]) / (g.mesh_hi[k] - g.mesh_lo[k]) * g.mesh_dims[k]);
-        c[k] = v > g.mesh_dims[k] - 1 ? g.mesh_dims[k] - 1 : v;
-    }
-    return (c[2] * g.mesh_dims[1] + c[1]) * g.mesh_dims[0] + c[0];
-}
-
-// Track-length score of a straight flight through the mesh: walk the cells it
-// crosses (3-D digital differential analyser), adding w * length per cell.
-__device__ void mesh_flight(const GeomDev &g, double *acc, double x, double y, double z, double u,
-                            double v, double w, double d, double wt)
-{
-    const double r0[3] = {x, y, z}, dir[3] = {u, v, w};
-    double h[3], tnext[3], tdelta[3];
-    int32_t c[3], step[3];
-    // start cell: the one holding the flight's first point (nudged along the
-    // flight by a hair so a start on a mesh plane picks the cell ahead)
-    for (int k = 0; k < 3; ++k) {
-        h[k] = (g.mesh_hi[k] - g.mesh_lo[k]) / g.mesh_dims[k];
-        double p = r0[k] + dir[k] * fmin(d, 1e-9) * 0.5;
-        int32_t v0 = (int32_t)floor((p - g.mesh_lo[k]) / h[k]);
-        c[k] = v0 < 0 ? 0 : (v0 > g.mesh_dims[k] - 1 ? g.mesh_dims[k] - 1 : v0);
-        if (dir[k] > 0.0) {
-            step[k] = 1;
-            tnext[k] = (g.mesh_lo[k] + (c[k] + 1) * h[k] - r0[k]) / dir[k];
-            tdelta[k] = h[k] / dir[k];
-        } else if (dir[k] < 0.0) {
-            step[k] = -1;
-            tnext[k] = (g.mesh_lo[k] + c[k] * h[k] - r0[k]) / dir[k];
-            tdelta[k] = -h[k] / dir[k];
-        } else {
-            step[k] = 0;
-            tnext[k] = INFINITY;
-            tdelta[k] = INFINITY;
-        }
-    }
-    double t = 0.0;
-    for (int guard = 0; guard < 100000 && t < d; ++guard) {
-        int k = 0;
-        if (tnext[1] < tnext[k]) k = 1;
-        if (tnext[2] < tnext[k]) k = 2;
-        const double t1 = fmin(fmax(tnext[k], t), d);
-        if (t1 > t) {
-            const int32_t idx = (c[2] * g.mesh_dims[1] + c[1]) * g.mesh_dims[0] + c[0];
-            atomicAdd(acc + idx, wt * (t1 - t));
-        }
-        t = t1;
-        if (t >= d) break;
-        c[k] += step[k];
-        if (c[k] < 0 || c[k] >= g.mesh_dims[k]) break;
-        tnext[k] += tdelta[k];
-    }
-}
-
-// ---------------------------------------------------------------------------
 // advance: sample the flight, move, score track length
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev tal, const Counters *ctr,
                                                 uint64_t seed, int64_t max_events, int32_t log_on)
 {
     extern __shared__ double slab[];
-    __shared__ double gl[4 * WAVES];
+    __shared__ double gl[N_GLOBAL * WAVES];
     const uint32_t n = ctr->nA;
     const uint32_t i0 = blockIdx.x * WG;
     if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
-    const bool valid = i < n;
-    int32_t bin = -1;
-    double val = 0.0, g_track = 0.0, g_tabs = 0.0;
-    if (valid) {
+    StepScore sc;
+    clear_score(sc);
+    if (i < n) {
         const uint32_t s = b.A[i];
         if ((int64_t)b.ncoll[s] + b.ncross[s] >= max_events) {
-            // event cap reached: handled by the cross kernel as a lost particle
-            b.event[s] = 0xFF;
+            b.event[s] = 0xFF;  // event cap reached: the cross kernel ends it as lost
         } else {
-            double x = b.x[s], y = b.y[s], z = b.z[s];
-            const double u = b.u[s], v = b.v[s], w = b.w[s];
-            const double e = b.E[s], wt = b.wt[s], sa = b.Sa[s], st = sa + b.Ss[s];
-            const int32_t cell = b.cell[s];
-            const bool inside = b.inside[s] != 0;
-            Rng rng(seed, b.pid[s], b.lineage[s], b.ndraw[s]);
-            const double dc = -log(rng.next()) / st;
-            uint8_t ev;
-            const double db = surface_distance(g, x, y, z, u, v, w, cell, inside, ev);
-            const double d = (db < dc) ? db : dc;
-            if (!(db < dc)) ev = EV_COLLIDE;
-            const double x0 = x, y0 = y, z0 = z;
-            x = x + d * u;
-            y = y + d * v;
-            z = z + d * w;
-            b.x[s] = x; b.y[s] = y; b.z[s] = z;
-            b.ndraw[s] = rng.n;
-            b.event[s] = ev;
-            if (log_on) b.track[s] = b.track[s] + d;
-            g_track = wt * d;
-            g_tabs = wt * d * sa;
-            if (tal.enabled) {
-                switch (g.tally_kind) {
-                case TALLY_ENERGY: bin = energy_bin(g, e); break;
-                case TALLY_PIN: bin = inside ? cell : -1; break;
-                case TALLY_SLAB: bin = cell; break;
-                case TALLY_MESH: mesh_flight(g, tal.mesh_tl, x0, y0, z0, u, v, w, d, wt); break;
-                }
-                val = wt * d;
-            }
+            Particle p = load_particle(b, s);
+            do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on != 0, sc);
+            b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+            b.ndraw[s] = p.ndraw;
+            b.event[s] = p.ev;
+            if (log_on) b.track[s] = p.track;
         }
     }
     if (tal.enabled && g.tally_kind != TALLY_MESH)
-        wg_bin_add(bin, val, slab, tal.n_bins, tal.tl + (size_t)blockIdx.x * tal.n_bins);
-    const int32_t slots[2] = {G_TRACK, G_TRACK_ABS};
-    const double vals[2] = {g_track, g_tabs};
-    wg_glob_add<2>(slots, vals, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
+        wg_bin_add(sc.tl_bin, sc.tl_val, slab, tal.n_bins, tal.tl + (size_t)blockIdx.x * tal.n_bins);
+    wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,115 +580,41 @@ __global__ void __launch_bounds__(WG) k_split_scatter(BankDev b, Counters *ctr)
 // ---------------------------------------------------------------------------
 // surface crossing
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void write_log(const BankDev &b, HistLog *log, uint64_t first_pid,
-                                          uint32_t s, int32_t fate, double e)
-{
-    HistLog h;
-    h.fate = fate;
-    h.n_coll = b.ncoll[s];
-    h.n_cross = b.ncross[s];
-    h.pad = 0;
-    h.n_draws = b.ndraw[s];
-    h.E_final = e;
-    h.track = b.track[s];
-    h.weight = b.wt[s];
-    log[b.pid[s] - first_pid] = h;
-}
-
 __global__ void __launch_bounds__(WG) k_cross(BankDev b, GeomDev g, TallyDev tal, const Counters *ctr,
-                                              HistLog *log, uint64_t first_pid,
-                                              unsigned long long *lost)
+                                              HistLog *log, uint64_t first_pid, unsigned long long *lost)
 {
-    __shared__ double gl[4 * WAVES];
+    __shared__ double gl[N_GLOBAL * WAVES];
     const uint32_t n = ctr->nX;
     const uint32_t i0 = blockIdx.x * WG;
     if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
-    double v_cross = 0.0, v_leak = 0.0, v_lx = 0.0, v_lxu = 0.0;
+    StepScore sc;
+    clear_score(sc);
     if (i < n) {
         const uint32_t s = b.Qx[i];
-        const uint8_t ev = b.event[s];
-        if (ev == 0xFF) {
+        Particle p = load_particle(b, s);
+        if (p.ev == 0xFF) {
             b.flags[s] = 0;
             atomicAdd(lost, 1ull);
-            if (log) write_log(b, log, first_pid, s, FATE_LOST, b.E[s]);
+            if (log) write_log(log, first_pid, p, FATE_LOST);
         } else {
-            v_cross = 1.0;
-            int32_t cell = b.cell[s];
-            bool inside = b.inside[s] != 0;
-            const int32_t nc = b.ncross[s] + 1;
-            b.ncross[s] = nc;
-            int face = -1;        // outer face reached (0..5)
-            double face_pos = 0.0;
-            bool leaked = false;
-            if (g.kind == GEOM_SLAB) {
-                if (ev == EV_XHI) {
-                    if (cell == g.n_layers - 1) { face = 1; face_pos = g.x_edges[g.n_layers]; }
-                    else { cell += 1; b.x[s] = g.x_edges[cell]; }
-                } else {
-                    if (cell == 0) { face = 0; face_pos = g.x_edges[0]; }
-                    else { b.x[s] = g.x_edges[cell]; cell -= 1; }
-                }
-            } else {
-                const int32_t ci = cell % g.nx, cj = cell / g.nx;
-                const double P = g.pitch;
-                switch (ev) {
-                case EV_CYL: inside = !inside; break;
-                case EV_XHI:
-                    if (ci == g.nx - 1) { face = 1; face_pos = (double)g.nx * P; }
-                    else { cell += 1; b.x[s] = (double)(ci + 1) * P; }
-                    break;
-                case EV_XLO:
-                    if (ci == 0) { face = 0; face_pos = 0.0; }
-                    else { b.x[s] = (double)ci * P; cell -= 1; }
-                    break;
-                case EV_YHI:
-                    if (cj == g.ny - 1) { face = 3; face_pos = (double)g.ny * P; }
-                    else { cell += g.nx; b.y[s] = (double)(cj + 1) * P; }
-                    break;
-                case EV_YLO:
-                    if (cj == 0) { face = 2; face_pos = 0.0; }
-                    else { b.y[s] = (double)cj * P; cell -= g.nx; }
-                    break;
-                case EV_ZHI: face = 5; face_pos = g.z1; break;
-                case EV_ZLO: face = 4; face_pos = g.z0; break;
-                default: break;
-                }
-            }
-            if (face >= 0) {
-                if (g.bc[face] == BC_VACUUM) {
-                    leaked = true;
-                } else {
-                    const int axis = face >> 1;
-                    if (axis == 0) { b.u[s] = -b.u[s]; b.x[s] = face_pos; }
-                    else if (axis == 1) { b.v[s] = -b.v[s]; b.y[s] = face_pos; }
-                    else { b.w[s] = -b.w[s]; b.z[s] = face_pos; }
-                }
-            }
-            if (leaked) {
-                const double wt = b.wt[s];
-                v_leak = wt;
-                if (face == 1) {
-                    v_lx = wt;
-                    if (b.ncoll[s] == 0) v_lxu = wt;
-                }
+            bool need_lookup;
+            const int32_t fate = do_cross(p, g, sc, need_lookup);
+            b.ncross[s] = p.ncross;
+            if (fate) {
                 b.flags[s] = 0;
-                if (log) write_log(b, log, first_pid, s, FATE_LEAKED, b.E[s]);
+                if (log) write_log(log, first_pid, p, fate);
             } else {
-                const int32_t m_old = b.mat[s];
-                const int32_t m_new = region_material(g, cell, inside);
-                b.cell[s] = cell;
-                b.inside[s] = inside ? 1 : 0;
-                if (m_new != m_old) {
-                    b.mat[s] = m_new;
-                    b.flags[s] = F_ALIVE | F_LOOKUP;
-                }
+                b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+                b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
+                b.cell[s] = p.cell;
+                b.inside[s] = p.inside ? 1 : 0;
+                b.mat[s] = p.mat;
+                if (need_lookup) b.flags[s] = F_ALIVE | F_LOOKUP;
             }
         }
     }
-    const int32_t slots[4] = {G_NCROSS, G_LEAK, G_LEAK_XHI, G_LEAK_XHI_UNC};
-    const double vals[4] = {v_cross, v_leak, v_lx, v_lxu};
-    wg_glob_add<4>(slots, vals, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
+    wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,77 +625,96 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, 
                                                 uint64_t first_pid)
 {
     extern __shared__ double slab[];
-    __shared__ double gl[4 * WAVES];
+    __shared__ double gl[N_GLOBAL * WAVES];
     const uint32_t n = ctr->nC;
     const uint32_t i0 = blockIdx.x * WG;
     if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
-    int32_t bin = -1;
-    double val = 0.0, v_coll = 0.0, v_n = 0.0, v_abs = 0.0, v_cut = 0.0;
+    StepScore sc;
+    clear_score(sc);
     if (i < n) {
         const uint32_t s = b.Qc[i];
-        const double e = b.E[s], wt = b.wt[s], sa = b.Sa[s], ssig = b.Ss[s];
-        const double st = sa + ssig;
-        const int32_t m = b.mat[s];
-        b.ncoll[s] = b.ncoll[s] + 1;
-        v_n = 1.0;
-        v_coll = wt / st;
-        if (tal.enabled) {
-            switch (g.tally_kind) {
-            case TALLY_ENERGY: bin = energy_bin(g, e); break;
-            case TALLY_PIN: bin = b.inside[s] ? b.cell[s] : -1; break;
-            case TALLY_SLAB: bin = b.cell[s]; break;
-            case TALLY_MESH: {
-                const int32_t c = mesh_index(g, b.x[s], b.y[s], b.z[s]);
-                if (c >= 0) atomicAdd(tal.mesh_coll + c, wt / st);
-            } break;
-            }
-            val = wt / st;
-        }
-        Rng rng(seed, b.pid[s], b.lineage[s], b.ndraw[s]);
-        if (rng.next() * st < sa) {
-            v_abs = wt;
+        Particle p = load_particle(b, s);
+        const int32_t fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc);
+        b.ncoll[s] = p.ncoll;
+        b.ndraw[s] = p.ndraw;
+        if (fate) {
             b.flags[s] = 0;
-            b.ndraw[s] = rng.n;
-            if (log) write_log(b, log, first_pid, s, FATE_ABSORBED, e);
+            if (log) write_log(log, first_pid, p, fate);
         } else {
-            // target: first nuclide whose running sum of density * sigma_s
-            // reaches xi * Sigma_s (sigma_s gathered again, material order)
-            const double target = rng.next() * ssig;
-            const int32_t q0 = xs.mat_off[m], nk = xs.mat_off[m + 1] - q0;
-            const int32_t hb = hash_bin(xs, e);
-            double cum = 0.0;
-            int32_t pick = -1;
-            for (int32_t q = 0; q < nk; ++q) {
-                const double term = xs.mnuc[q0 + q].dens * micro_scatter(xs, m, q, nk, hb, e);
-                cum = cum + term;
-                if (term > 0.0) pick = q;
-                if (cum >= target && term > 0.0) break;
-            }
-            const double A = xs.awr[xs.mat_nuc[q0 + (pick < 0 ? 0 : pick)]];
-            const double mu = 2.0 * rng.next() - 1.0;
-            const double phi = 2.0 * M_PI * rng.next();
-            double e2, mul;
-            elastic_at_rest(A, e, mu, e2, mul);
-            double u = b.u[s], v = b.v[s], w = b.w[s];
-            turn(u, v, w, mul, phi);
-            b.u[s] = u; b.v[s] = v; b.w[s] = w;
-            b.E[s] = e2;
-            b.ndraw[s] = rng.n;
-            if (e2 < g.e_cut) {
-                v_cut = wt;
-                b.flags[s] = 0;
-                if (log) write_log(b, log, first_pid, s, FATE_CUTOFF, e2);
-            } else {
-                b.flags[s] = F_ALIVE | F_LOOKUP;
-            }
+            b.E[s] = p.E;
+            b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
+            b.flags[s] = F_ALIVE | F_LOOKUP;
         }
     }
     if (tal.enabled && g.tally_kind != TALLY_MESH)
-        wg_bin_add(bin, val, slab, tal.n_bins, tal.coll + (size_t)blockIdx.x * tal.n_bins);
-    const int32_t slots[4] = {G_COLL_EST, G_NCOLL, G_ABSORB, G_CUTOFF};
-    const double vals[4] = {v_coll, v_n, v_abs, v_cut};
-    wg_glob_add<4>(slots, vals, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
+        wg_bin_add(sc.c_bin, sc.c_val, slab, tal.n_bins, tal.coll + (size_t)blockIdx.x * tal.n_bins);
+    wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
+}
+
+// ---------------------------------------------------------------------------
+// tail: the last particles of a batch, each run to its end by one lane
+// ---------------------------------------------------------------------------
+// When no history remains to start and few particles are in flight, one
+// launch finishes them: every lane keeps its particle in registers and the
+// workgroup steps through lookup, flight and collision-or-crossing together,
+// so the tallies are still added per step in a fixed order (workgroup row =
+// blockIdx.x) and the histories are the ones the event kernels would give.
+__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, const Counters *ctr,
+                                             uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                                             unsigned long long *lost)
+{
+    extern __shared__ double slab[];
+    __shared__ double gl[N_GLOBAL * WAVES];
+    const uint32_t n = ctr->nA;
+    const uint32_t i0 = blockIdx.x * WG;
+    if (i0 >= n) return;
+    const uint32_t i = i0 + threadIdx.x;
+    const bool binned = tal.enabled && g.tally_kind != TALLY_MESH;
+    const bool log_on = log != nullptr;
+    double *trow = tal.tl + (size_t)blockIdx.x * tal.n_bins;
+    double *crow = tal.coll + (size_t)blockIdx.x * tal.n_bins;
+    double *grow = tal.glob + (size_t)blockIdx.x * N_GLOBAL;
+    Particle p{};
+    uint32_t s = 0;
+    bool alive = false, need = false;
+    if (i < n) {
+        s = b.A[i];
+        p = load_particle(b, s);
+        alive = true;
+        need = (b.flags[s] & F_LOOKUP) != 0;
+    }
+    while (__syncthreads_or(alive)) {
+        StepScore sc;
+        clear_score(sc);
+        int32_t fate = 0;
+        if (alive && need) {
+            do_lookup<DEFAULT_LOOKUP_ILP>(p, xs);
+            need = false;
+        }
+        if (alive && (int64_t)p.ncoll + p.ncross >= max_events) {
+            fate = FATE_LOST;
+            atomicAdd(lost, 1ull);
+        } else if (alive) {
+            do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on, sc);
+        }
+        if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, tal.n_bins, trow);
+        if (alive && fate == 0) {
+            if (p.ev == EV_COLLIDE) {
+                fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc);
+                need = fate == 0;
+            } else {
+                fate = do_cross(p, g, sc, need);
+            }
+        }
+        if (binned) wg_bin_add(sc.c_bin, sc.c_val, slab, tal.n_bins, crow);
+        wg_glob_add(sc.g, gl, grow);
+        if (alive && fate != 0) {
+            alive = false;
+            b.flags[s] = 0;
+            if (log) write_log(log, first_pid, p, fate);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -914,18 +807,51 @@ hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, Counters *ctr,
 }
 
 hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_ptr, uint32_t n_bound,
-                       const double *E, const int32_t *mat, uint32_t *keys_tmp, uint32_t *hist,
-                       uint32_t *offs, uint32_t n_keys, uint32_t *out_list, uint32_t *out_keys,
-                       hipStream_t st)
+                       const double *E, const int32_t *mat, const SortBufs &sb, uint32_t n_keys,
+                       uint32_t *out_list, uint32_t *out_keys, hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sort_hist, dim3(blocks_for(n_bound, WG)), dim3(WG), 0, st, xs, list, n_ptr,
-                       n_bound, E, mat, keys_tmp, hist);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, hist, offs, n_keys);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(n_bound, WG)), dim3(WG), 0, st, list, n_ptr,
-                       n_bound, keys_tmp, offs, out_list, out_keys);
+    uint32_t bits = 1;
+    while (bits < 32 && (1ull << bits) < (uint64_t)n_keys) ++bits;
+    const int passes = (int)((bits + 7) / 8);
+    const unsigned tiles = blocks_for(n_bound, RS_TILE);
+    const uint32_t chunks = (tiles + RS_CHUNK - 1) / RS_CHUNK;
+    SortPassArgs a{};
+    a.xs = xs;
+    a.E = E;
+    a.mat = mat;
+    a.n_ptr = n_ptr;
+    a.n_fixed = n_bound;
+    a.tile_hist = sb.tile_hist;
+    a.chunk_total = sb.chunk_total;
+    a.chunk_off = sb.chunk_off;
+    for (int p = 0; p < passes; ++p) {
+        a.shift = 8 * p;
+        if (p == 0) {
+            a.keys_in = nullptr;
+            a.keys_first = sb.kA;
+            a.vals_in = list;
+        } else {
+            a.keys_in = (p & 1) ? sb.kB : sb.kA;
+            a.keys_first = nullptr;
+            a.vals_in = (p & 1) ? sb.vB : sb.vA;
+        }
+        if (p == passes - 1) {
+            a.keys_out = out_keys;
+            a.vals_out = out_list;
+        } else {
+            a.keys_out = (p & 1) ? sb.kA : sb.kB;
+            a.vals_out = (p & 1) ? sb.vA : sb.vB;
+        }
+        hipLaunchKernelGGL(k_radix_count, dim3(tiles), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(WG), 0, st, sb.chunk_total, sb.chunk_off, chunks);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(WG), 0, st, a);
+    }
     return hipGetLastError();
 }
+
+size_t sort_tile_count(size_t n) { return (n + RS_TILE - 1) / RS_TILE; }
+size_t sort_chunk_count(size_t n) { return (sort_tile_count(n) + RS_CHUNK - 1) / RS_CHUNK; }
 
 hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
 {
@@ -945,7 +871,12 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     a.sc_out = l.sc_out;
     a.ss_out = l.ss_out;
     a.nuc_count = l.nuc_count;
-    hipLaunchKernelGGL(k_lookup, dim3(blocks_for(l.n_bound, WG)), dim3(WG), 0, st, a);
+    const dim3 grid(blocks_for(l.n_bound, WG));
+    switch (l.ilp) {
+    case 1: hipLaunchKernelGGL(k_lookup<1>, grid, dim3(WG), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_lookup<2>, grid, dim3(WG), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_lookup<4>, grid, dim3(WG), 0, st, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -986,6 +917,17 @@ hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, c
     const size_t lds = slab_bytes(g, t);
     hipLaunchKernelGGL(k_collide, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed,
                        log, first_pid);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+                       uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                       unsigned long long *lost, hipStream_t st)
+{
+    if (n_bound == 0) return hipSuccess;
+    const size_t lds = slab_bytes(g, t);
+    hipLaunchKernelGGL(k_tail, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed, max_events,
+                       log, first_pid, lost);
     return hipGetLastError();
 }
 

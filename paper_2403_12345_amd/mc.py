@@ -58,10 +58,18 @@ class mc_run_opts(C.Structure):
 class mc_stats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("lookups", C.c_uint64), ("nuclide_lookups", C.c_uint64),
                 ("lookup_launches", C.c_uint64), ("sorted_lookups", C.c_uint64), ("lost", C.c_uint64),
-                ("lookup_bytes", C.c_uint64), ("lookup_ms", C.c_double), ("batch_ms", C.c_double)]
+                ("lookup_bytes", C.c_uint64), ("lookup_ms", C.c_double), ("batch_ms", C.c_double),
+                ("tail_particles", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mc_tuning(C.Structure):
+    _fields_ = [("lookup_ilp", C.c_int32), ("tail_particles", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+    def as_dict(self):
+        return {"lookup_ilp": self.lookup_ilp, "tail_particles": self.tail_particles}
 
 
 class mc_tally_meta(C.Structure):
@@ -103,6 +111,8 @@ def load():
         "mc_sort_queue": ([V, SZ, V, V, V, V], C.c_int),
         "mc_hash_bounds": ([P(D), I32, D, D, I32, P(I32)], C.c_int),
         "mc_set_timing": ([V, I32], C.c_int),
+        "mc_set_tuning": ([V, P(mc_tuning)], C.c_int),
+        "mc_get_tuning": ([V, P(mc_tuning)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -233,6 +243,19 @@ def mc_lookup_nuclides(ctx, mat: int, E, idx=None, sig_c=None, sig_s=None):
 def mc_sort_queue(ctx, E, mat, perm, keys_sorted=None):
     _check(ctx, load().mc_sort_queue(ctx, E.numel(), _ptr(E), _ptr(mat), _ptr(perm),
                                      _ptr(keys_sorted)))
+
+
+def mc_set_tuning(ctx, lookup_ilp: int = 0, tail_particles: int = 0):
+    t = mc_tuning()
+    t.lookup_ilp = int(lookup_ilp)
+    t.tail_particles = int(tail_particles)
+    _check(ctx, load().mc_set_tuning(ctx, C.byref(t)))
+
+
+def mc_get_tuning(ctx) -> dict:
+    t = mc_tuning()
+    _check(ctx, load().mc_get_tuning(ctx, C.byref(t)))
+    return t.as_dict()
 
 
 def mc_set_timing(ctx, on: bool):

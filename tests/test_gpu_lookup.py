@@ -81,10 +81,12 @@ def test_nuclide_indices_bit_exact_and_xs(c2, torch_cuda, mat):
             assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("sorted_", [False, True])
-def test_macro_lookup_matches_oracle(c2, torch_cuda, sorted_):
+@pytest.mark.parametrize("sorted_,ilp", [(False, 4), (True, 4), (False, 1), (True, 2)])
+def test_macro_lookup_matches_oracle(c2, torch_cuda, sorted_, ilp):
+    """Every launch shape of the lookup kernel gives the oracle's values."""
     torch = torch_cuda
     prob, t, op = c2
+    mc.mc_set_tuning(t.ctx, lookup_ilp=ilp)
     rng = np.random.default_rng(7)
     n = 200_003  # several tiles and a ragged tail
     e = mcsynth.lookup_energies(rng, n)
@@ -96,6 +98,7 @@ def test_macro_lookup_matches_oracle(c2, torch_cuda, sorted_):
     Ss = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
     mc.mc_lookup_macro(t.ctx, E, Mt, Sa, Ss, sorted_)
     torch.cuda.synchronize()
+    mc.mc_set_tuning(t.ctx)
     ra, rs = oracle.macro_xs(op, m, e)
     for got, ref in ((Sa.cpu().numpy(), ra), (Ss.cpu().numpy(), rs)):
         rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
@@ -103,14 +106,16 @@ def test_macro_lookup_matches_oracle(c2, torch_cuda, sorted_):
         assert np.array_equal(got, ref)
 
 
-def test_sort_queue_is_a_sorted_permutation(c2, torch_cuda):
+@pytest.mark.parametrize("n", [1, 4095, 4097, 100_000, 300_001])
+def test_sort_queue_is_a_sorted_permutation(c2, torch_cuda, n):
     torch = torch_cuda
     prob, t, op = c2
     rng = np.random.default_rng(8)
-    n = 100_000
     e = mcsynth.lookup_energies(rng, n)
     m = rng.integers(0, 3, n).astype(np.int32)
     _say(f"sort n={n}")
+    if n > 1000:
+        e[: n // 3] = 0.0253  # a third of the queue in one key: many equal keys
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     keys = torch.empty(n, dtype=torch.int32, device="cuda")
     mc.mc_sort_queue(t.ctx, torch.from_numpy(e).cuda(), torch.from_numpy(m).cuda(), perm, keys)
@@ -119,6 +124,9 @@ def test_sort_queue_is_a_sorted_permutation(c2, torch_cuda):
     keys = keys.cpu().numpy().view(np.uint32).astype(np.int64)
     assert np.array_equal(np.sort(perm), np.arange(n))
     assert np.all(np.diff(keys) >= 0)
+    # stable: equal keys keep their input order
+    same_key = np.diff(keys) == 0
+    assert np.all(np.diff(perm)[same_key] > 0)
     M = prob.n_hash_bins
     assert np.array_equal(keys // M, m[perm])
     # the bin part is the hash bin of E up to the last-ulp rounding of ln E at an edge

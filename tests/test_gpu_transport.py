@@ -54,14 +54,16 @@ def _compare_histories(g, o):
     np.testing.assert_allclose(g["track"], o["track"], rtol=1e-12)
 
 
-@pytest.mark.parametrize("in_flight", [0, 997])
-def test_c1_histories_identical_to_oracle(torch_cuda, in_flight):
-    """All 10^4 C1 histories, the whole bank in flight and a ragged bank of 997
-    slots refilled from the batch."""
+@pytest.mark.parametrize("in_flight,tail", [(0, 0), (0, -1), (997, 0), (997, -1)])
+def test_c1_histories_identical_to_oracle(torch_cuda, in_flight, tail):
+    """All 10^4 C1 histories: the whole bank in flight and a ragged bank of 997
+    slots refilled from the batch, each with the one-launch tail (the default)
+    and with every event in the event kernels (tail = -1)."""
     torch = torch_cuda
     prob = mcsynth.c1_problem()
-    _say(f"c1 identity in_flight={in_flight}")
+    _say(f"c1 identity in_flight={in_flight} tail={tail}")
     with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, tail_particles=tail)
         g = _gpu_histories(torch, t, 1, 0, prob.histories, in_flight=in_flight)
     o = oracle.run(oracle.OracleProblem(prob), 1, 0, prob.histories, history=True).history
     _compare_histories(g, o)
@@ -151,6 +153,30 @@ def test_c2_tallies_match_oracle_and_rerun_is_bitwise(torch_cuda):
     for k in (mc.MC_G_TRACK, mc.MC_G_COLL_EST, mc.MC_G_NCOLL, mc.MC_G_NCROSS, mc.MC_G_TRACK_ABS):
         assert abs(glm[k] - st.mean["glob"][k]) <= 3 * math.hypot(gls[k], st.stderr["glob"][k]), k
     assert glm[mc.MC_G_ABSORB] + glm[mc.MC_G_CUTOFF] == pytest.approx(1.0, abs=1e-12)
+
+
+def test_c2_tail_and_event_paths_agree(torch_cuda):
+    """The one-launch tail and the event kernels run the same histories; the
+    tallies differ only in summation order."""
+    torch = torch_cuda
+    prob = mcsynth.c2_problem()
+    n = 50_000
+    res = {}
+    for tail in (-1, 0, 60_000):
+        with Transport(prob) as t:
+            mc.mc_set_tuning(t.ctx, tail_particles=tail)
+            h = _gpu_histories(torch, t, 2, 0, n)
+            m, _, _ = t.tallies(mc.MC_T_FLUX_TRACK)
+            g, _, _ = t.tallies(mc.MC_T_GLOBAL)
+            res[tail] = (h, m, g, t.stats())
+    h0, m0, g0, s0 = res[-1]
+    assert s0["tail_particles"] == 0 and res[60_000][3]["tail_particles"] == n
+    for tail in (0, 60_000):
+        h, m, g, _ = res[tail]
+        for f in ("fate", "n_coll", "n_cross", "n_draws", "E_final"):
+            assert np.array_equal(h[f], h0[f]), (tail, f)
+        np.testing.assert_allclose(m, m0, rtol=1e-10)
+        np.testing.assert_allclose(g, g0, rtol=1e-10)
 
 
 def test_c2_same_seed_histories_mostly_identical(torch_cuda):
