@@ -109,6 +109,43 @@ def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(4,)):
     return out
 
 
+def problem_set_bench(batches: int = 3):
+    """The 64 uneven problems run together (persistent kernel, graph replay,
+    autotuned work-item size and grid) against the same problems run one after
+    another through the single-problem event loop."""
+    import torch
+
+    import mcsynth
+    from paper_2403_12345_amd import mc
+    from paper_2403_12345_amd.transport import ProblemSet, Transport
+
+    probs = mcsynth.c4_problem_set()
+    total = sum(p.histories for p in probs)
+    with ProblemSet(probs, device=0) as ps:
+        best = mc.mc_autotune_problem_set(ps.ctx)
+        ps.run_batch(use_graph=True)  # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(batches):
+            ps.run_batch(use_graph=True)
+        torch.cuda.synchronize()
+        set_s = (time.perf_counter() - t0) / batches
+    seq_s = 0.0
+    for p in probs:
+        with Transport(p, device=0) as t:
+            t.run_batch(p.seed, 0, p.histories)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t.run_batch(p.seed, p.histories, p.histories)
+            torch.cuda.synchronize()
+            seq_s += time.perf_counter() - t0
+    return {"workload": "64 independent fixed-source problems, histories log-uniform in [1e3, 1e5] "
+                        f"({total} in all), 2-80 synthetic nuclides, infinite media and reflective pin cells",
+            "histories_per_batch": total, "set_particles_per_s": total / set_s,
+            "sequential_particles_per_s": total / seq_s, "speedup": seq_s / set_s,
+            "set_ms_per_batch": set_s * 1e3, "sequential_ms_per_batch": seq_s * 1e3, "tuning": best}
+
+
 def copy_calibration(n_doubles: int = 1 << 28, reps: int = 5):
     """A plain device copy of known size (2 GiB read + 2 GiB written per launch),
     the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -135,7 +172,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-inactive", action="store_true", help="skip the tally-off contrast batch")
     ap.add_argument("--no-lookup-bench", action="store_true", help="skip the 300-nuclide lookup benchmark")
-    ap.add_argument("--mode", choices=("full", "lookup", "copy"), default="full",
+    ap.add_argument("--no-problem-set", action="store_true", help="skip the 64-problem batching benchmark")
+    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set"), default="full",
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -154,6 +192,9 @@ def main():
         return
     if args.mode == "lookup":
         print(json.dumps({"lookup_microbench": lookup_microbench(ilps=(1, 2, 4))}), flush=True)
+        return
+    if args.mode == "set":
+        print(json.dumps({"problem_set": problem_set_bench()}), flush=True)
         return
     prob = mcsynth.c2_problem()
     n = prob.histories
@@ -230,6 +271,8 @@ def main():
     }
     if not args.no_lookup_bench:
         line["lookup_microbench"] = lookup_microbench()
+    if not args.no_problem_set:
+        line["problem_set"] = problem_set_bench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, seed)
     print(json.dumps(line), flush=True)

@@ -310,25 +310,110 @@ int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t
 
 /*
  * Launch-shape parameters of the kernels (the autotuner's search space).
- * Zero fields keep the library default.  They change speed only: every
- * setting gives the same results bit for bit.
- *   lookup_ilp    nuclides each lane looks up in lockstep in the lookup
- *                 kernel (1, 2 or 4; default 2)
+ * Zero fields keep the library default.  They change speed only: histories
+ * are the same for every setting, and tallies agree to summation order.
+ *   lookup_ilp     nuclides each lane looks up in lockstep in the lookup
+ *                  kernel (1, 2 or 4; default 2)
  *   tail_particles when no history remains to start and at most this many
- *                 particles are in flight, the remaining histories are
- *                 finished by one kernel launch in which each lane runs its
- *                 particle to the end (0: default 32,768; -1: never)
+ *                  particles are in flight, the remaining histories are
+ *                  finished by one kernel launch in which each lane runs its
+ *                  particle to the end (0: default 32,768; -1: never)
+ *   sort_min       default of mc_run_opts.sort_min (0: 16,384)
+ *   in_flight      default of mc_run_opts.in_flight (0: 1,048,576)
+ *   set_tile_histories  histories per work item of the problem-set kernel,
+ *                  a multiple of 256 (0: 256)
+ *   set_grid       persistent workgroups of the problem-set kernel (0: two
+ *                  per compute unit)
  */
 typedef struct mc_tuning {
     int32_t lookup_ilp;
     int32_t tail_particles;
-    int32_t reserved[6];
+    int32_t sort_min;
+    int32_t in_flight;
+    int32_t set_tile_histories;
+    int32_t set_grid;
+    int32_t reserved[2];
 } mc_tuning;
 
 /* Set (mc_set_tuning) or read (mc_get_tuning) the context's launch shapes.
  * Errors: MC_EINVAL for a value outside the ranges above. */
 int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t);
 int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
+
+/*
+ * Autotuner of the single-problem path: times one batch of n histories
+ * (pids first_pid .. first_pid + n - 1, key seed) per candidate, searching one
+ * parameter at a time over lookup_ilp {1, 2, 4}, tail_particles {8192, 32768,
+ * 131072}, sort_min {4096, 16384, 65536} and in_flight {n/4, n/2, n} (capped
+ * at 2^20), keeps the fastest in the context (mc_set_tuning) and returns it in
+ * *best.  The tallies are reset afterwards.  cache_path (nullable) names a
+ * text file of one line per tuned problem: when it holds the signature of
+ * this problem and device, the stored setting is used without timing; else
+ * the result is appended.  Requires materials and geometry.
+ */
+int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const char *cache_path,
+                mc_tuning *best);
+
+/*
+ * Problem set: many small independent fixed-source problems run together in
+ * one persistent kernel (workgroups pull (problem, history range) tiles from a
+ * queue until none is left), the batching layer that stands in for the
+ * paper's concurrent streams on one GPU (section 2, "GPU Streams") and its
+ * refill of in-flight particles (section 2, "In-Flight Particles").
+ * Each problem has its own nuclides, materials (ids local to the problem),
+ * geometry, source, tally (not a mesh), histories per batch and seed; batch b
+ * of problem p runs pids first_pid + b * histories + [0, histories).  A
+ * problem's histories are the ones mc_run_batch would run for it alone.
+ */
+typedef struct mc_problem_desc {
+    int32_t n_nuc;
+    const int32_t *grid_len;
+    const double *const *E;
+    const double *const *sig_c;
+    const double *const *sig_s;
+    const double *awr;
+    int32_t n_mat;
+    const int32_t *mat_len;
+    const int32_t *mat_nuc;
+    const double *mat_dens;
+    const mc_geometry_desc *geometry;
+    uint64_t histories;
+    uint64_t seed;
+    uint64_t first_pid;
+} mc_problem_desc;
+
+/* Upload a problem set (host arrays, copied); replaces an earlier set and
+ * zeroes its tallies.  Errors: MC_EINVAL naming the problem. */
+int mc_set_problem_set(mc_ctx *ctx, int32_t n_problems, const mc_problem_desc *problems,
+                       int32_t n_hash_bins);
+
+typedef struct mc_set_opts {
+    int32_t use_graph;     /* 1: replay a captured hipGraph of the whole batch (zeroing,
+                              persistent kernel, statistics), captured on first use */
+    int32_t pad;
+    int64_t max_events;    /* per-history event cap (0: 100,000) */
+    void *history_log;     /* device, nullable: one mc_history per history of the
+                              batch, problem after problem in input order (not with
+                              use_graph) */
+} mc_set_opts;
+
+/* Run one batch of every problem of the set.  Synchronizes the stream. */
+int mc_run_problem_set(mc_ctx *ctx, const mc_set_opts *opts);
+
+/* Batch statistics of one problem's tally (as mc_get_tallies). */
+int mc_get_problem_tallies(mc_ctx *ctx, int32_t problem, int32_t tally_id, double *mean,
+                           double *stderr_, size_t n_bins, mc_tally_meta *meta);
+
+/* Zero the set's tallies and restart its batch count at 0. */
+int mc_reset_problem_set(mc_ctx *ctx);
+
+/*
+ * Autotuner of the problem set: times one batch per candidate over
+ * set_tile_histories {256, 512, 1024, 2048} x set_grid {1, 2, 4, 8 per
+ * compute unit}, keeps the fastest, resets the set (mc_reset_problem_set).
+ * cache_path as for mc_autotune.
+ */
+int mc_autotune_problem_set(mc_ctx *ctx, const char *cache_path, mc_tuning *best);
 
 /* Library version string. */
 const char *mc_version(void);

@@ -344,6 +344,43 @@ def slab_problem(sigma_t=(0.2, 1.5, 0.5), thickness=(60.0, 80.0, 40.0 + 20.0),
                    tally=Tally(TALLY_SLAB), histories=histories, batches=batches, seed=seed)
 
 
+def c4_problem_set(data_seed: int = 4004, seed: int = 4, n_problems: int = 64,
+                   histories_range=(1_000, 100_000), nuclide_range=(2, 80),
+                   grid_range=(2_000, 10_000)) -> List[Problem]:
+    """Independent fixed-source problems of uneven size: histories log-uniform
+    in [1e3, 1e5], 2-80 synthetic nuclides (the first with A = 1), clustered
+    grids of 2k-10k points, half infinite media (one material, isotropic 2 MeV
+    point source) and half single reflective pin cells (r 0.41, pitch 1.26,
+    height 1; fuel in the cylinder, the first one or two nuclides as
+    moderator outside; uniform source), each with a 50-bin log-energy flux
+    tally and its own Philox key (seed << 32 | problem index)."""
+    rng = np.random.default_rng(data_seed)
+    probs = []
+    for p in range(n_problems):
+        hist = int(round(_log_uniform(rng, *histories_range)))
+        n_nuc = int(rng.integers(nuclide_range[0], nuclide_range[1] + 1))
+        awr = np.concatenate([[1.0], rng.uniform(2.0, 240.0, n_nuc - 1)])
+        sizes = rng.integers(grid_range[0], grid_range[1] + 1, n_nuc)
+        nucs = [make_nuclide(rng, a, int(s), "clustered") for a, s in zip(awr, sizes)]
+        key = (seed << 32) | p
+        if p % 2 == 0:
+            mat = make_material(rng, nucs, np.arange(n_nuc), 0.5, fixed_fraction=(0, 0.5))
+            probs.append(Problem(name=f"c4_{p}_infinite", nuclides=nucs, materials=[mat],
+                                 geometry=Geometry(kind=GEOM_INFINITE, material=0),
+                                 source=Source(kind=SRC_POINT), tally=Tally(TALLY_ENERGY, energy_edges(50)),
+                                 histories=hist, batches=1, seed=key))
+        else:
+            n_mod = 1 if n_nuc == 2 else 2
+            mod = make_material(rng, nucs, np.arange(n_mod), 0.5, fixed_fraction=(0, 0.8) if n_mod == 2 else None)
+            fuel = make_material(rng, nucs, np.arange(n_mod, n_nuc), 0.6)
+            geom = _lattice_geometry(1, np.zeros(1, np.int32), 1)
+            probs.append(Problem(name=f"c4_{p}_pincell", nuclides=nucs, materials=[fuel, mod], geometry=geom,
+                                 source=Source(kind=SRC_BOX, box=(0.0, PIN_PITCH, 0.0, PIN_PITCH, 0.0, 1.0)),
+                                 tally=Tally(TALLY_ENERGY, energy_edges(50)), histories=hist, batches=1,
+                                 seed=key))
+    return probs
+
+
 def lookup_energies(rng, n: int) -> np.ndarray:
     """Energies log-uniform over [EMIN, EMAX] (the lookup benchmark's input)."""
     return _log_uniform(rng, EMIN, EMAX, n).astype(np.float64)

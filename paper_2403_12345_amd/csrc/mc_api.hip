@@ -83,6 +83,26 @@ struct mc_ctx {
     mc_stats stats{};
     bool timing = false;  // time the stand-alone lookups (mc_set_timing)
     mc_tuning tune{};      // launch shapes (0 = default)
+    int n_cu = 256;        // compute units of the device
+    std::string arch;      // gcnArchName of the device
+    uint64_t xs_sig = 0, geom_sig = 0, set_sig = 0;  // signatures for the autotuner cache
+
+    // problem set (batching layer)
+    bool have_set = false;
+    Buffers set_bufs, set_tile_bufs;
+    XsDev set_xs{};
+    SetDev set{};
+    std::vector<SetProblem> set_probs;  // input order
+    std::vector<int32_t> set_order;     // problems in tile order
+    int32_t set_max_bins = 0;
+    uint32_t set_tile_hist = 0;         // tile size the tiles were built for
+    uint64_t set_batches = 0;
+    uint64_t set_histories = 0;         // histories per batch over all problems
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint32_t graph_grid = 0, graph_tile = 0;
+    int64_t graph_max_events = 0;
 };
 
 static int lookup_ilp(const mc_ctx *ctx) { return ctx->tune.lookup_ilp ? ctx->tune.lookup_ilp : DEFAULT_LOOKUP_ILP; }
@@ -141,6 +161,25 @@ static void build_bounds(const double *E, int32_t N, double emin, double emax, i
     lo[M] = N - 2;
 }
 
+// FNV-1a over raw bytes: signatures of what the autotuner's timings depend on
+static uint64_t fnv(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+template <class T>
+static uint64_t fnv_vec(uint64_t h, const std::vector<T> &v)
+{
+    return fnv(h, v.data(), v.size() * sizeof(T));
+}
+static uint64_t geom_signature(uint64_t h, const GeomDev &g)
+{
+    const int32_t ints[] = {g.kind, g.nx, g.ny, g.n_layers, g.src_kind, g.tally_kind, g.n_bins};
+    const double dbl[] = {g.pitch, g.radius, g.z0, g.z1, g.src_E, g.e_cut};
+    return fnv(fnv(h, ints, sizeof(ints)), dbl, sizeof(dbl));
+}
+
 extern "C" {
 
 const char *mc_version(void) { return "mc355 0.1 (gfx950)"; }
@@ -159,6 +198,8 @@ int mc_create(mc_ctx **out, int device, void *hip_stream)
     if (!ctx) return MC_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    ctx->arch = prop.gcnArchName;
     int rc = dalloc(ctx, ctx->misc_bufs, &ctx->ctr, 2);
     if (!rc) rc = dalloc(ctx, ctx->misc_bufs, &ctx->dstat, 4);
     if (!rc && hipHostMalloc((void **)&ctx->ctr_host, 2 * sizeof(Counters), hipHostMallocDefault) != hipSuccess)
@@ -183,6 +224,11 @@ void mc_destroy(mc_ctx *ctx)
     ctx->bank_bufs.release();
     ctx->misc_bufs.release();
     ctx->scratch_bufs.release();
+    ctx->set_bufs.release();
+    ctx->set_tile_bufs.release();
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
     for (hipEvent_t e : ctx->ev_a) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_b) (void)hipEventDestroy(e);
@@ -207,119 +253,132 @@ int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t
     return MC_OK;
 }
 
-int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const double *const *E,
-                      const double *const *sig_c, const double *const *sig_s, const double *awr,
-                      int32_t n_mat, const int32_t *mat_len, const int32_t *mat_nuc,
-                      const double *mat_dens, int32_t n_hash_bins)
-{
-    if (!ctx) return MC_EINVAL;
-    if (n_nuc < 1 || !grid_len || !E || !sig_c || !sig_s || !awr || n_mat < 1 || !mat_len || !mat_nuc ||
-        !mat_dens || n_hash_bins < 1)
-        return fail(ctx, MC_EINVAL, "mc_init_materials: missing array or non-positive count");
-    HIPCHK(hipSetDevice(ctx->device));
-    // validate nuclides
-    uint64_t total = 0;
+// ---------------------------------------------------------------------------
+// cross-section tables: validation and host layout, shared by the single
+// problem and the problem set
+// ---------------------------------------------------------------------------
+struct NuclideInput {
+    int32_t n_nuc;
+    const int32_t *grid_len;
+    const double *const *E, *const *sig_c, *const *sig_s;
+    const double *awr;
+    int32_t n_mat;
+    const int32_t *mat_len, *mat_nuc;
+    const double *mat_dens;
+};
+
+struct HostXs {
+    std::vector<double> Eg, xs, awr;
+    std::vector<int32_t> moff{0}, mnucid, mat_len;
+    std::vector<MatNuc> mnuc;
+    std::vector<uint64_t> hoff;
+    std::vector<uint32_t> hash;
+    std::vector<const double *> grids;   // per nuclide (host, for the bounds)
+    std::vector<int32_t> glen;
+    std::vector<uint32_t> goff;
     double emin = INFINITY, emax = 0.0;
-    for (int32_t k = 0; k < n_nuc; ++k) {
-        const int32_t n = grid_len[k];
-        if (n < 2 || !E[k] || !sig_c[k] || !sig_s[k])
-            return fail(ctx, MC_EINVAL, "nuclide " + std::to_string(k) + ": grid shorter than 2 points");
-        if (!(awr[k] > 0.0) || !std::isfinite(awr[k]))
-            return fail(ctx, MC_EINVAL, "nuclide " + std::to_string(k) + ": mass ratio must be > 0");
+};
+
+// Validate one problem's nuclides and materials and append them (nuclide and
+// material ids shifted by what is already there).
+static int append_xs(mc_ctx *ctx, HostXs &H, const NuclideInput &in, const std::string &who)
+{
+    if (in.n_nuc < 1 || !in.grid_len || !in.E || !in.sig_c || !in.sig_s || !in.awr || in.n_mat < 1 ||
+        !in.mat_len || !in.mat_nuc || !in.mat_dens)
+        return fail(ctx, MC_EINVAL, who + "missing array or non-positive count");
+    const int32_t nuc_base = (int32_t)H.glen.size();
+    for (int32_t k = 0; k < in.n_nuc; ++k) {
+        const int32_t n = in.grid_len[k];
+        const std::string nk = who + "nuclide " + std::to_string(k) + ": ";
+        if (n < 2 || !in.E[k] || !in.sig_c[k] || !in.sig_s[k]) return fail(ctx, MC_EINVAL, nk + "grid shorter than 2 points");
+        if (!(in.awr[k] > 0.0) || !std::isfinite(in.awr[k])) return fail(ctx, MC_EINVAL, nk + "mass ratio must be > 0");
         for (int32_t j = 0; j < n; ++j) {
-            if (!std::isfinite(E[k][j]) || !(E[k][j] > 0.0))
-                return fail(ctx, MC_EINVAL, "nuclide " + std::to_string(k) + ": energy not finite and > 0");
-            if (j && !(E[k][j] > E[k][j - 1]))
-                return fail(ctx, MC_EINVAL,
-                            "nuclide " + std::to_string(k) + ": grid not strictly increasing at point " +
-                                std::to_string(j));
-            if (!(sig_c[k][j] >= 0.0) || !(sig_s[k][j] >= 0.0) || !std::isfinite(sig_c[k][j]) ||
-                !std::isfinite(sig_s[k][j]))
-                return fail(ctx, MC_EINVAL, "nuclide " + std::to_string(k) + ": cross section < 0 or not finite");
+            if (!std::isfinite(in.E[k][j]) || !(in.E[k][j] > 0.0))
+                return fail(ctx, MC_EINVAL, nk + "energy not finite and > 0");
+            if (j && !(in.E[k][j] > in.E[k][j - 1]))
+                return fail(ctx, MC_EINVAL, nk + "grid not strictly increasing at point " + std::to_string(j));
+            if (!(in.sig_c[k][j] >= 0.0) || !(in.sig_s[k][j] >= 0.0) || !std::isfinite(in.sig_c[k][j]) ||
+                !std::isfinite(in.sig_s[k][j]))
+                return fail(ctx, MC_EINVAL, nk + "cross section < 0 or not finite");
         }
-        total += (uint64_t)n;
-        emin = std::min(emin, E[k][0]);
-        emax = std::max(emax, E[k][n - 1]);
-    }
-    if (total >= (1ull << 32)) return fail(ctx, MC_EINVAL, "more than 2^32 grid points in total");
-    uint64_t n_entries = 0;
-    for (int32_t m = 0; m < n_mat; ++m) {
-        if (mat_len[m] < 1) return fail(ctx, MC_EINVAL, "material " + std::to_string(m) + " has no nuclides");
-        for (int32_t q = 0; q < mat_len[m]; ++q) {
-            const int32_t k = mat_nuc[n_entries + q];
-            const double d = mat_dens[n_entries + q];
-            if (k < 0 || k >= n_nuc)
-                return fail(ctx, MC_EINVAL, "material " + std::to_string(m) + ": unknown nuclide id " +
-                                                std::to_string(k));
-            if (!(d > 0.0) || !std::isfinite(d))
-                return fail(ctx, MC_EINVAL, "material " + std::to_string(m) + ": density must be > 0");
+        if ((uint64_t)H.Eg.size() + (uint64_t)n >= (1ull << 32))
+            return fail(ctx, MC_EINVAL, "more than 2^32 grid points in total");
+        H.goff.push_back((uint32_t)H.Eg.size());
+        H.glen.push_back(n);
+        H.grids.push_back(in.E[k]);
+        for (int32_t j = 0; j < n; ++j) {
+            H.Eg.push_back(in.E[k][j]);
+            H.xs.push_back(in.sig_c[k][j]);
+            H.xs.push_back(in.sig_s[k][j]);
         }
-        n_entries += (uint64_t)mat_len[m];
+        H.awr.push_back(in.awr[k]);
+        H.emin = std::min(H.emin, in.E[k][0]);
+        H.emax = std::max(H.emax, in.E[k][n - 1]);
     }
-    if ((uint64_t)n_mat * (uint64_t)n_hash_bins >= (1ull << 32))
-        return fail(ctx, MC_EINVAL, "n_mat * n_hash_bins must stay below 2^32");
+    uint64_t q = 0;
+    for (int32_t m = 0; m < in.n_mat; ++m) {
+        const std::string mk = who + "material " + std::to_string(m) + ": ";
+        if (in.mat_len[m] < 1) return fail(ctx, MC_EINVAL, mk + "no nuclides");
+        for (int32_t j = 0; j < in.mat_len[m]; ++j, ++q) {
+            const int32_t k = in.mat_nuc[q];
+            const double d = in.mat_dens[q];
+            if (k < 0 || k >= in.n_nuc) return fail(ctx, MC_EINVAL, mk + "unknown nuclide id " + std::to_string(k));
+            if (!(d > 0.0) || !std::isfinite(d)) return fail(ctx, MC_EINVAL, mk + "density must be > 0");
+            H.mnucid.push_back(nuc_base + k);
+            H.mnuc.push_back(MatNuc{0u, 0u, d});  // grid placement filled in finish_xs
+        }
+        H.mat_len.push_back(in.mat_len[m]);
+        H.moff.push_back(H.moff.back() + in.mat_len[m]);
+    }
+    return MC_OK;
+}
 
-    // host tables
-    std::vector<double> Eg(total);
-    std::vector<double> xs(2 * total);
-    std::vector<uint32_t> off(n_nuc);
-    uint64_t p = 0;
-    for (int32_t k = 0; k < n_nuc; ++k) {
-        off[k] = (uint32_t)p;
-        for (int32_t j = 0; j < grid_len[k]; ++j, ++p) {
-            Eg[p] = E[k][j];
-            xs[2 * p] = sig_c[k][j];
-            xs[2 * p + 1] = sig_s[k][j];
-        }
+// Hash bounds of every material over the common [emin, emax] with M bins.
+static int finish_xs(mc_ctx *ctx, HostXs &H, int32_t M)
+{
+    const size_t n_mat = H.mat_len.size();
+    if ((uint64_t)n_mat * (uint64_t)M >= (1ull << 32)) return fail(ctx, MC_EINVAL, "n_mat * n_hash_bins must stay below 2^32");
+    const size_t n_nuc = H.glen.size();
+    std::vector<int32_t> lo(n_nuc * (size_t)(M + 1));
+    for (size_t k = 0; k < n_nuc; ++k) build_bounds(H.grids[k], H.glen[k], H.emin, H.emax, M, &lo[k * (M + 1)]);
+    uint64_t words = 0;
+    H.hoff.resize(n_mat);
+    for (size_t m = 0; m < n_mat; ++m) {
+        H.hoff[m] = words;
+        words += (uint64_t)(M + 1) * (uint64_t)H.mat_len[m];
     }
-    const int32_t M = n_hash_bins;
-    std::vector<int32_t> lo((size_t)n_nuc * (M + 1));
-    for (int32_t k = 0; k < n_nuc; ++k) build_bounds(E[k], grid_len[k], emin, emax, M, &lo[(size_t)k * (M + 1)]);
-    std::vector<int32_t> moff(n_mat + 1);
-    std::vector<MatNuc> mnuc(n_entries);
-    std::vector<uint64_t> hoff(n_mat);
-    uint64_t hash_words = 0;
-    moff[0] = 0;
-    for (int32_t m = 0; m < n_mat; ++m) {
-        moff[m + 1] = moff[m] + mat_len[m];
-        hoff[m] = hash_words;
-        hash_words += (uint64_t)(M + 1) * (uint64_t)mat_len[m];
-    }
-    std::vector<uint32_t> hash(hash_words);
-    for (int32_t m = 0; m < n_mat; ++m) {
-        const int32_t nk = mat_len[m];
+    H.hash.assign(words, 0u);
+    for (size_t m = 0; m < n_mat; ++m) {
+        const int32_t nk = H.mat_len[m];
         for (int32_t q = 0; q < nk; ++q) {
-            const int32_t k = mat_nuc[moff[m] + q];
-            mnuc[moff[m] + q] = MatNuc{off[k], (uint32_t)grid_len[k], mat_dens[moff[m] + q]};
-            for (int32_t b = 0; b <= M; ++b)
-                hash[hoff[m] + (uint64_t)b * nk + q] = (uint32_t)lo[(size_t)k * (M + 1) + b];
+            const int32_t k = H.mnucid[H.moff[m] + q];
+            MatNuc &mn = H.mnuc[H.moff[m] + q];
+            mn.off = H.goff[k];
+            mn.len = (uint32_t)H.glen[k];
+            for (int32_t b = 0; b <= M; ++b) H.hash[H.hoff[m] + (uint64_t)b * nk + q] = (uint32_t)lo[(size_t)k * (M + 1) + b];
         }
     }
+    return MC_OK;
+}
 
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->mat_bufs.release();
-    ctx->have_mat = false;
-    ctx->have_geom = false;
-    XsDev x{};
+static int upload_xs(mc_ctx *ctx, const HostXs &H, int32_t M, Buffers &B, XsDev &x)
+{
     double *d_Eg, *d_awr;
     double2 *d_xs;
     int32_t *d_moff, *d_mnucid;
     MatNuc *d_mnuc;
     uint32_t *d_hash;
     uint64_t *d_hoff;
-    int rc = upload(ctx, ctx->mat_bufs, &d_Eg, Eg.data(), Eg.size());
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_xs, reinterpret_cast<const double2 *>(xs.data()), total);
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_awr, awr, (size_t)n_nuc);
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_moff, moff.data(), moff.size());
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_mnucid, mat_nuc, (size_t)n_entries);
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_mnuc, mnuc.data(), mnuc.size());
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_hash, hash.data(), hash.size());
-    if (!rc) rc = upload(ctx, ctx->mat_bufs, &d_hoff, hoff.data(), hoff.size());
-    ctx->n_keys = (uint32_t)((uint64_t)n_mat * (uint64_t)M);
-    if (rc) {
-        ctx->mat_bufs.release();
-        return rc;
-    }
+    int rc = upload(ctx, B, &d_Eg, H.Eg.data(), H.Eg.size());
+    if (!rc) rc = upload(ctx, B, &d_xs, reinterpret_cast<const double2 *>(H.xs.data()), H.Eg.size());
+    if (!rc) rc = upload(ctx, B, &d_awr, H.awr.data(), H.awr.size());
+    if (!rc) rc = upload(ctx, B, &d_moff, H.moff.data(), H.moff.size());
+    if (!rc) rc = upload(ctx, B, &d_mnucid, H.mnucid.data(), H.mnucid.size());
+    if (!rc) rc = upload(ctx, B, &d_mnuc, H.mnuc.data(), H.mnuc.size());
+    if (!rc) rc = upload(ctx, B, &d_hash, H.hash.data(), H.hash.size());
+    if (!rc) rc = upload(ctx, B, &d_hoff, H.hoff.data(), H.hoff.size());
+    if (rc) return rc;
+    x = XsDev{};
     x.Eg = d_Eg;
     x.xs = d_xs;
     x.awr = d_awr;
@@ -328,11 +387,38 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     x.mnuc = d_mnuc;
     x.hash = d_hash;
     x.hash_off = d_hoff;
-    x.n_mat = n_mat;
+    x.n_mat = (int32_t)H.mat_len.size();
     x.M = M;
-    x.ln_emin = std::log(emin);
-    x.inv_delta = (double)M / std::log(emax / emin);
-    ctx->xs = x;
+    x.ln_emin = std::log(H.emin);
+    x.inv_delta = (double)M / std::log(H.emax / H.emin);
+    return MC_OK;
+}
+
+int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const double *const *E,
+                      const double *const *sig_c, const double *const *sig_s, const double *awr,
+                      int32_t n_mat, const int32_t *mat_len, const int32_t *mat_nuc, const double *mat_dens,
+                      int32_t n_hash_bins)
+{
+    if (!ctx) return MC_EINVAL;
+    if (n_hash_bins < 1) return fail(ctx, MC_EINVAL, "mc_init_materials: n_hash_bins must be >= 1");
+    HIPCHK(hipSetDevice(ctx->device));
+    HostXs H;
+    const NuclideInput in{n_nuc, grid_len, E, sig_c, sig_s, awr, n_mat, mat_len, mat_nuc, mat_dens};
+    int rc = append_xs(ctx, H, in, "mc_init_materials: ");
+    if (!rc) rc = finish_xs(ctx, H, n_hash_bins);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->mat_bufs.release();
+    ctx->have_mat = false;
+    ctx->have_geom = false;
+    rc = upload_xs(ctx, H, n_hash_bins, ctx->mat_bufs, ctx->xs);
+    if (rc) {
+        ctx->mat_bufs.release();
+        return rc;
+    }
+    ctx->n_keys = (uint32_t)((uint64_t)n_mat * (uint64_t)n_hash_bins);
+    ctx->xs_sig = fnv(fnv_vec(fnv_vec(fnv_vec(1469598103934665603ull, H.glen), H.mnucid), H.awr), &n_hash_bins,
+                      sizeof(n_hash_bins));
     ctx->n_nuc = n_nuc;
     ctx->n_mat = n_mat;
     ctx->mat_len.assign(mat_len, mat_len + n_mat);
@@ -361,13 +447,13 @@ int mc_reset_tallies(mc_ctx *ctx)
     return reset_tallies(ctx);
 }
 
-int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
+// Validate a geometry description whose material ids lie in [0, n_mat), and
+// fill g (material ids shifted by mat_base; arrays uploaded into B).
+static int build_geometry(mc_ctx *ctx, const mc_geometry_desc *d, int32_t n_mat, int32_t mat_base, Buffers &B,
+                          GeomDev &g, const std::string &who)
 {
-    if (!ctx || !d) return MC_EINVAL;
-    if (!ctx->have_mat) return fail(ctx, MC_ESTATE, "mc_init_geometry: materials first");
-    HIPCHK(hipSetDevice(ctx->device));
-    auto bad = [&](const std::string &m) { return fail(ctx, MC_EINVAL, "mc_init_geometry: " + m); };
-    auto mat_ok = [&](int32_t m) { return m >= 0 && m < ctx->n_mat; };
+    auto bad = [&](const std::string &m) { return fail(ctx, MC_EINVAL, who + m); };
+    auto mat_ok = [&](int32_t m) { return m >= 0 && m < n_mat; };
     for (int f = 0; f < 6; ++f)
         if (d->bc[f] != MC_BC_REFLECT && d->bc[f] != MC_BC_VACUUM) return bad("unknown boundary condition");
     int32_t n_bins = 0;
@@ -418,8 +504,7 @@ int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
     default:
         return bad("unknown tally kind");
     }
-    if (d->tally_kind != MC_TALLY_MESH && n_bins > MAX_LDS_BINS)
-        return bad("more than 1024 bins needs a mesh tally");
+    if (d->tally_kind != MC_TALLY_MESH && n_bins > MAX_LDS_BINS) return bad("more than 1024 bins needs a mesh tally");
     if (d->source_kind != MC_SRC_POINT && d->source_kind != MC_SRC_BOX && d->source_kind != MC_SRC_BEAM)
         return bad("unknown source kind");
     if (!(d->source_energy > 0.0) || !(d->energy_cutoff >= 0.0)) return bad("energies must be > 0");
@@ -428,20 +513,16 @@ int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
                           d->source_dir[2] * d->source_dir[2];
         if (std::fabs(n2 - 1.0) > 1e-12) return bad("beam direction must be a unit vector");
     }
-
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->geom_bufs.release();
-    ctx->have_geom = false;
-    GeomDev g{};
+    g = GeomDev{};
     g.kind = d->kind;
-    g.inf_mat = d->material;
+    g.inf_mat = d->material + mat_base;
     g.nx = d->nx;
     g.ny = d->ny;
     g.pitch = d->pitch;
     g.radius = d->radius;
     g.z0 = d->z0;
     g.z1 = d->z1;
-    g.mod_mat = d->moderator_material;
+    g.mod_mat = d->moderator_material + mat_base;
     for (int f = 0; f < 6; ++f) g.bc[f] = d->bc[f];
     g.n_layers = d->n_layers;
     g.src_kind = d->source_kind;
@@ -460,27 +541,52 @@ int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
         g.mesh_hi[k] = d->mesh_box[2 * k + 1];
     }
     g.e_cut = d->energy_cutoff;
-    int rc = MC_OK;
-    int32_t *pm;
+    int32_t *pm, *lm;
     double *xe, *ee;
-    int32_t *lm;
     const int32_t zero_i = 0;
     const double zero_d[2] = {0.0, 0.0};
-    if (d->kind == MC_GEOM_LATTICE) rc = upload(ctx, ctx->geom_bufs, &pm, d->pin_material, (size_t)d->nx * d->ny);
-    else rc = upload(ctx, ctx->geom_bufs, &pm, &zero_i, 1);
+    int rc = MC_OK;
+    if (d->kind == MC_GEOM_LATTICE) {
+        std::vector<int32_t> pins((size_t)d->nx * d->ny);
+        for (size_t c = 0; c < pins.size(); ++c) pins[c] = d->pin_material[c] < 0 ? -1 : d->pin_material[c] + mat_base;
+        rc = upload(ctx, B, &pm, pins.data(), pins.size());
+    } else {
+        rc = upload(ctx, B, &pm, &zero_i, 1);
+    }
     if (!rc) {
         if (d->kind == MC_GEOM_SLAB) {
-            rc = upload(ctx, ctx->geom_bufs, &xe, d->x_edges, (size_t)d->n_layers + 1);
-            if (!rc) rc = upload(ctx, ctx->geom_bufs, &lm, d->layer_material, (size_t)d->n_layers);
+            std::vector<int32_t> lay(d->layer_material, d->layer_material + d->n_layers);
+            for (int32_t &m : lay) m += mat_base;
+            rc = upload(ctx, B, &xe, d->x_edges, (size_t)d->n_layers + 1);
+            if (!rc) rc = upload(ctx, B, &lm, lay.data(), lay.size());
         } else {
-            rc = upload(ctx, ctx->geom_bufs, &xe, zero_d, 2);
-            if (!rc) rc = upload(ctx, ctx->geom_bufs, &lm, &zero_i, 1);
+            rc = upload(ctx, B, &xe, zero_d, 2);
+            if (!rc) rc = upload(ctx, B, &lm, &zero_i, 1);
         }
     }
     if (!rc) {
-        if (d->tally_kind == MC_TALLY_ENERGY) rc = upload(ctx, ctx->geom_bufs, &ee, d->energy_edges, (size_t)n_bins + 1);
-        else rc = upload(ctx, ctx->geom_bufs, &ee, zero_d, 2);
+        if (d->tally_kind == MC_TALLY_ENERGY) rc = upload(ctx, B, &ee, d->energy_edges, (size_t)n_bins + 1);
+        else rc = upload(ctx, B, &ee, zero_d, 2);
     }
+    if (rc) return rc;
+    g.pin_mat = pm;
+    g.x_edges = xe;
+    g.layer_mat = lm;
+    g.e_edges = ee;
+    return MC_OK;
+}
+
+int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
+{
+    if (!ctx || !d) return MC_EINVAL;
+    if (!ctx->have_mat) return fail(ctx, MC_ESTATE, "mc_init_geometry: materials first");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->geom_bufs.release();
+    ctx->have_geom = false;
+    GeomDev g{};
+    int rc = build_geometry(ctx, d, ctx->n_mat, 0, ctx->geom_bufs, g, "mc_init_geometry: ");
+    const int32_t n_bins = rc ? 0 : g.n_bins;
     for (int t = 0; t < 3 && !rc; ++t) {
         const size_t n = (t == 2) ? (size_t)N_GLOBAL : (size_t)n_bins;
         rc = dalloc(ctx, ctx->geom_bufs, &ctx->S1[t], n);
@@ -490,12 +596,9 @@ int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *d)
         ctx->geom_bufs.release();
         return rc;
     }
-    g.pin_mat = pm;
-    g.x_edges = xe;
-    g.layer_mat = lm;
-    g.e_edges = ee;
     ctx->geom = g;
     ctx->n_bins = n_bins;
+    ctx->geom_sig = geom_signature(ctx->xs_sig, g);
     ctx->have_geom = true;
     return reset_tallies(ctx);
 }
@@ -606,10 +709,12 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     HIPCHK(hipSetDevice(ctx->device));
     mc_run_opts opts{};
     if (opts_in) opts = *opts_in;
-    uint64_t cap64 = opts.in_flight ? opts.in_flight : kDefaultInFlight;
+    uint64_t cap64 = opts.in_flight ? opts.in_flight
+                                    : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight : kDefaultInFlight);
     cap64 = std::min(cap64, n);
     if (cap64 > (1ull << 30)) return fail(ctx, MC_EINVAL, "in_flight above 2^30");
-    const uint64_t sort_min = opts.sort_min ? opts.sort_min : kDefaultSortMin;
+    const uint64_t sort_min = opts.sort_min ? opts.sort_min
+                                            : (ctx->tune.sort_min > 0 ? (uint64_t)ctx->tune.sort_min : kDefaultSortMin);
     const int64_t max_events = opts.max_events > 0 ? opts.max_events : kDefaultMaxEvents;
     HistLog *log = static_cast<HistLog *>(opts.history_log);
     const uint32_t cap = (uint32_t)cap64;
@@ -782,6 +887,9 @@ int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t)
     if (t->lookup_ilp != 0 && t->lookup_ilp != 1 && t->lookup_ilp != 2 && t->lookup_ilp != 4)
         return fail(ctx, MC_EINVAL, "lookup_ilp must be 0, 1, 2 or 4");
     if (t->tail_particles < -1) return fail(ctx, MC_EINVAL, "tail_particles must be >= -1");
+    if (t->sort_min < 0 || t->in_flight < 0 || t->set_grid < 0) return fail(ctx, MC_EINVAL, "negative tuning value");
+    if (t->set_tile_histories < 0 || t->set_tile_histories % WG != 0)
+        return fail(ctx, MC_EINVAL, "set_tile_histories must be a multiple of 256");
     ctx->tune = *t;
     return MC_OK;
 }
@@ -792,6 +900,10 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t)
     *t = ctx->tune;
     t->lookup_ilp = lookup_ilp(ctx);
     t->tail_particles = (int32_t)tail_particles(ctx);
+    if (!t->sort_min) t->sort_min = (int32_t)kDefaultSortMin;
+    if (!t->in_flight) t->in_flight = (int32_t)kDefaultInFlight;
+    if (!t->set_tile_histories) t->set_tile_histories = WG;
+    if (!t->set_grid) t->set_grid = 2 * ctx->n_cu;
     return MC_OK;
 }
 
@@ -890,6 +1002,408 @@ int mc_sort_queue(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, ui
     if (rc) return rc;
     HIPCHK(launch_sort(ctx->xs, nullptr, nullptr, (uint32_t)n, E, mat, ctx->s_sort, ctx->n_keys, perm,
                        keys_sorted ? keys_sorted : ctx->s_keys, ctx->stream));
+    return MC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// problem set
+// ---------------------------------------------------------------------------
+static void drop_graph(mc_ctx *ctx)
+{
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+}
+
+// Tiles of T histories, problems in cost order, and the rows they write.
+static int build_set_tiles(mc_ctx *ctx, uint32_t T)
+{
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);
+    ctx->set_tile_bufs.release();
+    std::vector<SetTile> tiles;
+    std::vector<SetProblem> probs = ctx->set_probs;
+    uint64_t row = 0;
+    for (int32_t p : ctx->set_order) {
+        SetProblem &P = probs[p];
+        P.first_tile = (uint32_t)tiles.size();
+        for (uint64_t h = 0; h < P.histories; h += T) {
+            SetTile t;
+            t.problem = p;
+            t.first = (uint32_t)h;
+            t.count = (uint32_t)std::min<uint64_t>(T, P.histories - h);
+            t.row = row;
+            row += (uint64_t)P.g.n_bins;
+            tiles.push_back(t);
+        }
+        P.n_tiles = (uint32_t)tiles.size() - P.first_tile;
+    }
+    if (tiles.size() >= (1ull << 31)) return fail(ctx, MC_EINVAL, "problem set: too many tiles");
+    Buffers &B = ctx->set_tile_bufs;
+    SetProblem *d_probs;
+    SetTile *d_tiles;
+    int rc = upload(ctx, B, &d_probs, probs.data(), probs.size());
+    if (!rc) rc = upload(ctx, B, &d_tiles, tiles.data(), tiles.size());
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.tl, (size_t)row);
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.coll, (size_t)row);
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.glob, tiles.size() * N_GLOBAL);
+    if (rc) {
+        B.release();
+        ctx->set_tile_hist = 0;
+        return rc;
+    }
+    ctx->set.problems = d_probs;
+    ctx->set.tiles = d_tiles;
+    ctx->set.n_tiles = (uint32_t)tiles.size();
+    ctx->set.n_rows_doubles = (size_t)row;
+    ctx->set_probs = probs;
+    ctx->set_tile_hist = T;
+    return MC_OK;
+}
+
+int mc_set_problem_set(mc_ctx *ctx, int32_t n_problems, const mc_problem_desc *pr, int32_t n_hash_bins)
+{
+    if (!ctx) return MC_EINVAL;
+    if (n_problems < 1 || !pr || n_hash_bins < 1) return fail(ctx, MC_EINVAL, "mc_set_problem_set: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    HostXs H;
+    std::vector<int32_t> mat_base(n_problems);
+    for (int32_t p = 0; p < n_problems; ++p) {
+        const std::string who = "problem " + std::to_string(p) + ": ";
+        if (!pr[p].geometry) return fail(ctx, MC_EINVAL, who + "no geometry");
+        if (pr[p].histories < 1 || pr[p].histories >= (1ull << 31))
+            return fail(ctx, MC_EINVAL, who + "histories must be in [1, 2^31)");
+        mat_base[p] = (int32_t)H.mat_len.size();
+        const NuclideInput in{pr[p].n_nuc, pr[p].grid_len, pr[p].E, pr[p].sig_c, pr[p].sig_s, pr[p].awr,
+                              pr[p].n_mat, pr[p].mat_len, pr[p].mat_nuc, pr[p].mat_dens};
+        int rc = append_xs(ctx, H, in, who);
+        if (rc) return rc;
+    }
+    int rc = finish_xs(ctx, H, n_hash_bins);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);
+    ctx->set_tile_bufs.release();
+    ctx->set_bufs.release();
+    ctx->have_set = false;
+    ctx->set_tile_hist = 0;
+    Buffers &B = ctx->set_bufs;
+    rc = upload_xs(ctx, H, n_hash_bins, B, ctx->set_xs);
+    std::vector<SetProblem> probs(n_problems);
+    std::vector<double> cost(n_problems);
+    uint64_t stat = 0, log_off = 0;
+    int32_t max_bins = 1;
+    for (int32_t p = 0; p < n_problems && !rc; ++p) {
+        const std::string who = "problem " + std::to_string(p) + ": ";
+        GeomDev g{};
+        rc = build_geometry(ctx, pr[p].geometry, pr[p].n_mat, mat_base[p], B, g, who);
+        if (rc) break;
+        if (g.tally_kind == TALLY_MESH) {
+            rc = fail(ctx, MC_EINVAL, who + "mesh tallies are not supported in a problem set");
+            break;
+        }
+        SetProblem &P = probs[p];
+        P = SetProblem{};
+        P.g = g;
+        P.seed = pr[p].seed;
+        P.histories = pr[p].histories;
+        P.pid_base = pr[p].first_pid;
+        P.log_off = log_off;
+        P.stat_off = stat;
+        log_off += pr[p].histories;
+        stat += 2ull * (uint64_t)g.n_bins + N_GLOBAL;
+        max_bins = std::max(max_bins, g.n_bins);
+        int32_t nk_max = 1;
+        for (int32_t m = 0; m < pr[p].n_mat; ++m) nk_max = std::max(nk_max, pr[p].mat_len[m]);
+        cost[p] = (double)pr[p].histories * (double)nk_max;
+    }
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.S1, stat);
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.S2, stat);
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.next_tile, 1);
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.batch, 1);
+    if (!rc) rc = dalloc(ctx, B, &ctx->set.lost, 1);
+    if (rc) {
+        B.release();
+        return rc;
+    }
+    HIPCHK(launch_fill_f64(ctx->set.S1, stat, 0.0, ctx->stream));
+    HIPCHK(launch_fill_f64(ctx->set.S2, stat, 0.0, ctx->stream));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->set.batch), 2, 0u, ctx->stream));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->set.lost), 2, 0u, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->set.n_problems = n_problems;
+    ctx->set.log = nullptr;
+    ctx->set_probs = probs;
+    ctx->set_order.resize(n_problems);
+    for (int32_t p = 0; p < n_problems; ++p) ctx->set_order[p] = p;
+    // costliest problems first, so that the queue ends on small tiles
+    std::stable_sort(ctx->set_order.begin(), ctx->set_order.end(),
+                     [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    ctx->set_max_bins = max_bins;
+    {
+        uint64_t h = fnv(fnv_vec(fnv_vec(1469598103934665603ull, H.glen), H.mnucid), &n_hash_bins, sizeof(n_hash_bins));
+        for (const SetProblem &P : probs) h = fnv(geom_signature(h, P.g), &P.histories, sizeof(P.histories));
+        ctx->set_sig = h;
+    }
+    ctx->set_batches = 0;
+    ctx->set_histories = log_off;
+    ctx->have_set = true;
+    return MC_OK;
+}
+
+int mc_reset_problem_set(mc_ctx *ctx)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_set) return fail(ctx, MC_ESTATE, "no problem set");
+    HIPCHK(hipSetDevice(ctx->device));
+    size_t stat = 0;
+    for (const SetProblem &P : ctx->set_probs) stat += 2ull * (size_t)P.g.n_bins + N_GLOBAL;
+    HIPCHK(launch_fill_f64(ctx->set.S1, stat, 0.0, ctx->stream));
+    HIPCHK(launch_fill_f64(ctx->set.S2, stat, 0.0, ctx->stream));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->set.batch), 2, 0u, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->set_batches = 0;
+    return MC_OK;
+}
+
+int mc_run_problem_set(mc_ctx *ctx, const mc_set_opts *opts_in)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_set) return fail(ctx, MC_ESTATE, "mc_run_problem_set: no problem set");
+    HIPCHK(hipSetDevice(ctx->device));
+    mc_set_opts opts{};
+    if (opts_in) opts = *opts_in;
+    const uint32_t T = ctx->tune.set_tile_histories > 0 ? (uint32_t)ctx->tune.set_tile_histories : (uint32_t)WG;
+    if (T != ctx->set_tile_hist) {
+        int rc = build_set_tiles(ctx, T);
+        if (rc) return rc;
+    }
+    const uint32_t grid = ctx->tune.set_grid > 0 ? (uint32_t)ctx->tune.set_grid : (uint32_t)(2 * ctx->n_cu);
+    const int64_t max_events = opts.max_events > 0 ? opts.max_events : kDefaultMaxEvents;
+    HistLog *log = static_cast<HistLog *>(opts.history_log);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->set.lost), 2, 0u, st));
+    HIPCHK(hipEventRecord(ctx->ev_batch0, st));
+    if (opts.use_graph && !log) {
+        if (!ctx->gexec || ctx->graph_grid != grid || ctx->graph_tile != T || ctx->graph_max_events != max_events) {
+            drop_graph(ctx);
+            if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t le = launch_problem_set(ctx->set, ctx->set_xs, max_events, grid, ctx->set_max_bins,
+                                                     ctx->cap_stream);
+            hipGraph_t gr = nullptr;
+            const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &gr);
+            if (le != hipSuccess || ce != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return fail(ctx, MC_EHIP, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+            }
+            ctx->graph = gr;
+            HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+            ctx->graph_grid = grid;
+            ctx->graph_tile = T;
+            ctx->graph_max_events = max_events;
+        }
+        HIPCHK(hipGraphLaunch(ctx->gexec, st));
+    } else {
+        SetDev s = ctx->set;
+        s.log = log;
+        HIPCHK(launch_problem_set(s, ctx->set_xs, max_events, grid, ctx->set_max_bins, st));
+    }
+    HIPCHK(hipEventRecord(ctx->ev_batch1, st));
+    unsigned long long lost = 0;
+    HIPCHK(hipMemcpyAsync(&lost, ctx->set.lost, sizeof(lost), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_batch0, ctx->ev_batch1));
+    mc_stats s{};
+    s.batch_ms = ms;
+    s.lost = lost;
+    ctx->stats = s;
+    ctx->set_batches += 1;
+    if (lost > 0) return fail(ctx, MC_ELOST, std::to_string(lost) + " particles lost (event cap reached)");
+    return MC_OK;
+}
+
+int mc_get_problem_tallies(mc_ctx *ctx, int32_t problem, int32_t tally_id, double *mean, double *stderr_,
+                           size_t n_bins, mc_tally_meta *meta)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_set) return fail(ctx, MC_ESTATE, "no problem set");
+    if (problem < 0 || problem >= ctx->set.n_problems) return fail(ctx, MC_EINVAL, "problem out of range");
+    if (tally_id < 0 || tally_id > 2) return fail(ctx, MC_EINVAL, "unknown tally id");
+    const SetProblem &P = ctx->set_probs[problem];
+    const size_t nbp = (size_t)P.g.n_bins;
+    const size_t nb = tally_id == MC_T_GLOBAL ? (size_t)N_GLOBAL : nbp;
+    if (n_bins != nb) return fail(ctx, MC_EINVAL, "n_bins does not match the tally (" + std::to_string(nb) + ")");
+    const size_t off = P.stat_off + (size_t)tally_id * nbp;
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<double> s1(nb), s2(nb);
+    HIPCHK(hipMemcpyAsync(s1.data(), ctx->set.S1 + off, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(s2.data(), ctx->set.S2 + off, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double B = (double)ctx->set_batches;
+    for (size_t k = 0; k < nb; ++k) {
+        const double m = B > 0 ? s1[k] / B : 0.0;
+        if (mean) mean[k] = m;
+        if (stderr_) stderr_[k] = (B > 1) ? std::sqrt(std::max(s2[k] / B - m * m, 0.0) / (B - 1.0)) : 0.0;
+    }
+    if (meta) {
+        meta->n_batches = ctx->set_batches;
+        meta->n_bins = nb;
+        meta->histories = ctx->set_batches * P.histories;
+    }
+    return MC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static std::string sig_text(const mc_ctx *ctx, const char *what, uint64_t sig)
+{
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%s-%s-%016llx", what, ctx->arch.c_str(), (unsigned long long)sig);
+    std::string s(buf);
+    for (char &c : s)
+        if (c == ' ' || c == ':') c = '_';
+    return s;
+}
+
+static bool cache_lookup(const char *path, const std::string &sig, mc_tuning &t)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char s[200];
+        mc_tuning r{};
+        double ms = 0.0;
+        if (std::sscanf(line, "%199s %d %d %d %d %d %d %lf", s, &r.lookup_ilp, &r.tail_particles, &r.sort_min,
+                        &r.in_flight, &r.set_tile_histories, &r.set_grid, &ms) == 8 &&
+            sig == s) {
+            t = r;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &sig, const mc_tuning &t, double ms)
+{
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %d %.4f\n", sig.c_str(), t.lookup_ilp, t.tail_particles, t.sort_min,
+                 t.in_flight, t.set_tile_histories, t.set_grid, ms);
+    std::fclose(f);
+}
+
+int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const char *cache_path, mc_tuning *best)
+{
+    if (!ctx || n == 0) return MC_EINVAL;
+    if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "mc_autotune: materials and geometry first");
+    const std::string sig = sig_text(ctx, "single", fnv(ctx->geom_sig, &n, sizeof(n)));
+    mc_tuning t = ctx->tune;
+    if (cache_lookup(cache_path, sig, t)) {
+        ctx->tune = t;
+        if (best) *best = t;
+        return MC_OK;
+    }
+    mc_tuning cur{};
+    int rc = mc_get_tuning(ctx, &cur);
+    if (rc) return rc;
+    const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
+    cur.in_flight = n_cap;
+    auto trial = [&](const mc_tuning &c, double &ms) -> int {
+        ctx->tune = c;
+        const int r = mc_run_batch(ctx, seed, first_pid, n, nullptr);
+        ms = ctx->stats.batch_ms;
+        return r;
+    };
+    double best_ms = 0.0;
+    rc = trial(cur, best_ms);  // warm-up (code and bank), then the baseline
+    if (!rc) rc = trial(cur, best_ms);
+    const int32_t ilps[] = {1, 2, 4};
+    const int32_t tails[] = {8192, 32768, 131072};
+    const int32_t sorts[] = {4096, 16384, 65536};
+    const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), n_cap};
+    for (int axis = 0; axis < 4 && !rc; ++axis) {
+        for (int k = 0; k < 3 && !rc; ++k) {
+            mc_tuning c = cur;
+            if (axis == 0) c.lookup_ilp = ilps[k];
+            if (axis == 1) c.tail_particles = tails[k];
+            if (axis == 2) c.sort_min = sorts[k];
+            if (axis == 3) c.in_flight = std::min(flights[k], n_cap);
+            if (std::memcmp(&c, &cur, sizeof c) == 0) continue;
+            double ms = 0.0;
+            rc = trial(c, ms);
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                cur = c;
+            }
+        }
+    }
+    ctx->tune = cur;
+    if (rc) return rc;
+    rc = reset_tallies(ctx);
+    if (rc) return rc;
+    cache_store(cache_path, sig, cur, best_ms);
+    if (best) *best = cur;
+    return MC_OK;
+}
+
+int mc_autotune_problem_set(mc_ctx *ctx, const char *cache_path, mc_tuning *best)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_set) return fail(ctx, MC_ESTATE, "mc_autotune_problem_set: no problem set");
+    const std::string sig = sig_text(ctx, "set", ctx->set_sig);
+    mc_tuning t = ctx->tune;
+    if (cache_lookup(cache_path, sig, t)) {
+        ctx->tune = t;
+        if (best) *best = t;
+        return MC_OK;
+    }
+    mc_tuning cur{};
+    int rc = mc_get_tuning(ctx, &cur);
+    if (rc) return rc;
+    auto trial = [&](const mc_tuning &c, double &ms) -> int {
+        ctx->tune = c;
+        const int r = mc_run_problem_set(ctx, nullptr);
+        ms = ctx->stats.batch_ms;
+        return r;
+    };
+    double best_ms = 0.0;
+    rc = trial(cur, best_ms);  // warm-up
+    if (!rc) rc = trial(cur, best_ms);
+    const int32_t tiles[] = {256, 512, 1024, 2048};
+    const int32_t per_cu[] = {1, 2, 4, 8};
+    mc_tuning pick = cur;
+    for (int a = 0; a < 4 && !rc; ++a) {
+        for (int b = 0; b < 4 && !rc; ++b) {
+            mc_tuning c = cur;
+            c.set_tile_histories = tiles[a];
+            c.set_grid = per_cu[b] * ctx->n_cu;
+            double ms = 0.0;
+            rc = trial(c, ms);
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                pick = c;
+            }
+        }
+    }
+    cur = pick;
+    ctx->tune = cur;
+    if (rc) return rc;
+    rc = mc_reset_problem_set(ctx);
+    if (rc) return rc;
+    cache_store(cache_path, sig, cur, best_ms);
+    if (best) *best = cur;
     return MC_OK;
 }
 

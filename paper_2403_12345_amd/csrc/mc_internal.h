@@ -58,6 +58,36 @@ hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, c
 hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
                        uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
                        unsigned long long *lost, hipStream_t st);
+// Many independent problems (batching layer).
+struct SetProblem {
+    GeomDev g;          // material ids index the shared tables
+    uint64_t seed;      // Philox key of the problem
+    uint64_t histories; // per batch
+    uint64_t pid_base;  // batch b runs pids pid_base + b * histories + [0, histories)
+    uint64_t log_off;   // first record of the problem in the history log
+    uint32_t first_tile, n_tiles;
+    uint64_t stat_off;  // first of the problem's 2 n_bins + N_GLOBAL batch sums
+};
+struct SetTile {
+    int32_t problem;
+    uint32_t first, count;  // histories [first, first + count) of the problem's batch
+    uint64_t row;           // offset (doubles) of the tile's tl / coll rows
+};
+struct SetDev {
+    const SetProblem *problems;
+    const SetTile *tiles;
+    int32_t n_problems;
+    uint32_t n_tiles;
+    double *tl, *coll, *glob;     // tile rows
+    size_t n_rows_doubles;        // doubles in tl (and coll)
+    double *S1, *S2;              // per-problem batch sums
+    uint32_t *next_tile;          // work-queue counter
+    uint64_t *batch;              // batches run so far
+    HistLog *log;                 // nullable
+    unsigned long long *lost;
+};
+hipError_t launch_problem_set(const SetDev &set, const XsDev &xs, int64_t max_events, uint32_t grid,
+                              int32_t max_bins, hipStream_t st);
 hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols, const double *direct,
                               double *partial, double inv_n, double *S1, double *S2, hipStream_t st);
 

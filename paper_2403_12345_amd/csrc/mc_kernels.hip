@@ -653,37 +653,23 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, 
 }
 
 // ---------------------------------------------------------------------------
-// tail: the last particles of a batch, each run to its end by one lane
+// tile transport: each lane runs its particle to the end, the workgroup steps
+// through lookup, flight and collision-or-crossing together so that the
+// tallies are still added per step, in a fixed order, into the tile's rows
 // ---------------------------------------------------------------------------
-// When no history remains to start and few particles are in flight, one
-// launch finishes them: every lane keeps its particle in registers and the
-// workgroup steps through lookup, flight and collision-or-crossing together,
-// so the tallies are still added per step in a fixed order (workgroup row =
-// blockIdx.x) and the histories are the ones the event kernels would give.
-__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, const Counters *ctr,
-                                             uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
-                                             unsigned long long *lost)
+struct TileRows {
+    double *tl, *coll, *glob;  // this tile's rows (tl/coll: n_bins doubles, glob: N_GLOBAL)
+    double *mesh_tl, *mesh_coll;
+    int32_t n_bins;
+    bool enabled;              // binned flux tallies on
+};
+
+__device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev &xs, const GeomDev &g,
+                                const TileRows &r, uint64_t seed, int64_t max_events, HistLog *log,
+                                uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl)
 {
-    extern __shared__ double slab[];
-    __shared__ double gl[N_GLOBAL * WAVES];
-    const uint32_t n = ctr->nA;
-    const uint32_t i0 = blockIdx.x * WG;
-    if (i0 >= n) return;
-    const uint32_t i = i0 + threadIdx.x;
-    const bool binned = tal.enabled && g.tally_kind != TALLY_MESH;
+    const bool binned = r.enabled && g.tally_kind != TALLY_MESH;
     const bool log_on = log != nullptr;
-    double *trow = tal.tl + (size_t)blockIdx.x * tal.n_bins;
-    double *crow = tal.coll + (size_t)blockIdx.x * tal.n_bins;
-    double *grow = tal.glob + (size_t)blockIdx.x * N_GLOBAL;
-    Particle p{};
-    uint32_t s = 0;
-    bool alive = false, need = false;
-    if (i < n) {
-        s = b.A[i];
-        p = load_particle(b, s);
-        alive = true;
-        need = (b.flags[s] & F_LOOKUP) != 0;
-    }
     while (__syncthreads_or(alive)) {
         StepScore sc;
         clear_score(sc);
@@ -696,26 +682,163 @@ __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, Tal
             fate = FATE_LOST;
             atomicAdd(lost, 1ull);
         } else if (alive) {
-            do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on, sc);
+            do_advance(p, g, seed, r.enabled, r.mesh_tl, log_on, sc);
         }
-        if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, tal.n_bins, trow);
+        if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
-                fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc);
+                fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc);
                 need = fate == 0;
             } else {
                 fate = do_cross(p, g, sc, need);
             }
         }
-        if (binned) wg_bin_add(sc.c_bin, sc.c_val, slab, tal.n_bins, crow);
-        wg_glob_add(sc.g, gl, grow);
+        if (binned) wg_bin_add(sc.c_bin, sc.c_val, slab, r.n_bins, r.coll);
+        wg_glob_add(sc.g, gl, r.glob);
         if (alive && fate != 0) {
             alive = false;
-            b.flags[s] = 0;
-            if (log) write_log(log, first_pid, p, fate);
+            if (log) write_log(log, log_first_pid, p, fate);
         }
     }
 }
+
+// Tail: when no history remains to start and few particles are in flight,
+// one launch finishes them (workgroup row = blockIdx.x); the histories are
+// the ones the event kernels would give.
+__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, const Counters *ctr,
+                                             uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                                             unsigned long long *lost)
+{
+    extern __shared__ double slab[];
+    __shared__ double gl[N_GLOBAL * WAVES];
+    const uint32_t n = ctr->nA;
+    const uint32_t i0 = blockIdx.x * WG;
+    if (i0 >= n) return;
+    const uint32_t i = i0 + threadIdx.x;
+    Particle p{};
+    uint32_t s = 0;
+    bool alive = false, need = false;
+    if (i < n) {
+        s = b.A[i];
+        p = load_particle(b, s);
+        alive = true;
+        need = (b.flags[s] & F_LOOKUP) != 0;
+    }
+    TileRows r;
+    r.tl = tal.tl + (size_t)blockIdx.x * tal.n_bins;
+    r.coll = tal.coll + (size_t)blockIdx.x * tal.n_bins;
+    r.glob = tal.glob + (size_t)blockIdx.x * N_GLOBAL;
+    r.mesh_tl = tal.mesh_tl;
+    r.mesh_coll = tal.mesh_coll;
+    r.n_bins = tal.n_bins;
+    r.enabled = tal.enabled != 0;
+    run_tile(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl);
+    if (i < n) b.flags[s] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// problem set: many independent problems in one persistent launch
+// ---------------------------------------------------------------------------
+// Workgroups pull tiles (problem, range of its histories) from a queue until
+// none is left.  Each tile writes only its own tally rows, so the per-problem
+// sums, taken over the problem's tiles in tile order, do not depend on which
+// workgroup ran which tile.
+__device__ __forceinline__ void source_particle(Particle &p, const GeomDev &g, uint64_t pid, uint64_t seed)
+{
+    Rng rng(seed, pid, 0u, 0u);
+    double x = g.src_pos[0], y = g.src_pos[1], z = g.src_pos[2];
+    double u = g.src_dir[0], v = g.src_dir[1], w = g.src_dir[2];
+    if (g.src_kind != SRC_BEAM) {
+        if (g.src_kind == SRC_BOX) {
+            x = g.src_box[0] + (g.src_box[1] - g.src_box[0]) * rng.next();
+            y = g.src_box[2] + (g.src_box[3] - g.src_box[2]) * rng.next();
+            z = g.src_box[4] + (g.src_box[5] - g.src_box[4]) * rng.next();
+        }
+        const double mu = 2.0 * rng.next() - 1.0;
+        const double phi = 2.0 * M_PI * rng.next();
+        const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+        double sp, cp;
+        sincos(phi, &sp, &cp);
+        u = st * cp; v = st * sp; w = mu;
+    }
+    int32_t cell;
+    bool inside;
+    locate_point(g, x, y, cell, inside);
+    p.x = x; p.y = y; p.z = z;
+    p.u = u; p.v = v; p.w = w;
+    p.E = g.src_E;
+    p.wt = 1.0;
+    p.Sa = 0.0; p.Ss = 0.0; p.track = 0.0;
+    p.pid = pid;
+    p.ndraw = rng.n;
+    p.lineage = 0u;
+    p.cell = cell;
+    p.inside = inside;
+    p.mat = region_material(g, cell, inside);
+    p.ncoll = 0;
+    p.ncross = 0;
+    p.ev = 0;
+}
+
+__global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_t max_events)
+{
+    extern __shared__ double slab[];
+    __shared__ double gl[N_GLOBAL * WAVES];
+    __shared__ uint32_t s_tile;
+    const uint64_t batch = *set.batch;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(set.next_tile, 1u);
+        __syncthreads();
+        const uint32_t t = s_tile;
+        __syncthreads();
+        if (t >= set.n_tiles) break;
+        const SetTile tile = set.tiles[t];
+        const SetProblem &P = set.problems[tile.problem];
+        const uint64_t first_pid = P.pid_base + batch * P.histories;
+        for (uint32_t r0 = 0; r0 < tile.count; r0 += WG) {
+            Particle p{};
+            const bool alive = r0 + threadIdx.x < tile.count;
+            if (alive) source_particle(p, P.g, first_pid + tile.first + r0 + threadIdx.x, P.seed);
+            TileRows r;
+            r.tl = set.tl + (size_t)tile.row;
+            r.coll = set.coll + (size_t)tile.row;
+            r.glob = set.glob + (size_t)t * N_GLOBAL;
+            r.mesh_tl = nullptr;
+            r.mesh_coll = nullptr;
+            r.n_bins = P.g.n_bins;
+            r.enabled = true;
+            HistLog *log = set.log ? set.log + P.log_off : nullptr;
+            run_tile(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid, set.lost, slab, gl);
+        }
+    }
+}
+
+// Per-problem batch statistics: T = (sum of the problem's tile rows in tile
+// order) / histories; S1 += T, S2 += T^2; then the batch counter advances.
+// One workgroup per problem.
+__global__ void __launch_bounds__(WG) k_problem_set_stats(SetDev set)
+{
+    const SetProblem &P = set.problems[blockIdx.x];
+    const int32_t nb = P.g.n_bins;
+    const double inv_n = 1.0 / (double)P.histories;
+    for (int32_t k = threadIdx.x; k < 2 * nb + N_GLOBAL; k += WG) {
+        double s = 0.0;
+        for (uint32_t t = P.first_tile; t < P.first_tile + P.n_tiles; ++t) {
+            const SetTile &tile = set.tiles[t];
+            double v;
+            if (k < nb) v = set.tl[tile.row + k];
+            else if (k < 2 * nb) v = set.coll[tile.row + (k - nb)];
+            else v = set.glob[(size_t)t * N_GLOBAL + (k - 2 * nb)];
+            s = s + v;
+        }
+        const double T = s * inv_n;
+        double *S1 = set.S1 + P.stat_off, *S2 = set.S2 + P.stat_off;
+        S1[k] = S1[k] + T;
+        S2[k] = S2[k] + T * T;
+    }
+}
+
+__global__ void k_problem_set_next(SetDev set) { *set.batch = *set.batch + 1; }
 
 // ---------------------------------------------------------------------------
 // batch end: fixed-order reduction of the per-workgroup rows, batch sums
@@ -928,6 +1051,26 @@ hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, cons
     const size_t lds = slab_bytes(g, t);
     hipLaunchKernelGGL(k_tail, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed, max_events,
                        log, first_pid, lost);
+    return hipGetLastError();
+}
+
+hipError_t launch_problem_set(const SetDev &set, const XsDev &xs, int64_t max_events, uint32_t grid,
+                              int32_t max_bins, hipStream_t st)
+{
+    // the queue counter and the tile rows start at zero (fill kernels: the
+    // sequence may be captured into a graph)
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(WG), 0, st, set.next_tile, (size_t)1, 0u);
+    unsigned g1 = blocks_for(set.n_rows_doubles, WG);
+    if (g1 > 4096) g1 = 4096;
+    hipLaunchKernelGGL(k_fill_f64, dim3(g1), dim3(WG), 0, st, set.tl, set.n_rows_doubles, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(g1), dim3(WG), 0, st, set.coll, set.n_rows_doubles, 0.0);
+    unsigned g2 = blocks_for((size_t)set.n_tiles * N_GLOBAL, WG);
+    if (g2 > 4096) g2 = 4096;
+    hipLaunchKernelGGL(k_fill_f64, dim3(g2), dim3(WG), 0, st, set.glob, (size_t)set.n_tiles * N_GLOBAL, 0.0);
+    const size_t lds = (size_t)WAVES * (size_t)max_bins * sizeof(double);
+    hipLaunchKernelGGL(k_problem_set, dim3(grid), dim3(WG), lds, st, set, xs, max_events);
+    hipLaunchKernelGGL(k_problem_set_stats, dim3(set.n_problems), dim3(WG), 0, st, set);
+    hipLaunchKernelGGL(k_problem_set_next, dim3(1), dim3(1), 0, st, set);
     return hipGetLastError();
 }
 

@@ -66,10 +66,27 @@ class mc_stats(C.Structure):
 
 
 class mc_tuning(C.Structure):
-    _fields_ = [("lookup_ilp", C.c_int32), ("tail_particles", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("lookup_ilp", C.c_int32), ("tail_particles", C.c_int32), ("sort_min", C.c_int32),
+                ("in_flight", C.c_int32), ("set_tile_histories", C.c_int32), ("set_grid", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+    KEYS = ("lookup_ilp", "tail_particles", "sort_min", "in_flight", "set_tile_histories", "set_grid")
 
     def as_dict(self):
-        return {"lookup_ilp": self.lookup_ilp, "tail_particles": self.tail_particles}
+        return {k: getattr(self, k) for k in self.KEYS}
+
+
+class mc_problem_desc(C.Structure):
+    _fields_ = [("n_nuc", C.c_int32), ("grid_len", C.POINTER(C.c_int32)),
+                ("E", C.POINTER(C.POINTER(C.c_double))), ("sig_c", C.POINTER(C.POINTER(C.c_double))),
+                ("sig_s", C.POINTER(C.POINTER(C.c_double))), ("awr", C.POINTER(C.c_double)),
+                ("n_mat", C.c_int32), ("mat_len", C.POINTER(C.c_int32)), ("mat_nuc", C.POINTER(C.c_int32)),
+                ("mat_dens", C.POINTER(C.c_double)), ("geometry", C.POINTER(mc_geometry_desc)),
+                ("histories", C.c_uint64), ("seed", C.c_uint64), ("first_pid", C.c_uint64)]
+
+
+class mc_set_opts(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("pad", C.c_int32), ("max_events", C.c_int64),
+                ("history_log", C.c_void_p)]
 
 
 class mc_tally_meta(C.Structure):
@@ -113,6 +130,12 @@ def load():
         "mc_set_timing": ([V, I32], C.c_int),
         "mc_set_tuning": ([V, P(mc_tuning)], C.c_int),
         "mc_get_tuning": ([V, P(mc_tuning)], C.c_int),
+        "mc_autotune": ([V, U64, U64, U64, C.c_char_p, P(mc_tuning)], C.c_int),
+        "mc_set_problem_set": ([V, I32, P(mc_problem_desc), I32], C.c_int),
+        "mc_run_problem_set": ([V, P(mc_set_opts)], C.c_int),
+        "mc_get_problem_tallies": ([V, I32, I32, P(D), P(D), SZ, P(mc_tally_meta)], C.c_int),
+        "mc_reset_problem_set": ([V], C.c_int),
+        "mc_autotune_problem_set": ([V, C.c_char_p, P(mc_tuning)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -245,11 +268,81 @@ def mc_sort_queue(ctx, E, mat, perm, keys_sorted=None):
                                      _ptr(keys_sorted)))
 
 
-def mc_set_tuning(ctx, lookup_ilp: int = 0, tail_particles: int = 0):
+def mc_set_tuning(ctx, **fields):
+    """Fields of mc_tuning by name (missing ones: 0 = library default)."""
     t = mc_tuning()
-    t.lookup_ilp = int(lookup_ilp)
-    t.tail_particles = int(tail_particles)
+    for k, v in fields.items():
+        if k not in mc_tuning.KEYS:
+            raise KeyError(k)
+        setattr(t, k, int(v))
     _check(ctx, load().mc_set_tuning(ctx, C.byref(t)))
+
+
+def mc_autotune(ctx, seed: int, first_pid: int, n: int, cache_path: str | None = None) -> dict:
+    t = mc_tuning()
+    _check(ctx, load().mc_autotune(ctx, seed, first_pid, n, cache_path.encode() if cache_path else None,
+                                   C.byref(t)))
+    return t.as_dict()
+
+
+def mc_set_problem_set(ctx, problems, n_hash_bins: int = 8192):
+    """problems: list of dicts with keys E, sig_c, sig_s, awr, mat_nuclides,
+    mat_densities (as mc_init_materials), geometry (an mc_geometry_desc),
+    histories, seed, first_pid."""
+    keep = []
+    arr = (mc_problem_desc * len(problems))()
+    PD = C.POINTER(C.c_double)
+    for i, p in enumerate(problems):
+        E = [np.ascontiguousarray(e, np.float64) for e in p["E"]]
+        sc = [np.ascontiguousarray(s, np.float64) for s in p["sig_c"]]
+        ss = [np.ascontiguousarray(s, np.float64) for s in p["sig_s"]]
+        n = len(E)
+        grid_len = np.array([e.size for e in E], np.int32)
+        pe = (PD * n)(*[_dp(x) for x in E])
+        pc = (PD * n)(*[_dp(x) for x in sc])
+        ps = (PD * n)(*[_dp(x) for x in ss])
+        awr = np.ascontiguousarray(p["awr"], np.float64)
+        mat_len = np.array([len(m) for m in p["mat_nuclides"]], np.int32)
+        mat_nuc = np.ascontiguousarray(np.concatenate([np.asarray(m, np.int32) for m in p["mat_nuclides"]]), np.int32)
+        mat_dens = np.ascontiguousarray(np.concatenate([np.asarray(d, np.float64) for d in p["mat_densities"]]))
+        keep += [E, sc, ss, grid_len, pe, pc, ps, awr, mat_len, mat_nuc, mat_dens, p["geometry"]]
+        d = arr[i]
+        d.n_nuc = n
+        d.grid_len = _ip(grid_len)
+        d.E, d.sig_c, d.sig_s = pe, pc, ps
+        d.awr = _dp(awr)
+        d.n_mat = len(mat_len)
+        d.mat_len, d.mat_nuc, d.mat_dens = _ip(mat_len), _ip(mat_nuc), _dp(mat_dens)
+        d.geometry = C.pointer(p["geometry"])
+        d.histories, d.seed, d.first_pid = int(p["histories"]), int(p["seed"]), int(p["first_pid"])
+    _check(ctx, load().mc_set_problem_set(ctx, len(problems), arr, int(n_hash_bins)))
+    del keep
+
+
+def mc_run_problem_set(ctx, use_graph: bool = False, max_events: int = 0, history_log=None):
+    o = mc_set_opts()
+    o.use_graph = 1 if use_graph else 0
+    o.max_events = int(max_events)
+    o.history_log = _ptr(history_log)
+    _check(ctx, load().mc_run_problem_set(ctx, C.byref(o)))
+
+
+def mc_get_problem_tallies(ctx, problem: int, tally_id: int, n_bins: int):
+    mean = np.zeros(n_bins)
+    se = np.zeros(n_bins)
+    meta = mc_tally_meta()
+    _check(ctx, load().mc_get_problem_tallies(ctx, problem, tally_id, _dp(mean), _dp(se), n_bins, C.byref(meta)))
+    return mean, se, meta
+
+
+def mc_reset_problem_set(ctx):
+    _check(ctx, load().mc_reset_problem_set(ctx))
+
+
+def mc_autotune_problem_set(ctx, cache_path: str | None = None) -> dict:
+    t = mc_tuning()
+    _check(ctx, load().mc_autotune_problem_set(ctx, cache_path.encode() if cache_path else None, C.byref(t)))
+    return t.as_dict()
 
 
 def mc_get_tuning(ctx) -> dict:

@@ -106,3 +106,54 @@ class Transport:
 
     def __exit__(self, *a):
         self.close()
+
+
+def problem_entry(prob, first_pid: int = 0):
+    """One problem of a problem set (dict for mc.mc_set_problem_set) plus the
+    arrays its geometry description points at."""
+    desc, keep = geometry_desc(prob)
+    return {"E": [n.E for n in prob.nuclides], "sig_c": [n.sig_c for n in prob.nuclides],
+            "sig_s": [n.sig_s for n in prob.nuclides], "awr": [n.awr for n in prob.nuclides],
+            "mat_nuclides": [m.nuclides for m in prob.materials],
+            "mat_densities": [m.densities for m in prob.materials],
+            "geometry": desc, "histories": prob.histories, "seed": prob.seed, "first_pid": first_pid,
+            "_keep": keep}
+
+
+class ProblemSet:
+    """One library context holding a problem set."""
+
+    def __init__(self, probs, device: int = 0, stream=None, n_hash_bins: int = 8192):
+        self.probs = probs
+        self.ctx = mc.mc_create(device, stream)
+        try:
+            entries = [problem_entry(p) for p in probs]
+            mc.mc_set_problem_set(self.ctx, entries, n_hash_bins)
+            del entries
+        except Exception:
+            mc.mc_destroy(self.ctx)
+            raise
+
+    def run_batch(self, use_graph=False, max_events=0, history_log=None):
+        mc.mc_run_problem_set(self.ctx, use_graph, max_events, history_log)
+
+    def tallies(self, problem, tally_id):
+        nb = mc.MC_N_GLOBAL if tally_id == mc.MC_T_GLOBAL else self.probs[problem].n_bins
+        return mc.mc_get_problem_tallies(self.ctx, problem, tally_id, nb)
+
+    def reset(self):
+        mc.mc_reset_problem_set(self.ctx)
+
+    def stats(self) -> dict:
+        return mc.mc_get_stats(self.ctx).as_dict()
+
+    def close(self):
+        if self.ctx is not None:
+            mc.mc_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
