@@ -96,6 +96,39 @@ class Tally:
         raise ValueError(self.kind)
 
 
+WW_OFF, WW_LINEAR, WW_MLP = 0, 1, 2
+
+
+@dataclass
+class WeightWindows:
+    """Weight windows from an importance map ln I(x, y, z, E): linear in the
+    features (``lin`` = c0, c1, c2 for c0 + c1 x/L + c2 (ln E - ln 1e-5)/ln(2e12))
+    or the importance network (``mlp``: its 4545 parameters, W1[4][64], b1,
+    W2[64][64], b2, w3[64], b3 in that order, row-major).  Window at a point:
+    w_L = exp(ln I_src - ln I) / kappa, w_U = ratio w_L."""
+    kind: int = WW_OFF
+    lin: tuple = (0.0, 0.0, 0.0)
+    mlp: Optional[np.ndarray] = None
+    length: float = 200.0
+    kappa: float = 3.0
+    ratio: float = 5.0
+    n_max: int = 10
+    depth: int = 24
+
+
+@dataclass
+class ImportanceGrid:
+    """x by ln E grid of the forward importance estimate (nx = 0: off)."""
+    nx: int = 0
+    ne: int = 0
+    x0: float = 0.0
+    x1: float = 200.0
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ne
+
+
 @dataclass
 class Problem:
     name: str
@@ -109,6 +142,8 @@ class Problem:
     histories: int = 10_000
     batches: int = 10
     seed: int = 1                # transport (Philox key) seed
+    ww: WeightWindows = field(default_factory=WeightWindows)
+    imp: ImportanceGrid = field(default_factory=ImportanceGrid)
     meta: dict = field(default_factory=dict)
 
     @property

@@ -24,8 +24,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # global tally slots (see oracle.c)
 G_TRACK, G_COLL_EST, G_ABSORB, G_CUTOFF, G_LEAK, G_TRACK_ABS = 0, 1, 2, 3, 4, 5
-G_NCOLL, G_NCROSS, G_LEAK_XHI, G_LEAK_XHI_UNC, N_GLOBAL = 6, 7, 8, 9, 10
-FATE_ABSORBED, FATE_CUTOFF, FATE_LEAKED, FATE_LOST = 1, 2, 3, 4
+G_NCOLL, G_NCROSS, G_LEAK_XHI, G_LEAK_XHI_UNC, G_SPLIT, G_ROULETTE, N_GLOBAL = 6, 7, 8, 9, 10, 11, 12
+FATE_ABSORBED, FATE_CUTOFF, FATE_LEAKED, FATE_LOST, FATE_ROULETTE = 1, 2, 3, 4, 5
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +57,10 @@ class _Problem(C.Structure):
         ("tally_kind", C.c_int32), ("n_ebins", C.c_int32), ("e_edges", C.POINTER(C.c_double)),
         ("mesh_dims", C.c_int32 * 3), ("mesh_box", C.c_double * 6),
         ("e_cut", C.c_double), ("max_events", C.c_int64),
+        ("ww_kind", C.c_int32), ("ww_lin", C.c_double * 3), ("ww_mlp", C.POINTER(C.c_double)),
+        ("ww_length", C.c_double), ("ww_kappa", C.c_double), ("ww_ratio", C.c_double),
+        ("ww_nmax", C.c_int32), ("ww_depth", C.c_int32),
+        ("imp_nx", C.c_int32), ("imp_ne", C.c_int32), ("imp_x0", C.c_double), ("imp_x1", C.c_double),
     ]
 
 
@@ -88,7 +92,15 @@ def lib():
         _lib.orc_elastic.argtypes = [D, D, D, P(D), P(D)]
         _lib.orc_rotate.argtypes = [P(D), D, D]
         _lib.orc_run.argtypes = [P(_Problem), C.c_uint64, C.c_uint64, C.c_uint64, P(D), P(D),
-                                 P(D), C.c_void_p, C.c_int]
+                                 P(D), C.c_void_p, C.c_void_p, C.c_int]
+        _lib.orc_bf16.argtypes = [D]
+        _lib.orc_bf16.restype = D
+        _lib.orc_mlp_forward.argtypes = [P(D), P(D)]
+        _lib.orc_mlp_forward.restype = D
+        _lib.orc_child_lineage.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+        _lib.orc_child_lineage.restype = C.c_uint32
+        _lib.orc_ln_importance_source.argtypes = [P(_Problem)]
+        _lib.orc_ln_importance_source.restype = D
         _lib.orc_run.restype = C.c_int
         _lib.orc_max_threads.restype = C.c_int
         _lib.orc_micro_xs_many.argtypes = [P(_Problem), C.c_int32, C.c_int64, P(D), P(C.c_int64), P(D), P(D)]
@@ -153,7 +165,16 @@ class OracleProblem:
         c.mesh_box = (C.c_double * 6)(*t.mesh_box)
         c.e_cut = prob.energy_cutoff
         c.max_events = max_events
+        ww = prob.ww
+        c.ww_kind = ww.kind
+        c.ww_lin = (C.c_double * 3)(*ww.lin)
+        self.ww_mlp = np.ascontiguousarray(ww.mlp if ww.mlp is not None else np.zeros(4545), np.float64)
+        c.ww_mlp = _dptr(self.ww_mlp)
+        c.ww_length, c.ww_kappa, c.ww_ratio = ww.length, ww.kappa, ww.ratio
+        c.ww_nmax, c.ww_depth = ww.n_max, ww.depth
+        c.imp_nx, c.imp_ne, c.imp_x0, c.imp_x1 = prob.imp.nx, prob.imp.ne, prob.imp.x0, prob.imp.x1
         self.c = c
+        self.n_cells = prob.imp.cells
         self.n_bins = prob.n_bins
 
     def ref(self):
@@ -222,6 +243,7 @@ class RunResult:
     coll: np.ndarray     # raw collision-estimator sums per bin
     glob: np.ndarray     # raw global sums (N_GLOBAL)
     history: np.ndarray | None = None
+    imp: np.ndarray | None = None   # [3, cells]: score credited, weight entered, credits
 
 
 def run(op: OracleProblem, seed: int, first_pid: int, n: int, history: bool = False,
@@ -231,12 +253,33 @@ def run(op: OracleProblem, seed: int, first_pid: int, n: int, history: bool = Fa
     tl = np.zeros(nb)
     coll = np.zeros(nb)
     glob = np.zeros(N_GLOBAL)
+    imp = np.zeros(3 * op.n_cells) if op.n_cells else None
     hist = np.zeros(n, HISTORY_DTYPE) if history else None
     rc = lib().orc_run(op.ref(), seed, first_pid, n, _dptr(tl), _dptr(coll), _dptr(glob),
+                       imp.ctypes.data if imp is not None else None,
                        hist.ctypes.data if history else None, threads)
     if rc != 0:
         raise MemoryError("oracle run failed")
-    return RunResult(n=n, tl=tl, coll=coll, glob=glob, history=hist)
+    return RunResult(n=n, tl=tl, coll=coll, glob=glob, history=hist,
+                     imp=imp.reshape(3, -1) if imp is not None else None)
+
+
+def bf16(x: float) -> float:
+    return float(lib().orc_bf16(float(x)))
+
+
+def mlp_forward(params: np.ndarray, f) -> float:
+    p = np.ascontiguousarray(params, np.float64)
+    ff = np.ascontiguousarray(f, np.float64)
+    return float(lib().orc_mlp_forward(_dptr(p), _dptr(ff)))
+
+
+def child_lineage(a: int, s: int, k: int) -> int:
+    return int(lib().orc_child_lineage(a, s, k))
+
+
+def ln_importance_source(op: OracleProblem) -> float:
+    return float(lib().orc_ln_importance_source(op.ref()))
 
 
 @dataclass

@@ -52,10 +52,13 @@ enum {
     G_NCROSS = 7,      /* number of surface crossings                     */
     G_LEAK_XHI = 8,    /* sum w leaked through the x+ face                */
     G_LEAK_XHI_UNC = 9,/* same, histories that never collided             */
-    N_GLOBAL = 10
+    G_SPLIT = 10,      /* copies created by weight-window splitting       */
+    G_ROULETTE = 11,   /* particles killed by weight-window roulette      */
+    N_GLOBAL = 12
 };
 
-enum { FATE_ALIVE = 0, FATE_ABSORBED = 1, FATE_CUTOFF = 2, FATE_LEAKED = 3, FATE_LOST = 4 };
+enum { FATE_ALIVE = 0, FATE_ABSORBED = 1, FATE_CUTOFF = 2, FATE_LEAKED = 3, FATE_LOST = 4, FATE_ROULETTE = 5 };
+enum { WW_OFF = 0, WW_LINEAR = 1, WW_MLP = 2 };
 
 typedef struct {
     /* nuclides: grid of nuclide k is E[nuc_off[k] .. nuc_off[k+1]) */
@@ -87,6 +90,18 @@ typedef struct {
     /* physics */
     double e_cut;
     int64_t max_events;
+    /* weight windows: ln I from a linear form or the importance network */
+    int32_t ww_kind;
+    double ww_lin[3];        /* ln I = c0 + c1 f_x + c2 f_E */
+    const double *ww_mlp;    /* network parameters, oracle/mlp.py flat order */
+    double ww_length;        /* feature scale L */
+    double ww_kappa;         /* w_L at the source point = 1 / kappa */
+    double ww_ratio;         /* w_U / w_L */
+    int32_t ww_nmax;         /* most copies of one split */
+    int32_t ww_depth;        /* most pending split records per history */
+    /* importance generation (forward estimate on an x by ln E grid) */
+    int32_t imp_nx, imp_ne;
+    double imp_x0, imp_x1;
 } orc_problem;
 
 typedef struct {
@@ -496,6 +511,80 @@ static void score_flight(const orc_problem *p, const particle *q, const double r
 }
 
 /* ------------------------------------------------------------------------ */
+/* importance network (forward only, FP64 with BF16 rounding points; the     */
+/* same network as oracle/mlp.py)                                            */
+/* ------------------------------------------------------------------------ */
+/* Nearest BF16 value of x (ties to even), via FP32. */
+double orc_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return x; /* NaN */
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+
+/* ln I of features f[4]: z1 = bf16(f) W1 + b1, h1 = bf16(silu(z1)),
+ * z2 = h1 W2 + b2, h2 = silu(z2), y = h2 w3 + b3 (W1, W2, w3 as BF16). */
+double orc_mlp_forward(const double *prm, const double f[4])
+{
+    const double *W1 = prm, *b1 = prm + 256, *W2 = prm + 320, *b2 = prm + 4416, *w3 = prm + 4480;
+    const double b3 = prm[4544];
+    double h1[64], y = 0.0;
+    double fr[4];
+    for (int k = 0; k < 4; ++k) fr[k] = orc_bf16(f[k]);
+    for (int j = 0; j < 64; ++j) {
+        double z = 0.0;
+        for (int k = 0; k < 4; ++k) z = z + fr[k] * orc_bf16(W1[k * 64 + j]);
+        h1[j] = orc_bf16(silu(z + b1[j]));
+    }
+    for (int j = 0; j < 64; ++j) {
+        double z = 0.0;
+        for (int k = 0; k < 64; ++k) z = z + h1[k] * orc_bf16(W2[k * 64 + j]);
+        y = y + silu(z + b2[j]) * orc_bf16(w3[j]);
+    }
+    return y + b3;
+}
+
+/* importance features: (x/L, clip(y/L), clip(z/L), (ln E - ln 1e-5)/ln(2e7/1e-5)) */
+static void ww_features(const orc_problem *p, const double r[3], double E, double f[4])
+{
+    const double L = p->ww_length;
+    f[0] = r[0] / L;
+    f[1] = fmin(1.0, fmax(-1.0, r[1] / L));
+    f[2] = fmin(1.0, fmax(-1.0, r[2] / L));
+    f[3] = (log(E) - log(1e-5)) / log(2e7 / 1e-5);
+}
+
+static double ln_importance(const orc_problem *p, const double r[3], double E)
+{
+    double f[4];
+    ww_features(p, r, E, f);
+    if (p->ww_kind == WW_LINEAR) return p->ww_lin[0] + p->ww_lin[1] * f[0] + p->ww_lin[2] * f[3];
+    return orc_mlp_forward(p->ww_mlp, f);
+}
+
+/* Lineage of split copy k (1..n-1) of split number s of a particle of
+ * lineage a: a hash of the three (MurmurHash3's 32-bit finaliser); never 0,
+ * which is the primary particles' lineage. */
+uint32_t orc_child_lineage(uint32_t a, uint32_t s, uint32_t k)
+{
+    uint32_t h = a * 0x9E3779B1u;
+    h ^= (s + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= (k + 1u) * 0xC2B2AE3Du;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h ? h : 1u;
+}
+
+/* ------------------------------------------------------------------------ */
 /* one history, birth to death (paper section 2: history-based mode)        */
 /* ------------------------------------------------------------------------ */
 static void sample_source(const orc_problem *p, particle *q, rng_stream *rs)
@@ -525,107 +614,271 @@ static void sample_source(const orc_problem *p, particle *q, rng_stream *rs)
     locate(p, q);
 }
 
-static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, double *tl,
-                          double *coll, double *glob, orc_history *h)
-{
-    rng_stream rs = {seed, pid, 0, 0};
+#define IMP_MAX_WORDS 64  /* importance grid of at most 4096 cells */
+#define WW_MAX_DEPTH 64
+
+/* A particle copy: its state, its random stream and the importance cells it
+ * (or the particle it was split from) has entered. */
+typedef struct {
     particle q;
-    sample_source(p, &q, &rs);
+    rng_stream rs;
+    uint32_t splits;     /* split events of this copy (numbers its children) */
+    uint64_t seen[IMP_MAX_WORDS];
+} copy_state;
+
+/* n - 1 identical pending copies of a split, handed out last-in first-out */
+typedef struct {
+    copy_state proto;    /* state at the split (weight already divided) */
+    uint32_t lineage, split_no, next_k, n;
+} split_record;
+
+typedef struct {
+    double *tl, *coll, *glob, *imp; /* imp: num[nc], den[nc], cnt[nc] */
+} scores;
+
+static int64_t imp_cell(const orc_problem *p, double x, double E)
+{
+    int64_t ix = (int64_t)floor((x - p->imp_x0) / (p->imp_x1 - p->imp_x0) * p->imp_nx);
+    int64_t ie = (int64_t)floor((log(E) - log(1e-5)) / log(2e7 / 1e-5) * p->imp_ne);
+    if (ix < 0) ix = 0;
+    if (ix > p->imp_nx - 1) ix = p->imp_nx - 1;
+    if (ie < 0) ie = 0;
+    if (ie > p->imp_ne - 1) ie = p->imp_ne - 1;
+    return ie * p->imp_nx + ix;
+}
+
+/* Mark the importance cells of x-bins between x0 and x1 at energy E as
+ * entered; the weight entering a cell counts the first time only. */
+static void imp_enter(const orc_problem *p, copy_state *c, double x0, double x1, double E, double *den)
+{
+    if (!p->imp_nx) return;
+    int64_t a = imp_cell(p, x0, E), b = imp_cell(p, x1, E);
+    if (a > b) { int64_t t = a; a = b; b = t; }
+    for (int64_t g = a; g <= b; ++g) {
+        uint64_t bit = 1ull << (g & 63);
+        if (!(c->seen[g >> 6] & bit)) {
+            c->seen[g >> 6] |= bit;
+            den[g] += c->q.w;
+        }
+    }
+}
+
+/* A detector score w credits every cell the copy's line has entered. */
+static void imp_credit(const orc_problem *p, const copy_state *c, double w, double *num, double *cnt)
+{
+    if (!p->imp_nx) return;
+    int64_t nc = (int64_t)p->imp_nx * p->imp_ne;
+    for (int64_t g = 0; g < nc; ++g)
+        if (c->seen[g >> 6] & (1ull << (g & 63))) {
+            num[g] += w;
+            cnt[g] += 1.0;
+        }
+}
+
+/* Weight-window game after a collision or a crossing.  Window of the point:
+ * w_L = exp(ln I_src - ln I) / kappa, w_U = ratio * w_L, survival weight
+ * w_S = (w_L + w_U) / 2.  Above w_U: split into n = min(n_max, ceil(w / w_U))
+ * copies of weight w / n (copy 0 goes on, n - 1 are pushed); below w_L:
+ * roulette, surviving with probability w / w_S at weight w_S (one draw).
+ * Returns 1 when the particle was killed. */
+static int weight_window(const orc_problem *p, copy_state *c, double ln_src, split_record *stack, int *depth,
+                         double *glob)
+{
+    const double lw = exp(ln_src - ln_importance(p, c->q.r, c->q.E)) / p->ww_kappa;
+    const double uw = p->ww_ratio * lw;
+    const double sw = 0.5 * (lw + uw);
+    const double w = c->q.w;
+    if (w > uw) {
+        int32_t n = (int32_t)ceil(w / uw);
+        if (n > p->ww_nmax) n = p->ww_nmax;
+        if (n >= 2 && *depth < p->ww_depth) {
+            c->q.w = w / (double)n;
+            split_record *r = &stack[(*depth)++];
+            r->proto = *c;
+            r->lineage = c->rs.lineage;
+            r->split_no = c->splits;
+            r->next_k = 1;
+            r->n = (uint32_t)n;
+            c->splits += 1;
+            glob[G_SPLIT] += (double)(n - 1);
+        }
+        return 0;
+    }
+    if (w < lw) {
+        if (next_u(&c->rs) < w / sw) {
+            c->q.w = sw;
+            return 0;
+        }
+        glob[G_ROULETTE] += 1.0;
+        return 1;
+    }
+    return 0;
+}
+
+static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, scores sc, double ln_src,
+                          orc_history *h)
+{
+    double *tl = sc.tl, *coll = sc.coll, *glob = sc.glob;
+    const int64_t ncell = (int64_t)p->imp_nx * p->imp_ne;
+    double *num = sc.imp, *den = sc.imp ? sc.imp + ncell : NULL, *cnt = sc.imp ? sc.imp + 2 * ncell : NULL;
+    split_record stack[WW_MAX_DEPTH];
+    int depth = 0;
+    copy_state c;
+    memset(&c, 0, sizeof c);
+    c.rs.seed = seed;
+    c.rs.pid = pid;
+    sample_source(p, &c.q, &c.rs);
+    if (den) imp_enter(p, &c, c.q.r[0], c.q.r[0], c.q.E, den);
     int fate = FATE_ALIVE;
     double track = 0.0;
-    while (fate == FATE_ALIVE) {
-        if ((int64_t)q.n_coll + q.n_cross >= p->max_events) { fate = FATE_LOST; break; }
+    int64_t n_coll = 0, n_cross = 0;
+    uint64_t n_draws = 0;
+    for (;;) {
+        if ((int64_t)c.q.n_coll + c.q.n_cross >= p->max_events) { fate = FATE_LOST; goto dead; }
         double Sa, Ss;
-        orc_macro_xs(p, q.mat, q.E, &Sa, &Ss);
+        orc_macro_xs(p, c.q.mat, c.q.E, &Sa, &Ss);
         double St = Sa + Ss;
         /* distance to collision: -ln(xi) / Sigma_t */
-        double dc = -log(next_u(&rs)) / St;
+        double dc = -log(next_u(&c.rs)) / St;
         int32_t surf;
-        double db = distance_to_boundary(p, &q, &surf);
+        double db = distance_to_boundary(p, &c.q, &surf);
         double d = (db < dc) ? db : dc;
-        double r0[3] = {q.r[0], q.r[1], q.r[2]};
-        for (int a = 0; a < 3; ++a) q.r[a] = q.r[a] + d * q.d[a];
-        score_flight(p, &q, r0, d, tl);
-        glob[G_TRACK] += q.w * d;
-        glob[G_TRACK_ABS] += q.w * d * Sa;
+        double r0[3] = {c.q.r[0], c.q.r[1], c.q.r[2]};
+        for (int a = 0; a < 3; ++a) c.q.r[a] = c.q.r[a] + d * c.q.d[a];
+        score_flight(p, &c.q, r0, d, tl);
+        glob[G_TRACK] += c.q.w * d;
+        glob[G_TRACK_ABS] += c.q.w * d * Sa;
         track += d;
+        if (den) imp_enter(p, &c, r0[0], c.q.r[0], c.q.E, den);
         if (db < dc) {
             glob[G_NCROSS] += 1.0;
             int face_xhi = (p->geom_kind != GEOM_INFINITE) && (surf == S_XHI) &&
-                           ((p->geom_kind == GEOM_SLAB) ? (q.layer == p->n_layers - 1) : (q.ci == p->nx - 1));
-            if (cross_surface(p, &q, surf)) {
+                           ((p->geom_kind == GEOM_SLAB) ? (c.q.layer == p->n_layers - 1) : (c.q.ci == p->nx - 1));
+            if (cross_surface(p, &c.q, surf)) {
                 fate = FATE_LEAKED;
-                glob[G_LEAK] += q.w;
+                glob[G_LEAK] += c.q.w;
                 if (face_xhi) {
-                    glob[G_LEAK_XHI] += q.w;
-                    if (q.n_coll == 0) glob[G_LEAK_XHI_UNC] += q.w;
+                    glob[G_LEAK_XHI] += c.q.w;
+                    if (c.q.n_coll == 0) glob[G_LEAK_XHI_UNC] += c.q.w;
+                    if (num) imp_credit(p, &c, c.q.w, num, cnt);
                 }
+                goto dead;
+            }
+            if (p->ww_kind && weight_window(p, &c, ln_src, stack, &depth, glob)) {
+                fate = FATE_ROULETTE;
+                goto dead;
             }
             continue;
         }
         /* collision */
-        q.n_coll += 1;
+        c.q.n_coll += 1;
         glob[G_NCOLL] += 1.0;
         {
-            int64_t b = point_bin(p, &q);
-            if (b >= 0) coll[b] += q.w / St;
-            glob[G_COLL_EST] += q.w / St;
+            int64_t b = point_bin(p, &c.q);
+            if (b >= 0) coll[b] += c.q.w / St;
+            glob[G_COLL_EST] += c.q.w / St;
         }
         /* analog absorption: absorbed when xi * Sigma_t < Sigma_a */
-        if (next_u(&rs) * St < Sa) {
-            glob[G_ABSORB] += q.w;
+        if (next_u(&c.rs) * St < Sa) {
+            glob[G_ABSORB] += c.q.w;
             fate = FATE_ABSORBED;
-            break;
+            goto dead;
         }
-        /* target nuclide: the first, in material order, whose running sum of
-         * density * sigma_s reaches xi * Sigma_s */
-        double target = next_u(&rs) * Ss;
-        double cum = 0.0;
-        int32_t nuc = -1;
-        for (int32_t qq = p->mat_off[q.mat]; qq < p->mat_off[q.mat + 1]; ++qq) {
-            double sc, ss;
-            orc_micro_xs(p, p->mat_nuc[qq], q.E, &sc, &ss, NULL);
-            double term = p->mat_dens[qq] * ss;
-            cum = cum + term;
-            if (term > 0.0) nuc = p->mat_nuc[qq];
-            if (cum >= target && term > 0.0) break;
+        {
+            /* target nuclide: the first, in material order, whose running
+             * sum of density * sigma_s reaches xi * Sigma_s */
+            double target = next_u(&c.rs) * Ss;
+            double cum = 0.0;
+            int32_t nuc = -1;
+            for (int32_t qq = p->mat_off[c.q.mat]; qq < p->mat_off[c.q.mat + 1]; ++qq) {
+                double sc_, ss_;
+                orc_micro_xs(p, p->mat_nuc[qq], c.q.E, &sc_, &ss_, NULL);
+                double term = p->mat_dens[qq] * ss_;
+                cum = cum + term;
+                if (term > 0.0) nuc = p->mat_nuc[qq];
+                if (cum >= target && term > 0.0) break;
+            }
+            double mu_cm = 2.0 * next_u(&c.rs) - 1.0;
+            double phi = 2.0 * M_PI * next_u(&c.rs);
+            double e_out, mu_lab;
+            orc_elastic(p->awr[nuc], c.q.E, mu_cm, &e_out, &mu_lab);
+            orc_rotate(c.q.d, mu_lab, phi);
+            c.q.E = e_out;
         }
-        double mu_cm = 2.0 * next_u(&rs) - 1.0;
-        double phi = 2.0 * M_PI * next_u(&rs);
-        double e_out, mu_lab;
-        orc_elastic(p->awr[nuc], q.E, mu_cm, &e_out, &mu_lab);
-        orc_rotate(q.d, mu_lab, phi);
-        q.E = e_out;
-        if (q.E < p->e_cut) {
-            glob[G_CUTOFF] += q.w;
+        if (c.q.E < p->e_cut) {
+            glob[G_CUTOFF] += c.q.w;
             fate = FATE_CUTOFF;
+            goto dead;
+        }
+        if (den) imp_enter(p, &c, c.q.r[0], c.q.r[0], c.q.E, den);
+        if (p->ww_kind && weight_window(p, &c, ln_src, stack, &depth, glob)) {
+            fate = FATE_ROULETTE;
+            goto dead;
+        }
+        continue;
+    dead:
+        n_coll += c.q.n_coll;
+        n_cross += c.q.n_cross;
+        n_draws += c.rs.n;
+        if (depth == 0) break;
+        {
+            /* next pending copy: fresh stream of its own lineage */
+            split_record *r = &stack[depth - 1];
+            const uint32_t k = r->next_k++;
+            c = r->proto;
+            c.rs.lineage = orc_child_lineage(r->lineage, r->split_no, k);
+            c.rs.n = 0;
+            c.splits = 0;
+            c.q.n_coll = r->proto.q.n_coll;
+            c.q.n_cross = r->proto.q.n_cross;
+            n_coll -= c.q.n_coll;   /* the copy's counts continue from its parent's */
+            n_cross -= c.q.n_cross;
+            if (r->next_k >= r->n) --depth;
+            fate = FATE_ALIVE;
         }
     }
     if (h) {
         h->fate = fate;
-        h->n_coll = q.n_coll;
-        h->n_cross = q.n_cross;
-        h->n_draws = rs.n;
-        h->E_final = q.E;
+        h->n_coll = (int32_t)n_coll;
+        h->n_cross = (int32_t)n_cross;
+        h->n_draws = n_draws;
+        h->E_final = c.q.E;
         h->track = track;
-        h->weight = q.w;
+        h->weight = c.q.w;
     }
 }
 
+static int64_t imp_cells(const orc_problem *p) { return (int64_t)p->imp_nx * p->imp_ne; }
+
+/* ln I at the source point (E0, the source position or the box centre) */
+double orc_ln_importance_source(const orc_problem *p)
+{
+    double r[3];
+    for (int a = 0; a < 3; ++a)
+        r[a] = (p->src_kind == SRC_BOX) ? 0.5 * (p->src_box[2 * a] + p->src_box[2 * a + 1]) : p->src_pos[a];
+    return ln_importance(p, r, p->src_E);
+}
+
 /* Run histories [first_pid, first_pid + n) and add their raw (un-normalised)
- * scores into tl[n_bins], coll[n_bins], glob[N_GLOBAL].  The pids are split
- * into at most 64 contiguous blocks, each tracked in pid order by one thread
- * and summed in block order, so the result does not depend on the thread
- * count.  hist (nullable) receives one record per pid. */
+ * scores into tl[n_bins], coll[n_bins], glob[N_GLOBAL] and, when the
+ * importance grid is on, imp[3 * cells] (numerators, weights entered, score
+ * counts).  The pids are split into at most 64 contiguous blocks, each
+ * tracked in pid order by one thread and summed in block order, so the result
+ * does not depend on the thread count.  hist (nullable) receives one record
+ * per pid. */
 int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *tl,
-            double *coll, double *glob, orc_history *hist, int n_threads)
+            double *coll, double *glob, double *imp, orc_history *hist, int n_threads)
 {
     int64_t nb = tally_bins(p);
+    int64_t ni = imp ? 3 * imp_cells(p) : 0;
+    if (imp_cells(p) > 64 * IMP_MAX_WORDS) return -2;
+    if (p->ww_kind && (p->ww_depth > WW_MAX_DEPTH || p->ww_depth < 0)) return -2;
     int64_t n_blocks = n < 64 ? (int64_t)n : 64;
     if (n_blocks == 0) return 0;
-    int64_t stride = nb * 2 + N_GLOBAL;
+    int64_t stride = nb * 2 + N_GLOBAL + ni;
     double *part = (double *)calloc((size_t)(n_blocks * stride), sizeof(double));
     if (!part) return -1;
+    const double ln_src = p->ww_kind ? orc_ln_importance_source(p) : 0.0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -634,13 +887,14 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n,
         uint64_t lo = (uint64_t)b * n / (uint64_t)n_blocks;
         uint64_t hi = (uint64_t)(b + 1) * n / (uint64_t)n_blocks;
         double *t = part + b * stride;
-        for (uint64_t i = lo; i < hi; ++i)
-            track_history(p, seed, first_pid + i, t, t + nb, t + 2 * nb, hist ? hist + i : NULL);
+        scores sc = {t, t + nb, t + 2 * nb, imp ? t + 2 * nb + N_GLOBAL : NULL};
+        for (uint64_t i = lo; i < hi; ++i) track_history(p, seed, first_pid + i, sc, ln_src, hist ? hist + i : NULL);
     }
     for (int64_t b = 0; b < n_blocks; ++b) {
         const double *t = part + b * stride;
         for (int64_t k = 0; k < nb; ++k) { tl[k] += t[k]; coll[k] += t[nb + k]; }
         for (int k = 0; k < N_GLOBAL; ++k) glob[k] += t[2 * nb + k];
+        for (int64_t k = 0; k < ni; ++k) imp[k] += t[2 * nb + N_GLOBAL + k];
     }
     free(part);
     return 0;
