@@ -68,7 +68,9 @@ enum {
     MC_G_NCROSS = 7,       /* surface crossings                                 */
     MC_G_LEAK_XHI = 8,     /* weight leaked through the x+ face                 */
     MC_G_LEAK_XHI_UNC = 9, /* the same, for particles that never collided       */
-    MC_N_GLOBAL = 10
+    MC_G_SPLIT = 10,       /* copies created by weight-window splitting         */
+    MC_G_ROULETTE = 11,    /* particles killed by weight-window roulette        */
+    MC_N_GLOBAL = 12
 };
 
 /* fate codes of mc_history.fate */
@@ -414,6 +416,49 @@ int mc_reset_problem_set(mc_ctx *ctx);
  * cache_path as for mc_autotune.
  */
 int mc_autotune_problem_set(mc_ctx *ctx, const char *cache_path, mc_tuning *best);
+
+/*
+ * Importance network (learned importance map for weight windows).
+ *
+ * A 4 -> 64 -> 64 -> 1 perceptron with SiLU hidden activations predicting
+ * ln I from the features (x/L, clip(y/L, -1, 1), clip(z/L, -1, 1),
+ * (ln E - ln 1e-5) / ln(2e12)).  Parameters are one flat FP32 array of
+ * MC_MLP_NPAR values in the order W1[4][64], b1[64], W2[64][64], b2[64],
+ * w3[64], b3 (W[k][j]: input k -> output j).  The kernels keep BF16 copies
+ * of W1, W2 and w3, feed the 64x64 products to the matrix cores with FP32
+ * accumulation, and round the inputs and the first hidden activation to
+ * BF16; biases and everything else are FP32.
+ */
+enum { MC_MLP_NPAR = 4545 };
+
+/* Load the parameters (host array of MC_MLP_NPAR floats, copied) and reset
+ * the Adam state.  Errors: MC_EINVAL (NULL or a non-finite value). */
+int mc_mlp_set(mc_ctx *ctx, const float *params);
+
+/* Copy the current FP32 parameters into a host array of MC_MLP_NPAR floats.
+ * Errors: MC_ESTATE (no network loaded). */
+int mc_mlp_get(mc_ctx *ctx, float *params);
+
+/* ln I of n feature vectors: features is a device array [n][4] (FP32, row
+ * major), out a device array [n].  Asynchronous on the context's stream; the
+ * caller owns both buffers.  Errors: MC_ESTATE, MC_EINVAL (n >= 2^31). */
+int mc_mlp_forward(mc_ctx *ctx, size_t n, const float *features, float *out);
+
+/* Gradient of the weighted squared error sum_i w_i (y_i - t_i)^2 / sum_i w_i
+ * over n samples (device arrays: features [n][4], target [n], weight [n]).
+ * grad (host, MC_MLP_NPAR floats, flat order) and loss (host) may be NULL.
+ * Summation order is fixed: results are reproducible run to run.
+ * Errors: MC_ESTATE, MC_EINVAL (n == 0 or n >= 2^24). */
+int mc_mlp_grad(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
+                float *grad, float *loss);
+
+/* Full-batch training: `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8,
+ * step counter continuing from earlier calls since mc_mlp_set) at learning
+ * rate lr on the samples above.  loss_curve (host, `steps` floats, may be
+ * NULL) receives the loss before each step.  Synchronous.
+ * Errors: MC_ESTATE, MC_EINVAL. */
+int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
+                 int32_t steps, float lr, float *loss_curve);
 
 /* Library version string. */
 const char *mc_version(void);

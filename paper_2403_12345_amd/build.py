@@ -6,8 +6,8 @@ import shutil
 import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("mc_kernels.hip", "mc_api.hip")]
-HEADERS = [os.path.join(_HERE, "csrc", f) for f in ("mc_device.h", "mc_internal.h")] + [
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("mc_kernels.hip", "mc_mlp.hip", "mc_api.hip")]
+HEADERS = [os.path.join(_HERE, "csrc", f) for f in ("mc_device.h", "mc_internal.h", "mc_physics.h", "mc_mlp.h")] + [
     os.path.join(os.path.dirname(_HERE), "include", "mc.h")]
 OUT = os.path.join(_HERE, "libmc.so")
 

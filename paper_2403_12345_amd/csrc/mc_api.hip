@@ -103,6 +103,16 @@ struct mc_ctx {
     hipGraphExec_t gexec = nullptr;
     uint32_t graph_grid = 0, graph_tile = 0;
     int64_t graph_max_events = 0;
+
+    // importance network
+    bool have_mlp = false;
+    Buffers mlp_bufs, mlp_scratch_bufs;
+    float *theta = nullptr, *mom = nullptr, *vel = nullptr, *grad = nullptr, *inv_wsum = nullptr;
+    uint16_t *W1b = nullptr, *W2b = nullptr, *W2tb = nullptr, *w3b = nullptr;
+    int mlp_step = 0;
+    float *mlp_partial = nullptr, *mlp_loss = nullptr;
+    size_t mlp_scratch_n = 0;
+    int32_t mlp_loss_cap = 0;
 };
 
 static int lookup_ilp(const mc_ctx *ctx) { return ctx->tune.lookup_ilp ? ctx->tune.lookup_ilp : DEFAULT_LOOKUP_ILP; }
@@ -226,6 +236,8 @@ void mc_destroy(mc_ctx *ctx)
     ctx->scratch_bufs.release();
     ctx->set_bufs.release();
     ctx->set_tile_bufs.release();
+    ctx->mlp_bufs.release();
+    ctx->mlp_scratch_bufs.release();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -1404,6 +1416,142 @@ int mc_autotune_problem_set(mc_ctx *ctx, const char *cache_path, mc_tuning *best
     if (rc) return rc;
     cache_store(cache_path, sig, cur, best_ms);
     if (best) *best = cur;
+    return MC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// importance network
+// ---------------------------------------------------------------------------
+static MlpDev mlp_dev(const mc_ctx *ctx)
+{
+    MlpDev m;
+    m.theta = ctx->theta;
+    m.W1 = ctx->W1b;
+    m.W2 = ctx->W2b;
+    m.W2t = ctx->W2tb;
+    m.w3 = ctx->w3b;
+    return m;
+}
+
+int mc_mlp_set(mc_ctx *ctx, const float *params)
+{
+    if (!ctx || !params) return MC_EINVAL;
+    for (int j = 0; j < MLP_NPAR; ++j)
+        if (!std::isfinite(params[j])) return fail(ctx, MC_EINVAL, "mc_mlp_set: parameter " + std::to_string(j) + " not finite");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->have_mlp) {
+        Buffers &B = ctx->mlp_bufs;
+        int rc = dalloc(ctx, B, &ctx->theta, MLP_NPAR);
+        if (!rc) rc = dalloc(ctx, B, &ctx->mom, MLP_NPAR);
+        if (!rc) rc = dalloc(ctx, B, &ctx->vel, MLP_NPAR);
+        if (!rc) rc = dalloc(ctx, B, &ctx->grad, MLP_NPAR + 1);
+        if (!rc) rc = dalloc(ctx, B, &ctx->inv_wsum, 1);
+        if (!rc) rc = dalloc(ctx, B, &ctx->W1b, 256);
+        if (!rc) rc = dalloc(ctx, B, &ctx->W2b, 4096);
+        if (!rc) rc = dalloc(ctx, B, &ctx->W2tb, 4096);
+        if (!rc) rc = dalloc(ctx, B, &ctx->w3b, 64);
+        if (rc) {
+            B.release();
+            return rc;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->theta, params, MLP_NPAR * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->mom), MLP_NPAR, 0u, ctx->stream));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->vel), MLP_NPAR, 0u, ctx->stream));
+    HIPCHK(launch_mlp_sync(ctx->theta, ctx->W1b, ctx->W2b, ctx->W2tb, ctx->w3b, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->mlp_step = 0;
+    ctx->have_mlp = true;
+    return MC_OK;
+}
+
+int mc_mlp_get(mc_ctx *ctx, float *params)
+{
+    if (!ctx || !params) return MC_EINVAL;
+    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_mlp_get: no network (mc_mlp_set first)");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMemcpyAsync(params, ctx->theta, MLP_NPAR * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+int mc_mlp_forward(mc_ctx *ctx, size_t n, const float *features, float *out)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_mlp_forward: no network (mc_mlp_set first)");
+    if (n == 0) return MC_OK;
+    if (!features || !out || n >= (1ull << 31)) return fail(ctx, MC_EINVAL, "mc_mlp_forward: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_mlp_forward(mlp_dev(ctx), (uint32_t)n, features, out, ctx->stream));
+    return MC_OK;
+}
+
+static int mlp_scratch(mc_ctx *ctx, size_t n, int32_t steps)
+{
+    const size_t need = mlp_partial_floats((uint32_t)n);
+    if (need <= ctx->mlp_scratch_n && steps <= ctx->mlp_loss_cap) return MC_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->mlp_scratch_bufs.release();
+    ctx->mlp_scratch_n = 0;
+    ctx->mlp_loss_cap = 0;
+    const size_t n2 = std::max(need, ctx->mlp_scratch_n);
+    const int32_t s2 = std::max<int32_t>(steps, 1);
+    int rc = dalloc(ctx, ctx->mlp_scratch_bufs, &ctx->mlp_partial, n2);
+    if (!rc) rc = dalloc(ctx, ctx->mlp_scratch_bufs, &ctx->mlp_loss, (size_t)s2);
+    if (rc) {
+        ctx->mlp_scratch_bufs.release();
+        return rc;
+    }
+    ctx->mlp_scratch_n = n2;
+    ctx->mlp_loss_cap = s2;
+    return MC_OK;
+}
+
+int mc_mlp_grad(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
+                float *grad, float *loss)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_mlp_grad: no network (mc_mlp_set first)");
+    if (n == 0 || n >= (1ull << 24) || !features || !target || !weight)
+        return fail(ctx, MC_EINVAL, "mc_mlp_grad: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = mlp_scratch(ctx, n, 1);
+    if (rc) return rc;
+    HIPCHK(launch_mlp_wsum(weight, (uint32_t)n, ctx->inv_wsum, ctx->stream));
+    HIPCHK(launch_mlp_grad(mlp_dev(ctx), (uint32_t)n, features, target, weight, ctx->inv_wsum, ctx->mlp_partial,
+                           ctx->grad, ctx->stream));
+    std::vector<float> g(MLP_NPAR + 1);
+    HIPCHK(hipMemcpyAsync(g.data(), ctx->grad, g.size() * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (grad) std::memcpy(grad, g.data(), MLP_NPAR * sizeof(float));
+    if (loss) *loss = g[MLP_NPAR];
+    return MC_OK;
+}
+
+int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
+                 int32_t steps, float lr, float *loss_curve)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_mlp_train: no network (mc_mlp_set first)");
+    if (n == 0 || n >= (1ull << 24) || !features || !target || !weight || steps < 1 || !(lr > 0.0f))
+        return fail(ctx, MC_EINVAL, "mc_mlp_train: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = mlp_scratch(ctx, n, steps);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_mlp_wsum(weight, (uint32_t)n, ctx->inv_wsum, st));
+    for (int32_t k = 0; k < steps; ++k) {
+        HIPCHK(launch_mlp_grad(mlp_dev(ctx), (uint32_t)n, features, target, weight, ctx->inv_wsum, ctx->mlp_partial,
+                               ctx->grad, st));
+        HIPCHK(hipMemcpyAsync(ctx->mlp_loss + k, ctx->grad + MLP_NPAR, sizeof(float), hipMemcpyDeviceToDevice, st));
+        ctx->mlp_step += 1;
+        HIPCHK(launch_mlp_adam(ctx->theta, ctx->mom, ctx->vel, ctx->grad, ctx->mlp_step, lr, ctx->W1b, ctx->W2b,
+                               ctx->W2tb, ctx->w3b, st));
+    }
+    if (loss_curve)
+        HIPCHK(hipMemcpyAsync(loss_curve, ctx->mlp_loss, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     return MC_OK;
 }
 

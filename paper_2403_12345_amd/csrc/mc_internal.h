@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "mc_device.h"
+#include "mc_mlp.h"
 
 namespace mc {
 
@@ -88,6 +89,15 @@ struct SetDev {
 };
 hipError_t launch_problem_set(const SetDev &set, const XsDev &xs, int64_t max_events, uint32_t grid,
                               int32_t max_bins, hipStream_t st);
+// importance network
+hipError_t launch_mlp_forward(const MlpDev &m, uint32_t n, const float *X, float *Y, hipStream_t st);
+size_t mlp_partial_floats(uint32_t n);
+hipError_t launch_mlp_wsum(const float *W, uint32_t n, float *inv_wsum, hipStream_t st);
+hipError_t launch_mlp_grad(const MlpDev &m, uint32_t n, const float *X, const float *T, const float *W,
+                           const float *inv_wsum, float *partial, float *grad_and_loss, hipStream_t st);
+hipError_t launch_mlp_adam(float *theta, float *mom, float *vel, const float *grad, int step, float lr, uint16_t *W1,
+                           uint16_t *W2, uint16_t *W2t, uint16_t *w3, hipStream_t st);
+hipError_t launch_mlp_sync(const float *theta, uint16_t *W1, uint16_t *W2, uint16_t *W2t, uint16_t *w3, hipStream_t st);
 hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols, const double *direct,
                               double *partial, double inv_n, double *S1, double *S2, hipStream_t st);
 

@@ -21,7 +21,7 @@ MC_GEOM_INFINITE, MC_GEOM_LATTICE, MC_GEOM_SLAB = 0, 1, 2
 MC_TALLY_ENERGY, MC_TALLY_PIN, MC_TALLY_MESH, MC_TALLY_SLAB = 0, 1, 2, 3
 MC_T_FLUX_TRACK, MC_T_FLUX_COLLISION, MC_T_GLOBAL = 0, 1, 2
 (MC_G_TRACK, MC_G_COLL_EST, MC_G_ABSORB, MC_G_CUTOFF, MC_G_LEAK, MC_G_TRACK_ABS, MC_G_NCOLL,
- MC_G_NCROSS, MC_G_LEAK_XHI, MC_G_LEAK_XHI_UNC, MC_N_GLOBAL) = range(11)
+ MC_G_NCROSS, MC_G_LEAK_XHI, MC_G_LEAK_XHI_UNC, MC_G_SPLIT, MC_G_ROULETTE, MC_N_GLOBAL) = range(13)
 MC_FATE_ABSORBED, MC_FATE_CUTOFF, MC_FATE_LEAKED, MC_FATE_LOST = 1, 2, 3, 4
 
 _STATUS = {MC_EINVAL: "MC_EINVAL", MC_ENOMEM: "MC_ENOMEM", MC_EHIP: "MC_EHIP", MC_ELOST: "MC_ELOST",
@@ -136,6 +136,11 @@ def load():
         "mc_get_problem_tallies": ([V, I32, I32, P(D), P(D), SZ, P(mc_tally_meta)], C.c_int),
         "mc_reset_problem_set": ([V], C.c_int),
         "mc_autotune_problem_set": ([V, C.c_char_p, P(mc_tuning)], C.c_int),
+        "mc_mlp_set": ([V, P(C.c_float)], C.c_int),
+        "mc_mlp_get": ([V, P(C.c_float)], C.c_int),
+        "mc_mlp_forward": ([V, SZ, V, V], C.c_int),
+        "mc_mlp_grad": ([V, SZ, V, V, V, P(C.c_float), P(C.c_float)], C.c_int),
+        "mc_mlp_train": ([V, SZ, V, V, V, I32, C.c_float, P(C.c_float)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -343,6 +348,49 @@ def mc_autotune_problem_set(ctx, cache_path: str | None = None) -> dict:
     t = mc_tuning()
     _check(ctx, load().mc_autotune_problem_set(ctx, cache_path.encode() if cache_path else None, C.byref(t)))
     return t.as_dict()
+
+
+MC_MLP_NPAR = 4545
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mc_mlp_set(ctx, params):
+    """Load the flat parameter vector (MC_MLP_NPAR values) and reset Adam."""
+    p = np.ascontiguousarray(params, np.float32)
+    if p.size != MC_MLP_NPAR:
+        raise ValueError(f"mc_mlp_set: {p.size} parameters, expected {MC_MLP_NPAR}")
+    _check(ctx, load().mc_mlp_set(ctx, _fp(p)))
+
+
+def mc_mlp_get(ctx) -> np.ndarray:
+    p = np.zeros(MC_MLP_NPAR, np.float32)
+    _check(ctx, load().mc_mlp_get(ctx, _fp(p)))
+    return p
+
+
+def mc_mlp_forward(ctx, n: int, features, out):
+    """features: device float32 [n, 4]; out: device float32 [n]."""
+    _check(ctx, load().mc_mlp_forward(ctx, int(n), _ptr(features), _ptr(out)))
+
+
+def mc_mlp_grad(ctx, n: int, features, target, weight):
+    """Returns (gradient [MC_MLP_NPAR] float32, loss)."""
+    g = np.zeros(MC_MLP_NPAR, np.float32)
+    loss = C.c_float()
+    _check(ctx, load().mc_mlp_grad(ctx, int(n), _ptr(features), _ptr(target), _ptr(weight), _fp(g),
+                                   C.byref(loss)))
+    return g, float(loss.value)
+
+
+def mc_mlp_train(ctx, n: int, features, target, weight, steps: int, lr: float) -> np.ndarray:
+    """Returns the loss before each of the `steps` Adam steps."""
+    curve = np.zeros(int(steps), np.float32)
+    _check(ctx, load().mc_mlp_train(ctx, int(n), _ptr(features), _ptr(target), _ptr(weight), int(steps),
+                                    float(lr), _fp(curve)))
+    return curve
 
 
 def mc_get_tuning(ctx) -> dict:

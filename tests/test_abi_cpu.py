@@ -36,6 +36,21 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(mc.mc_stats) == 8 * 10
 
 
+def _header_enum(name):
+    src = open(os.path.join(ROOT, "include", "mc.h")).read()
+    return int(re.search(r"\b" + name + r"\s*=\s*(\d+)", src).group(1))
+
+
+def test_binding_constants_match_header_and_oracle():
+    import oracle
+    for k in ("MC_G_LEAK_XHI", "MC_G_SPLIT", "MC_G_ROULETTE", "MC_N_GLOBAL", "MC_MLP_NPAR"):
+        assert getattr(mc, k) == _header_enum(k), k
+    assert mc.MC_N_GLOBAL == oracle.N_GLOBAL
+    assert mc.MC_G_SPLIT == oracle.G_SPLIT and mc.MC_G_ROULETTE == oracle.G_ROULETTE
+    from oracle import mlp
+    assert mc.MC_MLP_NPAR == mlp.N_PARAMS
+
+
 def test_create_without_gpu_reports_no_device():
     import torch
     if torch.cuda.is_available():
