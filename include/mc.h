@@ -74,7 +74,7 @@ enum {
 };
 
 /* fate codes of mc_history.fate */
-enum { MC_FATE_ABSORBED = 1, MC_FATE_CUTOFF = 2, MC_FATE_LEAKED = 3, MC_FATE_LOST = 4 };
+enum { MC_FATE_ABSORBED = 1, MC_FATE_CUTOFF = 2, MC_FATE_LEAKED = 3, MC_FATE_LOST = 4, MC_FATE_ROULETTE = 5 };
 
 /*
  * Problem geometry, source and tally (one struct; unused members are ignored).
@@ -459,6 +459,66 @@ int mc_mlp_grad(mc_ctx *ctx, size_t n, const float *features, const float *targe
  * Errors: MC_ESTATE, MC_EINVAL. */
 int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
                  int32_t steps, float lr, float *loss_curve);
+
+/*
+ * Weight windows and the forward importance estimate.
+ *
+ * The paper's transport is analog; weight windows are the textbook
+ * split / roulette game driven by an importance map ln I(x, y, z, E).  The
+ * window at a point is w_L = exp(ln I_src - ln I) / kappa, w_U = ratio * w_L,
+ * w_S = (w_L + w_U) / 2, with ln I_src the map at the source point (the box
+ * centre for a box source), evaluated at the start of every mc_run_batch.  It
+ * is checked after every collision the particle survives and every crossing
+ * it does not leak through: above w_U the particle splits into
+ * n = min(n_max, ceil(w / w_U)) copies of weight w / n (none when the
+ * history already holds `depth` pending splits); below w_L it plays roulette
+ * with one draw and survives at w_S with probability w / w_S.  Pending copies
+ * wait on a last-in first-out stack of the history and run when the copy
+ * ahead of them ends; copy k of split number s of a copy of lineage a draws
+ * from lineage child_lineage(a, s, k) of the same pid (MurmurHash3's 32-bit
+ * finaliser of the three, never 0), so a history with all its copies depends
+ * on (seed, pid) only.  Features: f_x = x / length, f_E = (ln E - ln 1e-5) /
+ * ln(2e12); the network sees (x, clip(y), clip(z)) / length and f_E.
+ *
+ * Forward importance estimate (after Booth), on imp_nx x-bins over
+ * [imp_x0, imp_x1) by imp_ne ln E-bins over [1e-5, 2e7] eV (points outside
+ * fall in the end bins): the weight of a copy entering a cell for the first
+ * time (copies inherit what their parent entered) adds to den[cell]; weight
+ * leaking through the x+ face adds to num[cell] (and 1 to cnt[cell]) of every
+ * cell that copy has entered.  num / den estimates the expected score of unit
+ * weight entering the cell.  Cells are indexed e * imp_nx + x.  The sums use
+ * FP64 atomics: they are exact up to the order of the additions.
+ */
+enum { MC_WW_OFF = 0, MC_WW_LINEAR = 1, MC_WW_MLP = 2 };
+
+typedef struct {
+    int32_t kind;          /* MC_WW_OFF, MC_WW_LINEAR (ln I = lin[0] + lin[1] f_x + lin[2] f_E)
+                              or MC_WW_MLP (the context's network, mc_mlp_set)          */
+    int32_t n_max;         /* most copies per split, 2..1000                              */
+    int32_t depth;         /* most pending splits per history, 1..64                      */
+    int32_t imp_nx;        /* importance grid x-bins, 0 (no estimate) .. 256              */
+    int32_t imp_ne;        /* importance grid ln E-bins, 1..64 when imp_nx > 0           */
+    int32_t reserved;
+    double lin[3];
+    double length;         /* feature scale (cm), > 0                                     */
+    double kappa;          /* w_L at the source point is 1 / kappa, > 0                   */
+    double ratio;          /* w_U / w_L, > 1                                               */
+    double imp_x0, imp_x1; /* x range of the importance grid                              */
+} mc_ww_desc;
+
+/* Configure (or, with NULL or kind MC_WW_OFF and imp_nx 0, remove) the
+ * windows and the estimate for the following mc_run_batch calls; zeroes the
+ * importance sums.  The problem-set path (mc_run_problem_set) stays analog.
+ * Device memory for the pending copies: depth x in-flight slots x ~100 B
+ * (plus 2 B per ln E-bin with the estimate on).  Errors: MC_EINVAL naming the
+ * field; MC_ESTATE from mc_run_batch when MC_WW_MLP is set and no network is
+ * loaded. */
+int mc_set_weight_windows(mc_ctx *ctx, const mc_ww_desc *desc);
+
+/* Importance sums since the last mc_set_weight_windows / tally reset, into
+ * host arrays of n_cells = imp_nx * imp_ne doubles (each may be NULL).
+ * Errors: MC_ESTATE (no grid), MC_EINVAL (n_cells). */
+int mc_get_importance(mc_ctx *ctx, double *num, double *den, double *cnt, size_t n_cells);
 
 /* Library version string. */
 const char *mc_version(void);

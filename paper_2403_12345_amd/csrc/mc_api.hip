@@ -113,7 +113,26 @@ struct mc_ctx {
     float *mlp_partial = nullptr, *mlp_loss = nullptr;
     size_t mlp_scratch_n = 0;
     int32_t mlp_loss_cap = 0;
+
+    // weight windows and the forward importance estimate
+    mc_ww_desc ww_desc{};              // kind MC_WW_OFF, imp_nx 0: analog, no estimate
+    Buffers ww_bufs, imp_bufs;
+    WwDev ww{};                        // device arrays for ww_cap slots
+    uint32_t ww_cap = 0;
+    double *ln_src = nullptr;          // device scalar
+    double *imp_num = nullptr, *imp_den = nullptr, *imp_cnt = nullptr;
 };
+
+static MlpDev mlp_dev(const mc_ctx *ctx)
+{
+    MlpDev m;
+    m.theta = ctx->theta;
+    m.W1 = ctx->W1b;
+    m.W2 = ctx->W2b;
+    m.W2t = ctx->W2tb;
+    m.w3 = ctx->w3b;
+    return m;
+}
 
 static int lookup_ilp(const mc_ctx *ctx) { return ctx->tune.lookup_ilp ? ctx->tune.lookup_ilp : DEFAULT_LOOKUP_ILP; }
 static int64_t tail_particles(const mc_ctx *ctx)
@@ -238,6 +257,8 @@ void mc_destroy(mc_ctx *ctx)
     ctx->set_tile_bufs.release();
     ctx->mlp_bufs.release();
     ctx->mlp_scratch_bufs.release();
+    ctx->ww_bufs.release();
+    ctx->imp_bufs.release();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -445,6 +466,12 @@ static int reset_tallies(mc_ctx *ctx)
         HIPCHK(launch_fill_f64(ctx->S1[t], n, 0.0, ctx->stream));
         HIPCHK(launch_fill_f64(ctx->S2[t], n, 0.0, ctx->stream));
     }
+    if (ctx->imp_num) {
+        const size_t cells = (size_t)ctx->ww_desc.imp_nx * (size_t)ctx->ww_desc.imp_ne;
+        HIPCHK(launch_fill_f64(ctx->imp_num, cells, 0.0, ctx->stream));
+        HIPCHK(launch_fill_f64(ctx->imp_den, cells, 0.0, ctx->stream));
+        HIPCHK(launch_fill_f64(ctx->imp_cnt, cells, 0.0, ctx->stream));
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->n_batches = 0;
     ctx->histories = 0;
@@ -634,8 +661,10 @@ static int alloc_sort(mc_ctx *ctx, Buffers &B, SortBufs &sb, size_t n)
 static int ensure_bank(mc_ctx *ctx, uint32_t cap)
 {
     if (ctx->cap >= cap && ctx->bank_bins == ctx->n_bins && ctx->tal.n_bins == ctx->n_bins &&
-        (ctx->geom.tally_kind == TALLY_MESH) == (ctx->tal.mesh_tl != nullptr))
+        (ctx->geom.tally_kind == TALLY_MESH) == (ctx->tal.mesh_tl != nullptr)) {
+        ctx->bank.C = cap;  // the first cap slots of the (larger) allocation are in use
         return MC_OK;
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->bank_bufs.release();
     ctx->cap = 0;
@@ -713,6 +742,80 @@ static int timing_event_pair(mc_ctx *ctx, size_t k)
     return MC_OK;
 }
 
+// Split stacks and per-slot importance state for cap slots (only what the
+// windows and the estimate configured on the context need).
+static int ensure_ww(mc_ctx *ctx, uint32_t cap)
+{
+    const mc_ww_desc &d = ctx->ww_desc;
+    const bool stacks = d.kind != MC_WW_OFF, imp = d.imp_nx > 0;
+    if (!stacks && !imp) {
+        ctx->ww = WwDev{};
+        return MC_OK;
+    }
+    if (ctx->ww_cap < cap || !ctx->ln_src) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->ww_bufs.release();
+        ctx->ww_cap = 0;
+        Buffers &B = ctx->ww_bufs;
+        WwDev w{};
+        int rc = dalloc(ctx, B, &ctx->ln_src, 1);
+        if (stacks) {
+            const size_t nrec = (size_t)d.depth * cap;
+            double **dd[] = {&w.sx, &w.sy, &w.sz, &w.su, &w.sv, &w.sw, &w.sE, &w.swt};
+            for (double **q : dd)
+                if (!rc) rc = dalloc(ctx, B, q, nrec);
+            int32_t **ii[] = {&w.scell, &w.smat, &w.sncoll, &w.sncross};
+            for (int32_t **q : ii)
+                if (!rc) rc = dalloc(ctx, B, q, nrec);
+            uint32_t **uu[] = {&w.slin, &w.ssplit, &w.snext, &w.sn};
+            for (uint32_t **q : uu)
+                if (!rc) rc = dalloc(ctx, B, q, nrec);
+            if (!rc) rc = dalloc(ctx, B, &w.sinside, nrec);
+            if (!rc) rc = dalloc(ctx, B, &w.depth_of, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.splits, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.hcoll, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.hcross, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.hdraw, cap);
+            if (!rc && imp) rc = dalloc(ctx, B, &w.siv, nrec * (size_t)d.imp_ne);
+        }
+        if (!rc && imp) rc = dalloc(ctx, B, &w.iv, (size_t)cap * (size_t)d.imp_ne);
+        if (rc) {
+            B.release();
+            ctx->ln_src = nullptr;
+            return rc;
+        }
+        ctx->ww = w;
+        ctx->ww_cap = cap;
+    }
+    WwDev &w = ctx->ww;
+    w.kind = d.kind;
+    w.nmax = d.n_max;
+    w.depth = d.depth;
+    w.lin0 = d.lin[0];
+    w.lin1 = d.lin[1];
+    w.lin2 = d.lin[2];
+    w.length = d.length;
+    w.kappa = d.kappa;
+    w.ratio = d.ratio;
+    w.ln_emin = std::log(1e-5);
+    w.ln_erange = std::log(2e7 / 1e-5);
+    w.ln_src = ctx->ln_src;
+    w.C = cap;
+    w.imp_nx = d.imp_nx;
+    w.imp_ne = d.imp_ne;
+    w.imp_x0 = d.imp_x0;
+    w.imp_x1 = d.imp_x1;
+    w.num = ctx->imp_num;
+    w.den = ctx->imp_den;
+    w.cnt = ctx->imp_cnt;
+    if (d.kind == MC_WW_MLP) {
+        if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "weight windows from the network: mc_mlp_set first");
+        w.mlp = mlp_dev(ctx);
+    }
+    if (d.kind != MC_WW_OFF) HIPCHK(launch_ww_source(w, ctx->geom, ctx->ln_src, ctx->stream));
+    return MC_OK;
+}
+
 int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const mc_run_opts *opts_in)
 {
     if (!ctx) return MC_EINVAL;
@@ -731,9 +834,11 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     HistLog *log = static_cast<HistLog *>(opts.history_log);
     const uint32_t cap = (uint32_t)cap64;
     int rc = ensure_bank(ctx, cap);
+    if (!rc) rc = ensure_ww(ctx, cap);
     if (rc) return rc;
     hipStream_t st = ctx->stream;
     BankDev &b = ctx->bank;
+    const WwDev &W = ctx->ww;
     TallyDev tal = ctx->tal;
     tal.enabled = opts.no_tally ? 0 : 1;
     const GeomDev &g = ctx->geom;
@@ -758,12 +863,14 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     uint64_t it = 0;
     // every history ends within max_events + 1 iterations of its start, so the
     // loop is bounded by the number of bank refills times that
-    const uint64_t max_iter = (n / cap + 2) * ((uint64_t)max_events + 2);
+    // (with weight windows a history also runs its pending copies one by one)
+    uint64_t max_iter = (n / cap + 2) * ((uint64_t)max_events + 2);
+    if (W.kind != WW_OFF) max_iter *= 1ull + (uint64_t)W.depth * (uint64_t)W.nmax;
     for (;; ++it) {
         if (it >= max_iter) return fail(ctx, MC_EHIP, "event loop did not terminate");
         const int cur = (int)(it & 1);
         HIPCHK(launch_slots_count(b, st));
-        HIPCHK(launch_slots_queue(b, g, ctx->ctr, cur, first_pid, n, seed, st));
+        HIPCHK(launch_slots_queue(b, g, W, ctx->ctr, cur, first_pid, n, seed, st));
         HIPCHK(hipMemcpyAsync(ctx->ctr_host + cur, ctx->ctr + cur, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const Counters c = ctx->ctr_host[cur];
@@ -775,7 +882,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         const int64_t tail = tail_particles(ctx);
         if (tail > 0 && c.issued == n && (int64_t)c.nA <= tail) {
             // every history has started and few remain: finish them in one launch
-            HIPCHK(launch_tail(b, ctx->xs, g, tal, dc, c.nA, seed, max_events, log, first_pid, ctx->dstat + 1, st));
+            HIPCHK(launch_tail(b, ctx->xs, g, tal, W, dc, c.nA, seed, max_events, log, first_pid, ctx->dstat + 1, st));
             s.tail_particles = c.nA;
             ++it;
             break;
@@ -815,10 +922,10 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
             s.lookups += c.nL;
             s.lookup_launches += 1;
         }
-        HIPCHK(launch_advance(b, g, tal, dc, c.nA, seed, max_events, log ? 1 : 0, st));
+        HIPCHK(launch_advance(b, g, tal, W, dc, c.nA, seed, max_events, log ? 1 : 0, st));
         HIPCHK(launch_split(b, dc, c.nA, st));
-        HIPCHK(launch_cross(b, g, tal, dc, c.nA, log, first_pid, ctx->dstat + 1, st));
-        HIPCHK(launch_collide(b, ctx->xs, g, tal, dc, c.nA, seed, log, first_pid, st));
+        HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
+        HIPCHK(launch_collide(b, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
     }
     // batch statistics: per-workgroup rows summed in a fixed order
     const double inv_n = 1.0 / (double)n;
@@ -1423,17 +1530,6 @@ int mc_autotune_problem_set(mc_ctx *ctx, const char *cache_path, mc_tuning *best
 // ---------------------------------------------------------------------------
 // importance network
 // ---------------------------------------------------------------------------
-static MlpDev mlp_dev(const mc_ctx *ctx)
-{
-    MlpDev m;
-    m.theta = ctx->theta;
-    m.W1 = ctx->W1b;
-    m.W2 = ctx->W2b;
-    m.W2t = ctx->W2tb;
-    m.w3 = ctx->w3b;
-    return m;
-}
-
 int mc_mlp_set(mc_ctx *ctx, const float *params)
 {
     if (!ctx || !params) return MC_EINVAL;
@@ -1552,6 +1648,78 @@ int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *targ
     if (loss_curve)
         HIPCHK(hipMemcpyAsync(loss_curve, ctx->mlp_loss, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    return MC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// weight windows and the forward importance estimate
+// ---------------------------------------------------------------------------
+int mc_set_weight_windows(mc_ctx *ctx, const mc_ww_desc *desc)
+{
+    if (!ctx) return MC_EINVAL;
+    mc_ww_desc d{};
+    if (desc) d = *desc;
+    auto bad = [&](const std::string &m) { return fail(ctx, MC_EINVAL, "mc_set_weight_windows: " + m); };
+    if (d.kind != MC_WW_OFF && d.kind != MC_WW_LINEAR && d.kind != MC_WW_MLP) return bad("unknown kind");
+    if (d.kind != MC_WW_OFF) {
+        if (d.n_max < 2 || d.n_max > 1000) return bad("n_max outside [2, 1000]");
+        if (d.depth < 1 || d.depth > WW_MAX_DEPTH) return bad("depth outside [1, 64]");
+        if (!(d.length > 0.0) || !(d.kappa > 0.0) || !(d.ratio > 1.0)) return bad("need length > 0, kappa > 0, ratio > 1");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(d.lin[k])) return bad("lin not finite");
+    }
+    if (d.imp_nx < 0 || d.imp_nx > IMP_MAX_NX) return bad("imp_nx outside [0, 256]");
+    if (d.imp_nx > 0 && (d.imp_ne < 1 || d.imp_ne > IMP_MAX_NE || !(d.imp_x1 > d.imp_x0)))
+        return bad("importance grid needs 1 <= imp_ne <= 64 and imp_x1 > imp_x0");
+    if (d.imp_nx == 0) d.imp_ne = 0;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const bool same_shape = d.kind == ctx->ww_desc.kind && d.depth == ctx->ww_desc.depth &&
+                            d.imp_nx == ctx->ww_desc.imp_nx && d.imp_ne == ctx->ww_desc.imp_ne;
+    if (!same_shape) {
+        ctx->ww_bufs.release();
+        ctx->ww_cap = 0;
+        ctx->ln_src = nullptr;
+        ctx->ww = WwDev{};
+    }
+    const size_t cells = (size_t)d.imp_nx * (size_t)d.imp_ne;
+    if (cells != (size_t)ctx->ww_desc.imp_nx * (size_t)ctx->ww_desc.imp_ne || (cells && !ctx->imp_num)) {
+        ctx->imp_bufs.release();
+        ctx->imp_num = ctx->imp_den = ctx->imp_cnt = nullptr;
+        if (cells) {
+            int rc = dalloc(ctx, ctx->imp_bufs, &ctx->imp_num, cells);
+            if (!rc) rc = dalloc(ctx, ctx->imp_bufs, &ctx->imp_den, cells);
+            if (!rc) rc = dalloc(ctx, ctx->imp_bufs, &ctx->imp_cnt, cells);
+            if (rc) {
+                ctx->imp_bufs.release();
+                ctx->imp_num = ctx->imp_den = ctx->imp_cnt = nullptr;
+                ctx->ww_desc = mc_ww_desc{};
+                return rc;
+            }
+        }
+    }
+    ctx->ww_desc = d;
+    if (cells) {
+        HIPCHK(launch_fill_f64(ctx->imp_num, cells, 0.0, ctx->stream));
+        HIPCHK(launch_fill_f64(ctx->imp_den, cells, 0.0, ctx->stream));
+        HIPCHK(launch_fill_f64(ctx->imp_cnt, cells, 0.0, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return MC_OK;
+}
+
+int mc_get_importance(mc_ctx *ctx, double *num, double *den, double *cnt, size_t n_cells)
+{
+    if (!ctx) return MC_EINVAL;
+    const size_t cells = (size_t)ctx->ww_desc.imp_nx * (size_t)ctx->ww_desc.imp_ne;
+    if (!cells) return fail(ctx, MC_ESTATE, "mc_get_importance: no importance grid (mc_set_weight_windows)");
+    if (n_cells != cells) return fail(ctx, MC_EINVAL, "mc_get_importance: n_cells must be imp_nx * imp_ne");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (num) HIPCHK(hipMemcpyAsync(num, ctx->imp_num, cells * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (den) HIPCHK(hipMemcpyAsync(den, ctx->imp_den, cells * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (cnt) HIPCHK(hipMemcpyAsync(cnt, ctx->imp_cnt, cells * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return MC_OK;
 }
 

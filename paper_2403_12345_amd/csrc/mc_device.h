@@ -30,7 +30,7 @@ enum { TALLY_ENERGY = 0, TALLY_PIN = 1, TALLY_MESH = 2, TALLY_SLAB = 3 };
 enum { G_TRACK = 0, G_COLL_EST = 1, G_ABSORB = 2, G_CUTOFF = 3, G_LEAK = 4, G_TRACK_ABS = 5,
        G_NCOLL = 6, G_NCROSS = 7, G_LEAK_XHI = 8, G_LEAK_XHI_UNC = 9, G_SPLIT = 10, G_ROULETTE = 11,
        N_GLOBAL = 12 };
-enum { FATE_ABSORBED = 1, FATE_CUTOFF = 2, FATE_LEAKED = 3, FATE_LOST = 4 };
+enum { FATE_ABSORBED = 1, FATE_CUTOFF = 2, FATE_LEAKED = 3, FATE_LOST = 4, FATE_ROULETTE = 5 };
 
 // One nuclide entry of a material, in material order: where its grid lives
 // in the concatenated tables, how long it is, and its atom density.

@@ -6,6 +6,7 @@
 
 #include "mc_device.h"
 #include "mc_mlp.h"
+#include "mc_ww.h"
 
 namespace mc {
 
@@ -29,7 +30,7 @@ hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 hipError_t launch_slots_count(const BankDev &b, hipStream_t st);
-hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, Counters *ctr, int cur,
+hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, const WwDev &W, Counters *ctr, int cur,
                               uint64_t first_pid, uint64_t n_hist, uint64_t seed, hipStream_t st);
 // Scratch of the radix sort of up to `cap` items.
 struct SortBufs {
@@ -46,19 +47,21 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
                        const double *E, const int32_t *mat, const SortBufs &sb, uint32_t n_keys,
                        uint32_t *out_list, uint32_t *out_keys, hipStream_t st);
 hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st);
-hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
                           uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on,
                           hipStream_t st);
 hipError_t launch_split(const BankDev &b, Counters *ctr, uint32_t n_bound, hipStream_t st);
-hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
-                        uint32_t n_bound, HistLog *log, uint64_t first_pid, unsigned long long *lost,
+hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
+                        uint32_t n_bound, uint64_t seed, HistLog *log, uint64_t first_pid, unsigned long long *lost,
                         hipStream_t st);
-hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t,
+hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
                           const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
                           uint64_t first_pid, hipStream_t st);
-hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
-                       uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
-                       unsigned long long *lost, hipStream_t st);
+hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
+                       const Counters *ctr, uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log,
+                       uint64_t first_pid, unsigned long long *lost, hipStream_t st);
+// ln I at the source point into *out (device), for the weight windows.
+hipError_t launch_ww_source(const WwDev &W, const GeomDev &g, double *out, hipStream_t st);
 // Many independent problems (batching layer).
 struct SetProblem {
     GeomDev g;          // material ids index the shared tables

@@ -19,6 +19,7 @@
 #include "mc_device.h"
 #include "mc_internal.h"
 #include "mc_physics.h"
+#include "mc_ww.h"
 
 #pragma clang fp contract(off)
 
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(WG) k_slots_count(BankDev bank)
 
 // Sample a source particle into slot s (draw order: position for a box
 // source, then the isotropic direction: cosine, azimuth).
-__device__ __forceinline__ void init_particle(const BankDev &b, const GeomDev &g, uint32_t s,
+__device__ __forceinline__ void init_particle(const BankDev &b, const GeomDev &g, const WwDev &W, uint32_t s,
                                               uint64_t pid, uint64_t seed)
 {
     Rng rng(seed, pid, 0u, 0u);
@@ -178,9 +179,10 @@ __device__ __forceinline__ void init_particle(const BankDev &b, const GeomDev &g
     b.ncross[s] = 0;
     b.track[s] = 0.0;
     b.flags[s] = F_ALIVE | F_LOOKUP;
+    ww_start(W, s, x, g.src_E);
 }
 
-__global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, Counters *ctr,
+__global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, WwDev W, Counters *ctr,
                                                     int cur, uint64_t first_pid, uint64_t n_hist,
                                                     uint64_t seed)
 {
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
         if (fr) {
             const uint32_t k = pre[2] + run[2] + rk.rank[2];
             if (k < n_new) {
-                init_particle(bank, geom, s, first_pid + prev.issued + k, seed);
+                init_particle(bank, geom, W, s, first_pid + prev.issued + k, seed);
                 bank.A[tot[0] + k] = s;
                 bank.L[tot[1] + k] = s;
             }
@@ -497,7 +499,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 // ---------------------------------------------------------------------------
 // advance: sample the flight, move, score track length
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev tal, const Counters *ctr,
+__global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev tal, WwDev W, const Counters *ctr,
                                                 uint64_t seed, int64_t max_events, int32_t log_on)
 {
     extern __shared__ double slab[];
@@ -514,7 +516,9 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
             b.event[s] = 0xFF;  // event cap reached: the cross kernel ends it as lost
         } else {
             Particle p = load_particle(b, s);
+            const double x0 = p.x;
             do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on != 0, sc);
+            if (W.imp_nx) imp_enter(W, s, x0, p.x, p.E, p.wt);
             b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
             b.ndraw[s] = p.ndraw;
             b.event[s] = p.ev;
@@ -578,40 +582,83 @@ __global__ void __launch_bounds__(WG) k_split_scatter(BankDev b, Counters *ctr)
 }
 
 // ---------------------------------------------------------------------------
+// end of a copy, and the state a step leaves in the bank
+// ---------------------------------------------------------------------------
+// The copy in slot s died with `fate`: the next pending copy of its history
+// takes the slot (alive, lookup due), or the history ends (slot free).
+template <int WWK>
+__device__ __forceinline__ void end_copy(const BankDev &b, const WwDev &W, uint32_t s, Particle &p, int32_t fate,
+                                         HistLog *log, uint64_t first_pid)
+{
+    if constexpr (WWK != WW_OFF) {
+        if (ww_pending(W, s)) {
+            ww_pop(W, s, p);
+            b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+            b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
+            b.E[s] = p.E; b.wt[s] = p.wt;
+            b.cell[s] = p.cell; b.mat[s] = p.mat; b.inside[s] = p.inside ? 1 : 0;
+            b.ncoll[s] = p.ncoll; b.ncross[s] = p.ncross;
+            b.lineage[s] = p.lineage; b.ndraw[s] = p.ndraw;
+            b.flags[s] = F_ALIVE | F_LOOKUP;
+            return;
+        }
+    }
+    b.flags[s] = 0;
+    if (log) write_log_ww(log, first_pid, p, fate, W, s);
+}
+
+// ---------------------------------------------------------------------------
 // surface crossing
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_cross(BankDev b, GeomDev g, TallyDev tal, const Counters *ctr,
-                                              HistLog *log, uint64_t first_pid, unsigned long long *lost)
+template <int WWK>
+__global__ void __launch_bounds__(WG) k_cross(BankDev b, GeomDev g, TallyDev tal, WwDev W, const Counters *ctr,
+                                              uint64_t seed, HistLog *log, uint64_t first_pid,
+                                              unsigned long long *lost)
 {
     __shared__ double gl[N_GLOBAL * WAVES];
     const uint32_t n = ctr->nX;
     const uint32_t i0 = blockIdx.x * WG;
     if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
+    const bool act = i < n;
     StepScore sc;
     clear_score(sc);
-    if (i < n) {
-        const uint32_t s = b.Qx[i];
-        Particle p = load_particle(b, s);
+    Particle p{};
+    uint32_t s = 0;
+    int32_t fate = 0;
+    bool need_lookup = false;
+    if (act) {
+        s = b.Qx[i];
+        p = load_particle(b, s);
         if (p.ev == 0xFF) {
-            b.flags[s] = 0;
+            fate = FATE_LOST;
             atomicAdd(lost, 1ull);
-            if (log) write_log(log, first_pid, p, FATE_LOST);
         } else {
-            bool need_lookup;
-            const int32_t fate = do_cross(p, g, sc, need_lookup);
-            b.ncross[s] = p.ncross;
-            if (fate) {
-                b.flags[s] = 0;
-                if (log) write_log(log, first_pid, p, fate);
-            } else {
-                b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
-                b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
-                b.cell[s] = p.cell;
-                b.inside[s] = p.inside ? 1 : 0;
-                b.mat[s] = p.mat;
-                if (need_lookup) b.flags[s] = F_ALIVE | F_LOOKUP;
+            bool leak_xhi;
+            fate = do_cross(p, g, sc, need_lookup, leak_xhi);
+            if (leak_xhi && W.imp_nx) imp_credit(W, s, p.wt);
+        }
+    }
+    if constexpr (WWK != WW_OFF) {
+        const bool chk = act && fate == 0;
+        const double ln_i = ww_ln_importance<WWK>(W, p, chk);
+        if (chk) fate = ww_check(W, s, p, ln_i, seed, sc);
+    }
+    if (act) {
+        b.ncross[s] = p.ncross;
+        if (fate) {
+            end_copy<WWK>(b, W, s, p, fate, log, first_pid);
+        } else {
+            b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+            b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
+            b.cell[s] = p.cell;
+            b.inside[s] = p.inside ? 1 : 0;
+            b.mat[s] = p.mat;
+            if constexpr (WWK != WW_OFF) {
+                b.wt[s] = p.wt;
+                b.ndraw[s] = p.ndraw;
             }
+            if (need_lookup) b.flags[s] = F_ALIVE | F_LOOKUP;
         }
     }
     wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
@@ -620,7 +667,8 @@ __global__ void __launch_bounds__(WG) k_cross(BankDev b, GeomDev g, TallyDev tal
 // ---------------------------------------------------------------------------
 // collision: analog capture or elastic scattering off a target at rest
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, TallyDev tal,
+template <int WWK>
+__global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, TallyDev tal, WwDev W,
                                                 const Counters *ctr, uint64_t seed, HistLog *log,
                                                 uint64_t first_pid)
 {
@@ -630,20 +678,32 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, 
     const uint32_t i0 = blockIdx.x * WG;
     if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
+    const bool act = i < n;
     StepScore sc;
     clear_score(sc);
-    if (i < n) {
-        const uint32_t s = b.Qc[i];
-        Particle p = load_particle(b, s);
-        const int32_t fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc);
+    Particle p{};
+    uint32_t s = 0;
+    int32_t fate = 0;
+    if (act) {
+        s = b.Qc[i];
+        p = load_particle(b, s);
+        fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc);
+        if (fate == 0 && W.imp_nx) imp_enter(W, s, p.x, p.x, p.E, p.wt);
+    }
+    if constexpr (WWK != WW_OFF) {
+        const bool chk = act && fate == 0;
+        const double ln_i = ww_ln_importance<WWK>(W, p, chk);
+        if (chk) fate = ww_check(W, s, p, ln_i, seed, sc);
+    }
+    if (act) {
         b.ncoll[s] = p.ncoll;
         b.ndraw[s] = p.ndraw;
         if (fate) {
-            b.flags[s] = 0;
-            if (log) write_log(log, first_pid, p, fate);
+            end_copy<WWK>(b, W, s, p, fate, log, first_pid);
         } else {
             b.E[s] = p.E;
             b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
+            if constexpr (WWK != WW_OFF) b.wt[s] = p.wt;
             b.flags[s] = F_ALIVE | F_LOOKUP;
         }
     }
@@ -664,12 +724,15 @@ struct TileRows {
     bool enabled;              // binned flux tallies on
 };
 
+template <int WWK>
 __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev &xs, const GeomDev &g,
-                                const TileRows &r, uint64_t seed, int64_t max_events, HistLog *log,
-                                uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl)
+                                const TileRows &r, const WwDev &W, uint32_t s, uint64_t seed, int64_t max_events,
+                                HistLog *log, uint64_t log_first_pid, unsigned long long *lost, double *slab,
+                                double *gl)
 {
     const bool binned = r.enabled && g.tally_kind != TALLY_MESH;
     const bool log_on = log != nullptr;
+    const bool imp_on = W.imp_nx != 0;
     while (__syncthreads_or(alive)) {
         StepScore sc;
         clear_score(sc);
@@ -682,22 +745,39 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
             fate = FATE_LOST;
             atomicAdd(lost, 1ull);
         } else if (alive) {
+            const double x0 = p.x;
             do_advance(p, g, seed, r.enabled, r.mesh_tl, log_on, sc);
+            if (imp_on) imp_enter(W, s, x0, p.x, p.E, p.wt);
         }
         if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
                 fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc);
                 need = fate == 0;
+                if (fate == 0 && imp_on) imp_enter(W, s, p.x, p.x, p.E, p.wt);
             } else {
-                fate = do_cross(p, g, sc, need);
+                bool leak_xhi;
+                fate = do_cross(p, g, sc, need, leak_xhi);
+                if (leak_xhi && imp_on) imp_credit(W, s, p.wt);
             }
+        }
+        if constexpr (WWK != WW_OFF) {
+            const bool chk = alive && fate == 0;
+            const double ln_i = ww_ln_importance<WWK>(W, p, chk);
+            if (chk) fate = ww_check(W, s, p, ln_i, seed, sc);
         }
         if (binned) wg_bin_add(sc.c_bin, sc.c_val, slab, r.n_bins, r.coll);
         wg_glob_add(sc.g, gl, r.glob);
         if (alive && fate != 0) {
-            alive = false;
-            if (log) write_log(log, log_first_pid, p, fate);
+            bool next = false;
+            if constexpr (WWK != WW_OFF) next = ww_pending(W, s);
+            if (next) {
+                ww_pop(W, s, p);
+                need = true;
+            } else {
+                alive = false;
+                if (log) write_log_ww(log, log_first_pid, p, fate, W, s);
+            }
         }
     }
 }
@@ -705,9 +785,10 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
 // Tail: when no history remains to start and few particles are in flight,
 // one launch finishes them (workgroup row = blockIdx.x); the histories are
 // the ones the event kernels would give.
-__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, const Counters *ctr,
-                                             uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
-                                             unsigned long long *lost)
+template <int WWK>
+__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, WwDev W,
+                                             const Counters *ctr, uint64_t seed, int64_t max_events, HistLog *log,
+                                             uint64_t first_pid, unsigned long long *lost)
 {
     extern __shared__ double slab[];
     __shared__ double gl[N_GLOBAL * WAVES];
@@ -732,7 +813,7 @@ __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, Tal
     r.mesh_coll = tal.mesh_coll;
     r.n_bins = tal.n_bins;
     r.enabled = tal.enabled != 0;
-    run_tile(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl);
+    run_tile<WWK>(p, alive, need, xs, g, r, W, s, seed, max_events, log, first_pid, lost, slab, gl);
     if (i < n) b.flags[s] = 0;
 }
 
@@ -786,6 +867,7 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
     __shared__ double gl[N_GLOBAL * WAVES];
     __shared__ uint32_t s_tile;
     const uint64_t batch = *set.batch;
+    const WwDev no_ww{};  // problem sets run analog
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(set.next_tile, 1u);
         __syncthreads();
@@ -808,7 +890,8 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
             r.n_bins = P.g.n_bins;
             r.enabled = true;
             HistLog *log = set.log ? set.log + P.log_off : nullptr;
-            run_tile(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid, set.lost, slab, gl);
+            run_tile<WW_OFF>(p, alive, true, xs, P.g, r, no_ww, 0u, P.seed, max_events, log, first_pid, set.lost,
+                             slab, gl);
         }
     }
 }
@@ -921,10 +1004,10 @@ hipError_t launch_slots_count(const BankDev &b, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, Counters *ctr, int cur,
+hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, const WwDev &W, Counters *ctr, int cur,
                               uint64_t first_pid, uint64_t n_hist, uint64_t seed, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_slots_queue, dim3(blocks_for(b.C, TILE)), dim3(WG), 0, st, b, g, ctr, cur,
+    hipLaunchKernelGGL(k_slots_queue, dim3(blocks_for(b.C, TILE)), dim3(WG), 0, st, b, g, W, ctr, cur,
                        first_pid, n_hist, seed);
     return hipGetLastError();
 }
@@ -1003,13 +1086,13 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
                           uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on,
                           hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    hipLaunchKernelGGL(k_advance, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, ctr, seed,
+    hipLaunchKernelGGL(k_advance, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, W, ctr, seed,
                        max_events, log_on);
     return hipGetLastError();
 }
@@ -1022,35 +1105,92 @@ hipError_t launch_split(const BankDev &b, Counters *ctr, uint32_t n_bound, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const Counters *ctr,
-                        uint32_t n_bound, HistLog *log, uint64_t first_pid, unsigned long long *lost,
+hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
+                        uint32_t n_bound, uint64_t seed, HistLog *log, uint64_t first_pid, unsigned long long *lost,
                         hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cross, dim3(blocks_for(n_bound, WG)), dim3(WG), 0, st, b, g, t, ctr, log,
-                       first_pid, lost);
+    const dim3 grid(blocks_for(n_bound, WG));
+    switch (W.kind) {
+    case WW_LINEAR:
+        hipLaunchKernelGGL(k_cross<WW_LINEAR>, grid, dim3(WG), 0, st, b, g, t, W, ctr, seed, log, first_pid, lost);
+        break;
+    case WW_MLP:
+        hipLaunchKernelGGL(k_cross<WW_MLP>, grid, dim3(WG), 0, st, b, g, t, W, ctr, seed, log, first_pid, lost);
+        break;
+    default:
+        hipLaunchKernelGGL(k_cross<WW_OFF>, grid, dim3(WG), 0, st, b, g, t, W, ctr, seed, log, first_pid, lost);
+        break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t,
+hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
                           const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
                           uint64_t first_pid, hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    hipLaunchKernelGGL(k_collide, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed,
-                       log, first_pid);
+    const dim3 grid(blocks_for(n_bound, WG));
+    switch (W.kind) {
+    case WW_LINEAR:
+        hipLaunchKernelGGL(k_collide<WW_LINEAR>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, log, first_pid);
+        break;
+    case WW_MLP:
+        hipLaunchKernelGGL(k_collide<WW_MLP>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, log, first_pid);
+        break;
+    default:
+        hipLaunchKernelGGL(k_collide<WW_OFF>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, log, first_pid);
+        break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
-                       uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
-                       unsigned long long *lost, hipStream_t st)
+hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
+                       const Counters *ctr, uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log,
+                       uint64_t first_pid, unsigned long long *lost, hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    hipLaunchKernelGGL(k_tail, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed, max_events,
-                       log, first_pid, lost);
+    const dim3 grid(blocks_for(n_bound, WG));
+    switch (W.kind) {
+    case WW_LINEAR:
+        hipLaunchKernelGGL(k_tail<WW_LINEAR>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, max_events, log,
+                           first_pid, lost);
+        break;
+    case WW_MLP:
+        hipLaunchKernelGGL(k_tail<WW_MLP>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, max_events, log,
+                           first_pid, lost);
+        break;
+    default:
+        hipLaunchKernelGGL(k_tail<WW_OFF>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, max_events, log,
+                           first_pid, lost);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// ln I at the source point (one lane), for the windows of the next batch
+__global__ void __launch_bounds__(WG) k_ww_source(WwDev W, GeomDev g, double *out)
+{
+    double x = g.src_pos[0], y = g.src_pos[1], z = g.src_pos[2];
+    if (g.src_kind == SRC_BOX) {
+        x = 0.5 * (g.src_box[0] + g.src_box[1]);
+        y = 0.5 * (g.src_box[2] + g.src_box[3]);
+        z = 0.5 * (g.src_box[4] + g.src_box[5]);
+    }
+    Particle p{};
+    p.x = x; p.y = y; p.z = z;
+    p.E = g.src_E;
+    double v = 0.0;
+    if (W.kind == WW_LINEAR) v = ww_ln_importance_linear(W, p);
+    else v = ww_ln_importance<WW_MLP>(W, p, threadIdx.x == 0);
+    if (threadIdx.x == 0) *out = v;
+}
+
+hipError_t launch_ww_source(const WwDev &W, const GeomDev &g, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ww_source, dim3(1), dim3(WG), 0, st, W, g, out);
     return hipGetLastError();
 }
 

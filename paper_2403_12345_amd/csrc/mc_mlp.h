@@ -126,13 +126,15 @@ __device__ inline float wave_mlp(const MlpDev &m, const float (&f)[4], uint16_t 
     return ys[lane];
 }
 
-// Importance features of a point (fp64 in, fp32 out).
-__device__ __forceinline__ void mlp_features(double x, double y, double z, double E, double L, float (&f)[4])
+// Importance features of a point, computed in FP64 and handed over as FP32:
+// (x/L, clip(y/L, -1, 1), clip(z/L, -1, 1), (ln E - ln_emin) / ln_erange).
+__device__ __forceinline__ void mlp_features(double x, double y, double z, double E, double L, double ln_emin,
+                                             double ln_erange, float (&f)[4])
 {
     f[0] = (float)(x / L);
     f[1] = (float)fmin(1.0, fmax(-1.0, y / L));
     f[2] = (float)fmin(1.0, fmax(-1.0, z / L));
-    f[3] = (float)((log(E) - log(1e-5)) / log(2e7 / 1e-5));
+    f[3] = (float)((log(E) - ln_emin) / ln_erange);
 }
 
 }  // namespace mc

@@ -259,10 +259,12 @@ __device__ inline void do_advance(Particle &p, const GeomDev &g, uint64_t seed, 
 
 // Surface crossing p.ev: lattice step (the coordinate snaps onto the plane),
 // cylinder sense, reflection or leakage at an outer face.  Returns
-// FATE_LEAKED or 0; need_lookup tells whether the material changed.
-__device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc, bool &need_lookup)
+// FATE_LEAKED or 0; need_lookup tells whether the material changed, leak_xhi
+// whether the particle leaked through the x+ face.
+__device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc, bool &need_lookup, bool &leak_xhi)
 {
     need_lookup = false;
+    leak_xhi = false;
     sc.g[G_NCROSS] += 1.0;
     p.ncross += 1;
     int32_t cell = p.cell;
@@ -307,6 +309,7 @@ __device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc,
         if (g.bc[face] == BC_VACUUM) {
             sc.g[G_LEAK] += p.wt;
             if (face == 1) {
+                leak_xhi = true;
                 sc.g[G_LEAK_XHI] += p.wt;
                 if (p.ncoll == 0) sc.g[G_LEAK_XHI_UNC] += p.wt;
             }

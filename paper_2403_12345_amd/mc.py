@@ -22,7 +22,8 @@ MC_TALLY_ENERGY, MC_TALLY_PIN, MC_TALLY_MESH, MC_TALLY_SLAB = 0, 1, 2, 3
 MC_T_FLUX_TRACK, MC_T_FLUX_COLLISION, MC_T_GLOBAL = 0, 1, 2
 (MC_G_TRACK, MC_G_COLL_EST, MC_G_ABSORB, MC_G_CUTOFF, MC_G_LEAK, MC_G_TRACK_ABS, MC_G_NCOLL,
  MC_G_NCROSS, MC_G_LEAK_XHI, MC_G_LEAK_XHI_UNC, MC_G_SPLIT, MC_G_ROULETTE, MC_N_GLOBAL) = range(13)
-MC_FATE_ABSORBED, MC_FATE_CUTOFF, MC_FATE_LEAKED, MC_FATE_LOST = 1, 2, 3, 4
+MC_FATE_ABSORBED, MC_FATE_CUTOFF, MC_FATE_LEAKED, MC_FATE_LOST, MC_FATE_ROULETTE = 1, 2, 3, 4, 5
+MC_WW_OFF, MC_WW_LINEAR, MC_WW_MLP = 0, 1, 2
 
 _STATUS = {MC_EINVAL: "MC_EINVAL", MC_ENOMEM: "MC_ENOMEM", MC_EHIP: "MC_EHIP", MC_ELOST: "MC_ELOST",
            MC_ESTATE: "MC_ESTATE", MC_ENODEV: "MC_ENODEV"}
@@ -89,6 +90,12 @@ class mc_set_opts(C.Structure):
                 ("history_log", C.c_void_p)]
 
 
+class mc_ww_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_max", C.c_int32), ("depth", C.c_int32), ("imp_nx", C.c_int32),
+                ("imp_ne", C.c_int32), ("reserved", C.c_int32), ("lin", C.c_double * 3), ("length", C.c_double),
+                ("kappa", C.c_double), ("ratio", C.c_double), ("imp_x0", C.c_double), ("imp_x1", C.c_double)]
+
+
 class mc_tally_meta(C.Structure):
     _fields_ = [("n_batches", C.c_uint64), ("n_bins", C.c_uint64), ("histories", C.c_uint64)]
 
@@ -141,6 +148,8 @@ def load():
         "mc_mlp_forward": ([V, SZ, V, V], C.c_int),
         "mc_mlp_grad": ([V, SZ, V, V, V, P(C.c_float), P(C.c_float)], C.c_int),
         "mc_mlp_train": ([V, SZ, V, V, V, I32, C.c_float, P(C.c_float)], C.c_int),
+        "mc_set_weight_windows": ([V, P(mc_ww_desc)], C.c_int),
+        "mc_get_importance": ([V, P(D), P(D), P(D), SZ], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -391,6 +400,24 @@ def mc_mlp_train(ctx, n: int, features, target, weight, steps: int, lr: float) -
     _check(ctx, load().mc_mlp_train(ctx, int(n), _ptr(features), _ptr(target), _ptr(weight), int(steps),
                                     float(lr), _fp(curve)))
     return curve
+
+
+def mc_set_weight_windows(ctx, kind=MC_WW_OFF, lin=(0.0, 0.0, 0.0), length=200.0, kappa=3.0, ratio=5.0,
+                          n_max=10, depth=24, imp_nx=0, imp_ne=0, imp_x0=0.0, imp_x1=200.0):
+    d = mc_ww_desc()
+    d.kind, d.n_max, d.depth = int(kind), int(n_max), int(depth)
+    d.imp_nx, d.imp_ne = int(imp_nx), int(imp_ne)
+    d.lin = (C.c_double * 3)(*[float(v) for v in lin])
+    d.length, d.kappa, d.ratio = float(length), float(kappa), float(ratio)
+    d.imp_x0, d.imp_x1 = float(imp_x0), float(imp_x1)
+    _check(ctx, load().mc_set_weight_windows(ctx, C.byref(d)))
+
+
+def mc_get_importance(ctx, n_cells: int):
+    """Returns (num, den, cnt), each [n_cells] float64."""
+    num, den, cnt = np.zeros(n_cells), np.zeros(n_cells), np.zeros(n_cells)
+    _check(ctx, load().mc_get_importance(ctx, _dp(num), _dp(den), _dp(cnt), int(n_cells)))
+    return num, den, cnt
 
 
 def mc_get_tuning(ctx) -> dict:

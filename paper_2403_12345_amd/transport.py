@@ -77,10 +77,31 @@ class Transport:
             desc, keep = geometry_desc(prob)
             mc.mc_init_geometry(self.ctx, desc)
             del keep
+            self.set_weight_windows(getattr(prob, "ww", None), getattr(prob, "imp", None))
         except Exception:
             mc.mc_destroy(self.ctx)
             raise
         self.n_bins = prob.n_bins
+
+    def set_weight_windows(self, ww=None, imp=None):
+        """Weight windows (an object with the attributes of mcsynth.WeightWindows)
+        and the importance grid (mcsynth.ImportanceGrid); the network of an
+        MLP window is loaded into the context first."""
+        kind = ww.kind if ww is not None else mc.MC_WW_OFF
+        if kind == mc.MC_WW_MLP:
+            mc.mc_mlp_set(self.ctx, ww.mlp)
+        kw = {}
+        if ww is not None:
+            kw.update(kind=kind, lin=ww.lin, length=ww.length, kappa=ww.kappa, ratio=ww.ratio, n_max=ww.n_max,
+                      depth=ww.depth)
+        if imp is not None and imp.nx > 0:
+            kw.update(imp_nx=imp.nx, imp_ne=imp.ne, imp_x0=imp.x0, imp_x1=imp.x1)
+        mc.mc_set_weight_windows(self.ctx, **kw)
+        self.n_imp_cells = imp.nx * imp.ne if imp is not None else 0
+
+    def importance(self):
+        """(num, den, cnt) of the importance grid, [3, cells]."""
+        return np.stack(mc.mc_get_importance(self.ctx, self.n_imp_cells))
 
     def run_batch(self, seed, first_pid, n, **opts):
         mc.mc_run_batch(self.ctx, seed, first_pid, n, run_opts(**opts))

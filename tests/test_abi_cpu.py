@@ -34,6 +34,7 @@ def test_struct_sizes_match_header_layout():
     assert mc.HISTORY_DTYPE.itemsize == 48
     assert ctypes.sizeof(mc.mc_run_opts) == 48
     assert ctypes.sizeof(mc.mc_stats) == 8 * 10
+    assert ctypes.sizeof(mc.mc_ww_desc) == 6 * 4 + 8 * 8
 
 
 def _header_enum(name):
@@ -43,7 +44,8 @@ def _header_enum(name):
 
 def test_binding_constants_match_header_and_oracle():
     import oracle
-    for k in ("MC_G_LEAK_XHI", "MC_G_SPLIT", "MC_G_ROULETTE", "MC_N_GLOBAL", "MC_MLP_NPAR"):
+    for k in ("MC_G_LEAK_XHI", "MC_G_SPLIT", "MC_G_ROULETTE", "MC_N_GLOBAL", "MC_MLP_NPAR", "MC_FATE_ROULETTE",
+              "MC_WW_LINEAR", "MC_WW_MLP"):
         assert getattr(mc, k) == _header_enum(k), k
     assert mc.MC_N_GLOBAL == oracle.N_GLOBAL
     assert mc.MC_G_SPLIT == oracle.G_SPLIT and mc.MC_G_ROULETTE == oracle.G_ROULETTE
