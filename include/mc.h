@@ -504,6 +504,9 @@ typedef struct {
     double kappa;          /* w_L at the source point is 1 / kappa, > 0                   */
     double ratio;          /* w_U / w_L, > 1                                               */
     double imp_x0, imp_x1; /* x range of the importance grid                              */
+    double ln_lo, ln_hi;   /* ln I (either kind, the source point too) is clamped to
+                              [ln_lo, ln_hi] when ln_lo < ln_hi: a fitted map is trusted
+                              over the span of its targets only                           */
 } mc_ww_desc;
 
 /* Configure (or, with NULL or kind MC_WW_OFF and imp_nx 0, remove) the
@@ -519,6 +522,51 @@ int mc_set_weight_windows(mc_ctx *ctx, const mc_ww_desc *desc);
  * host arrays of n_cells = imp_nx * imp_ne doubles (each may be NULL).
  * Errors: MC_ESTATE (no grid), MC_EINVAL (n_cells). */
 int mc_get_importance(mc_ctx *ctx, double *num, double *den, double *cnt, size_t n_cells);
+
+/*
+ * Training the network on the forward importance estimate.
+ *
+ * Samples: every cell of the importance grid with at least min_credits
+ * detector credits (cnt) gives `replicas` samples, cells in index order
+ * (e * nx + x): features (x centre / length, f_y, f_z, (e + 1/2) / ne), target
+ * ln(num / den), weight 1 / (1 / cnt + rel_floor^2) (the inverse relative
+ * variance of the ratio, floored).  The slab is invariant in y and z, so f_y
+ * and f_z are drawn uniform on [-1, 1]: draws 2r and 2r + 1 of the Philox
+ * stream (key seed, pid = cell, lineage 0x5EED0002).
+ */
+typedef struct {
+    int32_t steps;      /* Adam steps, >= 1                                   */
+    int32_t replicas;   /* samples per cell, 1..64                            */
+    float lr;           /* Adam learning rate, > 0                            */
+    float pad;
+    double min_credits; /* cells with fewer credits are left out, >= 1        */
+    double rel_floor;   /* relative-error floor of the weights, >= 0          */
+    double length;      /* feature scale (cm), the windows' length            */
+    uint64_t seed;      /* Philox key of the (f_y, f_z) draws                 */
+} mc_train_opts;
+
+/* Initial network: W1 ~ U(-1/2, 1/2), W2 and w3 ~ U(-1/8, 1/8), biases 0
+ * (parameter j is 2u - 1 scaled, u draw 0 of pid j, lineage 0x5EED0001 of
+ * key seed); Adam state reset. */
+int mc_mlp_init(mc_ctx *ctx, uint64_t seed);
+
+/* Training samples from host importance sums num, den, cnt [ne][nx] (x-bins
+ * over [x0, x1)) into caller-owned device arrays features [nx ne replicas][4],
+ * target and weight [nx ne replicas]; *n_samples (host) receives the count.
+ * Errors: MC_EINVAL. */
+int mc_importance_samples(mc_ctx *ctx, const double *num, const double *den, const double *cnt, int32_t nx,
+                          int32_t ne, double x0, double x1, const mc_train_opts *opts, float *features,
+                          float *target, float *weight, int32_t *n_samples);
+
+/* Build the samples from the context's importance sums (mc_set_weight_windows
+ * grid, accumulated by mc_run_batch) on the device and train the context's
+ * network on them (opts->steps full-batch Adam steps, as mc_mlp_train).
+ * loss_curve (host, steps floats), n_samples and target_range (host, the
+ * smallest and largest target: the span to clamp the windows' ln I to) may be
+ * NULL.  Synchronous.  Errors: MC_ESTATE (no network, no grid, or no cell with
+ * enough credits), MC_EINVAL. */
+int mc_importance_train(mc_ctx *ctx, const mc_train_opts *opts, float *loss_curve, int32_t *n_samples,
+                        float *target_range);
 
 /* Library version string. */
 const char *mc_version(void);

@@ -105,7 +105,8 @@ class WeightWindows:
     features (``lin`` = c0, c1, c2 for c0 + c1 x/L + c2 (ln E - ln 1e-5)/ln(2e12))
     or the importance network (``mlp``: its 4545 parameters, W1[4][64], b1,
     W2[64][64], b2, w3[64], b3 in that order, row-major).  Window at a point:
-    w_L = exp(ln I_src - ln I) / kappa, w_U = ratio w_L."""
+    w_L = exp(ln I_src - ln I) / kappa, w_U = ratio w_L; ln I is clamped to
+    [ln_lo, ln_hi] when ln_lo < ln_hi."""
     kind: int = WW_OFF
     lin: tuple = (0.0, 0.0, 0.0)
     mlp: Optional[np.ndarray] = None
@@ -114,6 +115,8 @@ class WeightWindows:
     ratio: float = 5.0
     n_max: int = 10
     depth: int = 24
+    ln_lo: float = 0.0
+    ln_hi: float = 0.0
 
 
 @dataclass
@@ -414,6 +417,40 @@ def c4_problem_set(data_seed: int = 4004, seed: int = 4, n_problems: int = 64,
                                  tally=Tally(TALLY_ENERGY, energy_edges(50)), histories=hist, batches=1,
                                  seed=key))
     return probs
+
+
+def c5_problem(data_seed: int = 5005, seed: int = 5, histories: int = 10_000_000, batches: int = 20,
+               thickness=(100.0, 10.0, 90.0), sigma_t=(0.2, 1.5, 0.2), capture_ratio=(0.005, 0.01, 0.005),
+               generator_capture_scale: float = 0.01,
+               awr=((56.0, 90.0, 120.0), (184.0, 207.0, 238.0, 56.0), (12.0, 56.0, 120.0)),
+               grid_range=(5_000, 20_000)) -> Problem:
+    """Deep-penetration slab, x in [0, 200] cm, infinite in y and z: three layers of synthetic
+    absorber/scatterer, 100 / 10 / 90 cm thick with Sigma_t(2 MeV) = 0.2 / 1.5 / 0.2 per cm
+    (a heavy scatterer, a dense shield, a scatterer with a light component), 53 mean free
+    paths at the source energy.  Each layer mixes synthetic nuclides (clustered grids of
+    U[5k, 20k] points) whose generated capture is scaled by generator_capture_scale and
+    raised by a constant so that capture is capture_ratio[k] of each nuclide's cross
+    section at 2 MeV.  With these defaults the analog transmission is about 4e-5 (a few
+    hundred scoring histories in 1e7).  A normally incident 2 MeV beam enters at x = 0;
+    both x faces are vacuum (the detector is the weight leaking through x = 200); flux
+    tally per layer."""
+    rng = np.random.default_rng(data_seed)
+    nucs, mats = [], []
+    for k in range(3):
+        first = len(nucs)
+        for a in awr[k]:
+            nuc = make_nuclide(rng, float(a), int(rng.integers(grid_range[0], grid_range[1] + 1)), "clustered")
+            st2 = _analytic_sigma_t(nuc, SOURCE_ENERGY)
+            p = float(capture_ratio[k])
+            nuc.sig_c = generator_capture_scale * nuc.sig_c + p / (1.0 - p) * st2
+            nucs.append(nuc)
+        mats.append(make_material(rng, nucs, np.arange(first, len(nucs)), sigma_t[k], density_range=(1e-4, 1e-2)))
+    edges = np.concatenate([[0.0], np.cumsum(thickness)]).astype(np.float64)
+    geom = Geometry(kind=GEOM_SLAB, x_edges=edges, layer_material=np.arange(3, dtype=np.int32),
+                    bc=(BC_VACUUM, BC_VACUUM, BC_REFLECT, BC_REFLECT, BC_REFLECT, BC_REFLECT))
+    return Problem(name="c5_deep_penetration_slab", nuclides=nucs, materials=mats, geometry=geom,
+                   source=Source(kind=SRC_BEAM, position=(0.0, 0.0, 0.0), direction=(1.0, 0.0, 0.0)),
+                   tally=Tally(TALLY_SLAB), histories=histories, batches=batches, seed=seed)
 
 
 def lookup_energies(rng, n: int) -> np.ndarray:

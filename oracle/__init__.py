@@ -12,6 +12,7 @@ forms batch statistics.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -61,6 +62,7 @@ class _Problem(C.Structure):
         ("ww_length", C.c_double), ("ww_kappa", C.c_double), ("ww_ratio", C.c_double),
         ("ww_nmax", C.c_int32), ("ww_depth", C.c_int32),
         ("imp_nx", C.c_int32), ("imp_ne", C.c_int32), ("imp_x0", C.c_double), ("imp_x1", C.c_double),
+        ("ww_ln_lo", C.c_double), ("ww_ln_hi", C.c_double),
     ]
 
 
@@ -172,6 +174,7 @@ class OracleProblem:
         c.ww_mlp = _dptr(self.ww_mlp)
         c.ww_length, c.ww_kappa, c.ww_ratio = ww.length, ww.kappa, ww.ratio
         c.ww_nmax, c.ww_depth = ww.n_max, ww.depth
+        c.ww_ln_lo, c.ww_ln_hi = ww.ln_lo, ww.ln_hi
         c.imp_nx, c.imp_ne, c.imp_x0, c.imp_x1 = prob.imp.nx, prob.imp.ne, prob.imp.x0, prob.imp.x1
         self.c = c
         self.n_cells = prob.imp.cells
@@ -280,6 +283,38 @@ def child_lineage(a: int, s: int, k: int) -> int:
 
 def ln_importance_source(op: OracleProblem) -> float:
     return float(lib().orc_ln_importance_source(op.ref()))
+
+
+IMP_SAMPLE_LINEAGE = 0x5EED0002
+
+
+def importance_samples(num, den, cnt, nx: int, ne: int, x0: float, x1: float, length: float, replicas: int,
+                       min_credits: float, rel_floor: float, seed: int):
+    """Training samples of the importance network from forward importance sums
+    (cells e * nx + x, in index order).  A cell with at least ``min_credits``
+    detector credits and positive sums gives ``replicas`` samples: features
+    (x centre / length, f_y, f_z, (e + 1/2) / ne) with f_y, f_z = 2u - 1 from
+    draws 2r and 2r + 1 of the Philox stream (seed, pid = cell, lineage
+    IMP_SAMPLE_LINEAGE), target ln(num / den) (the forward estimate of the
+    importance), weight 1 / (1 / cnt + rel_floor^2) (its inverse relative
+    variance, floored).  Returns float32 arrays X [n, 4], T [n], W [n]."""
+    X, T, W = [], [], []
+    for g in range(nx * ne):
+        if not (cnt[g] >= min_credits and num[g] > 0.0 and den[g] > 0.0):
+            continue
+        ix, e = g % nx, g // nx
+        xc = x0 + (x1 - x0) * (ix + 0.5) / nx
+        fx = np.float32(xc / length)
+        fe = np.float32((e + 0.5) / ne)
+        tg = np.float32(math.log(num[g] / den[g]))
+        wt = np.float32(1.0 / (1.0 / cnt[g] + rel_floor * rel_floor))
+        for r in range(replicas):
+            uy = uniform(seed, IMP_SAMPLE_LINEAGE, g, 2 * r)
+            uz = uniform(seed, IMP_SAMPLE_LINEAGE, g, 2 * r + 1)
+            X.append([fx, np.float32(2.0 * uy - 1.0), np.float32(2.0 * uz - 1.0), fe])
+            T.append(tg)
+            W.append(wt)
+    return (np.array(X, np.float32).reshape(-1, 4), np.array(T, np.float32), np.array(W, np.float32))
 
 
 @dataclass

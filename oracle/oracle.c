@@ -98,12 +98,17 @@ typedef struct {
     double ww_kappa;         /* w_L at the source point = 1 / kappa */
     double ww_ratio;         /* w_U / w_L */
     int32_t ww_nmax;         /* most copies of one split */
-    int32_t ww_depth;        /* most pending split records per history */
+    int32_t ww_depth;        /* most split generations of a copy (a copy made by g splits
+                                along its line splits no further once g reaches it) */
     /* importance generation (forward estimate on an x by ln E grid) */
     int32_t imp_nx, imp_ne;
     double imp_x0, imp_x1;
+    double ww_ln_lo, ww_ln_hi; /* ln I is clamped to [lo, hi] (no clamp when lo >= hi) */
 } orc_problem;
 
+/* One history: fate, final energy and weight of the source particle's own
+ * copy (lineage 0); collisions, crossings, draws and path length summed over
+ * the source particle and all its weight-window copies. */
 typedef struct {
     int32_t fate, n_coll, n_cross, pad;
     uint64_t n_draws;
@@ -562,10 +567,13 @@ static void ww_features(const orc_problem *p, const double r[3], double E, doubl
 
 static double ln_importance(const orc_problem *p, const double r[3], double E)
 {
-    double f[4];
+    double f[4], v;
     ww_features(p, r, E, f);
-    if (p->ww_kind == WW_LINEAR) return p->ww_lin[0] + p->ww_lin[1] * f[0] + p->ww_lin[2] * f[3];
-    return orc_mlp_forward(p->ww_mlp, f);
+    if (p->ww_kind == WW_LINEAR) v = p->ww_lin[0] + p->ww_lin[1] * f[0] + p->ww_lin[2] * f[3];
+    else v = orc_mlp_forward(p->ww_mlp, f);
+    /* a map is trusted over the span it was fitted on */
+    if (p->ww_ln_lo < p->ww_ln_hi) v = fmin(fmax(v, p->ww_ln_lo), p->ww_ln_hi);
+    return v;
 }
 
 /* Lineage of split copy k (1..n-1) of split number s of a particle of
@@ -623,6 +631,7 @@ typedef struct {
     particle q;
     rng_stream rs;
     uint32_t splits;     /* split events of this copy (numbers its children) */
+    uint32_t gen;        /* splits along the line from the source particle to this copy */
     uint64_t seen[IMP_MAX_WORDS];
 } copy_state;
 
@@ -691,7 +700,8 @@ static int weight_window(const orc_problem *p, copy_state *c, double ln_src, spl
     if (w > uw) {
         int32_t n = (int32_t)ceil(w / uw);
         if (n > p->ww_nmax) n = p->ww_nmax;
-        if (n >= 2 && *depth < p->ww_depth) {
+        if (n >= 2 && c->gen < (uint32_t)p->ww_depth) {
+            c->gen += 1; /* the copy that goes on and its n - 1 siblings */
             c->q.w = w / (double)n;
             split_record *r = &stack[(*depth)++];
             r->proto = *c;
@@ -729,7 +739,8 @@ static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, sco
     c.rs.pid = pid;
     sample_source(p, &c.q, &c.rs);
     if (den) imp_enter(p, &c, c.q.r[0], c.q.r[0], c.q.E, den);
-    int fate = FATE_ALIVE;
+    int fate = FATE_ALIVE, fate0 = FATE_ALIVE;
+    double E0 = 0.0, w0 = 0.0;
     double track = 0.0;
     int64_t n_coll = 0, n_cross = 0;
     uint64_t n_draws = 0;
@@ -820,6 +831,13 @@ static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, sco
         n_coll += c.q.n_coll;
         n_cross += c.q.n_cross;
         n_draws += c.rs.n;
+        if (c.rs.lineage == 0) {
+            /* the source particle's own copy (it keeps lineage 0 through its
+             * splits) ends first: its fate, energy and weight are the record's */
+            fate0 = fate;
+            E0 = c.q.E;
+            w0 = c.q.w;
+        }
         if (depth == 0) break;
         {
             /* next pending copy: fresh stream of its own lineage */
@@ -838,13 +856,13 @@ static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, sco
         }
     }
     if (h) {
-        h->fate = fate;
+        h->fate = fate0;
         h->n_coll = (int32_t)n_coll;
         h->n_cross = (int32_t)n_cross;
         h->n_draws = n_draws;
-        h->E_final = c.q.E;
+        h->E_final = E0;
         h->track = track;
-        h->weight = c.q.w;
+        h->weight = w0;
     }
 }
 

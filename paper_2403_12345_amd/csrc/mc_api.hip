@@ -121,6 +121,11 @@ struct mc_ctx {
     uint32_t ww_cap = 0;
     double *ln_src = nullptr;          // device scalar
     double *imp_num = nullptr, *imp_den = nullptr, *imp_cnt = nullptr;
+    Buffers imp_sample_bufs;           // training samples built from the sums
+    size_t imp_sample_cap = 0;
+    float *imp_X = nullptr, *imp_T = nullptr, *imp_W = nullptr;
+    int32_t *imp_n = nullptr;
+    float *imp_range = nullptr;
 };
 
 static MlpDev mlp_dev(const mc_ctx *ctx)
@@ -259,6 +264,7 @@ void mc_destroy(mc_ctx *ctx)
     ctx->mlp_scratch_bufs.release();
     ctx->ww_bufs.release();
     ctx->imp_bufs.release();
+    ctx->imp_sample_bufs.release();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -771,12 +777,27 @@ static int ensure_ww(mc_ctx *ctx, uint32_t cap)
             for (uint32_t **q : uu)
                 if (!rc) rc = dalloc(ctx, B, q, nrec);
             if (!rc) rc = dalloc(ctx, B, &w.sinside, nrec);
+            if (!rc) rc = dalloc(ctx, B, &w.sgen, nrec);
             if (!rc) rc = dalloc(ctx, B, &w.depth_of, cap);
             if (!rc) rc = dalloc(ctx, B, &w.splits, cap);
-            if (!rc) rc = dalloc(ctx, B, &w.hcoll, cap);
-            if (!rc) rc = dalloc(ctx, B, &w.hcross, cap);
-            if (!rc) rc = dalloc(ctx, B, &w.hdraw, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.gen, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.inh_coll, cap);
+            if (!rc) rc = dalloc(ctx, B, &w.inh_cross, cap);
             if (!rc && imp) rc = dalloc(ctx, B, &w.siv, nrec * (size_t)d.imp_ne);
+            // copy bank: twice the slots
+            const size_t Q = std::max<size_t>((size_t)2 * cap, 256);
+            double **qd[] = {&w.qx, &w.qy, &w.qz, &w.qu, &w.qv, &w.qw, &w.qE, &w.qwt};
+            for (double **q : qd)
+                if (!rc) rc = dalloc(ctx, B, q, Q);
+            int32_t **qi[] = {&w.qcell, &w.qmat, &w.qncoll, &w.qncross};
+            for (int32_t **q : qi)
+                if (!rc) rc = dalloc(ctx, B, q, Q);
+            if (!rc) rc = dalloc(ctx, B, &w.qinside, Q);
+            if (!rc) rc = dalloc(ctx, B, &w.qgen, Q);
+            if (!rc) rc = dalloc(ctx, B, &w.qlin, Q);
+            if (!rc) rc = dalloc(ctx, B, &w.qpid, Q);
+            if (!rc && imp) rc = dalloc(ctx, B, &w.qiv, Q * (size_t)d.imp_ne);
+            w.Q = (uint32_t)Q;
         }
         if (!rc && imp) rc = dalloc(ctx, B, &w.iv, (size_t)cap * (size_t)d.imp_ne);
         if (rc) {
@@ -799,6 +820,8 @@ static int ensure_ww(mc_ctx *ctx, uint32_t cap)
     w.ratio = d.ratio;
     w.ln_emin = std::log(1e-5);
     w.ln_erange = std::log(2e7 / 1e-5);
+    w.ln_lo = d.ln_lo;
+    w.ln_hi = d.ln_hi;
     w.ln_src = ctx->ln_src;
     w.C = cap;
     w.imp_nx = d.imp_nx;
@@ -826,7 +849,10 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     if (opts_in) opts = *opts_in;
     uint64_t cap64 = opts.in_flight ? opts.in_flight
                                     : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight : kDefaultInFlight);
-    cap64 = std::min(cap64, n);
+    // analog: no more slots than histories; with weight windows the copies
+    // of split particles take free slots too
+    const bool windows = ctx->ww_desc.kind != MC_WW_OFF;
+    if (!windows || opts.in_flight) cap64 = std::min(cap64, n);
     if (cap64 > (1ull << 30)) return fail(ctx, MC_EINVAL, "in_flight above 2^30");
     const uint64_t sort_min = opts.sort_min ? opts.sort_min
                                             : (ctx->tune.sort_min > 0 ? (uint64_t)ctx->tune.sort_min : kDefaultSortMin);
@@ -855,6 +881,11 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         HIPCHK(launch_fill_f64(tal.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
     }
     HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->ctr), 2 * sizeof(Counters) / 4, 0u, st));
+    // with windows, copies add into their history's record: it starts zeroed
+    if (log && W.kind != WW_OFF) HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(log), n * sizeof(HistLog) / 4, 0u, st));
+    // every slot's stack starts empty (the flush reads the depth of all slots,
+    // also of slots that never held a particle)
+    if (W.kind != WW_OFF) HIPCHK(launch_fill_u8(W.depth_of, cap, 0, st));
     HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->dstat), 8, 0u, st));
 
     mc_stats s{};
@@ -875,14 +906,15 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         HIPCHK(hipStreamSynchronize(st));
         const Counters c = ctx->ctr_host[cur];
         if (c.nA == 0) {
-            if (c.issued != n) return fail(ctx, MC_EHIP, "event loop ended before every history was issued");
+            if (c.issued != n || c.top != 0)
+                return fail(ctx, MC_EHIP, "event loop ended before every history (and copy) was run");
             break;
         }
         Counters *dc = ctx->ctr + cur;
         const int64_t tail = tail_particles(ctx);
-        if (tail > 0 && c.issued == n && (int64_t)c.nA <= tail) {
+        if (tail > 0 && W.kind == WW_OFF && W.imp_nx == 0 && c.issued == n && (int64_t)c.nA <= tail) {
             // every history has started and few remain: finish them in one launch
-            HIPCHK(launch_tail(b, ctx->xs, g, tal, W, dc, c.nA, seed, max_events, log, first_pid, ctx->dstat + 1, st));
+            HIPCHK(launch_tail(b, ctx->xs, g, tal, dc, c.nA, seed, max_events, log, first_pid, ctx->dstat + 1, st));
             s.tail_particles = c.nA;
             ++it;
             break;
@@ -926,6 +958,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         HIPCHK(launch_split(b, dc, c.nA, st));
         HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
         HIPCHK(launch_collide(b, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
+        if (W.kind != WW_OFF) HIPCHK(launch_ww_flush(b, W, dc, st));
     }
     // batch statistics: per-workgroup rows summed in a fixed order
     const double inv_n = 1.0 / (double)n;
@@ -1530,29 +1563,26 @@ int mc_autotune_problem_set(mc_ctx *ctx, const char *cache_path, mc_tuning *best
 // ---------------------------------------------------------------------------
 // importance network
 // ---------------------------------------------------------------------------
-int mc_mlp_set(mc_ctx *ctx, const float *params)
+static int mlp_alloc(mc_ctx *ctx)
 {
-    if (!ctx || !params) return MC_EINVAL;
-    for (int j = 0; j < MLP_NPAR; ++j)
-        if (!std::isfinite(params[j])) return fail(ctx, MC_EINVAL, "mc_mlp_set: parameter " + std::to_string(j) + " not finite");
-    HIPCHK(hipSetDevice(ctx->device));
-    if (!ctx->have_mlp) {
-        Buffers &B = ctx->mlp_bufs;
-        int rc = dalloc(ctx, B, &ctx->theta, MLP_NPAR);
-        if (!rc) rc = dalloc(ctx, B, &ctx->mom, MLP_NPAR);
-        if (!rc) rc = dalloc(ctx, B, &ctx->vel, MLP_NPAR);
-        if (!rc) rc = dalloc(ctx, B, &ctx->grad, MLP_NPAR + 1);
-        if (!rc) rc = dalloc(ctx, B, &ctx->inv_wsum, 1);
-        if (!rc) rc = dalloc(ctx, B, &ctx->W1b, 256);
-        if (!rc) rc = dalloc(ctx, B, &ctx->W2b, 4096);
-        if (!rc) rc = dalloc(ctx, B, &ctx->W2tb, 4096);
-        if (!rc) rc = dalloc(ctx, B, &ctx->w3b, 64);
-        if (rc) {
-            B.release();
-            return rc;
-        }
-    }
-    HIPCHK(hipMemcpyAsync(ctx->theta, params, MLP_NPAR * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->have_mlp) return MC_OK;
+    Buffers &B = ctx->mlp_bufs;
+    int rc = dalloc(ctx, B, &ctx->theta, MLP_NPAR);
+    if (!rc) rc = dalloc(ctx, B, &ctx->mom, MLP_NPAR);
+    if (!rc) rc = dalloc(ctx, B, &ctx->vel, MLP_NPAR);
+    if (!rc) rc = dalloc(ctx, B, &ctx->grad, MLP_NPAR + 1);
+    if (!rc) rc = dalloc(ctx, B, &ctx->inv_wsum, 1);
+    if (!rc) rc = dalloc(ctx, B, &ctx->W1b, 256);
+    if (!rc) rc = dalloc(ctx, B, &ctx->W2b, 4096);
+    if (!rc) rc = dalloc(ctx, B, &ctx->W2tb, 4096);
+    if (!rc) rc = dalloc(ctx, B, &ctx->w3b, 64);
+    if (rc) B.release();
+    return rc;
+}
+
+// Adam state to zero and the BF16 copies from the FP32 parameters.
+static int mlp_reset_state(mc_ctx *ctx)
+{
     HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->mom), MLP_NPAR, 0u, ctx->stream));
     HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->vel), MLP_NPAR, 0u, ctx->stream));
     HIPCHK(launch_mlp_sync(ctx->theta, ctx->W1b, ctx->W2b, ctx->W2tb, ctx->w3b, ctx->stream));
@@ -1560,6 +1590,18 @@ int mc_mlp_set(mc_ctx *ctx, const float *params)
     ctx->mlp_step = 0;
     ctx->have_mlp = true;
     return MC_OK;
+}
+
+int mc_mlp_set(mc_ctx *ctx, const float *params)
+{
+    if (!ctx || !params) return MC_EINVAL;
+    for (int j = 0; j < MLP_NPAR; ++j)
+        if (!std::isfinite(params[j])) return fail(ctx, MC_EINVAL, "mc_mlp_set: parameter " + std::to_string(j) + " not finite");
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = mlp_alloc(ctx);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->theta, params, MLP_NPAR * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    return mlp_reset_state(ctx);
 }
 
 int mc_mlp_get(mc_ctx *ctx, float *params)
@@ -1625,14 +1667,9 @@ int mc_mlp_grad(mc_ctx *ctx, size_t n, const float *features, const float *targe
     return MC_OK;
 }
 
-int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
-                 int32_t steps, float lr, float *loss_curve)
+static int mlp_train_loop(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
+                          int32_t steps, float lr, float *loss_curve)
 {
-    if (!ctx) return MC_EINVAL;
-    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_mlp_train: no network (mc_mlp_set first)");
-    if (n == 0 || n >= (1ull << 24) || !features || !target || !weight || steps < 1 || !(lr > 0.0f))
-        return fail(ctx, MC_EINVAL, "mc_mlp_train: bad arguments");
-    HIPCHK(hipSetDevice(ctx->device));
     int rc = mlp_scratch(ctx, n, steps);
     if (rc) return rc;
     hipStream_t st = ctx->stream;
@@ -1651,6 +1688,138 @@ int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *targ
     return MC_OK;
 }
 
+int mc_mlp_train(mc_ctx *ctx, size_t n, const float *features, const float *target, const float *weight,
+                 int32_t steps, float lr, float *loss_curve)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_mlp_train: no network (mc_mlp_set first)");
+    if (n == 0 || n >= (1ull << 24) || !features || !target || !weight || steps < 1 || !(lr > 0.0f))
+        return fail(ctx, MC_EINVAL, "mc_mlp_train: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    return mlp_train_loop(ctx, n, features, target, weight, steps, lr, loss_curve);
+}
+
+int mc_mlp_init(mc_ctx *ctx, uint64_t seed)
+{
+    if (!ctx) return MC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = mlp_alloc(ctx);
+    if (rc) return rc;
+    HIPCHK(launch_mlp_init(ctx->theta, seed, ctx->stream));
+    return mlp_reset_state(ctx);
+}
+
+static int imp_sample_args(mc_ctx *ctx, const mc_train_opts *o, int32_t nx, int32_t ne, double x0, double x1,
+                           ImpSampleArgs &a, const std::string &who)
+{
+    if (!o) return fail(ctx, MC_EINVAL, who + ": options required");
+    if (o->replicas < 1 || o->replicas > 64) return fail(ctx, MC_EINVAL, who + ": replicas outside [1, 64]");
+    if (!(o->min_credits >= 1.0) || !(o->rel_floor >= 0.0) || !(o->length > 0.0))
+        return fail(ctx, MC_EINVAL, who + ": need min_credits >= 1, rel_floor >= 0, length > 0");
+    if (nx < 1 || ne < 1 || (int64_t)nx * ne > (1 << 20) || !(x1 > x0))
+        return fail(ctx, MC_EINVAL, who + ": bad importance grid");
+    a.nx = nx;
+    a.ne = ne;
+    a.x0 = x0;
+    a.x1 = x1;
+    a.length = o->length;
+    a.replicas = o->replicas;
+    a.min_credits = o->min_credits;
+    a.rel_floor = o->rel_floor;
+    a.seed = o->seed;
+    return MC_OK;
+}
+
+int mc_importance_samples(mc_ctx *ctx, const double *num, const double *den, const double *cnt, int32_t nx,
+                          int32_t ne, double x0, double x1, const mc_train_opts *opts, float *features,
+                          float *target, float *weight, int32_t *n_samples)
+{
+    if (!ctx) return MC_EINVAL;
+    ImpSampleArgs a{};
+    int rc = imp_sample_args(ctx, opts, nx, ne, x0, x1, a, "mc_importance_samples");
+    if (rc) return rc;
+    if (!num || !den || !cnt || !features || !target || !weight || !n_samples)
+        return fail(ctx, MC_EINVAL, "mc_importance_samples: NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t cells = (size_t)nx * (size_t)ne;
+    Buffers tmp;
+    double *d_num = nullptr, *d_den = nullptr, *d_cnt = nullptr;
+    int32_t *d_n = nullptr;
+    rc = upload(ctx, tmp, &d_num, num, cells);
+    if (!rc) rc = upload(ctx, tmp, &d_den, den, cells);
+    if (!rc) rc = upload(ctx, tmp, &d_cnt, cnt, cells);
+    if (!rc) rc = dalloc(ctx, tmp, &d_n, 1);
+    if (rc) {
+        tmp.release();
+        return rc;
+    }
+    a.num = d_num;
+    a.den = d_den;
+    a.cnt = d_cnt;
+    a.X = features;
+    a.T = target;
+    a.W = weight;
+    a.n_out = d_n;
+    a.range_out = nullptr;
+    hipError_t e = launch_imp_samples(a, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(n_samples, d_n, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    tmp.release();
+    if (e != hipSuccess) return fail(ctx, MC_EHIP, std::string("mc_importance_samples: ") + hipGetErrorString(e));
+    return MC_OK;
+}
+
+int mc_importance_train(mc_ctx *ctx, const mc_train_opts *opts, float *loss_curve, int32_t *n_samples,
+                        float *target_range)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mlp) return fail(ctx, MC_ESTATE, "mc_importance_train: no network (mc_mlp_init or mc_mlp_set)");
+    const mc_ww_desc &d = ctx->ww_desc;
+    if (d.imp_nx < 1 || !ctx->imp_num) return fail(ctx, MC_ESTATE, "mc_importance_train: no importance grid");
+    ImpSampleArgs a{};
+    int rc = imp_sample_args(ctx, opts, d.imp_nx, d.imp_ne, d.imp_x0, d.imp_x1, a, "mc_importance_train");
+    if (rc) return rc;
+    if (opts->steps < 1 || !(opts->lr > 0.0f)) return fail(ctx, MC_EINVAL, "mc_importance_train: steps >= 1, lr > 0");
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t cap = (size_t)d.imp_nx * (size_t)d.imp_ne * (size_t)opts->replicas;
+    if (cap > ctx->imp_sample_cap) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->imp_sample_bufs.release();
+        ctx->imp_sample_cap = 0;
+        Buffers &B = ctx->imp_sample_bufs;
+        rc = dalloc(ctx, B, &ctx->imp_X, cap * 4);
+        if (!rc) rc = dalloc(ctx, B, &ctx->imp_T, cap);
+        if (!rc) rc = dalloc(ctx, B, &ctx->imp_W, cap);
+        if (!rc) rc = dalloc(ctx, B, &ctx->imp_n, 1);
+        if (!rc) rc = dalloc(ctx, B, &ctx->imp_range, 2);
+        if (rc) {
+            B.release();
+            return rc;
+        }
+        ctx->imp_sample_cap = cap;
+    }
+    a.num = ctx->imp_num;
+    a.den = ctx->imp_den;
+    a.cnt = ctx->imp_cnt;
+    a.X = ctx->imp_X;
+    a.T = ctx->imp_T;
+    a.W = ctx->imp_W;
+    a.n_out = ctx->imp_n;
+    a.range_out = ctx->imp_range;
+    HIPCHK(launch_imp_samples(a, ctx->stream));
+    int32_t n = 0;
+    float range[2] = {0.f, 0.f};
+    HIPCHK(hipMemcpyAsync(&n, ctx->imp_n, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(range, ctx->imp_range, sizeof(range), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (n_samples) *n_samples = n;
+    if (target_range && n > 0) {
+        target_range[0] = range[0];
+        target_range[1] = range[1];
+    }
+    if (n == 0) return fail(ctx, MC_ESTATE, "mc_importance_train: no cell has min_credits detector credits");
+    return mlp_train_loop(ctx, (size_t)n, ctx->imp_X, ctx->imp_T, ctx->imp_W, opts->steps, opts->lr, loss_curve);
+}
 
 // ---------------------------------------------------------------------------
 // weight windows and the forward importance estimate
@@ -1668,6 +1837,7 @@ int mc_set_weight_windows(mc_ctx *ctx, const mc_ww_desc *desc)
         if (!(d.length > 0.0) || !(d.kappa > 0.0) || !(d.ratio > 1.0)) return bad("need length > 0, kappa > 0, ratio > 1");
         for (int k = 0; k < 3; ++k)
             if (!std::isfinite(d.lin[k])) return bad("lin not finite");
+        if (!std::isfinite(d.ln_lo) || !std::isfinite(d.ln_hi)) return bad("ln_lo / ln_hi not finite");
     }
     if (d.imp_nx < 0 || d.imp_nx > IMP_MAX_NX) return bad("imp_nx outside [0, 256]");
     if (d.imp_nx > 0 && (d.imp_ne < 1 || d.imp_ne > IMP_MAX_NE || !(d.imp_x1 > d.imp_x0)))

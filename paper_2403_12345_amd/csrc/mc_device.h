@@ -96,7 +96,10 @@ struct Counters {
     uint64_t issued;   // histories started so far in this batch
     uint32_t nA, nL;   // alive and lookup queue lengths
     uint32_t nC, nX;   // collide and cross queue lengths
-    uint32_t n_new, pad;
+    uint32_t n_new;    // source particles started by this iteration's refill
+    uint32_t top;      // weight-window copies waiting in the copy bank after the refill
+    uint32_t top_after;  // ... and after this iteration's flush
+    uint32_t pad;
 };
 
 // Per-workgroup tally rows: workgroup g of an event kernel adds its partial

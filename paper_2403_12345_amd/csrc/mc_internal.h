@@ -57,9 +57,11 @@ hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, c
 hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
                           const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
                           uint64_t first_pid, hipStream_t st);
-hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
-                       const Counters *ctr, uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log,
-                       uint64_t first_pid, unsigned long long *lost, hipStream_t st);
+hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+                       uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                       unsigned long long *lost, hipStream_t st);
+// Weight windows: pending copies of every slot's stack into the copy bank.
+hipError_t launch_ww_flush(const BankDev &b, const WwDev &W, Counters *ctr, hipStream_t st);
 // ln I at the source point into *out (device), for the weight windows.
 hipError_t launch_ww_source(const WwDev &W, const GeomDev &g, double *out, hipStream_t st);
 // Many independent problems (batching layer).
@@ -101,6 +103,21 @@ hipError_t launch_mlp_grad(const MlpDev &m, uint32_t n, const float *X, const fl
 hipError_t launch_mlp_adam(float *theta, float *mom, float *vel, const float *grad, int step, float lr, uint16_t *W1,
                            uint16_t *W2, uint16_t *W2t, uint16_t *w3, hipStream_t st);
 hipError_t launch_mlp_sync(const float *theta, uint16_t *W1, uint16_t *W2, uint16_t *W2t, uint16_t *w3, hipStream_t st);
+constexpr uint32_t MLP_INIT_LINEAGE = 0x5EED0001u;    // Philox lineage of the initial parameters
+constexpr uint32_t IMP_SAMPLE_LINEAGE = 0x5EED0002u;  // Philox lineage of the (y, z) replicas
+hipError_t launch_mlp_init(float *theta, uint64_t seed, hipStream_t st);
+struct ImpSampleArgs {
+    const double *num, *den, *cnt;  // [ne][nx] importance sums
+    int32_t nx, ne;
+    double x0, x1, length;
+    int32_t replicas;
+    double min_credits, rel_floor;
+    uint64_t seed;
+    float *X, *T, *W;                // [cells * replicas][4], [..], [..]
+    int32_t *n_out;                  // samples written
+    float *range_out;                // [2] smallest and largest target
+};
+hipError_t launch_imp_samples(const ImpSampleArgs &a, hipStream_t st);
 hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols, const double *direct,
                               double *partial, double inv_n, double *S1, double *S2, hipStream_t st);
 

@@ -182,6 +182,31 @@ __device__ __forceinline__ void init_particle(const BankDev &b, const GeomDev &g
     ww_start(W, s, x, g.src_E);
 }
 
+// Copy q of the copy bank into slot s: a weight-window copy starting with its
+// own stream at draw 0, a path length of 0, its parent's counts, cells and
+// split generation; lookup due.
+__device__ __forceinline__ void load_copy(const BankDev &b, const WwDev &W, uint32_t s, uint32_t q)
+{
+    b.x[s] = W.qx[q]; b.y[s] = W.qy[q]; b.z[s] = W.qz[q];
+    b.u[s] = W.qu[q]; b.v[s] = W.qv[q]; b.w[s] = W.qw[q];
+    b.E[s] = W.qE[q]; b.wt[s] = W.qwt[q];
+    b.cell[s] = W.qcell[q]; b.mat[s] = W.qmat[q]; b.inside[s] = W.qinside[q];
+    b.ncoll[s] = W.qncoll[q]; b.ncross[s] = W.qncross[q];
+    b.pid[s] = W.qpid[q];
+    b.lineage[s] = W.qlin[q];
+    b.ndraw[s] = 0u;
+    b.track[s] = 0.0;
+    b.flags[s] = F_ALIVE | F_LOOKUP;
+    W.depth_of[s] = 0;
+    W.splits[s] = 0;
+    W.gen[s] = W.qgen[q];
+    W.inh_coll[s] = W.qncoll[q];
+    W.inh_cross[s] = W.qncross[q];
+    if (W.imp_nx) {
+        for (int32_t e = 0; e < W.imp_ne; ++e) W.iv[(size_t)e * W.C + s] = W.qiv[(size_t)e * W.Q + q];
+    }
+}
+
 __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, WwDev W, Counters *ctr,
                                                     int cur, uint64_t first_pid, uint64_t n_hist,
                                                     uint64_t seed)
@@ -192,7 +217,11 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
     tile_prefix3(bank.tile_cnt, n_tiles, blockIdx.x, lds, pre, tot);
     const Counters prev = ctr[cur ^ 1];
     const uint64_t remaining = n_hist - prev.issued;
-    const uint32_t n_new = (uint32_t)((uint64_t)tot[2] < remaining ? (uint64_t)tot[2] : remaining);
+    // free slots take waiting weight-window copies first, then new histories
+    const uint32_t qtop = prev.top_after;
+    const uint32_t n_copy = tot[2] < qtop ? tot[2] : qtop;
+    const uint32_t n_free = tot[2] - n_copy;
+    const uint32_t n_new = (uint32_t)((uint64_t)n_free < remaining ? (uint64_t)n_free : remaining);
     const uint32_t base = blockIdx.x * (uint32_t)TILE;
     uint32_t run[3] = {0, 0, 0};
     for (int r = 0; r < TILE_ITEMS; ++r) {
@@ -207,8 +236,12 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
         if (look) bank.L[pre[1] + run[1] + rk.rank[1]] = s;
         if (fr) {
             const uint32_t k = pre[2] + run[2] + rk.rank[2];
-            if (k < n_new) {
-                init_particle(bank, geom, W, s, first_pid + prev.issued + k, seed);
+            if (k < n_copy) {
+                load_copy(bank, W, s, qtop - 1u - k);
+                bank.A[tot[0] + k] = s;
+                bank.L[tot[1] + k] = s;
+            } else if (k - n_copy < n_new) {
+                init_particle(bank, geom, W, s, first_pid + prev.issued + (k - n_copy), seed);
                 bank.A[tot[0] + k] = s;
                 bank.L[tot[1] + k] = s;
             }
@@ -219,11 +252,13 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Counters c;
         c.issued = prev.issued + n_new;
-        c.nA = tot[0] + n_new;
-        c.nL = tot[1] + n_new;
+        c.nA = tot[0] + n_copy + n_new;
+        c.nL = tot[1] + n_copy + n_new;
         c.nC = 0;
         c.nX = 0;
         c.n_new = n_new;
+        c.top = qtop - n_copy;
+        c.top_after = qtop - n_copy;
         c.pad = 0;
         ctr[cur] = c;
     }
@@ -591,6 +626,7 @@ __device__ __forceinline__ void end_copy(const BankDev &b, const WwDev &W, uint3
                                          HistLog *log, uint64_t first_pid)
 {
     if constexpr (WWK != WW_OFF) {
+        if (log) log_copy(log, first_pid, p, fate, W, s);
         if (ww_pending(W, s)) {
             ww_pop(W, s, p);
             b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
@@ -599,12 +635,15 @@ __device__ __forceinline__ void end_copy(const BankDev &b, const WwDev &W, uint3
             b.cell[s] = p.cell; b.mat[s] = p.mat; b.inside[s] = p.inside ? 1 : 0;
             b.ncoll[s] = p.ncoll; b.ncross[s] = p.ncross;
             b.lineage[s] = p.lineage; b.ndraw[s] = p.ndraw;
+            b.track[s] = p.track;
             b.flags[s] = F_ALIVE | F_LOOKUP;
-            return;
+        } else {
+            b.flags[s] = 0;
         }
+    } else {
+        b.flags[s] = 0;
+        if (log) write_log(log, first_pid, p, fate);
     }
-    b.flags[s] = 0;
-    if (log) write_log_ww(log, first_pid, p, fate, W, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,15 +763,12 @@ struct TileRows {
     bool enabled;              // binned flux tallies on
 };
 
-template <int WWK>
 __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev &xs, const GeomDev &g,
-                                const TileRows &r, const WwDev &W, uint32_t s, uint64_t seed, int64_t max_events,
-                                HistLog *log, uint64_t log_first_pid, unsigned long long *lost, double *slab,
-                                double *gl)
+                                const TileRows &r, uint64_t seed, int64_t max_events, HistLog *log,
+                                uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl)
 {
     const bool binned = r.enabled && g.tally_kind != TALLY_MESH;
     const bool log_on = log != nullptr;
-    const bool imp_on = W.imp_nx != 0;
     while (__syncthreads_or(alive)) {
         StepScore sc;
         clear_score(sc);
@@ -745,50 +781,34 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
             fate = FATE_LOST;
             atomicAdd(lost, 1ull);
         } else if (alive) {
-            const double x0 = p.x;
             do_advance(p, g, seed, r.enabled, r.mesh_tl, log_on, sc);
-            if (imp_on) imp_enter(W, s, x0, p.x, p.E, p.wt);
         }
         if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
                 fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc);
                 need = fate == 0;
-                if (fate == 0 && imp_on) imp_enter(W, s, p.x, p.x, p.E, p.wt);
             } else {
                 bool leak_xhi;
                 fate = do_cross(p, g, sc, need, leak_xhi);
-                if (leak_xhi && imp_on) imp_credit(W, s, p.wt);
             }
-        }
-        if constexpr (WWK != WW_OFF) {
-            const bool chk = alive && fate == 0;
-            const double ln_i = ww_ln_importance<WWK>(W, p, chk);
-            if (chk) fate = ww_check(W, s, p, ln_i, seed, sc);
         }
         if (binned) wg_bin_add(sc.c_bin, sc.c_val, slab, r.n_bins, r.coll);
         wg_glob_add(sc.g, gl, r.glob);
         if (alive && fate != 0) {
-            bool next = false;
-            if constexpr (WWK != WW_OFF) next = ww_pending(W, s);
-            if (next) {
-                ww_pop(W, s, p);
-                need = true;
-            } else {
-                alive = false;
-                if (log) write_log_ww(log, log_first_pid, p, fate, W, s);
-            }
+            alive = false;
+            if (log) write_log(log, log_first_pid, p, fate);
         }
     }
 }
 
 // Tail: when no history remains to start and few particles are in flight,
 // one launch finishes them (workgroup row = blockIdx.x); the histories are
-// the ones the event kernels would give.
-template <int WWK>
-__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, WwDev W,
-                                             const Counters *ctr, uint64_t seed, int64_t max_events, HistLog *log,
-                                             uint64_t first_pid, unsigned long long *lost)
+// the ones the event kernels would give.  Analog transport only: with weight
+// windows a history's copies run in parallel in the event kernels.
+__global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, const Counters *ctr,
+                                             uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                                             unsigned long long *lost)
 {
     extern __shared__ double slab[];
     __shared__ double gl[N_GLOBAL * WAVES];
@@ -813,7 +833,7 @@ __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, Tal
     r.mesh_coll = tal.mesh_coll;
     r.n_bins = tal.n_bins;
     r.enabled = tal.enabled != 0;
-    run_tile<WWK>(p, alive, need, xs, g, r, W, s, seed, max_events, log, first_pid, lost, slab, gl);
+    run_tile(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl);
     if (i < n) b.flags[s] = 0;
 }
 
@@ -867,7 +887,6 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
     __shared__ double gl[N_GLOBAL * WAVES];
     __shared__ uint32_t s_tile;
     const uint64_t batch = *set.batch;
-    const WwDev no_ww{};  // problem sets run analog
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(set.next_tile, 1u);
         __syncthreads();
@@ -890,8 +909,7 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
             r.n_bins = P.g.n_bins;
             r.enabled = true;
             HistLog *log = set.log ? set.log + P.log_off : nullptr;
-            run_tile<WW_OFF>(p, alive, true, xs, P.g, r, no_ww, 0u, P.seed, max_events, log, first_pid, set.lost,
-                             slab, gl);
+            run_tile(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid, set.lost, slab, gl);
         }
     }
 }
@@ -1146,27 +1164,85 @@ hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, c
     return hipGetLastError();
 }
 
-hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
-                       const Counters *ctr, uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log,
-                       uint64_t first_pid, unsigned long long *lost, hipStream_t st)
+hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
+                       uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
+                       unsigned long long *lost, hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    const dim3 grid(blocks_for(n_bound, WG));
-    switch (W.kind) {
-    case WW_LINEAR:
-        hipLaunchKernelGGL(k_tail<WW_LINEAR>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, max_events, log,
-                           first_pid, lost);
-        break;
-    case WW_MLP:
-        hipLaunchKernelGGL(k_tail<WW_MLP>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, max_events, log,
-                           first_pid, lost);
-        break;
-    default:
-        hipLaunchKernelGGL(k_tail<WW_OFF>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, max_events, log,
-                           first_pid, lost);
-        break;
+    hipLaunchKernelGGL(k_tail, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed, max_events,
+                       log, first_pid, lost);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// weight-window copies: stacks -> copy bank, in slot order
+// ---------------------------------------------------------------------------
+// Exclusive prefix of v over the workgroup's threads and the total.
+__device__ __forceinline__ uint32_t block_exscan_u32(uint32_t v, uint32_t *lds, uint32_t &total)
+{
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = lds[w];
+        pre += (w < wave) ? c : 0u;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+__global__ void __launch_bounds__(WG) k_ww_flush_count(BankDev b, WwDev W)
+{
+    __shared__ uint32_t lds[32];
+    const uint32_t base = blockIdx.x * (uint32_t)TILE;
+    uint32_t c = 0;
+    for (int r = 0; r < TILE_ITEMS; ++r) {
+        const uint32_t s = base + r * WG + threadIdx.x;
+        if (s < b.C) c += ww_pending_copies(W, s);
+    }
+    block_count3(c, 0u, 0u, lds, b.tile_cnt + blockIdx.x * 3);
+}
+
+// Every slot's pending copies go to the bank at top + (copies of the slots
+// before it), unless they would not all fit: then every stack keeps its own.
+__global__ void __launch_bounds__(WG) k_ww_flush_scatter(BankDev b, WwDev W, Counters *ctr)
+{
+    __shared__ uint32_t lds[32];
+    const uint32_t n_tiles = (b.C + TILE - 1) / TILE;
+    uint32_t pre[3], tot[3];
+    tile_prefix3(b.tile_cnt, n_tiles, blockIdx.x, lds, pre, tot);
+    const uint32_t top = ctr->top;
+    const bool fits = (uint64_t)top + tot[0] <= (uint64_t)W.Q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->top_after = fits ? top + tot[0] : top;
+    if (!fits || tot[0] == 0) return;
+    const uint32_t base = blockIdx.x * (uint32_t)TILE;
+    uint32_t run = 0;
+    for (int r = 0; r < TILE_ITEMS; ++r) {
+        const uint32_t s = base + r * WG + threadIdx.x;
+        const uint32_t c = s < b.C ? ww_pending_copies(W, s) : 0u;
+        uint32_t round_total;
+        const uint32_t off = block_exscan_u32(c, lds, round_total);
+        if (c) ww_flush_slot(W, s, b.pid[s], top + pre[0] + run + off);
+        run += round_total;
+    }
+}
+
+hipError_t launch_ww_flush(const BankDev &b, const WwDev &W, Counters *ctr, hipStream_t st)
+{
+    const unsigned nt = blocks_for(b.C, TILE);
+    hipLaunchKernelGGL(k_ww_flush_count, dim3(nt), dim3(WG), 0, st, b, W);
+    hipLaunchKernelGGL(k_ww_flush_scatter, dim3(nt), dim3(WG), 0, st, b, W, ctr);
     return hipGetLastError();
 }
 
@@ -1183,7 +1259,7 @@ __global__ void __launch_bounds__(WG) k_ww_source(WwDev W, GeomDev g, double *ou
     p.x = x; p.y = y; p.z = z;
     p.E = g.src_E;
     double v = 0.0;
-    if (W.kind == WW_LINEAR) v = ww_ln_importance_linear(W, p);
+    if (W.kind == WW_LINEAR) v = ww_ln_importance<WW_LINEAR>(W, p, true);
     else v = ww_ln_importance<WW_MLP>(W, p, threadIdx.x == 0);
     if (threadIdx.x == 0) *out = v;
 }

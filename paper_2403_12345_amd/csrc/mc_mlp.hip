@@ -10,6 +10,8 @@
 #include "mc_mlp.h"
 #include "mc_internal.h"
 
+#pragma clang fp contract(off)
+
 namespace mc {
 
 // ---------------------------------------------------------------------------
@@ -243,8 +245,118 @@ __global__ void __launch_bounds__(256) k_mlp_sync(const float *theta, uint16_t *
 }
 
 // ---------------------------------------------------------------------------
+// initial parameters: W1 ~ U(-1/2, 1/2), W2 and w3 ~ U(-1/8, 1/8) (uniform in
+// +-1/sqrt(fan in)), biases 0; draw j of the key `seed` from the Philox stream
+// of pid j, lineage MLP_INIT_LINEAGE
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_mlp_init(float *theta, uint64_t seed)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= (uint32_t)MLP_NPAR) return;
+    Rng rng(seed, (uint64_t)j, MLP_INIT_LINEAGE, 0u);
+    const double u = 2.0 * rng.next() - 1.0;
+    double v = 0.0;
+    if (j < (uint32_t)MLP_B1) v = 0.5 * u;
+    else if (j >= (uint32_t)MLP_W2 && j < (uint32_t)MLP_B2) v = 0.125 * u;
+    else if (j >= (uint32_t)MLP_W3 && j < (uint32_t)MLP_B3) v = 0.125 * u;
+    theta[j] = (float)v;
+}
+
+// ---------------------------------------------------------------------------
+// training samples from the forward importance sums: every cell with at least
+// min_credits detector credits gives `replicas` samples (cells in index
+// order): features (x centre / L, f_y, f_z, ln E-bin centre), target
+// ln(num / den), weight 1 / (1 / cnt + rel_floor^2).  The slab is invariant
+// in y and z: f_y and f_z are drawn uniform on [-1, 1] (draws 2r and 2r + 1 of
+// pid = cell, lineage IMP_SAMPLE_LINEAGE) so the network learns that.  One
+// workgroup, a running block scan over the cells.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_imp_samples(ImpSampleArgs a)
+{
+    __shared__ uint32_t wsum[4];
+    __shared__ float wmin[4], wmax[4];
+    __shared__ uint32_t base;
+    __shared__ float tmin, tmax;
+    if (threadIdx.x == 0) {
+        base = 0;
+        tmin = INFINITY;
+        tmax = -INFINITY;
+    }
+    __syncthreads();
+    const int32_t cells = a.nx * a.ne;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int32_t c0 = 0; c0 < cells; c0 += 256) {
+        const int32_t g = c0 + (int32_t)threadIdx.x;
+        bool ok = false;
+        if (g < cells) ok = a.cnt[g] >= a.min_credits && a.num[g] > 0.0 && a.den[g] > 0.0;
+        const uint64_t m = __ballot(ok);
+        float tg = 0.f;
+        if (ok) tg = (float)log(a.num[g] / a.den[g]);
+        float lo = ok ? tg : INFINITY, hi = ok ? tg : -INFINITY;
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, o, 64));
+            hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+        }
+        if (lane == 0) {
+            wsum[wave] = (uint32_t)__popcll(m);
+            wmin[wave] = lo;
+            wmax[wave] = hi;
+        }
+        __syncthreads();
+        uint32_t pre = base;
+        for (int w = 0; w < wave; ++w) pre += wsum[w];
+        pre += (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (ok) {
+            const int32_t ix = g % a.nx, e = g / a.nx;
+            const double xc = a.x0 + (a.x1 - a.x0) * ((double)ix + 0.5) / (double)a.nx;
+            const float fx = (float)(xc / a.length);
+            const float fe = (float)(((double)e + 0.5) / (double)a.ne);
+            const float wt = (float)(1.0 / (1.0 / a.cnt[g] + a.rel_floor * a.rel_floor));
+            Rng rng(a.seed, (uint64_t)g, IMP_SAMPLE_LINEAGE, 0u);
+            for (int32_t r = 0; r < a.replicas; ++r) {
+                const size_t k = (size_t)pre * a.replicas + r;
+                const double uy = rng.next(), uz = rng.next();
+                a.X[k * 4 + 0] = fx;
+                a.X[k * 4 + 1] = (float)(2.0 * uy - 1.0);
+                a.X[k * 4 + 2] = (float)(2.0 * uz - 1.0);
+                a.X[k * 4 + 3] = fe;
+                a.T[k] = tg;
+                a.W[k] = wt;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+            for (int w = 0; w < 4; ++w) {
+                tmin = fminf(tmin, wmin[w]);
+                tmax = fmaxf(tmax, wmax[w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *a.n_out = (int32_t)(base * (uint32_t)a.replicas);
+        if (a.range_out) {
+            a.range_out[0] = tmin;
+            a.range_out[1] = tmax;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_mlp_init(float *theta, uint64_t seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_init, dim3((MLP_NPAR + 255) / 256), dim3(256), 0, st, theta, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_imp_samples(const ImpSampleArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_imp_samples, dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
 hipError_t launch_mlp_forward(const MlpDev &m, uint32_t n, const float *X, float *Y, hipStream_t st)
 {
     if (n == 0) return hipSuccess;

@@ -4,14 +4,21 @@
 // is analog and says nothing of it): the window at a point follows from an
 // importance map ln I(x, y, z, E), w_L = exp(ln I_src - ln I) / kappa,
 // w_U = ratio * w_L, w_S = (w_L + w_U) / 2.  A copy heavier than w_U is split
-// into n = min(n_max, ceil(w / w_U)) copies of weight w / n; one goes on, the
-// other n - 1 wait on a last-in first-out stack of the history's slot and run,
-// one after the other, when the copy ahead of them dies.  A copy lighter than
-// w_L plays roulette (one draw) and survives at w_S with probability w / w_S.
-// Checks happen after a collision the particle survives and after a crossing
-// it does not leak through.  Copy k of split number s of a copy of lineage a
-// draws from the stream of lineage child_lineage(a, s, k) of the same pid,
-// so a history and all its copies are fixed by (seed, pid) alone.
+// into n = min(n_max, ceil(w / w_U)) copies of weight w / n (unless `depth`
+// splits already lie on its line from the source particle); one goes on, the
+// other n - 1 are pushed on the slot's stack of pending splits.  A copy
+// lighter than w_L plays roulette (one draw) and survives at w_S with
+// probability w / w_S.  Checks happen after a collision the particle survives
+// and after a crossing it does not leak through.  Copy k of split number s of
+// a copy of lineage a draws from the stream of lineage child_lineage(a, s, k)
+// of the same pid, so every copy is fixed by (seed, pid) and its line alone,
+// whatever slot runs it and when.
+//
+// Pending copies run in parallel: after every event step the stacks are
+// flushed, in slot order, into a copy bank, and the refill step gives free
+// slots copies from the bank before new source particles.  When the bank is
+// full the stacks keep their records and a slot runs its own pending copies
+// (last in, first out) when its copy ends.
 //
 // Forward importance estimate (after Booth): on a grid of x-bins by ln E-bins
 // each copy remembers which cells it (or the copy it was split from) has
@@ -43,6 +50,7 @@ struct WwDev {
     double lin0, lin1, lin2;      // WW_LINEAR: ln I = lin0 + lin1 f_x + lin2 f_E
     double length, kappa, ratio;  // feature scale L; w_L at the source = 1 / kappa; w_U / w_L
     double ln_emin, ln_erange;    // ln 1e-5 and ln(2e7 / 1e-5)
+    double ln_lo, ln_hi;          // ln I clamped to [ln_lo, ln_hi] when ln_lo < ln_hi
     const double *ln_src;         // device scalar: ln I at the source point
     MlpDev mlp;                   // WW_MLP: the network
     uint32_t C;                   // slots
@@ -50,11 +58,19 @@ struct WwDev {
     double *sx, *sy, *sz, *su, *sv, *sw, *sE, *swt;
     int32_t *scell, *smat, *sncoll, *sncross;
     uint32_t *slin, *ssplit, *snext, *sn;
-    uint8_t *sinside;
+    uint8_t *sinside, *sgen;
     uint8_t *depth_of;            // [slot] pending records
     uint32_t *splits;             // [slot] split events of the running copy
-    int32_t *hcoll, *hcross;      // [slot] finished copies' counts minus what the next copy inherits
-    uint32_t *hdraw;              // [slot] draws of finished copies
+    uint8_t *gen;                 // [slot] splits on the running copy's line
+    int32_t *inh_coll, *inh_cross;  // [slot] counts the running copy inherited
+    // copy bank: Q entries, filled from the stacks, emptied by the refill
+    double *qx, *qy, *qz, *qu, *qv, *qw, *qE, *qwt;
+    int32_t *qcell, *qmat, *qncoll, *qncross;
+    uint8_t *qinside, *qgen;
+    uint32_t *qlin;
+    uint64_t *qpid;
+    uint16_t *qiv;                // [e][Q]
+    uint32_t Q;
     // importance estimate (imp_nx == 0: off)
     int32_t imp_nx, imp_ne;
     double imp_x0, imp_x1;
@@ -145,9 +161,9 @@ __device__ inline void ww_start(const WwDev &W, uint32_t s, double x, double E)
     if (W.depth_of) {
         W.depth_of[s] = 0;
         W.splits[s] = 0;
-        W.hcoll[s] = 0;
-        W.hcross[s] = 0;
-        W.hdraw[s] = 0;
+        W.gen[s] = 0;
+        W.inh_coll[s] = 0;
+        W.inh_cross[s] = 0;
     }
     if (W.imp_nx) {
         for (int32_t e = 0; e < W.imp_ne; ++e) W.iv[(size_t)e * W.C + s] = IV_EMPTY;
@@ -168,11 +184,16 @@ __device__ __forceinline__ double ww_ln_importance_linear(const WwDev &W, const 
 // ln I of the particles of a workgroup.  WW_MLP: the network, one sample per
 // lane, on the matrix cores -- every thread of the workgroup must call it
 // (lanes with chk false pass zeros and get a value to ignore).
+__device__ __forceinline__ double ww_clamp(const WwDev &W, double v)
+{
+    return W.ln_lo < W.ln_hi ? fmin(fmax(v, W.ln_lo), W.ln_hi) : v;
+}
+
 template <int WWK>
 __device__ inline double ww_ln_importance(const WwDev &W, const Particle &p, bool chk)
 {
     if constexpr (WWK == WW_LINEAR) {
-        return chk ? ww_ln_importance_linear(W, p) : 0.0;
+        return chk ? ww_clamp(W, ww_ln_importance_linear(W, p)) : 0.0;
     } else {
         __shared__ __attribute__((aligned(16))) uint16_t h1s[WAVES][64 * H1_STRIDE];
         __shared__ float ys[WAVES][64];
@@ -180,7 +201,7 @@ __device__ inline double ww_ln_importance(const WwDev &W, const Particle &p, boo
         float f[4] = {0.f, 0.f, 0.f, 0.f};
         if (chk) mlp_features(p.x, p.y, p.z, p.E, W.length, W.ln_emin, W.ln_erange, f);
         const int wave = threadIdx.x >> 6;
-        return (double)wave_mlp(W.mlp, f, h1s[wave], ys[wave]);
+        return ww_clamp(W, (double)wave_mlp(W.mlp, f, h1s[wave], ys[wave]));
     }
 }
 
@@ -194,6 +215,7 @@ __device__ inline void ww_push(const WwDev &W, uint32_t s, const Particle &p, ui
     W.scell[k] = p.cell; W.smat[k] = p.mat; W.sinside[k] = p.inside ? 1 : 0;
     W.sncoll[k] = p.ncoll; W.sncross[k] = p.ncross;
     W.slin[k] = p.lineage; W.ssplit[k] = W.splits[s]; W.snext[k] = 1u; W.sn[k] = n;
+    W.sgen[k] = W.gen[s];
     if (W.imp_nx) {
         for (int32_t e = 0; e < W.imp_ne; ++e)
             W.siv[((size_t)d * W.imp_ne + e) * W.C + s] = W.iv[(size_t)e * W.C + s];
@@ -215,8 +237,9 @@ __device__ inline int32_t ww_check(const WwDev &W, uint32_t s, Particle &p, doub
     if (w > uw) {
         const double nd = ceil(w / uw);
         const int32_t n = nd > (double)W.nmax ? W.nmax : (int32_t)nd;
-        if (n >= 2 && (int32_t)W.depth_of[s] < W.depth) {
+        if (n >= 2 && (int32_t)W.gen[s] < W.depth) {
             p.wt = w / (double)n;
+            W.gen[s] += 1;  // the copy that goes on and its n - 1 siblings
             ww_push(W, s, p, (uint32_t)n);
             sc.g[G_SPLIT] += (double)(n - 1);
         }
@@ -238,16 +261,16 @@ __device__ inline int32_t ww_check(const WwDev &W, uint32_t s, Particle &p, doub
 
 // The copy in p (slot s) has died and the slot has a pending copy: take the
 // next one off the stack into p.  Its state is the parent's at the split, its
-// stream the child lineage's from draw 0; the slot's history counters keep
-// what the dead copy added.
+// stream the child lineage's from draw 0, its path length starts at 0.
 __device__ inline void ww_pop(const WwDev &W, uint32_t s, Particle &p)
 {
     const uint32_t d = (uint32_t)W.depth_of[s] - 1u;
     const size_t k = (size_t)d * W.C + s;
     const uint32_t kk = W.snext[k], n = W.sn[k];
-    W.hcoll[s] += p.ncoll - W.sncoll[k];
-    W.hcross[s] += p.ncross - W.sncross[k];
-    W.hdraw[s] += p.ndraw;
+    W.inh_coll[s] = W.sncoll[k];
+    W.inh_cross[s] = W.sncross[k];
+    W.gen[s] = W.sgen[k];
+    p.track = 0.0;
     p.x = W.sx[k]; p.y = W.sy[k]; p.z = W.sz[k];
     p.u = W.su[k]; p.v = W.sv[k]; p.w = W.sw[k];
     p.E = W.sE[k]; p.wt = W.swt[k];
@@ -266,25 +289,61 @@ __device__ inline void ww_pop(const WwDev &W, uint32_t s, Particle &p)
 
 __device__ __forceinline__ bool ww_pending(const WwDev &W, uint32_t s) { return W.depth_of && W.depth_of[s] > 0; }
 
-// History record of the slot's history (the counts over all its copies).
-__device__ __forceinline__ void write_log_ww(HistLog *log, uint64_t first_pid, const Particle &p, int32_t fate,
-                                             const WwDev &W, uint32_t s)
+// History record of a copy that ended: its collisions, crossings, draws and
+// path length add to its history's (the record starts zeroed; copies of one
+// history may end in any order and in parallel); the source particle's own
+// copy (lineage 0) also sets the fate, final energy and weight.
+__device__ __forceinline__ void log_copy(HistLog *log, uint64_t first_pid, const Particle &p, int32_t fate,
+                                         const WwDev &W, uint32_t s)
 {
-    HistLog h;
-    h.fate = fate;
-    h.n_coll = p.ncoll;
-    h.n_cross = p.ncross;
-    h.pad = 0;
-    h.n_draws = p.ndraw;
-    if (W.depth_of) {
-        h.n_coll += W.hcoll[s];
-        h.n_cross += W.hcross[s];
-        h.n_draws += W.hdraw[s];
+    HistLog *h = log + (p.pid - first_pid);
+    atomicAdd(&h->n_coll, p.ncoll - W.inh_coll[s]);
+    atomicAdd(&h->n_cross, p.ncross - W.inh_cross[s]);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&h->n_draws), (unsigned long long)p.ndraw);
+    atomicAdd(&h->track, p.track);
+    if (p.lineage == 0u) {
+        h->fate = fate;
+        h->E_final = p.E;
+        h->weight = p.wt;
     }
-    h.E_final = p.E;
-    h.track = p.track;
-    h.weight = p.wt;
-    log[p.pid - first_pid] = h;
+}
+
+// Pending copies in the stack of slot s.
+__device__ __forceinline__ uint32_t ww_pending_copies(const WwDev &W, uint32_t s)
+{
+    uint32_t c = 0;
+    const uint32_t depth = W.depth_of[s] < (uint32_t)W.depth ? W.depth_of[s] : (uint32_t)W.depth;
+    for (uint32_t d = 0; d < depth; ++d) {
+        const size_t k = (size_t)d * W.C + s;
+        c += W.sn[k] - W.snext[k];
+    }
+    return c;
+}
+
+// Move the pending copies of slot s (pid `pid`) into the copy bank at q0..;
+// the stack ends empty.
+__device__ inline void ww_flush_slot(const WwDev &W, uint32_t s, uint64_t pid, uint32_t q0)
+{
+    uint32_t q = q0;
+    const uint32_t depth = W.depth_of[s] < (uint32_t)W.depth ? W.depth_of[s] : (uint32_t)W.depth;
+    for (uint32_t d = 0; d < depth; ++d) {
+        const size_t k = (size_t)d * W.C + s;
+        for (uint32_t kk = W.snext[k]; kk < W.sn[k]; ++kk, ++q) {
+            W.qx[q] = W.sx[k]; W.qy[q] = W.sy[k]; W.qz[q] = W.sz[k];
+            W.qu[q] = W.su[k]; W.qv[q] = W.sv[k]; W.qw[q] = W.sw[k];
+            W.qE[q] = W.sE[k]; W.qwt[q] = W.swt[k];
+            W.qcell[q] = W.scell[k]; W.qmat[q] = W.smat[k]; W.qinside[q] = W.sinside[k];
+            W.qncoll[q] = W.sncoll[k]; W.qncross[q] = W.sncross[k];
+            W.qgen[q] = W.sgen[k];
+            W.qlin[q] = child_lineage(W.slin[k], W.ssplit[k], kk);
+            W.qpid[q] = pid;
+            if (W.imp_nx) {
+                for (int32_t e = 0; e < W.imp_ne; ++e)
+                    W.qiv[(size_t)e * W.Q + q] = W.siv[((size_t)d * W.imp_ne + e) * W.C + s];
+            }
+        }
+    }
+    W.depth_of[s] = 0;
 }
 
 }  // namespace mc

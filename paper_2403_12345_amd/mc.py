@@ -93,7 +93,14 @@ class mc_set_opts(C.Structure):
 class mc_ww_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_max", C.c_int32), ("depth", C.c_int32), ("imp_nx", C.c_int32),
                 ("imp_ne", C.c_int32), ("reserved", C.c_int32), ("lin", C.c_double * 3), ("length", C.c_double),
-                ("kappa", C.c_double), ("ratio", C.c_double), ("imp_x0", C.c_double), ("imp_x1", C.c_double)]
+                ("kappa", C.c_double), ("ratio", C.c_double), ("imp_x0", C.c_double), ("imp_x1", C.c_double),
+                ("ln_lo", C.c_double), ("ln_hi", C.c_double)]
+
+
+class mc_train_opts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("replicas", C.c_int32), ("lr", C.c_float), ("pad", C.c_float),
+                ("min_credits", C.c_double), ("rel_floor", C.c_double), ("length", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class mc_tally_meta(C.Structure):
@@ -150,6 +157,10 @@ def load():
         "mc_mlp_train": ([V, SZ, V, V, V, I32, C.c_float, P(C.c_float)], C.c_int),
         "mc_set_weight_windows": ([V, P(mc_ww_desc)], C.c_int),
         "mc_get_importance": ([V, P(D), P(D), P(D), SZ], C.c_int),
+        "mc_mlp_init": ([V, U64], C.c_int),
+        "mc_importance_samples": ([V, P(D), P(D), P(D), I32, I32, D, D, P(mc_train_opts), V, V, V, P(I32)],
+                                  C.c_int),
+        "mc_importance_train": ([V, P(mc_train_opts), P(C.c_float), P(I32), P(C.c_float)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -403,13 +414,14 @@ def mc_mlp_train(ctx, n: int, features, target, weight, steps: int, lr: float) -
 
 
 def mc_set_weight_windows(ctx, kind=MC_WW_OFF, lin=(0.0, 0.0, 0.0), length=200.0, kappa=3.0, ratio=5.0,
-                          n_max=10, depth=24, imp_nx=0, imp_ne=0, imp_x0=0.0, imp_x1=200.0):
+                          n_max=10, depth=24, imp_nx=0, imp_ne=0, imp_x0=0.0, imp_x1=200.0, ln_lo=0.0, ln_hi=0.0):
     d = mc_ww_desc()
     d.kind, d.n_max, d.depth = int(kind), int(n_max), int(depth)
     d.imp_nx, d.imp_ne = int(imp_nx), int(imp_ne)
     d.lin = (C.c_double * 3)(*[float(v) for v in lin])
     d.length, d.kappa, d.ratio = float(length), float(kappa), float(ratio)
     d.imp_x0, d.imp_x1 = float(imp_x0), float(imp_x1)
+    d.ln_lo, d.ln_hi = float(ln_lo), float(ln_hi)
     _check(ctx, load().mc_set_weight_windows(ctx, C.byref(d)))
 
 
@@ -418,6 +430,39 @@ def mc_get_importance(ctx, n_cells: int):
     num, den, cnt = np.zeros(n_cells), np.zeros(n_cells), np.zeros(n_cells)
     _check(ctx, load().mc_get_importance(ctx, _dp(num), _dp(den), _dp(cnt), int(n_cells)))
     return num, den, cnt
+
+
+def train_opts(steps=2000, replicas=4, lr=1e-2, min_credits=10.0, rel_floor=0.1, length=200.0, seed=0):
+    o = mc_train_opts()
+    o.steps, o.replicas, o.lr = int(steps), int(replicas), float(lr)
+    o.min_credits, o.rel_floor, o.length, o.seed = float(min_credits), float(rel_floor), float(length), int(seed)
+    return o
+
+
+def mc_mlp_init(ctx, seed: int = 0):
+    _check(ctx, load().mc_mlp_init(ctx, int(seed)))
+
+
+def mc_importance_samples(ctx, num, den, cnt, nx: int, ne: int, x0: float, x1: float, opts, features, target,
+                          weight) -> int:
+    """Host sums in, device samples out (features [cells * replicas, 4] float32 ...); returns the count."""
+    num = np.ascontiguousarray(num, np.float64)
+    den = np.ascontiguousarray(den, np.float64)
+    cnt = np.ascontiguousarray(cnt, np.float64)
+    n = C.c_int32()
+    _check(ctx, load().mc_importance_samples(ctx, _dp(num), _dp(den), _dp(cnt), int(nx), int(ne), float(x0),
+                                             float(x1), C.byref(opts), _ptr(features), _ptr(target), _ptr(weight),
+                                             C.byref(n)))
+    return int(n.value)
+
+
+def mc_importance_train(ctx, opts):
+    """Returns (loss curve [steps] float32, number of samples, (smallest, largest target))."""
+    curve = np.zeros(max(int(opts.steps), 1), np.float32)
+    n = C.c_int32()
+    rng = np.zeros(2, np.float32)
+    _check(ctx, load().mc_importance_train(ctx, C.byref(opts), _fp(curve), C.byref(n), _fp(rng)))
+    return curve, int(n.value), (float(rng[0]), float(rng[1]))
 
 
 def mc_get_tuning(ctx) -> dict:

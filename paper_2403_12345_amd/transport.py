@@ -93,7 +93,7 @@ class Transport:
         kw = {}
         if ww is not None:
             kw.update(kind=kind, lin=ww.lin, length=ww.length, kappa=ww.kappa, ratio=ww.ratio, n_max=ww.n_max,
-                      depth=ww.depth)
+                      depth=ww.depth, ln_lo=getattr(ww, "ln_lo", 0.0), ln_hi=getattr(ww, "ln_hi", 0.0))
         if imp is not None and imp.nx > 0:
             kw.update(imp_nx=imp.nx, imp_ne=imp.ne, imp_x0=imp.x0, imp_x1=imp.x1)
         mc.mc_set_weight_windows(self.ctx, **kw)

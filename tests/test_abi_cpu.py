@@ -34,7 +34,8 @@ def test_struct_sizes_match_header_layout():
     assert mc.HISTORY_DTYPE.itemsize == 48
     assert ctypes.sizeof(mc.mc_run_opts) == 48
     assert ctypes.sizeof(mc.mc_stats) == 8 * 10
-    assert ctypes.sizeof(mc.mc_ww_desc) == 6 * 4 + 8 * 8
+    assert ctypes.sizeof(mc.mc_ww_desc) == 6 * 4 + 10 * 8
+    assert ctypes.sizeof(mc.mc_train_opts) == 48
 
 
 def _header_enum(name):

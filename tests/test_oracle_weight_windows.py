@@ -94,6 +94,32 @@ def test_weight_windows_agree_with_analog_in_a_scattering_slab():
     assert ww.stderr["glob"][k] < an.stderr["glob"][k]
 
 
+def test_split_generation_limit_bounds_splits_and_keeps_closed_form():
+    """A copy made by `depth` splits along its line splits no further: with
+    depth 1 and n_max 3 a history makes at most 2 copies, and the infinite
+    medium track length stays 1/Sigma_a."""
+    prob = mcsynth.c1_constant_problem(sig_c=10.0, sig_s=40.0, awr=12.0, density=0.01)
+    prob.ww = mcsynth.WeightWindows(kind=mcsynth.WW_LINEAR, lin=(0.0, 3.0, 4.0), length=20.0, depth=1, n_max=3)
+    op = oracle.OracleProblem(prob)
+    n = 4000
+    r = oracle.run(op, 13, 0, n, history=True)
+    assert 0 < r.glob[oracle.G_SPLIT] <= 2 * n
+    st = oracle.run_batches(op, 13, 20, 2000)
+    assert abs(st.mean["glob"][oracle.G_TRACK] - 10.0) <= 3 * st.stderr["glob"][oracle.G_TRACK]
+
+
+def test_history_record_keeps_the_source_copy_fate():
+    """With windows, the record's fate, energy and weight are those of the
+    source particle's own copy; roulette can end it, and its weight is then
+    what it carried when it died (never above the window's survival weight)."""
+    prob = mcsynth.c1_constant_problem(sig_c=10.0, sig_s=40.0, awr=12.0, density=0.01)
+    prob.ww = mcsynth.WeightWindows(kind=mcsynth.WW_LINEAR, lin=(0.0, 3.0, 4.0), length=20.0)
+    h = oracle.run(oracle.OracleProblem(prob), 17, 0, 3000, history=True).history
+    assert set(np.unique(h["fate"])) <= {oracle.FATE_ABSORBED, oracle.FATE_CUTOFF, oracle.FATE_ROULETTE}
+    assert np.any(h["fate"] == oracle.FATE_ROULETTE)
+    assert np.all(h["weight"] > 0) and np.all(h["E_final"] > 0)
+
+
 def test_forward_importance_of_a_pure_absorber():
     """Beam into a pure absorber: every transmitted particle entered every
     x-bin, so the forward estimate of bin g is exp(-Sigma_t (L - x_g)), x_g its
