@@ -146,6 +146,54 @@ def problem_set_bench(batches: int = 3):
             "set_ms_per_batch": set_s * 1e3, "sequential_ms_per_batch": seq_s * 1e3, "tuning": best}
 
 
+def fom_bench(analog_histories: int = 10_000_000, learned_histories: int = 1_000_000, batches: int = 20):
+    """Deep-penetration slab: figure of merit 1/(R^2 T) of the far-face leakage
+    with windows from the learned importance map against analog transport, the
+    two estimates checked for agreement within 3 sigma.  Also the linear
+    bootstrap windows, and the learned FOM with the generation and training
+    time added to T."""
+    import math
+
+    import mcsynth
+    from paper_2403_12345_amd import importance
+    from paper_2403_12345_amd.transport import Transport
+
+    prob = mcsynth.c5_problem()
+    seed = prob.seed
+    out = {"workload": "3-layer slab 100/10/90 cm, Sigma_t(2 MeV) 0.2/1.5/0.2 per cm, synthetic "
+                       "absorber/scatterers (10 nuclides), normal 2 MeV beam, detector = leakage through x = 200",
+           "analog_histories": analog_histories, "learned_histories": learned_histories, "batches": batches}
+    with Transport(prob) as t:
+        t.run_batch(seed, 0, 100_000)  # warm-up (allocation, first launches)
+        tic = time.perf_counter()
+        li = importance.learn(t, seed=seed, pilot=1_000_000, boot=250_000, steps=2000)
+        t_learn = time.perf_counter() - tic
+        an = importance.production(t, seed=seed + 1, histories=analog_histories, batches=batches,
+                                   windows="analog")
+        lin = importance.production(t, seed=seed + 2, histories=learned_histories, batches=batches,
+                                    windows="linear", lin=(0.0, li.slope, 0.0))
+        ml = importance.production(t, seed=seed + 3, histories=learned_histories, batches=batches,
+                                   windows="mlp", ln_range=li.ln_range)
+
+    def entry(p):
+        return {"mean": p.mean, "rel_err": p.rel, "seconds": p.seconds, "fom": p.fom,
+                "histories": p.histories, "splits_per_history": p.splits, "roulette_per_history": p.roulette}
+
+    out["analog"] = entry(an)
+    out["linear_bootstrap"] = entry(lin)
+    out["learned"] = entry(ml)
+    out["learn_seconds"] = t_learn
+    out["learn_breakdown"] = li.seconds
+    out["training_samples"] = li.n_samples[-1]
+    out["final_loss"] = float(li.loss_curves[-1][-1])
+    out["ln_importance_span"] = li.ln_range
+    out["gain_vs_analog"] = ml.fom / an.fom if an.fom > 0 else None
+    rel = ml.rel
+    out["learned_fom_incl_training"] = 1.0 / (rel * rel * (ml.seconds + t_learn)) if ml.mean > 0 else 0.0
+    out["agree_3sigma"] = bool(abs(ml.mean - an.mean) <= 3 * math.hypot(ml.stderr, an.stderr))
+    return out
+
+
 def copy_calibration(n_doubles: int = 1 << 28, reps: int = 5):
     """A plain device copy of known size (2 GiB read + 2 GiB written per launch),
     the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -173,7 +221,8 @@ def main():
     ap.add_argument("--no-inactive", action="store_true", help="skip the tally-off contrast batch")
     ap.add_argument("--no-lookup-bench", action="store_true", help="skip the 300-nuclide lookup benchmark")
     ap.add_argument("--no-problem-set", action="store_true", help="skip the 64-problem batching benchmark")
-    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set"), default="full",
+    ap.add_argument("--no-fom", action="store_true", help="skip the learned-importance figure-of-merit benchmark")
+    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom"), default="full",
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -195,6 +244,9 @@ def main():
         return
     if args.mode == "set":
         print(json.dumps({"problem_set": problem_set_bench()}), flush=True)
+        return
+    if args.mode == "fom":
+        print(json.dumps({"fom": fom_bench()}), flush=True)
         return
     prob = mcsynth.c2_problem()
     n = prob.histories
@@ -273,6 +325,8 @@ def main():
         line["lookup_microbench"] = lookup_microbench()
     if not args.no_problem_set:
         line["problem_set"] = problem_set_bench()
+    if not args.no_fom:
+        line["fom"] = fom_bench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, seed)
     print(json.dumps(line), flush=True)
