@@ -130,11 +130,14 @@ typedef struct mc_geometry_desc {
 
 /* Options of one mc_run_batch call (all-zero = defaults). */
 typedef struct mc_run_opts {
-    uint64_t in_flight;    /* particle-bank capacity; 0: min(n, 1,048,576).  The paper
-                              caps particles in flight and refills from the batch
-                              (section 2, "In-Flight Particles"). */
+    uint64_t in_flight;    /* particle-bank capacity; 0: min(n, 1,048,576), with weight
+                              windows min(max(4 n, 4096), 1,048,576) (copies take free
+                              slots).  The paper caps particles in flight and refills
+                              from the batch (section 2, "In-Flight Particles"). */
     uint64_t sort_min;     /* sort the lookup queue by (material, energy bin) when it holds
-                              at least this many particles; 0: 16,384; UINT64_MAX: never */
+                              at least this many particles; 0: 262,144; UINT64_MAX or
+                              2^30: never (tables that fit the caches gain less from the
+                              sort than it costs) */
     int32_t no_tally;      /* 1: inactive batch (no flux tallies scored); global tallies
                               are still scored */
     int32_t time_kernels;  /* 1: time every lookup launch with HIP events (mc_get_stats) */
@@ -167,7 +170,9 @@ typedef struct mc_stats {
     double lookup_ms;           /* summed lookup-kernel time (time_kernels = 1), ms */
     double batch_ms;            /* wall time of the batch on the stream, ms */
     uint64_t tail_particles;    /* particles finished by the one-launch tail (their
-                                   later lookups are not in the counters above) */
+                                   later lookups are not in the counters above; the
+                                   tail runs analog batches without an importance
+                                   grid only) */
 } mc_stats;
 
 /* Batch statistics of one tally bin range (mc_get_tallies). */
@@ -319,8 +324,8 @@ int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t
  *   tail_particles when no history remains to start and at most this many
  *                  particles are in flight, the remaining histories are
  *                  finished by one kernel launch in which each lane runs its
- *                  particle to the end (0: default 32,768; -1: never)
- *   sort_min       default of mc_run_opts.sort_min (0: 16,384)
+ *                  particle to the end (0: default 131,072; -1: never)
+ *   sort_min       default of mc_run_opts.sort_min (0: 262,144; 2^30: never)
  *   in_flight      default of mc_run_opts.in_flight (0: 1,048,576)
  *   set_tile_histories  histories per work item of the problem-set kernel,
  *                  a multiple of 256 (0: 256)
@@ -345,10 +350,10 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
 /*
  * Autotuner of the single-problem path: times one batch of n histories
  * (pids first_pid .. first_pid + n - 1, key seed) per candidate, searching one
- * parameter at a time over lookup_ilp {1, 2, 4}, tail_particles {8192, 32768,
- * 131072}, sort_min {4096, 16384, 65536} and in_flight {n/4, n/2, n} (capped
- * at 2^20), keeps the fastest in the context (mc_set_tuning) and returns it in
- * *best.  The tallies are reset afterwards.  cache_path (nullable) names a
+ * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
+ * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}
+ * and in_flight {n/4, n/2, n} (capped at 2^20), keeps the fastest in the
+ * context (mc_set_tuning) and returns it in *best.  The tallies are reset afterwards.  cache_path (nullable) names a
  * text file of one line per tuned problem: when it holds the signature of
  * this problem and device, the stored setting is used without timing; else
  * the result is appended.  Requires materials and geometry.

@@ -20,9 +20,10 @@ using namespace mc;
 namespace {
 
 constexpr uint64_t kDefaultInFlight = 1ull << 20;
-constexpr uint64_t kDefaultSortMin = 16384;
+constexpr uint64_t kDefaultSortMin = 262144;
+constexpr uint64_t kSortNever = 1ull << 30;  // no queue is that long: never sort
 constexpr int64_t kDefaultMaxEvents = 100000;
-constexpr int64_t kDefaultTailParticles = 32768;
+constexpr int64_t kDefaultTailParticles = 131072;
 
 struct Buffers {
     std::vector<void *> ptrs;
@@ -850,9 +851,10 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     uint64_t cap64 = opts.in_flight ? opts.in_flight
                                     : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight : kDefaultInFlight);
     // analog: no more slots than histories; with weight windows the copies
-    // of split particles take free slots too
+    // of split particles take free slots too (up to four per history)
     const bool windows = ctx->ww_desc.kind != MC_WW_OFF;
     if (!windows || opts.in_flight) cap64 = std::min(cap64, n);
+    else cap64 = std::min(cap64, std::max<uint64_t>(4 * n, 4096));
     if (cap64 > (1ull << 30)) return fail(ctx, MC_EINVAL, "in_flight above 2^30");
     const uint64_t sort_min = opts.sort_min ? opts.sort_min
                                             : (ctx->tune.sort_min > 0 ? (uint64_t)ctx->tune.sort_min : kDefaultSortMin);
@@ -1481,23 +1483,29 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     double best_ms = 0.0;
     rc = trial(cur, best_ms);  // warm-up (code and bank), then the baseline
     if (!rc) rc = trial(cur, best_ms);
+    // coordinate descent, two sweeps over the axes (tail and sort interact)
     const int32_t ilps[] = {1, 2, 4};
-    const int32_t tails[] = {8192, 32768, 131072};
-    const int32_t sorts[] = {4096, 16384, 65536};
+    const int32_t tails[] = {8192, 32768, 131072, 262144};
+    const int32_t sorts[] = {4096, 16384, 65536, 262144, (int32_t)kSortNever};
     const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), n_cap};
-    for (int axis = 0; axis < 4 && !rc; ++axis) {
-        for (int k = 0; k < 3 && !rc; ++k) {
-            mc_tuning c = cur;
-            if (axis == 0) c.lookup_ilp = ilps[k];
-            if (axis == 1) c.tail_particles = tails[k];
-            if (axis == 2) c.sort_min = sorts[k];
-            if (axis == 3) c.in_flight = std::min(flights[k], n_cap);
-            if (std::memcmp(&c, &cur, sizeof c) == 0) continue;
-            double ms = 0.0;
-            rc = trial(c, ms);
-            if (!rc && ms < best_ms) {
-                best_ms = ms;
-                cur = c;
+    const int32_t *axes[] = {tails, sorts, ilps, flights};
+    const int counts[] = {4, 5, 3, 3};
+    for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
+        for (int axis = 0; axis < 4 && !rc; ++axis) {
+            for (int k = 0; k < counts[axis] && !rc; ++k) {
+                mc_tuning c = cur;
+                const int32_t v = axes[axis][k];
+                if (axis == 0) c.tail_particles = v;
+                if (axis == 1) c.sort_min = v;
+                if (axis == 2) c.lookup_ilp = v;
+                if (axis == 3) c.in_flight = std::min(v, n_cap);
+                if (std::memcmp(&c, &cur, sizeof c) == 0) continue;
+                double ms = 0.0;
+                rc = trial(c, ms);
+                if (!rc && ms < best_ms) {
+                    best_ms = ms;
+                    cur = c;
+                }
             }
         }
     }

@@ -1225,7 +1225,8 @@ __global__ void __launch_bounds__(WG) k_ww_flush_scatter(BankDev b, WwDev W, Cou
     const uint32_t top = ctr->top;
     const bool fits = (uint64_t)top + tot[0] <= (uint64_t)W.Q;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->top_after = fits ? top + tot[0] : top;
-    if (!fits || tot[0] == 0) return;
+    // nothing to move, or nothing in this tile (its count is uniform over the block)
+    if (!fits || tot[0] == 0 || b.tile_cnt[blockIdx.x * 3] == 0) return;
     const uint32_t base = blockIdx.x * (uint32_t)TILE;
     uint32_t run = 0;
     for (int r = 0; r < TILE_ITEMS; ++r) {
