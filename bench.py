@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "active particles/s and macro-XS lookups/s (HBM GB/s % peak); FOM learned vs analog"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lookup_traffic_c2.json")
+# launch shapes found by the library's autotuner on an MI355X (its cache format:
+# one line per problem signature); missing or stale entries are tuned afresh
+TUNING_CACHE = os.path.join(ROOT, "paper_2403_12345_amd", "tuning_cache.txt")
 
 
 def kernel_source_digest() -> str:
@@ -221,6 +224,7 @@ def main():
     ap.add_argument("--no-lookup-bench", action="store_true", help="skip the 300-nuclide lookup benchmark")
     ap.add_argument("--no-problem-set", action="store_true", help="skip the 64-problem batching benchmark")
     ap.add_argument("--no-fom", action="store_true", help="skip the learned-importance figure-of-merit benchmark")
+    ap.add_argument("--tuning-cache", default=TUNING_CACHE, help="autotuner cache file")
     ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom"), default="full",
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
@@ -253,8 +257,9 @@ def main():
     n = prob.histories
     seed = prob.seed
     t = Transport(prob, device=0)
-    # launch shapes from the library's autotuner (timed on batches of other pids)
-    tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n)
+    # launch shapes from the library's autotuner (from its cache when this
+    # problem was tuned on this device kind, else timed on batches of other pids)
+    tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n, args.tuning_cache)
     for w in range(args.warmup):
         t.run_batch(seed, w * n, n)
     t.reset()
