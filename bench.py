@@ -148,7 +148,8 @@ def problem_set_bench(batches: int = 3):
             "set_ms_per_batch": set_s * 1e3, "sequential_ms_per_batch": seq_s * 1e3, "tuning": best}
 
 
-def fom_bench(analog_histories: int = 10_000_000, learned_histories: int = 1_000_000, batches: int = 20):
+def fom_bench(analog_histories: int = 40_000_000, learned_histories: int = 4_000_000, analog_batches: int = 40,
+              batches: int = 20):
     """Deep-penetration slab: figure of merit 1/(R^2 T) of the far-face leakage
     with windows from the learned importance map (bootstrap, training, one
     refinement round) against analog transport, the two estimates checked for
@@ -164,13 +165,14 @@ def fom_bench(analog_histories: int = 10_000_000, learned_histories: int = 1_000
     seed = prob.seed
     out = {"workload": "3-layer slab 100/10/90 cm, Sigma_t(2 MeV) 0.2/1.5/0.2 per cm, synthetic "
                        "absorber/scatterers (10 nuclides), normal 2 MeV beam, detector = leakage through x = 200",
-           "analog_histories": analog_histories, "learned_histories": learned_histories, "batches": batches}
+           "analog_histories": analog_histories, "learned_histories": learned_histories,
+           "analog_batches": analog_batches, "batches": batches}
     with Transport(prob) as t:
         t.run_batch(seed, 0, 100_000)  # warm-up (allocation, first launches)
         tic = time.perf_counter()
         li = importance.learn(t, seed=seed, pilot=1_000_000, boot=250_000, steps=2000, refine=1)
         t_learn = time.perf_counter() - tic
-        an = importance.production(t, seed=seed + 1, histories=analog_histories, batches=batches,
+        an = importance.production(t, seed=seed + 1, histories=analog_histories, batches=analog_batches,
                                    windows="analog")
         lin = importance.production(t, seed=seed + 2, histories=learned_histories, batches=batches,
                                     windows="linear", lin=(0.0, li.slope, 0.0))

@@ -14,7 +14,7 @@ namespace mc {
 
 constexpr int WG = 256;          // threads per workgroup of every event kernel
 constexpr int WAVES = WG / 64;   // wave64
-constexpr int TILE_ITEMS = 16;   // items per thread in the queue-building kernels
+constexpr int TILE_ITEMS = 4;    // items per thread in the queue-building kernels
 constexpr int TILE = WG * TILE_ITEMS;
 constexpr int MAX_LDS_BINS = 1024;  // tallies with more bins use the mesh path
 
