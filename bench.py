@@ -71,7 +71,36 @@ def cpu_baseline(prob, seed: int, target_s: float = 12.0):
                       f"history-based OpenMP over {threads} threads, {t2:.1f} s"}
 
 
-def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(2,)):
+def c3_transport(tuning_cache: str, histories: int = 20_000_000, tune_histories: int = 2_000_000, prob=None):
+    """One batch of the lookup-bound scale case: 15x15 assemblies of 17x17 pins
+    (255x255 lattice), one material of 300 nuclides (605 MB of tables), 2e7
+    histories with 1e6 in flight, 100x100x10 mesh flux tally; launch shapes
+    from the autotuner (tuned on batches of 2e6 histories)."""
+    import mcsynth
+    from paper_2403_12345_amd import mc
+    from paper_2403_12345_amd.transport import Transport
+
+    prob = prob if prob is not None else mcsynth.c3_problem()
+    with Transport(prob, device=0) as t:
+        tuning = mc.mc_autotune(t.ctx, prob.seed, 1 << 40, tune_histories, tuning_cache)
+        t.run_batch(prob.seed, 0, histories, time_kernels=True)
+        s = t.stats()
+        mesh, _, _ = t.tallies(mc.MC_T_FLUX_TRACK)
+        glob, _, _ = t.tallies(mc.MC_T_GLOBAL)
+    sec = s["batch_ms"] / 1e3
+    lk = s["lookup_ms"] / 1e3
+    gbs = s["lookup_bytes"] / lk / 1e9 if lk > 0 else 0.0
+    return {"workload": "255x255 pin lattice (15x15 assemblies of 17x17), one material of 300 synthetic nuclides "
+                        "(grids of 20k-150k points, 605 MB), uniform 2 MeV source, 2e7 histories per batch, "
+                        "100x100x10 mesh flux tally",
+            "histories": histories, "particles_per_s": histories / sec, "batch_s": sec,
+            "lookups": s["lookups"], "lookups_per_s_insitu": s["lookups"] / sec,
+            "lookup_kernel_s": lk, "lookup_GBs": gbs, "lookup_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "sorted_lookups": s["sorted_lookups"], "iterations": s["iterations"],
+            "mesh_track_sum": float(mesh.sum()), "total_track": float(glob[0]), "tuning": tuning}
+
+
+def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(2,), prob=None):
     """Stand-alone lookup of n (energy, material) pairs on the 300-nuclide
     material (grids of 20k-150k points, ~0.6 GB of tables, far above the
     on-chip caches): the lookup-bound case, unsorted and sorted, for each
@@ -83,7 +112,7 @@ def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(2,)):
     from paper_2403_12345_amd import mc
     from paper_2403_12345_amd.transport import Transport
 
-    prob = mcsynth.c3_problem()
+    prob = prob if prob is not None else mcsynth.c3_problem()
     rng = np.random.default_rng(12345)
     E = torch.from_numpy(mcsynth.lookup_energies(rng, n)).cuda()
     M = torch.zeros(n, dtype=torch.int32, device="cuda")
@@ -226,8 +255,9 @@ def main():
     ap.add_argument("--no-lookup-bench", action="store_true", help="skip the 300-nuclide lookup benchmark")
     ap.add_argument("--no-problem-set", action="store_true", help="skip the 64-problem batching benchmark")
     ap.add_argument("--no-fom", action="store_true", help="skip the learned-importance figure-of-merit benchmark")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 300-nuclide lattice transport batch")
     ap.add_argument("--tuning-cache", default=TUNING_CACHE, help="autotuner cache file")
-    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom"), default="full",
+    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom", "c3"), default="full",
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -252,6 +282,9 @@ def main():
         return
     if args.mode == "fom":
         print(json.dumps({"fom": fom_bench()}), flush=True)
+        return
+    if args.mode == "c3":
+        print(json.dumps({"c3_transport": c3_transport(args.tuning_cache)}), flush=True)
         return
     from paper_2403_12345_amd import mc
 
@@ -332,8 +365,11 @@ def main():
         "iterations_per_step": tot["iterations"] / args.steps,
         "inactive_particles_per_s": inactive,
     }
+    c3 = mcsynth.c3_problem() if not (args.no_lookup_bench and args.no_c3) else None
     if not args.no_lookup_bench:
-        line["lookup_microbench"] = lookup_microbench()
+        line["lookup_microbench"] = lookup_microbench(prob=c3)
+    if not args.no_c3:
+        line["c3_transport"] = c3_transport(args.tuning_cache, prob=c3)
     if not args.no_problem_set:
         line["problem_set"] = problem_set_bench()
     if not args.no_fom:

@@ -285,6 +285,22 @@ def c1_problem(data_seed: int = 1001, seed: int = 1, histories: int = 10_000,
                    histories=histories, batches=batches, seed=seed)
 
 
+def infinite_many_nuclides_problem(n_nuclides: int = 60, data_seed: int = 1101, seed: int = 7,
+                                   histories: int = 4000, n_points: int = 2000) -> Problem:
+    """Infinite medium of one material of many synthetic nuclides (the first
+    hydrogen-like at half of Sigma_t(2 MeV)), log-uniform grids, isotropic 2 MeV
+    point source, 50-bin energy flux tally (the C1 set-up with a larger
+    material)."""
+    rng = np.random.default_rng(data_seed)
+    awrs = np.concatenate([[1.0], rng.uniform(2.0, 240.0, n_nuclides - 1)])
+    nucs = [make_nuclide(rng, float(a), n_points, "loguniform") for a in awrs]
+    mat = make_material(rng, nucs, np.arange(n_nuclides), 0.5, fixed_fraction=(0, 0.5))
+    return Problem(name=f"infinite_{n_nuclides}nuc", nuclides=nucs, materials=[mat],
+                   geometry=Geometry(kind=GEOM_INFINITE, material=0),
+                   source=Source(kind=SRC_POINT), tally=Tally(TALLY_ENERGY, energy_edges(50)),
+                   histories=histories, batches=1, seed=seed)
+
+
 def c1_constant_problem(sig_c: float, sig_s: float, awr: float = 1.0, density: float = 0.01,
                         seed: int = 11, histories: int = 10_000, batches: int = 10,
                         n_bins: int = 50) -> Problem:

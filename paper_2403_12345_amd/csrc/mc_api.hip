@@ -682,6 +682,7 @@ static int ensure_bank(mc_ctx *ctx, uint32_t cap)
     double **dd[] = {&b.x, &b.y, &b.z, &b.u, &b.v, &b.w, &b.E, &b.wt, &b.Sa, &b.Ss, &b.track};
     for (double **p : dd)
         if (!rc) rc = dalloc(ctx, B, p, cap);
+    if (!rc) rc = dalloc(ctx, B, &b.cp, (size_t)CP_MAX * cap);
     int32_t **ii[] = {&b.mat, &b.cell, &b.ncoll, &b.ncross};
     for (int32_t **p : ii)
         if (!rc) rc = dalloc(ctx, B, p, cap);
@@ -933,6 +934,8 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
             l.flags = b.flags;
             l.nuc_count = ctx->dstat;
             l.ilp = lookup_ilp(ctx);
+            l.cp = b.cp;
+            l.cp_slots = b.C;
             const bool sort = (uint64_t)c.nL >= sort_min && sort_min != UINT64_MAX;
             if (sort) {
                 HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, c.nL, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls,
@@ -959,7 +962,16 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         HIPCHK(launch_advance(b, g, tal, W, dc, c.nA, seed, max_events, log ? 1 : 0, st));
         HIPCHK(launch_split(b, dc, c.nA, st));
         HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
-        HIPCHK(launch_collide(b, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
+        // collisions re-gather sigma_s: in (material, energy) order when the
+        // queues are long enough to sort (the sorted lookup queue is no longer
+        // needed, its buffers take the sorted collide queue)
+        const uint32_t *qc = b.Qc;
+        if ((uint64_t)c.nA >= sort_min && sort_min != UINT64_MAX) {
+            HIPCHK(launch_sort(ctx->xs, b.Qc, &dc->nC, c.nA, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls, b.Lkey,
+                               st));
+            qc = b.Ls;
+        }
+        HIPCHK(launch_collide(b, qc, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
         if (W.kind != WW_OFF) HIPCHK(launch_ww_flush(b, W, dc, st));
     }
     // batch statistics: per-workgroup rows summed in a fixed order

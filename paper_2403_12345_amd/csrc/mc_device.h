@@ -80,7 +80,25 @@ struct GeomDev {
 };
 
 // Structure-of-arrays particle bank (capacity C slots) and its queues.
+// Checkpoints of the running sum of N_k sigma_s,k over a material's nuclides
+// (material order), written by the lookup for materials of more than
+// CP_MIN_NUC nuclides: checkpoint j holds the sum over nuclides
+// [0, (j + 1) S), S = cp_stride(nk), at most CP_MAX of them.  The collision
+// starts its walk for the sampled nuclide at the checkpoint before the target
+// instead of at nuclide 0: the same partial sums, far fewer gathers.
+constexpr int CP_MAX = 16, CP_MIN_NUC = 16;
+__host__ __device__ __forceinline__ int32_t cp_stride(int32_t nk)
+{
+    const int32_t s = (nk + CP_MAX - 1) / CP_MAX;
+    return s < 8 ? 8 : s;
+}
+__host__ __device__ __forceinline__ int32_t cp_count(int32_t nk)
+{
+    return nk > CP_MIN_NUC ? nk / cp_stride(nk) : 0;
+}
+
 struct BankDev {
+    double *cp;  // [CP_MAX][slot] checkpoints of the scattering sum (see above)
     double *x, *y, *z, *u, *v, *w, *E, *wt, *Sa, *Ss, *track;
     int32_t *mat, *cell, *ncoll, *ncross;
     uint8_t *flags, *inside, *event;

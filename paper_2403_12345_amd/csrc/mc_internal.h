@@ -24,6 +24,8 @@ struct LookupLaunch {
     double *sc_out = nullptr, *ss_out = nullptr;
     unsigned long long *nuc_count = nullptr;
     int32_t ilp = 4;  // nuclides looked up in lockstep per lane (1, 2 or 4)
+    double *cp = nullptr;     // scattering-sum checkpoints (transport lookups only)
+    uint32_t cp_slots = 0;    // slots of the bank
 };
 
 hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);
@@ -54,9 +56,9 @@ hipError_t launch_split(const BankDev &b, Counters *ctr, uint32_t n_bound, hipSt
 hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
                         uint32_t n_bound, uint64_t seed, HistLog *log, uint64_t first_pid, unsigned long long *lost,
                         hipStream_t st);
-hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
-                          const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
-                          uint64_t first_pid, hipStream_t st);
+hipError_t launch_collide(const BankDev &b, const uint32_t *list, const XsDev &xs, const GeomDev &g,
+                          const TallyDev &t, const WwDev &W, const Counters *ctr, uint32_t n_bound, uint64_t seed,
+                          HistLog *log, uint64_t first_pid, hipStream_t st);
 hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const Counters *ctr,
                        uint32_t n_bound, uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
                        unsigned long long *lost, hipStream_t st);

@@ -433,6 +433,8 @@ struct LookupArgs {
     int32_t *idx_out;         // nullable, per nuclide [p * nk + q]
     double *sc_out, *ss_out;  // nullable, per nuclide
     unsigned long long *nuc_count;  // nullable: adds sum of nk over the queue
+    double *cp;               // nullable: scattering-sum checkpoints [CP_MAX][cp_slots]
+    uint32_t cp_slots;        // slots of the bank
 };
 
 constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
@@ -497,6 +499,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     const int32_t nk = xs.mat_off[m + 1] - q0;
     double sa = 0.0, ss = 0.0;
     const MatNuc *mnuc = xs.mnuc + q0;
+    const int32_t cps = cp_stride(nk), ncp = a.cp ? cp_count(nk) : 0;
     // the nuclide loop, once with the brackets in LDS and once in global memory
     auto nuclides = [&](const uint32_t *h0) {
         for (int32_t q = 0; q < nk; q += ILP) {
@@ -510,6 +513,8 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
                 if (k < cnt) {
                     sa = sa + dens[k] * c[k];
                     ss = ss + dens[k] * s[k];
+                    const int32_t done = q + k + 1;
+                    if (done % cps == 0 && done / cps <= ncp) a.cp[(size_t)(done / cps - 1) * a.cp_slots + p] = ss;
                     if (a.idx_out) a.idx_out[(size_t)p * nk + q + k] = (int32_t)ix[k];
                     if (a.sc_out) a.sc_out[(size_t)p * nk + q + k] = c[k];
                     if (a.ss_out) a.ss_out[(size_t)p * nk + q + k] = s[k];
@@ -706,9 +711,11 @@ __global__ void __launch_bounds__(WG) k_cross(BankDev b, GeomDev g, TallyDev tal
 // ---------------------------------------------------------------------------
 // collision: analog capture or elastic scattering off a target at rest
 // ---------------------------------------------------------------------------
+// `list` is the collide queue, in split order or sorted by (material, hash
+// bin of E) so that the gathers of neighbouring lanes share cache lines.
 template <int WWK>
-__global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, TallyDev tal, WwDev W,
-                                                const Counters *ctr, uint64_t seed, HistLog *log,
+__global__ void __launch_bounds__(WG) k_collide(BankDev b, const uint32_t *list, XsDev xs, GeomDev g, TallyDev tal,
+                                                WwDev W, const Counters *ctr, uint64_t seed, HistLog *log,
                                                 uint64_t first_pid)
 {
     extern __shared__ double slab[];
@@ -724,9 +731,9 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, XsDev xs, GeomDev g, 
     uint32_t s = 0;
     int32_t fate = 0;
     if (act) {
-        s = b.Qc[i];
+        s = list[i];
         p = load_particle(b, s);
-        fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc);
+        fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc, b.cp, b.C, s);
         if (fate == 0 && W.imp_nx) imp_enter(W, s, p.x, p.x, p.E, p.wt);
     }
     if constexpr (WWK != WW_OFF) {
@@ -786,7 +793,7 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
-                fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc);
+                fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr, 0u, 0u);
                 need = fate == 0;
             } else {
                 bool leak_xhi;
@@ -1095,6 +1102,8 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     a.sc_out = l.sc_out;
     a.ss_out = l.ss_out;
     a.nuc_count = l.nuc_count;
+    a.cp = l.cp;
+    a.cp_slots = l.cp_slots;
     const dim3 grid(blocks_for(l.n_bound, WG));
     switch (l.ilp) {
     case 1: hipLaunchKernelGGL(k_lookup<1>, grid, dim3(WG), 0, st, a); break;
@@ -1143,22 +1152,25 @@ hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, c
     return hipGetLastError();
 }
 
-hipError_t launch_collide(const BankDev &b, const XsDev &xs, const GeomDev &g, const TallyDev &t, const WwDev &W,
-                          const Counters *ctr, uint32_t n_bound, uint64_t seed, HistLog *log,
-                          uint64_t first_pid, hipStream_t st)
+hipError_t launch_collide(const BankDev &b, const uint32_t *list, const XsDev &xs, const GeomDev &g,
+                          const TallyDev &t, const WwDev &W, const Counters *ctr, uint32_t n_bound, uint64_t seed,
+                          HistLog *log, uint64_t first_pid, hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
     const dim3 grid(blocks_for(n_bound, WG));
     switch (W.kind) {
     case WW_LINEAR:
-        hipLaunchKernelGGL(k_collide<WW_LINEAR>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, log, first_pid);
+        hipLaunchKernelGGL(k_collide<WW_LINEAR>, grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
+                           first_pid);
         break;
     case WW_MLP:
-        hipLaunchKernelGGL(k_collide<WW_MLP>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, log, first_pid);
+        hipLaunchKernelGGL(k_collide<WW_MLP>, grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
+                           first_pid);
         break;
     default:
-        hipLaunchKernelGGL(k_collide<WW_OFF>, grid, dim3(WG), lds, st, b, xs, g, t, W, ctr, seed, log, first_pid);
+        hipLaunchKernelGGL(k_collide<WW_OFF>, grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
+                           first_pid);
         break;
     }
     return hipGetLastError();

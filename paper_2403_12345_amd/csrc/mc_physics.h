@@ -333,10 +333,14 @@ __device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc,
 // Collision: collision estimator; analog capture when xi * Sigma_t < Sigma_a;
 // otherwise the target is the first nuclide whose running sum of
 // density * sigma_s reaches xi * Sigma_s (sigma_s gathered again, material
-// order), elastic scattering off it at rest with an isotropic centre-of-mass
-// cosine, and the energy cutoff.  Returns FATE_ABSORBED, FATE_CUTOFF or 0.
+// order; with checkpoints of that running sum from the particle's lookup --
+// cp != nullptr, slot s of cp_slots -- the walk starts at the last checkpoint
+// below the target, with the same partial sum), elastic scattering off it at
+// rest with an isotropic centre-of-mass cosine, and the energy cutoff.
+// Returns FATE_ABSORBED, FATE_CUTOFF or 0.
 __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev &g, uint64_t seed,
-                                     bool tally_on, double *mesh_coll, StepScore &sc)
+                                     bool tally_on, double *mesh_coll, StepScore &sc, const double *cp,
+                                     uint32_t cp_slots, uint32_t s)
 {
     const double st = p.Sa + p.Ss;
     p.ncoll += 1;
@@ -364,10 +368,21 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
     const uint32_t *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
     double cum = 0.0;
-    int32_t pick = -1;
+    int32_t pick = -1, qstart = 0;
+    const int32_t ncp = cp ? cp_count(nk) : 0;
+    if (ncp > 0) {
+        // the first checkpoint at or above the target bounds the segment
+        const int32_t cps = cp_stride(nk);
+        int32_t j = 0;
+        while (j < ncp && cp[(size_t)j * cp_slots + s] < target) ++j;
+        if (j > 0) {
+            cum = cp[(size_t)(j - 1) * cp_slots + s];
+            qstart = j * cps;
+        }
+    }
     bool done = false;
     constexpr int CILP = DEFAULT_LOOKUP_ILP;
-    for (int32_t q = 0; q < nk && !done; q += CILP) {
+    for (int32_t q = qstart; q < nk && !done; q += CILP) {
         const int32_t cnt = nk - q < CILP ? nk - q : CILP;
         double dens[CILP], c[CILP], sg[CILP];
         uint32_t ix[CILP];

@@ -70,6 +70,22 @@ def test_c1_histories_identical_to_oracle(torch_cuda, in_flight, tail):
     assert np.all(g["fate"] > 0)
 
 
+@pytest.mark.parametrize("n_nuc,in_flight", [(60, 0), (300, 997)])
+def test_many_nuclide_histories_identical_to_oracle(torch_cuda, n_nuc, in_flight):
+    """Materials of more than 16 nuclides: the collision starts its walk for the
+    target nuclide at a checkpoint of the running scattering sum written by the
+    lookup; the histories must still be the oracle's, collision for
+    collision."""
+    torch = torch_cuda
+    prob = mcsynth.infinite_many_nuclides_problem(n_nuclides=n_nuc, histories=3000)
+    _say(f"infinite medium of {n_nuc} nuclides, identity, in_flight={in_flight}")
+    with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, tail_particles=-1, sort_min=1024)
+        g = _gpu_histories(torch, t, 7, 0, prob.histories, in_flight=in_flight)
+    o = oracle.run(oracle.OracleProblem(prob), 7, 0, prob.histories, history=True).history
+    _compare_histories(g, o)
+
+
 def test_c1_same_seed_tallies_match_oracle_to_rounding(torch_cuda):
     """Same seed and pids: identical histories, so the batch tallies differ only
     in summation order and the last ulp of ln(xi)."""
