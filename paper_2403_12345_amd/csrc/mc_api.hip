@@ -935,7 +935,6 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
             l.nuc_count = ctx->dstat;
             l.ilp = lookup_ilp(ctx);
             l.cp = b.cp;
-            l.cp_slots = b.C;
             const bool sort = (uint64_t)c.nL >= sort_min && sort_min != UINT64_MAX;
             if (sort) {
                 HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, c.nL, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls,

@@ -98,7 +98,7 @@ __host__ __device__ __forceinline__ int32_t cp_count(int32_t nk)
 }
 
 struct BankDev {
-    double *cp;  // [CP_MAX][slot] checkpoints of the scattering sum (see above)
+    double *cp;  // [slot][CP_MAX] checkpoints of the scattering sum (see above): one row per slot
     double *x, *y, *z, *u, *v, *w, *E, *wt, *Sa, *Ss, *track;
     int32_t *mat, *cell, *ncoll, *ncross;
     uint8_t *flags, *inside, *event;

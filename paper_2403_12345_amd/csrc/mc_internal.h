@@ -24,8 +24,7 @@ struct LookupLaunch {
     double *sc_out = nullptr, *ss_out = nullptr;
     unsigned long long *nuc_count = nullptr;
     int32_t ilp = 4;  // nuclides looked up in lockstep per lane (1, 2 or 4)
-    double *cp = nullptr;     // scattering-sum checkpoints (transport lookups only)
-    uint32_t cp_slots = 0;    // slots of the bank
+    double *cp = nullptr;     // scattering-sum checkpoints [slot][CP_MAX] (transport lookups only)
 };
 
 hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);

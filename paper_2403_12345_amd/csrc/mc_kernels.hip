@@ -433,8 +433,7 @@ struct LookupArgs {
     int32_t *idx_out;         // nullable, per nuclide [p * nk + q]
     double *sc_out, *ss_out;  // nullable, per nuclide
     unsigned long long *nuc_count;  // nullable: adds sum of nk over the queue
-    double *cp;               // nullable: scattering-sum checkpoints [CP_MAX][cp_slots]
-    uint32_t cp_slots;        // slots of the bank
+    double *cp;               // nullable: scattering-sum checkpoints [slot][CP_MAX]
 };
 
 constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
@@ -500,6 +499,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     double sa = 0.0, ss = 0.0;
     const MatNuc *mnuc = xs.mnuc + q0;
     const int32_t cps = cp_stride(nk), ncp = a.cp ? cp_count(nk) : 0;
+    int32_t next_cp = ncp > 0 ? cps : nk + 1, jcp = 0;  // nuclides done at the next checkpoint
     // the nuclide loop, once with the brackets in LDS and once in global memory
     auto nuclides = [&](const uint32_t *h0) {
         for (int32_t q = 0; q < nk; q += ILP) {
@@ -513,8 +513,11 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
                 if (k < cnt) {
                     sa = sa + dens[k] * c[k];
                     ss = ss + dens[k] * s[k];
-                    const int32_t done = q + k + 1;
-                    if (done % cps == 0 && done / cps <= ncp) a.cp[(size_t)(done / cps - 1) * a.cp_slots + p] = ss;
+                    if (q + k + 1 == next_cp) {  // a checkpoint of the scattering sum
+                        a.cp[(size_t)p * CP_MAX + jcp] = ss;
+                        ++jcp;
+                        next_cp = jcp < ncp ? next_cp + cps : nk + 1;
+                    }
                     if (a.idx_out) a.idx_out[(size_t)p * nk + q + k] = (int32_t)ix[k];
                     if (a.sc_out) a.sc_out[(size_t)p * nk + q + k] = c[k];
                     if (a.ss_out) a.ss_out[(size_t)p * nk + q + k] = s[k];
@@ -733,7 +736,7 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, const uint32_t *list,
     if (act) {
         s = list[i];
         p = load_particle(b, s);
-        fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc, b.cp, b.C, s);
+        fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc, b.cp ? b.cp + (size_t)s * CP_MAX : nullptr);
         if (fate == 0 && W.imp_nx) imp_enter(W, s, p.x, p.x, p.E, p.wt);
     }
     if constexpr (WWK != WW_OFF) {
@@ -793,7 +796,7 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
-                fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr, 0u, 0u);
+                fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr);
                 need = fate == 0;
             } else {
                 bool leak_xhi;
@@ -1103,7 +1106,6 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     a.ss_out = l.ss_out;
     a.nuc_count = l.nuc_count;
     a.cp = l.cp;
-    a.cp_slots = l.cp_slots;
     const dim3 grid(blocks_for(l.n_bound, WG));
     switch (l.ilp) {
     case 1: hipLaunchKernelGGL(k_lookup<1>, grid, dim3(WG), 0, st, a); break;

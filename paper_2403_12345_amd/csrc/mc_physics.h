@@ -334,13 +334,12 @@ __device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc,
 // otherwise the target is the first nuclide whose running sum of
 // density * sigma_s reaches xi * Sigma_s (sigma_s gathered again, material
 // order; with checkpoints of that running sum from the particle's lookup --
-// cp != nullptr, slot s of cp_slots -- the walk starts at the last checkpoint
+// cp != nullptr, the particle's row -- the walk starts at the last checkpoint
 // below the target, with the same partial sum), elastic scattering off it at
 // rest with an isotropic centre-of-mass cosine, and the energy cutoff.
 // Returns FATE_ABSORBED, FATE_CUTOFF or 0.
 __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev &g, uint64_t seed,
-                                     bool tally_on, double *mesh_coll, StepScore &sc, const double *cp,
-                                     uint32_t cp_slots, uint32_t s)
+                                     bool tally_on, double *mesh_coll, StepScore &sc, const double *cp)
 {
     const double st = p.Sa + p.Ss;
     p.ncoll += 1;
@@ -374,9 +373,9 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
         // the first checkpoint at or above the target bounds the segment
         const int32_t cps = cp_stride(nk);
         int32_t j = 0;
-        while (j < ncp && cp[(size_t)j * cp_slots + s] < target) ++j;
+        while (j < ncp && cp[j] < target) ++j;
         if (j > 0) {
-            cum = cp[(size_t)(j - 1) * cp_slots + s];
+            cum = cp[j - 1];
             qstart = j * cps;
         }
     }
