@@ -83,18 +83,22 @@ struct GeomDev {
 // Checkpoints of the running sum of N_k sigma_s,k over a material's nuclides
 // (material order), written by the lookup for materials of more than
 // CP_MIN_NUC nuclides: checkpoint j holds the sum over nuclides
-// [0, (j + 1) S), S = cp_stride(nk), at most CP_MAX of them.  The collision
-// starts its walk for the sampled nuclide at the checkpoint before the target
-// instead of at nuclide 0: the same partial sums, far fewer gathers.
+// [0, (j + 1) 2^sh), sh = cp_shift(nk) the smallest shift of at least 3 that
+// leaves at most CP_MAX of them.  The collision starts its walk for the
+// sampled nuclide at the checkpoint before the target instead of at nuclide
+// 0: the same partial sums, far fewer gathers.  (The rows are written by
+// scattered 8-byte stores, so a few checkpoints per lookup, not one per
+// nuclide: each store can cost the lookup a partial-line write-back.)
 constexpr int CP_MAX = 16, CP_MIN_NUC = 16;
-__host__ __device__ __forceinline__ int32_t cp_stride(int32_t nk)
+__host__ __device__ __forceinline__ int32_t cp_shift(int32_t nk)
 {
-    const int32_t s = (nk + CP_MAX - 1) / CP_MAX;
-    return s < 8 ? 8 : s;
+    int32_t sh = 3;
+    while ((nk >> sh) > CP_MAX) ++sh;
+    return sh;
 }
 __host__ __device__ __forceinline__ int32_t cp_count(int32_t nk)
 {
-    return nk > CP_MIN_NUC ? nk / cp_stride(nk) : 0;
+    return nk > CP_MIN_NUC ? nk >> cp_shift(nk) : 0;
 }
 
 struct BankDev {

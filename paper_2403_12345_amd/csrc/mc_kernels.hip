@@ -438,7 +438,9 @@ struct LookupArgs {
 
 constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
 
-template <int ILP>
+// DIAG: the per-nuclide outputs (idx_out, sc_out, ss_out) may be set; the
+// transport's lookups run without them, in fewer registers.
+template <int ILP, bool DIAG>
 __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 {
     __shared__ uint32_t sh[LDS_HASH_WORDS];
@@ -498,8 +500,8 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     const int32_t nk = xs.mat_off[m + 1] - q0;
     double sa = 0.0, ss = 0.0;
     const MatNuc *mnuc = xs.mnuc + q0;
-    const int32_t cps = cp_stride(nk), ncp = a.cp ? cp_count(nk) : 0;
-    int32_t next_cp = ncp > 0 ? cps : nk + 1, jcp = 0;  // nuclides done at the next checkpoint
+    const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
+    const int32_t cp_mask = (1 << cp_sh) - 1;
     // the nuclide loop, once with the brackets in LDS and once in global memory
     auto nuclides = [&](const uint32_t *h0) {
         for (int32_t q = 0; q < nk; q += ILP) {
@@ -513,14 +515,13 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
                 if (k < cnt) {
                     sa = sa + dens[k] * c[k];
                     ss = ss + dens[k] * s[k];
-                    if (q + k + 1 == next_cp) {  // a checkpoint of the scattering sum
-                        a.cp[(size_t)p * CP_MAX + jcp] = ss;
-                        ++jcp;
-                        next_cp = jcp < ncp ? next_cp + cps : nk + 1;
+                    const int32_t done = q + k + 1;  // a checkpoint of the scattering sum
+                    if ((done & cp_mask) == 0) a.cp[(size_t)p * CP_MAX + ((done >> cp_sh) - 1)] = ss;
+                    if (DIAG) {
+                        if (a.idx_out) a.idx_out[(size_t)p * nk + q + k] = (int32_t)ix[k];
+                        if (a.sc_out) a.sc_out[(size_t)p * nk + q + k] = c[k];
+                        if (a.ss_out) a.ss_out[(size_t)p * nk + q + k] = s[k];
                     }
-                    if (a.idx_out) a.idx_out[(size_t)p * nk + q + k] = (int32_t)ix[k];
-                    if (a.sc_out) a.sc_out[(size_t)p * nk + q + k] = c[k];
-                    if (a.ss_out) a.ss_out[(size_t)p * nk + q + k] = s[k];
                 }
             }
         }
@@ -1107,10 +1108,18 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     a.nuc_count = l.nuc_count;
     a.cp = l.cp;
     const dim3 grid(blocks_for(l.n_bound, WG));
-    switch (l.ilp) {
-    case 1: hipLaunchKernelGGL(k_lookup<1>, grid, dim3(WG), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_lookup<2>, grid, dim3(WG), 0, st, a); break;
-    default: hipLaunchKernelGGL(k_lookup<4>, grid, dim3(WG), 0, st, a); break;
+    if (a.idx_out || a.sc_out || a.ss_out) {
+        switch (l.ilp) {
+        case 1: hipLaunchKernelGGL((k_lookup<1, true>), grid, dim3(WG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_lookup<2, true>), grid, dim3(WG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_lookup<4, true>), grid, dim3(WG), 0, st, a); break;
+        }
+    } else {
+        switch (l.ilp) {
+        case 1: hipLaunchKernelGGL((k_lookup<1, false>), grid, dim3(WG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_lookup<2, false>), grid, dim3(WG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_lookup<4, false>), grid, dim3(WG), 0, st, a); break;
+        }
     }
     return hipGetLastError();
 }

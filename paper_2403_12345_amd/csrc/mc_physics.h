@@ -371,12 +371,20 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
     const int32_t ncp = cp ? cp_count(nk) : 0;
     if (ncp > 0) {
         // the first checkpoint at or above the target bounds the segment
-        const int32_t cps = cp_stride(nk);
-        int32_t j = 0;
-        while (j < ncp && cp[j] < target) ++j;
+        // (checkpoints never decrease: bisection for the first cp[j] >= target)
+        int32_t j = 0, len = ncp;
+        while (len > 0) {
+            const int32_t half = len >> 1;
+            if (cp[j + half] < target) {
+                j += half + 1;
+                len -= half + 1;
+            } else {
+                len = half;
+            }
+        }
         if (j > 0) {
             cum = cp[j - 1];
-            qstart = j * cps;
+            qstart = j << cp_shift(nk);
         }
     }
     bool done = false;
