@@ -71,11 +71,11 @@ def cpu_baseline(prob, seed: int, target_s: float = 12.0):
                       f"history-based OpenMP over {threads} threads, {t2:.1f} s"}
 
 
-def c3_transport(tuning_cache: str, histories: int = 20_000_000, tune_histories: int = 2_000_000, prob=None):
+def c3_transport(tuning_cache: str, histories: int = 20_000_000, tune_histories: int = 20_000_000, prob=None):
     """One batch of the lookup-bound scale case: 15x15 assemblies of 17x17 pins
     (255x255 lattice), one material of 300 nuclides (605 MB of tables), 2e7
-    histories with 1e6 in flight, 100x100x10 mesh flux tally; launch shapes
-    from the autotuner (tuned on batches of 2e6 histories)."""
+    histories, 100x100x10 mesh flux tally; launch shapes (particles in flight
+    among them) from the autotuner, tuned on batches of the same size."""
     import mcsynth
     from paper_2403_12345_amd import mc
     from paper_2403_12345_amd.transport import Transport

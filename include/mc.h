@@ -130,10 +130,12 @@ typedef struct mc_geometry_desc {
 
 /* Options of one mc_run_batch call (all-zero = defaults). */
 typedef struct mc_run_opts {
-    uint64_t in_flight;    /* particle-bank capacity; 0: min(n, 1,048,576), with weight
+    uint64_t in_flight;    /* particle-bank capacity; 0: min(n, 4,194,304), with weight
                               windows min(max(4 n, 4096), 1,048,576) (copies take free
                               slots).  The paper caps particles in flight and refills
-                              from the batch (section 2, "In-Flight Particles"). */
+                              from the batch (section 2, "In-Flight Particles"); its
+                              GPUs peaked near 1e6, an MI355X keeps gaining to ~4e6
+                              on lookup-bound problems (denser sorted queues). */
     uint64_t sort_min;     /* sort the lookup queue by (material, energy bin) when it holds
                               at least this many particles; 0: 262,144; UINT64_MAX or
                               2^30: never (tables that fit the caches gain less from the
@@ -326,7 +328,8 @@ int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t
  *                  finished by one kernel launch in which each lane runs its
  *                  particle to the end (0: default 131,072; -1: never)
  *   sort_min       default of mc_run_opts.sort_min (0: 262,144; 2^30: never)
- *   in_flight      default of mc_run_opts.in_flight (0: 1,048,576)
+ *   in_flight      default of mc_run_opts.in_flight (0: 4,194,304; 1,048,576
+ *                  with weight windows)
  *   set_tile_histories  histories per work item of the problem-set kernel,
  *                  a multiple of 256 (0: 256)
  *   set_grid       persistent workgroups of the problem-set kernel (0: two
@@ -352,7 +355,8 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
  * (pids first_pid .. first_pid + n - 1, key seed) per candidate, searching one
  * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
  * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}
- * and in_flight {n/4, n/2, n} (capped at 2^20), keeps the fastest in the
+ * and in_flight {n/4, n/2, 2^20, 2^22, n} (each at most n and 2^24; the
+ * search starts from min(n, 2^22)), keeps the fastest in the
  * context (mc_set_tuning) and returns it in *best.  The tallies are reset afterwards.  cache_path (nullable) names a
  * text file of one line per tuned problem: when it holds the signature of
  * this problem and device, the stored setting is used without timing; else

@@ -19,7 +19,9 @@ using namespace mc;
 
 namespace {
 
-constexpr uint64_t kDefaultInFlight = 1ull << 20;
+constexpr uint64_t kDefaultInFlight = 1ull << 22;         // analog bank: more particles, denser sorted queues
+constexpr uint64_t kDefaultInFlightWindows = 1ull << 20;  // with weight windows (stacks of depth x slots)
+constexpr uint64_t kMaxTunedInFlight = 1ull << 24;
 constexpr uint64_t kDefaultSortMin = 262144;
 constexpr uint64_t kSortNever = 1ull << 30;  // no queue is that long: never sort
 constexpr int64_t kDefaultMaxEvents = 100000;
@@ -849,11 +851,12 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     HIPCHK(hipSetDevice(ctx->device));
     mc_run_opts opts{};
     if (opts_in) opts = *opts_in;
+    const bool windows = ctx->ww_desc.kind != MC_WW_OFF;
     uint64_t cap64 = opts.in_flight ? opts.in_flight
-                                    : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight : kDefaultInFlight);
+                                    : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight
+                                                               : (windows ? kDefaultInFlightWindows : kDefaultInFlight));
     // analog: no more slots than histories; with weight windows the copies
     // of split particles take free slots too (up to four per history)
-    const bool windows = ctx->ww_desc.kind != MC_WW_OFF;
     if (!windows || opts.in_flight) cap64 = std::min(cap64, n);
     else cap64 = std::min(cap64, std::max<uint64_t>(4 * n, 4096));
     if (cap64 > (1ull << 30)) return fail(ctx, MC_EINVAL, "in_flight above 2^30");
@@ -1483,8 +1486,8 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     mc_tuning cur{};
     int rc = mc_get_tuning(ctx, &cur);
     if (rc) return rc;
-    const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
-    cur.in_flight = n_cap;
+    const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kMaxTunedInFlight);
+    cur.in_flight = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
     auto trial = [&](const mc_tuning &c, double &ms) -> int {
         ctx->tune = c;
         const int r = mc_run_batch(ctx, seed, first_pid, n, nullptr);
@@ -1498,9 +1501,9 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t ilps[] = {1, 2, 4};
     const int32_t tails[] = {8192, 32768, 131072, 262144};
     const int32_t sorts[] = {4096, 16384, 65536, 262144, (int32_t)kSortNever};
-    const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), n_cap};
+    const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), 1 << 20, 1 << 22, n_cap};
     const int32_t *axes[] = {tails, sorts, ilps, flights};
-    const int counts[] = {4, 5, 3, 3};
+    const int counts[] = {4, 5, 3, 5};
     for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
         for (int axis = 0; axis < 4 && !rc; ++axis) {
             for (int k = 0; k < counts[axis] && !rc; ++k) {
