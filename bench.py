@@ -68,7 +68,41 @@ def cpu_baseline(prob, seed: int, target_s: float = 12.0):
     t2 = time.perf_counter() - t0
     return {"value": n2 / t2, "unit": "particles/s", "cores": threads, "kind": "oracle",
             "sample": f"histories [0, {n2}) of one batch of the same problem, seed {seed}, "
-                      f"history-based OpenMP over {threads} threads, {t2:.1f} s"}
+                      f"history-based OpenMP over {threads} threads, {t2:.1f} s",
+            "per_core": n2 / t2 / threads}
+
+
+def cpu_oracle_extra(c2, c3, target_s: float = 6.0):
+    """The oracle's other rates on the host: the 300-nuclide lattice on the
+    first pids of its batch (the full 2e7 would take hours) and macroscopic
+    lookups/s on log-uniform energies for the 30-nuclide fuel and the
+    300-nuclide material."""
+    import numpy as np
+
+    import mcsynth
+    import oracle
+    threads = oracle.max_threads()
+    op3 = oracle.OracleProblem(c3)
+    n1 = 2000
+    t0 = time.perf_counter()
+    oracle.run(op3, c3.seed, 0, n1)
+    t1 = time.perf_counter() - t0
+    n2 = int(max(n1, n1 * target_s / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.run(op3, c3.seed, 0, n2)
+    t2 = time.perf_counter() - t0
+    rng = np.random.default_rng(12345)
+    out = {"cores": threads, "kind": "oracle",
+           "c3_subset": {"particles_per_s": n2 / t2, "per_core": n2 / t2 / threads,
+                         "sample": f"histories [0, {n2}) of the 300-nuclide lattice batch, seed {c3.seed}, "
+                                   f"{t2:.1f} s"}}
+    for name, prob, n in (("c2_fuel_lookups_per_s", c2, 200_000), ("c3_lookups_per_s", c3, 20_000)):
+        op = op3 if prob is c3 else oracle.OracleProblem(prob)
+        E = mcsynth.lookup_energies(rng, n)
+        t0 = time.perf_counter()
+        oracle.macro_xs(op, np.zeros(n, np.int32), E)
+        out[name] = n / (time.perf_counter() - t0)
+    return out
 
 
 def c3_transport(tuning_cache: str, histories: int = 20_000_000, tune_histories: int = 20_000_000, prob=None):
@@ -376,6 +410,7 @@ def main():
         line["fom"] = fom_bench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, seed)
+        line["cpu_oracle"] = cpu_oracle_extra(prob, c3 if c3 is not None else mcsynth.c3_problem())
     print(json.dumps(line), flush=True)
 
 

@@ -774,6 +774,10 @@ struct TileRows {
     bool enabled;              // binned flux tallies on
 };
 
+// ILP: nuclides per lane in lockstep in the lookup and the collision's walk
+// (the tail runs few particles per compute unit: latency, not registers,
+// bounds it, so it takes more).
+template <int ILP>
 __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev &xs, const GeomDev &g,
                                 const TileRows &r, uint64_t seed, int64_t max_events, HistLog *log,
                                 uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl)
@@ -785,7 +789,7 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         clear_score(sc);
         int32_t fate = 0;
         if (alive && need) {
-            do_lookup<DEFAULT_LOOKUP_ILP>(p, xs);
+            do_lookup<ILP>(p, xs);
             need = false;
         }
         if (alive && (int64_t)p.ncoll + p.ncross >= max_events) {
@@ -797,7 +801,7 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
-                fate = do_collide(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr);
+                fate = do_collide<ILP>(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr);
                 need = fate == 0;
             } else {
                 bool leak_xhi;
@@ -812,6 +816,8 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         }
     }
 }
+
+constexpr int TAIL_ILP = 4;
 
 // Tail: when no history remains to start and few particles are in flight,
 // one launch finishes them (workgroup row = blockIdx.x); the histories are
@@ -844,7 +850,7 @@ __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, Tal
     r.mesh_coll = tal.mesh_coll;
     r.n_bins = tal.n_bins;
     r.enabled = tal.enabled != 0;
-    run_tile(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl);
+    run_tile<TAIL_ILP>(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl);
     if (i < n) b.flags[s] = 0;
 }
 
@@ -920,7 +926,8 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
             r.n_bins = P.g.n_bins;
             r.enabled = true;
             HistLog *log = set.log ? set.log + P.log_off : nullptr;
-            run_tile(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid, set.lost, slab, gl);
+            run_tile<DEFAULT_LOOKUP_ILP>(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid, set.lost, slab,
+                                         gl);
         }
     }
 }

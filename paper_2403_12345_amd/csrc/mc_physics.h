@@ -338,6 +338,7 @@ __device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc,
 // below the target, with the same partial sum), elastic scattering off it at
 // rest with an isotropic centre-of-mass cosine, and the energy cutoff.
 // Returns FATE_ABSORBED, FATE_CUTOFF or 0.
+template <int CILP = DEFAULT_LOOKUP_ILP>
 __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev &g, uint64_t seed,
                                      bool tally_on, double *mesh_coll, StepScore &sc, const double *cp)
 {
@@ -388,7 +389,6 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
         }
     }
     bool done = false;
-    constexpr int CILP = DEFAULT_LOOKUP_ILP;
     for (int32_t q = qstart; q < nk && !done; q += CILP) {
         const int32_t cnt = nk - q < CILP ? nk - q : CILP;
         double dens[CILP], c[CILP], sg[CILP];
