@@ -334,6 +334,10 @@ int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t
  *                  a multiple of 256 (0: 256)
  *   set_grid       persistent workgroups of the problem-set kernel (0: two
  *                  per compute unit)
+ *   collide_sort_min  sort the collide queue (by material and energy bin, for
+ *                  the collision's re-gathers) when at least this many
+ *                  particles are alive (0: the lookup queue's sort_min;
+ *                  2^30: never)
  */
 typedef struct mc_tuning {
     int32_t lookup_ilp;
@@ -342,7 +346,8 @@ typedef struct mc_tuning {
     int32_t in_flight;
     int32_t set_tile_histories;
     int32_t set_grid;
-    int32_t reserved[2];
+    int32_t collide_sort_min;
+    int32_t reserved;
 } mc_tuning;
 
 /* Set (mc_set_tuning) or read (mc_get_tuning) the context's launch shapes.
@@ -355,8 +360,9 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
  * (pids first_pid .. first_pid + n - 1, key seed) per candidate, searching one
  * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
  * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}
- * and in_flight {n/4, n/2, 2^20, 2^22, n} (each at most n and 2^24; the
- * search starts from min(n, 2^22)), keeps the fastest in the
+ * in_flight {n/4, n/2, 2^20, 2^22, n} (each at most n and 2^24; the
+ * search starts from min(n, 2^22)) and collide_sort_min {0, never}, keeps the
+ * fastest in the
  * context (mc_set_tuning) and returns it in *best.  The tallies are reset afterwards.  cache_path (nullable) names a
  * text file of one line per tuned problem: when it holds the signature of
  * this problem and device, the stored setting is used without timing; else

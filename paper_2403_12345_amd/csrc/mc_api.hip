@@ -862,6 +862,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     if (cap64 > (1ull << 30)) return fail(ctx, MC_EINVAL, "in_flight above 2^30");
     const uint64_t sort_min = opts.sort_min ? opts.sort_min
                                             : (ctx->tune.sort_min > 0 ? (uint64_t)ctx->tune.sort_min : kDefaultSortMin);
+    const uint64_t collide_sort_min = ctx->tune.collide_sort_min > 0 ? (uint64_t)ctx->tune.collide_sort_min : sort_min;
     const int64_t max_events = opts.max_events > 0 ? opts.max_events : kDefaultMaxEvents;
     HistLog *log = static_cast<HistLog *>(opts.history_log);
     const uint32_t cap = (uint32_t)cap64;
@@ -968,7 +969,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         // queues are long enough to sort (the sorted lookup queue is no longer
         // needed, its buffers take the sorted collide queue)
         const uint32_t *qc = b.Qc;
-        if ((uint64_t)c.nA >= sort_min && sort_min != UINT64_MAX) {
+        if ((uint64_t)c.nA >= collide_sort_min && collide_sort_min != UINT64_MAX) {
             HIPCHK(launch_sort(ctx->xs, b.Qc, &dc->nC, c.nA, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls, b.Lkey,
                                st));
             qc = b.Ls;
@@ -1055,7 +1056,8 @@ int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t)
     if (t->lookup_ilp != 0 && t->lookup_ilp != 1 && t->lookup_ilp != 2 && t->lookup_ilp != 4)
         return fail(ctx, MC_EINVAL, "lookup_ilp must be 0, 1, 2 or 4");
     if (t->tail_particles < -1) return fail(ctx, MC_EINVAL, "tail_particles must be >= -1");
-    if (t->sort_min < 0 || t->in_flight < 0 || t->set_grid < 0) return fail(ctx, MC_EINVAL, "negative tuning value");
+    if (t->sort_min < 0 || t->in_flight < 0 || t->set_grid < 0 || t->collide_sort_min < 0)
+        return fail(ctx, MC_EINVAL, "negative tuning value");
     if (t->set_tile_histories < 0 || t->set_tile_histories % WG != 0)
         return fail(ctx, MC_EINVAL, "set_tile_histories must be a multiple of 256");
     ctx->tune = *t;
@@ -1069,6 +1071,7 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t)
     t->lookup_ilp = lookup_ilp(ctx);
     t->tail_particles = (int32_t)tail_particles(ctx);
     if (!t->sort_min) t->sort_min = (int32_t)kDefaultSortMin;
+    if (!t->collide_sort_min) t->collide_sort_min = t->sort_min;
     if (!t->in_flight) t->in_flight = (int32_t)kDefaultInFlight;
     if (!t->set_tile_histories) t->set_tile_histories = WG;
     if (!t->set_grid) t->set_grid = 2 * ctx->n_cu;
@@ -1451,9 +1454,12 @@ static bool cache_lookup(const char *path, const std::string &sig, mc_tuning &t)
         char s[200];
         mc_tuning r{};
         double ms = 0.0;
-        if (std::sscanf(line, "%199s %d %d %d %d %d %d %lf", s, &r.lookup_ilp, &r.tail_particles, &r.sort_min,
-                        &r.in_flight, &r.set_tile_histories, &r.set_grid, &ms) == 8 &&
-            sig == s) {
+        // fields: signature, lookup_ilp, tail, sort_min, in_flight, set tile,
+        // set grid, best ms, collide_sort_min (absent in older lines: 0)
+        const int got = std::sscanf(line, "%199s %d %d %d %d %d %d %lf %d", s, &r.lookup_ilp, &r.tail_particles,
+                                    &r.sort_min, &r.in_flight, &r.set_tile_histories, &r.set_grid, &ms,
+                                    &r.collide_sort_min);
+        if ((got == 8 || got == 9) && sig == s) {
             t = r;
             found = true;
         }
@@ -1467,8 +1473,8 @@ static void cache_store(const char *path, const std::string &sig, const mc_tunin
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %.4f\n", sig.c_str(), t.lookup_ilp, t.tail_particles, t.sort_min,
-                 t.in_flight, t.set_tile_histories, t.set_grid, ms);
+    std::fprintf(f, "%s %d %d %d %d %d %d %.4f %d\n", sig.c_str(), t.lookup_ilp, t.tail_particles, t.sort_min,
+                 t.in_flight, t.set_tile_histories, t.set_grid, ms, t.collide_sort_min);
     std::fclose(f);
 }
 
@@ -1488,6 +1494,7 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     if (rc) return rc;
     const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kMaxTunedInFlight);
     cur.in_flight = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
+    cur.collide_sort_min = 0;  // follows sort_min unless the search turns it off
     auto trial = [&](const mc_tuning &c, double &ms) -> int {
         ctx->tune = c;
         const int r = mc_run_batch(ctx, seed, first_pid, n, nullptr);
@@ -1502,10 +1509,11 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t tails[] = {8192, 32768, 131072, 262144};
     const int32_t sorts[] = {4096, 16384, 65536, 262144, (int32_t)kSortNever};
     const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), 1 << 20, 1 << 22, n_cap};
-    const int32_t *axes[] = {tails, sorts, ilps, flights};
-    const int counts[] = {4, 5, 3, 5};
+    const int32_t csorts[] = {0, (int32_t)kSortNever};
+    const int32_t *axes[] = {tails, sorts, ilps, flights, csorts};
+    const int counts[] = {4, 5, 3, 5, 2};
     for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
-        for (int axis = 0; axis < 4 && !rc; ++axis) {
+        for (int axis = 0; axis < 5 && !rc; ++axis) {
             for (int k = 0; k < counts[axis] && !rc; ++k) {
                 mc_tuning c = cur;
                 const int32_t v = axes[axis][k];
@@ -1513,6 +1521,7 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
                 if (axis == 1) c.sort_min = v;
                 if (axis == 2) c.lookup_ilp = v;
                 if (axis == 3) c.in_flight = std::min(v, n_cap);
+                if (axis == 4) c.collide_sort_min = v;
                 if (std::memcmp(&c, &cur, sizeof c) == 0) continue;
                 double ms = 0.0;
                 rc = trial(c, ms);

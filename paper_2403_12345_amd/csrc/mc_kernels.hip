@@ -273,9 +273,26 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
 // Ranks come from ballots, not atomics, so the order is stable and the same
 // run to run.
 // ---------------------------------------------------------------------------
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = WG * RS_ITEMS;  // 4096 items per tile
-constexpr int RS_CHUNK = 16;            // tiles per chunk of the offset scan
+// Tiles of WG * items keys, items in [1, 16] chosen per sort so that a
+// queue of a few hundred thousand keys still spreads over ~1024 workgroups;
+// chunks of at least 16 tiles, at most 128 chunks for the one-workgroup scan.
+struct SortShape {
+    uint32_t items, tiles, chunk, chunks;
+};
+
+static SortShape sort_shape(uint32_t n)
+{
+    SortShape s;
+    const uint32_t per = 1024u * WG;
+    s.items = (n + per - 1) / per;
+    s.items = s.items < 1u ? 1u : (s.items > 16u ? 16u : s.items);
+    const uint32_t tile = s.items * WG;
+    s.tiles = (n + tile - 1) / tile;
+    s.chunk = (s.tiles + 127u) / 128u;
+    s.chunk = s.chunk < 16u ? 16u : s.chunk;
+    s.chunks = (s.tiles + s.chunk - 1) / s.chunk;
+    return s;
+}
 
 // Lanes of the wave holding the same 8-bit digit (0 for an invalid lane).
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid)
@@ -304,6 +321,7 @@ struct SortPassArgs {
     const uint32_t *n_ptr;
     uint32_t n_fixed;
     int32_t shift;
+    uint32_t items, chunk;     // keys per thread of a tile, tiles per chunk
     const uint32_t *keys_in;   // null on the first pass: keys computed from (E, mat) of vals_in
     uint32_t *keys_first;      // first pass: where the computed keys go
     const uint32_t *vals_in;   // null: identity
@@ -317,11 +335,11 @@ __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
 {
     __shared__ uint32_t h[256];
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
-    const uint32_t base = blockIdx.x * (uint32_t)RS_TILE;
+    const uint32_t base = blockIdx.x * a.items * (uint32_t)WG;
     if (base >= n) return;
     h[threadIdx.x] = 0u;
     __syncthreads();
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    for (uint32_t r = 0; r < a.items; ++r) {
         const uint32_t i = base + r * WG + threadIdx.x;
         const bool valid = i < n;
         uint32_t key = 0;
@@ -340,7 +358,7 @@ __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
     __syncthreads();
     const uint32_t c = h[threadIdx.x];
     a.tile_hist[blockIdx.x * 256 + threadIdx.x] = c;
-    if (c) atomicAdd(&a.chunk_total[(blockIdx.x / RS_CHUNK) * 256 + threadIdx.x], c);
+    if (c) atomicAdd(&a.chunk_total[(blockIdx.x / a.chunk) * 256 + threadIdx.x], c);
 }
 
 // chunk_off[c][d] = (items with digit < d) + (items of digit d in chunks < c);
@@ -349,12 +367,20 @@ __global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32
 {
     __shared__ uint32_t tot[256];
     const uint32_t d = threadIdx.x;
+    constexpr uint32_t B = 8;  // chunk totals loaded together (independent loads in flight)
     uint32_t run = 0;
-    for (uint32_t c = 0; c < n_chunks; ++c) {
-        const uint32_t v = chunk_total[c * 256 + d];
-        chunk_off[c * 256 + d] = run;
-        chunk_total[c * 256 + d] = 0u;
-        run += v;
+    for (uint32_t c0 = 0; c0 < n_chunks; c0 += B) {
+        uint32_t v[B];
+#pragma unroll
+        for (uint32_t k = 0; k < B; ++k) v[k] = c0 + k < n_chunks ? chunk_total[(c0 + k) * 256 + d] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < B; ++k) {
+            if (c0 + k < n_chunks) {
+                chunk_off[(c0 + k) * 256 + d] = run;
+                chunk_total[(c0 + k) * 256 + d] = 0u;
+            }
+            run += v[k];
+        }
     }
     tot[d] = run;
     __syncthreads();
@@ -366,7 +392,14 @@ __global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32
         __syncthreads();
     }
     const uint32_t base = tot[d] - run;
-    for (uint32_t c = 0; c < n_chunks; ++c) chunk_off[c * 256 + d] += base;
+    for (uint32_t c0 = 0; c0 < n_chunks; c0 += B) {
+        uint32_t v[B];
+#pragma unroll
+        for (uint32_t k = 0; k < B; ++k) v[k] = c0 + k < n_chunks ? chunk_off[(c0 + k) * 256 + d] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < B; ++k)
+            if (c0 + k < n_chunks) chunk_off[(c0 + k) * 256 + d] = v[k] + base;
+    }
 }
 
 __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
@@ -374,18 +407,18 @@ __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
     __shared__ uint32_t off[256];
     __shared__ uint32_t wc[WAVES * 256];
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
-    const uint32_t base = blockIdx.x * (uint32_t)RS_TILE;
+    const uint32_t base = blockIdx.x * a.items * (uint32_t)WG;
     if (base >= n) return;
-    const uint32_t t = blockIdx.x, c0 = (t / RS_CHUNK) * RS_CHUNK;
+    const uint32_t t = blockIdx.x, c0 = (t / a.chunk) * a.chunk;
     {
-        uint32_t o = a.chunk_off[(t / RS_CHUNK) * 256 + threadIdx.x];
+        uint32_t o = a.chunk_off[(t / a.chunk) * 256 + threadIdx.x];
         for (uint32_t u = c0; u < t; ++u) o += a.tile_hist[u * 256 + threadIdx.x];
         off[threadIdx.x] = o;
     }
     const int wave = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
     const uint32_t *keys_in = a.keys_in ? a.keys_in : a.keys_first;
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    for (uint32_t r = 0; r < a.items; ++r) {
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) wc[w * 256 + threadIdx.x] = 0u;
         __syncthreads();
@@ -1056,9 +1089,12 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
     uint32_t bits = 1;
     while (bits < 32 && (1ull << bits) < (uint64_t)n_keys) ++bits;
     const int passes = (int)((bits + 7) / 8);
-    const unsigned tiles = blocks_for(n_bound, RS_TILE);
-    const uint32_t chunks = (tiles + RS_CHUNK - 1) / RS_CHUNK;
+    const SortShape sh = sort_shape(n_bound);
+    const unsigned tiles = sh.tiles;
+    const uint32_t chunks = sh.chunks;
     SortPassArgs a{};
+    a.items = sh.items;
+    a.chunk = sh.chunk;
     a.xs = xs;
     a.E = E;
     a.mat = mat;
@@ -1092,8 +1128,9 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
     return hipGetLastError();
 }
 
-size_t sort_tile_count(size_t n) { return (n + RS_TILE - 1) / RS_TILE; }
-size_t sort_chunk_count(size_t n) { return (sort_tile_count(n) + RS_CHUNK - 1) / RS_CHUNK; }
+// bounds over every shape of a sort of at most n keys (one key per thread)
+size_t sort_tile_count(size_t n) { return (n + WG - 1) / WG; }
+size_t sort_chunk_count(size_t n) { return sort_tile_count(n) / 16 + 1; }
 
 hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
 {

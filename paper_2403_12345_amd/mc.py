@@ -69,8 +69,9 @@ class mc_stats(C.Structure):
 class mc_tuning(C.Structure):
     _fields_ = [("lookup_ilp", C.c_int32), ("tail_particles", C.c_int32), ("sort_min", C.c_int32),
                 ("in_flight", C.c_int32), ("set_tile_histories", C.c_int32), ("set_grid", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
-    KEYS = ("lookup_ilp", "tail_particles", "sort_min", "in_flight", "set_tile_histories", "set_grid")
+                ("collide_sort_min", C.c_int32), ("reserved", C.c_int32)]
+    KEYS = ("lookup_ilp", "tail_particles", "sort_min", "in_flight", "set_tile_histories", "set_grid",
+            "collide_sort_min")
 
     def as_dict(self):
         return {k: getattr(self, k) for k in self.KEYS}
@@ -122,6 +123,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; "
                           f"g.build()') -- there is no CPU fallback")
+    # The library is handed PyTorch's device pointers and streams, so it must
+    # run on the HIP runtime PyTorch loaded: load that first.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, V, D, I32, U64, SZ = C.POINTER, C.c_void_p, C.c_double, C.c_int32, C.c_uint64, C.c_size_t
     sig = {
