@@ -148,13 +148,20 @@ class Problem:
     ww: WeightWindows = field(default_factory=WeightWindows)
     imp: ImportanceGrid = field(default_factory=ImportanceGrid)
     meta: dict = field(default_factory=dict)
+    # reaction channels: per nuclide a [grid points, n_chan] float64 array (or None)
+    channels: Optional[List[np.ndarray]] = None
 
     @property
     def n_bins(self) -> int:
         return self.tally.n_bins(self.geometry)
 
+    @property
+    def n_chan(self) -> int:
+        return 0 if not self.channels else int(self.channels[0].shape[1])
+
     def data_bytes(self) -> int:
-        return int(sum(n.E.nbytes + n.sig_c.nbytes + n.sig_s.nbytes for n in self.nuclides))
+        b = sum(n.E.nbytes + n.sig_c.nbytes + n.sig_s.nbytes for n in self.nuclides)
+        return int(b + (sum(c.nbytes for c in self.channels) if self.channels else 0))
 
 
 # ---------------------------------------------------------------------------
@@ -227,6 +234,30 @@ def make_nuclide(rng, awr: float, n_points: int, grid: str = "loguniform",
     assert np.all(np.diff(E) > 0) and np.all(sc >= 0) and np.all(ss >= 0)
     return Nuclide(E=E.astype(np.float64), sig_c=sc.astype(np.float64),
                    sig_s=ss.astype(np.float64), awr=float(awr))
+
+
+def make_channels(rng, nuc: Nuclide, n_chan: int, n_res: int = 3) -> np.ndarray:
+    """[grid points, n_chan] reaction-channel cross sections on the nuclide's
+    grid: per channel a constant a ~ U[0, 2] b, a 1/v term b ~ logU[0.01, 10] b
+    and n_res Lorentzians (energies and widths drawn like the nuclide's,
+    heights logU[1, 1e3] b)."""
+    out = np.empty((nuc.E.size, n_chan))
+    for x in range(n_chan):
+        e_res, g_res = _resonance_params(rng, n_res)
+        a = rng.uniform(0.0, 2.0)
+        b = _log_uniform(rng, 0.01, 10.0)
+        h = _log_uniform(rng, 1.0, 1.0e3, n_res)
+        out[:, x] = _channel(nuc.E, a, b, e_res, g_res, h)
+    assert np.all(out >= 0)
+    return np.ascontiguousarray(out, np.float64)
+
+
+def with_channels(prob: "Problem", n_chan: int, data_seed: int = 9009) -> "Problem":
+    """The problem with n_chan synthetic reaction channels on every nuclide
+    (the per-nuclide reaction data a depletion tally gathers)."""
+    rng = np.random.default_rng(data_seed)
+    prob.channels = [make_channels(rng, n, n_chan) for n in prob.nuclides]
+    return prob
 
 
 def constant_nuclide(sig_c: float, sig_s: float, awr: float, n_points: int = 2000) -> Nuclide:

@@ -63,6 +63,7 @@ class _Problem(C.Structure):
         ("ww_nmax", C.c_int32), ("ww_depth", C.c_int32),
         ("imp_nx", C.c_int32), ("imp_ne", C.c_int32), ("imp_x0", C.c_double), ("imp_x1", C.c_double),
         ("ww_ln_lo", C.c_double), ("ww_ln_hi", C.c_double),
+        ("n_chan", C.c_int32), ("chan", C.POINTER(C.c_double)),
     ]
 
 
@@ -94,7 +95,7 @@ def lib():
         _lib.orc_elastic.argtypes = [D, D, D, P(D), P(D)]
         _lib.orc_rotate.argtypes = [P(D), D, D]
         _lib.orc_run.argtypes = [P(_Problem), C.c_uint64, C.c_uint64, C.c_uint64, P(D), P(D),
-                                 P(D), C.c_void_p, C.c_void_p, C.c_int]
+                                 P(D), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         _lib.orc_bf16.argtypes = [D]
         _lib.orc_bf16.restype = D
         _lib.orc_mlp_forward.argtypes = [P(D), P(D)]
@@ -107,6 +108,7 @@ def lib():
         _lib.orc_max_threads.restype = C.c_int
         _lib.orc_micro_xs_many.argtypes = [P(_Problem), C.c_int32, C.c_int64, P(D), P(C.c_int64), P(D), P(D)]
         _lib.orc_macro_xs_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D), P(D)]
+        _lib.orc_macro_channels_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D)]
     return _lib
 
 
@@ -176,6 +178,16 @@ class OracleProblem:
         c.ww_nmax, c.ww_depth = ww.n_max, ww.depth
         c.ww_ln_lo, c.ww_ln_hi = ww.ln_lo, ww.ln_hi
         c.imp_nx, c.imp_ne, c.imp_x0, c.imp_x1 = prob.imp.nx, prob.imp.ne, prob.imp.x0, prob.imp.x1
+        chans = getattr(prob, "channels", None)
+        self.n_chan = 0 if not chans else int(chans[0].shape[1])
+        if self.n_chan:
+            assert all(ch.shape == (n.E.size, self.n_chan) for ch, n in zip(chans, nucs))
+            self.chan = np.ascontiguousarray(np.concatenate(chans, axis=0), np.float64)
+        else:
+            self.chan = np.zeros(1)
+        c.n_chan = self.n_chan
+        c.chan = _dptr(self.chan)
+        self.n_mat = len(mats)
         self.c = c
         self.n_cells = prob.imp.cells
         self.n_bins = prob.n_bins
@@ -227,6 +239,16 @@ def macro_xs(op: OracleProblem, mats, energies):
     return Sa, Ss
 
 
+def macro_channels(op: OracleProblem, mats, energies):
+    """[n, n_chan] macroscopic reaction-channel cross sections of each
+    (material, energy) pair."""
+    e = np.ascontiguousarray(energies, np.float64).ravel()
+    m = np.ascontiguousarray(np.broadcast_to(np.asarray(mats, np.int32), np.shape(energies)), np.int32).ravel()
+    out = np.empty((e.size, op.n_chan))
+    lib().orc_macro_channels_many(op.ref(), e.size, _iptr(m), _dptr(e), _dptr(out))
+    return out
+
+
 def elastic(A: float, E: float, mu_cm: float):
     a, b = C.c_double(), C.c_double()
     lib().orc_elastic(A, E, mu_cm, C.byref(a), C.byref(b))
@@ -247,6 +269,7 @@ class RunResult:
     glob: np.ndarray     # raw global sums (N_GLOBAL)
     history: np.ndarray | None = None
     imp: np.ndarray | None = None   # [3, cells]: score credited, weight entered, credits
+    rr: np.ndarray | None = None    # [n_mat, n_chan] raw track-length reaction rates
 
 
 def run(op: OracleProblem, seed: int, first_pid: int, n: int, history: bool = False,
@@ -258,13 +281,16 @@ def run(op: OracleProblem, seed: int, first_pid: int, n: int, history: bool = Fa
     glob = np.zeros(N_GLOBAL)
     imp = np.zeros(3 * op.n_cells) if op.n_cells else None
     hist = np.zeros(n, HISTORY_DTYPE) if history else None
+    rr = np.zeros(op.n_mat * op.n_chan) if op.n_chan else None
     rc = lib().orc_run(op.ref(), seed, first_pid, n, _dptr(tl), _dptr(coll), _dptr(glob),
                        imp.ctypes.data if imp is not None else None,
+                       rr.ctypes.data if rr is not None else None,
                        hist.ctypes.data if history else None, threads)
     if rc != 0:
         raise MemoryError("oracle run failed")
     return RunResult(n=n, tl=tl, coll=coll, glob=glob, history=hist,
-                     imp=imp.reshape(3, -1) if imp is not None else None)
+                     imp=imp.reshape(3, -1) if imp is not None else None,
+                     rr=rr.reshape(op.n_mat, op.n_chan) if rr is not None else None)
 
 
 def bf16(x: float) -> float:
@@ -328,7 +354,7 @@ def run_batches(op: OracleProblem, seed: int, n_batches: int, per_batch: int,
                 first_pid: int = 0, threads: int = 0) -> BatchStats:
     """Batch statistics: each batch's per-source-particle tally T_b; mean = S1/B,
     standard error = sqrt((S2/B - mean^2) / (B - 1))."""
-    acc = {k: [0.0, 0.0] for k in ("tl", "coll", "glob")}
+    acc = {k: [0.0, 0.0] for k in ("tl", "coll", "glob") + (("rr",) if op.n_chan else ())}
     for b in range(n_batches):
         r = run(op, seed, first_pid + b * per_batch, per_batch, threads=threads)
         for k in acc:

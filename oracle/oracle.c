@@ -104,6 +104,10 @@ typedef struct {
     int32_t imp_nx, imp_ne;
     double imp_x0, imp_x1;
     double ww_ln_lo, ww_ln_hi; /* ln I is clamped to [lo, hi] (no clamp when lo >= hi) */
+    /* reaction channels: n_chan extra cross sections per grid point, channel x
+     * of point j of nuclide k at chan[(nuc_off[k] + j) * n_chan + x] */
+    int32_t n_chan;
+    const double *chan;
 } orc_problem;
 
 /* One history: fate, final energy and weight of the source particle's own
@@ -219,6 +223,37 @@ void orc_macro_xs(const orc_problem *p, int32_t m, double e, double *Sa, double 
     }
     *Sa = a;
     *Ss = s;
+}
+
+/* Reaction channels (the per-nuclide reaction rates a depletion calculation
+ * tallies, paper section 2 "Tallying"): each channel is tabulated on the
+ * nuclide's grid and interpolated like the capture and scattering cross
+ * sections, with the same index and fraction; the macroscopic value of
+ * channel x is the sum over the material's nuclides, in material order, of
+ * density times the microscopic value. */
+#define ORC_MAX_CHAN 16
+
+void orc_micro_channels(const orc_problem *p, int32_t k, double e, double *out)
+{
+    const int64_t off = p->nuc_off[k];
+    const int64_t n = p->nuc_off[k + 1] - off;
+    const double *g = p->E + off;
+    int64_t i = orc_grid_index(g, n, e);
+    double f = (e - g[i]) / (g[i + 1] - g[i]);
+    const int32_t K = p->n_chan;
+    const double *c0 = p->chan + (off + i) * K, *c1 = p->chan + (off + i + 1) * K;
+    for (int32_t x = 0; x < K; ++x) out[x] = c0[x] + f * (c1[x] - c0[x]);
+}
+
+void orc_macro_channels(const orc_problem *p, int32_t m, double e, double *out)
+{
+    const int32_t K = p->n_chan;
+    double micro[ORC_MAX_CHAN];
+    for (int32_t x = 0; x < K; ++x) out[x] = 0.0;
+    for (int32_t q = p->mat_off[m]; q < p->mat_off[m + 1]; ++q) {
+        orc_micro_channels(p, p->mat_nuc[q], e, micro);
+        for (int32_t x = 0; x < K; ++x) out[x] = out[x] + p->mat_dens[q] * micro[x];
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -643,6 +678,7 @@ typedef struct {
 
 typedef struct {
     double *tl, *coll, *glob, *imp; /* imp: num[nc], den[nc], cnt[nc] */
+    double *rr;                     /* reaction rates [n_mat][n_chan] (track length) */
 } scores;
 
 static int64_t imp_cell(const orc_problem *p, double x, double E)
@@ -749,6 +785,8 @@ static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, sco
         double Sa, Ss;
         orc_macro_xs(p, c.q.mat, c.q.E, &Sa, &Ss);
         double St = Sa + Ss;
+        double Sx[ORC_MAX_CHAN];
+        if (sc.rr) orc_macro_channels(p, c.q.mat, c.q.E, Sx);
         /* distance to collision: -ln(xi) / Sigma_t */
         double dc = -log(next_u(&c.rs)) / St;
         int32_t surf;
@@ -759,6 +797,11 @@ static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, sco
         score_flight(p, &c.q, r0, d, tl);
         glob[G_TRACK] += c.q.w * d;
         glob[G_TRACK_ABS] += c.q.w * d * Sa;
+        if (sc.rr) {
+            /* track-length reaction rates: weight * path * Sigma_x in the flight's material */
+            double *r = sc.rr + (int64_t)c.q.mat * p->n_chan;
+            for (int32_t x = 0; x < p->n_chan; ++x) r[x] += c.q.w * d * Sx[x];
+        }
         track += d;
         if (den) imp_enter(p, &c, r0[0], c.q.r[0], c.q.E, den);
         if (db < dc) {
@@ -878,22 +921,24 @@ double orc_ln_importance_source(const orc_problem *p)
 }
 
 /* Run histories [first_pid, first_pid + n) and add their raw (un-normalised)
- * scores into tl[n_bins], coll[n_bins], glob[N_GLOBAL] and, when the
- * importance grid is on, imp[3 * cells] (numerators, weights entered, score
- * counts).  The pids are split into at most 64 contiguous blocks, each
- * tracked in pid order by one thread and summed in block order, so the result
- * does not depend on the thread count.  hist (nullable) receives one record
- * per pid. */
+ * scores into tl[n_bins], coll[n_bins], glob[N_GLOBAL], when the importance
+ * grid is on imp[3 * cells] (numerators, weights entered, score counts), and
+ * when the problem has reaction channels and rr is given rr[n_mat * n_chan].
+ * The pids are split into at most 64 contiguous blocks, each tracked in pid
+ * order by one thread and summed in block order, so the result does not
+ * depend on the thread count.  hist (nullable) receives one record per pid. */
 int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *tl,
-            double *coll, double *glob, double *imp, orc_history *hist, int n_threads)
+            double *coll, double *glob, double *imp, double *rr, orc_history *hist, int n_threads)
 {
     int64_t nb = tally_bins(p);
     int64_t ni = imp ? 3 * imp_cells(p) : 0;
+    if (p->n_chan < 0 || p->n_chan > ORC_MAX_CHAN) return -2;
+    int64_t nr = (rr && p->n_chan > 0) ? (int64_t)p->n_mat * p->n_chan : 0;
     if (imp_cells(p) > 64 * IMP_MAX_WORDS) return -2;
     if (p->ww_kind && (p->ww_depth > WW_MAX_DEPTH || p->ww_depth < 0)) return -2;
     int64_t n_blocks = n < 64 ? (int64_t)n : 64;
     if (n_blocks == 0) return 0;
-    int64_t stride = nb * 2 + N_GLOBAL + ni;
+    int64_t stride = nb * 2 + N_GLOBAL + ni + nr;
     double *part = (double *)calloc((size_t)(n_blocks * stride), sizeof(double));
     if (!part) return -1;
     const double ln_src = p->ww_kind ? orc_ln_importance_source(p) : 0.0;
@@ -905,7 +950,8 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n,
         uint64_t lo = (uint64_t)b * n / (uint64_t)n_blocks;
         uint64_t hi = (uint64_t)(b + 1) * n / (uint64_t)n_blocks;
         double *t = part + b * stride;
-        scores sc = {t, t + nb, t + 2 * nb, imp ? t + 2 * nb + N_GLOBAL : NULL};
+        scores sc = {t, t + nb, t + 2 * nb, imp ? t + 2 * nb + N_GLOBAL : NULL,
+                     nr ? t + 2 * nb + N_GLOBAL + ni : NULL};
         for (uint64_t i = lo; i < hi; ++i) track_history(p, seed, first_pid + i, sc, ln_src, hist ? hist + i : NULL);
     }
     for (int64_t b = 0; b < n_blocks; ++b) {
@@ -913,6 +959,7 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n,
         for (int64_t k = 0; k < nb; ++k) { tl[k] += t[k]; coll[k] += t[nb + k]; }
         for (int k = 0; k < N_GLOBAL; ++k) glob[k] += t[2 * nb + k];
         for (int64_t k = 0; k < ni; ++k) imp[k] += t[2 * nb + N_GLOBAL + k];
+        for (int64_t k = 0; k < nr; ++k) rr[k] += t[2 * nb + N_GLOBAL + ni + k];
     }
     free(part);
     return 0;
@@ -932,6 +979,12 @@ void orc_micro_xs_many(const orc_problem *p, int32_t k, int64_t n, const double 
                        double *sc, double *ss)
 {
     for (int64_t i = 0; i < n; ++i) orc_micro_xs(p, k, e[i], sc + i, ss + i, idx + i);
+}
+
+void orc_macro_channels_many(const orc_problem *p, int64_t n, const int32_t *mat, const double *e,
+                             double *out)
+{
+    for (int64_t i = 0; i < n; ++i) orc_macro_channels(p, mat[i], e[i], out + i * p->n_chan);
 }
 
 void orc_macro_xs_many(const orc_problem *p, int64_t n, const int32_t *mat, const double *e, double *Sa,
