@@ -53,8 +53,13 @@ enum { MC_BC_REFLECT = 0, MC_BC_VACUUM = 1 };
 enum { MC_SRC_POINT = 0, MC_SRC_BOX = 1, MC_SRC_BEAM = 2 };
 enum { MC_TALLY_ENERGY = 0, MC_TALLY_PIN = 1, MC_TALLY_MESH = 2, MC_TALLY_SLAB = 3 };
 
-/* tally ids for mc_get_tallies */
-enum { MC_T_FLUX_TRACK = 0, MC_T_FLUX_COLLISION = 1, MC_T_GLOBAL = 2 };
+/* tally ids for mc_get_tallies (MC_T_REACTION: with reaction channels,
+ * n_mat * n_chan bins, material-major: the track-length rate sum of
+ * w * d * Sigma_x over the flights in material m, channel x at m * n_chan + x) */
+enum { MC_T_FLUX_TRACK = 0, MC_T_FLUX_COLLISION = 1, MC_T_GLOBAL = 2, MC_T_REACTION = 3 };
+
+/* most reaction channels (mc_init_channels) */
+#define MC_MAX_CHANNELS 16
 
 /* bins of the MC_T_GLOBAL tally (each a per-source-particle mean) */
 enum {
@@ -267,6 +272,39 @@ int mc_get_stats(mc_ctx *ctx, mc_stats *out);
  * stream).  on = 0: stop timing the stand-alone calls.
  */
 int mc_set_timing(mc_ctx *ctx, int32_t on);
+
+/*
+ * Reaction channels: n_chan further cross sections per grid point of every
+ * nuclide (the per-nuclide reaction data a depletion calculation tallies,
+ * paper section 2 "Tallying"; each adds to what every lookup gathers).  Each
+ * channel is interpolated with the same grid index and fraction as the
+ * capture and scattering cross sections and summed over the material's
+ * nuclides in material order, times the densities; with channels every
+ * lookup of mc_run_batch assembles them in the same pass, and the flights
+ * score the MC_T_REACTION tally (track-length rates w * d * Sigma_x, per
+ * material and channel) in active batches.  The problem-set path does not
+ * use them.
+ *   n_chan   0 .. MC_MAX_CHANNELS; 0 removes the channels (sig_x unused)
+ *   sig_x    host, n_nuc pointers; sig_x[k] holds grid_len[k] * n_chan fp64
+ *            values of nuclide k, point-major (channel x of point j at
+ *            j * n_chan + x), finite and >= 0; copied during the call
+ * mc_init_materials removes the channels.  Errors: MC_ESTATE (no materials),
+ * MC_EINVAL (n_chan out of range, missing array, negative or non-finite
+ * value), MC_ENOMEM.
+ */
+int mc_init_channels(mc_ctx *ctx, int32_t n_chan, const double *const *sig_x);
+
+/*
+ * The channel lookup on its own: for n (energy, material) pairs, out[i *
+ * n_chan + x] = sum over the material's nuclides of density * channel x
+ * (device, n * n_chan fp64), and, when non-null, sig_a / sig_s as in
+ * mc_lookup_macro (device, n fp64 each).  Timed like mc_lookup_macro (with
+ * 8 B per channel and lookup and 16 B per channel and nuclide added to the
+ * algorithmic bytes).  Errors: MC_ESTATE (no materials or no channels),
+ * MC_EINVAL.
+ */
+int mc_lookup_channels(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *out, double *sig_a,
+                       double *sig_s);
 
 /*
  * Macroscopic cross sections of n (energy, material) pairs, the lookup step on

@@ -50,13 +50,19 @@ struct mc_ctx {
     int32_t n_nuc = 0, n_mat = 0;
     std::vector<int32_t> mat_len;
     uint32_t n_keys = 0;  // n_mat * M sort keys
+    std::vector<int32_t> nuc_glen;   // grid points per nuclide
+    std::vector<uint32_t> nuc_goff;  // first point of each nuclide in the tables
+
+    // reaction channels (tables, and the reaction-rate tally's batch sums)
+    int32_t n_chan = 0;
+    Buffers chan_bufs;
 
     // geometry and tallies
     bool have_geom = false;
     Buffers geom_bufs;
     GeomDev geom{};
     int32_t n_bins = 0;
-    double *S1[3] = {nullptr, nullptr, nullptr}, *S2[3] = {nullptr, nullptr, nullptr};
+    double *S1[4] = {nullptr, nullptr, nullptr, nullptr}, *S2[4] = {nullptr, nullptr, nullptr, nullptr};
     uint64_t n_batches = 0, histories = 0;
 
     // particle bank and per-workgroup tally rows
@@ -451,9 +457,14 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->mat_bufs.release();
+    ctx->chan_bufs.release();  // new tables: no reaction channels until mc_init_channels
+    ctx->n_chan = 0;
+    ctx->S1[3] = ctx->S2[3] = nullptr;
     ctx->have_mat = false;
     ctx->have_geom = false;
     rc = upload_xs(ctx, H, n_hash_bins, ctx->mat_bufs, ctx->xs);
+    ctx->xs.n_chan = 0;
+    ctx->xs.xc = nullptr;
     if (rc) {
         ctx->mat_bufs.release();
         return rc;
@@ -464,14 +475,68 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     ctx->n_nuc = n_nuc;
     ctx->n_mat = n_mat;
     ctx->mat_len.assign(mat_len, mat_len + n_mat);
+    ctx->nuc_glen = H.glen;
+    ctx->nuc_goff = H.goff;
     ctx->have_mat = true;
+    return MC_OK;
+}
+
+int mc_init_channels(mc_ctx *ctx, int32_t n_chan, const double *const *sig_x)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mat) return fail(ctx, MC_ESTATE, "mc_init_channels: materials first");
+    if (n_chan < 0 || n_chan > MAX_CHAN)
+        return fail(ctx, MC_EINVAL, "mc_init_channels: n_chan must be in [0, " + std::to_string(MAX_CHAN) + "]");
+    if (n_chan > 0 && !sig_x) return fail(ctx, MC_EINVAL, "mc_init_channels: missing sig_x");
+    std::vector<double> xc;
+    if (n_chan > 0) {
+        const size_t pts = ctx->nuc_goff.back() + (size_t)ctx->nuc_glen.back();
+        xc.resize(pts * (size_t)n_chan);
+        for (int32_t k = 0; k < ctx->n_nuc; ++k) {
+            if (!sig_x[k]) return fail(ctx, MC_EINVAL, "mc_init_channels: missing nuclide " + std::to_string(k));
+            const size_t cnt = (size_t)ctx->nuc_glen[k] * (size_t)n_chan;
+            for (size_t j = 0; j < cnt; ++j) {
+                const double v = sig_x[k][j];
+                if (!(v >= 0.0) || !std::isfinite(v))
+                    return fail(ctx, MC_EINVAL, "mc_init_channels: negative or non-finite value, nuclide " +
+                                                    std::to_string(k));
+            }
+            std::memcpy(xc.data() + (size_t)ctx->nuc_goff[k] * (size_t)n_chan, sig_x[k], cnt * sizeof(double));
+        }
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->chan_bufs.release();
+    ctx->n_chan = 0;
+    ctx->xs.n_chan = 0;
+    ctx->xs.xc = nullptr;
+    ctx->S1[3] = ctx->S2[3] = nullptr;
+    if (n_chan == 0) return MC_OK;
+    double *d = nullptr;
+    const size_t nb = (size_t)ctx->n_mat * (size_t)n_chan;
+    int rc = upload(ctx, ctx->chan_bufs, &d, xc.data(), xc.size());
+    if (!rc) rc = dalloc(ctx, ctx->chan_bufs, &ctx->S1[3], nb);
+    if (!rc) rc = dalloc(ctx, ctx->chan_bufs, &ctx->S2[3], nb);
+    if (rc) {
+        ctx->chan_bufs.release();
+        ctx->S1[3] = ctx->S2[3] = nullptr;
+        return rc;
+    }
+    ctx->xs.n_chan = n_chan;
+    ctx->xs.xc = d;
+    ctx->n_chan = n_chan;
+    HIPCHK(launch_fill_f64(ctx->S1[3], nb, 0.0, ctx->stream));
+    HIPCHK(launch_fill_f64(ctx->S2[3], nb, 0.0, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return MC_OK;
 }
 
 static int reset_tallies(mc_ctx *ctx)
 {
-    for (int t = 0; t < 3; ++t) {
-        const size_t n = (t == 2) ? (size_t)N_GLOBAL : (size_t)ctx->n_bins;
+    for (int t = 0; t < 4; ++t) {
+        if (t == 3 && !ctx->n_chan) break;
+        const size_t n = (t == 2) ? (size_t)N_GLOBAL
+                                  : (t == 3 ? (size_t)ctx->n_mat * (size_t)ctx->n_chan : (size_t)ctx->n_bins);
         HIPCHK(launch_fill_f64(ctx->S1[t], n, 0.0, ctx->stream));
         HIPCHK(launch_fill_f64(ctx->S2[t], n, 0.0, ctx->stream));
     }
@@ -669,8 +734,10 @@ static int alloc_sort(mc_ctx *ctx, Buffers &B, SortBufs &sb, size_t n)
 // Particle bank of capacity cap and the tally rows of its workgroups.
 static int ensure_bank(mc_ctx *ctx, uint32_t cap)
 {
+    const int32_t chan_bins = ctx->n_chan ? ctx->n_mat * ctx->n_chan : 0;
     if (ctx->cap >= cap && ctx->bank_bins == ctx->n_bins && ctx->tal.n_bins == ctx->n_bins &&
-        (ctx->geom.tally_kind == TALLY_MESH) == (ctx->tal.mesh_tl != nullptr)) {
+        (ctx->geom.tally_kind == TALLY_MESH) == (ctx->tal.mesh_tl != nullptr) && ctx->tal.n_chan == ctx->n_chan &&
+        ctx->tal.chan_bins == chan_bins) {
         ctx->bank.C = cap;  // the first cap slots of the (larger) allocation are in use
         return MC_OK;
     }
@@ -685,6 +752,7 @@ static int ensure_bank(mc_ctx *ctx, uint32_t cap)
     for (double **p : dd)
         if (!rc) rc = dalloc(ctx, B, p, cap);
     if (!rc) rc = dalloc(ctx, B, &b.cp, (size_t)CP_MAX * cap);
+    if (!rc && ctx->n_chan) rc = dalloc(ctx, B, &b.sx, (size_t)ctx->n_chan * cap);
     int32_t **ii[] = {&b.mat, &b.cell, &b.ncoll, &b.ncross};
     for (int32_t **p : ii)
         if (!rc) rc = dalloc(ctx, B, p, cap);
@@ -707,7 +775,11 @@ static int ensure_bank(mc_ctx *ctx, uint32_t cap)
     if (!rc) rc = dalloc(ctx, B, &t.glob, (size_t)t.rows * N_GLOBAL);
     if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins);
     if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins);
-    if (!rc) rc = dalloc(ctx, B, &ctx->partial, (size_t)64 * std::max<size_t>(ctx->n_bins, N_GLOBAL));
+    t.n_chan = ctx->n_chan;
+    t.chan_bins = chan_bins;
+    if (!rc && chan_bins) rc = dalloc(ctx, B, &t.chan, (size_t)t.rows * (size_t)chan_bins);
+    const size_t part_bins = std::max<size_t>(std::max<size_t>(ctx->n_bins, N_GLOBAL), (size_t)chan_bins);
+    if (!rc) rc = dalloc(ctx, B, &ctx->partial, (size_t)64 * part_bins);
     SortBufs sb{};
     if (!rc) rc = alloc_sort(ctx, B, sb, cap);
     if (rc) {
@@ -883,6 +955,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     HIPCHK(launch_fill_f64(tal.tl, (size_t)tal.rows * row_bins, 0.0, st));
     HIPCHK(launch_fill_f64(tal.coll, (size_t)tal.rows * row_bins, 0.0, st));
     HIPCHK(launch_fill_f64(tal.glob, (size_t)tal.rows * N_GLOBAL, 0.0, st));
+    if (tal.chan) HIPCHK(launch_fill_f64(tal.chan, (size_t)tal.rows * (size_t)tal.chan_bins, 0.0, st));
     if (mesh) {
         HIPCHK(launch_fill_f64(tal.mesh_tl, (size_t)ctx->n_bins, 0.0, st));
         HIPCHK(launch_fill_f64(tal.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
@@ -939,6 +1012,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
             l.nuc_count = ctx->dstat;
             l.ilp = lookup_ilp(ctx);
             l.cp = b.cp;
+            l.sx = b.sx;
             const bool sort = (uint64_t)c.nL >= sort_min && sort_min != UINT64_MAX;
             if (sort) {
                 HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, c.nL, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls,
@@ -992,6 +1066,9 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     }
     HIPCHK(launch_batch_stats(tal.glob, tal.rows, N_GLOBAL, nullptr, ctx->partial, inv_n, ctx->S1[2],
                               ctx->S2[2], st));
+    if (tal.chan)
+        HIPCHK(launch_batch_stats(tal.chan, tal.rows, tal.chan_bins, nullptr, ctx->partial, inv_n, ctx->S1[3],
+                                  ctx->S2[3], st));
     HIPCHK(hipEventRecord(ctx->ev_batch1, st));
     unsigned long long dstat[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(dstat, ctx->dstat, sizeof(dstat), hipMemcpyDeviceToHost, st));
@@ -1007,7 +1084,9 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     s.iterations = it;
     s.nuclide_lookups = dstat[0];
     s.lost = dstat[1];
-    s.lookup_bytes = 36ull * s.lookups + 56ull * s.nuclide_lookups;
+    // per lookup 36 B (+ 8 B per channel written), per nuclide 56 B (+ 16 B per channel)
+    s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +
+                     (56ull + 16ull * (uint64_t)ctx->n_chan) * s.nuclide_lookups;
     ctx->stats = s;
     ctx->n_batches += 1;
     ctx->histories += n;
@@ -1021,8 +1100,11 @@ int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_,
 {
     if (!ctx) return MC_EINVAL;
     if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "no geometry");
-    if (tally_id < 0 || tally_id > 2) return fail(ctx, MC_EINVAL, "unknown tally id");
-    const size_t nb = (tally_id == MC_T_GLOBAL) ? (size_t)N_GLOBAL : (size_t)ctx->n_bins;
+    if (tally_id < 0 || tally_id > 3) return fail(ctx, MC_EINVAL, "unknown tally id");
+    if (tally_id == MC_T_REACTION && !ctx->n_chan) return fail(ctx, MC_ESTATE, "no reaction channels");
+    const size_t nb = (tally_id == MC_T_GLOBAL)     ? (size_t)N_GLOBAL
+                      : (tally_id == MC_T_REACTION) ? (size_t)ctx->n_mat * (size_t)ctx->n_chan
+                                                    : (size_t)ctx->n_bins;
     if (n_bins != nb) return fail(ctx, MC_EINVAL, "n_bins does not match the tally (" + std::to_string(nb) + ")");
     HIPCHK(hipSetDevice(ctx->device));
     std::vector<double> s1(nb), s2(nb);
@@ -1132,6 +1214,49 @@ int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, 
     s.lookup_launches += 1;
     s.sorted_lookups += sorted ? n : 0;
     s.lookup_bytes += 36ull * n + 56ull * nuc;
+    s.lookup_ms += ms;
+    return MC_OK;
+}
+
+int mc_lookup_channels(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *out, double *sig_a,
+                       double *sig_s)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mat) return fail(ctx, MC_ESTATE, "mc_lookup_channels: no materials");
+    if (n == 0) return MC_OK;
+    if (!ctx->n_chan) return fail(ctx, MC_ESTATE, "mc_lookup_channels: no reaction channels");
+    if (n >= (1ull << 31) || !E || !mat || !out) return fail(ctx, MC_EINVAL, "mc_lookup_channels: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    LookupLaunch l;
+    l.xs = ctx->xs;
+    l.n_bound = (uint32_t)n;
+    l.E = E;
+    l.mat = mat;
+    l.Sa = sig_a;
+    l.Ss = sig_s;
+    l.ilp = lookup_ilp(ctx);
+    l.sx = out;
+    if (!ctx->timing) {
+        HIPCHK(launch_lookup(l, ctx->stream));
+        return MC_OK;
+    }
+    int rc = timing_event_pair(ctx, 0);
+    if (rc) return rc;
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->dstat), 2, 0u, ctx->stream));
+    l.nuc_count = ctx->dstat;
+    HIPCHK(hipEventRecord(ctx->ev_a[0], ctx->stream));
+    HIPCHK(launch_lookup(l, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev_b[0], ctx->stream));
+    unsigned long long nuc = 0;
+    HIPCHK(hipMemcpyAsync(&nuc, ctx->dstat, sizeof(nuc), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_a[0], ctx->ev_b[0]));
+    mc_stats &s = ctx->stats;
+    s.lookups += n;
+    s.nuclide_lookups += nuc;
+    s.lookup_launches += 1;
+    s.lookup_bytes += (36ull + 8ull * (uint64_t)ctx->n_chan) * n + (56ull + 16ull * (uint64_t)ctx->n_chan) * nuc;
     s.lookup_ms += ms;
     return MC_OK;
 }

@@ -58,7 +58,12 @@ struct XsDev {
     int32_t n_mat;
     int32_t M;                 // hash bins
     double ln_emin, inv_delta; // bin b = floor((ln E - ln emin) * inv_delta)
+    // reaction channels: n_chan values per grid point, point p's at xc[p * n_chan]
+    int32_t n_chan;
+    const double *xc;
 };
+
+constexpr int MAX_CHAN = 16;  // most reaction channels
 
 struct GeomDev {
     int32_t kind, inf_mat;
@@ -103,6 +108,7 @@ __host__ __device__ __forceinline__ int32_t cp_count(int32_t nk)
 
 struct BankDev {
     double *cp;  // [slot][CP_MAX] checkpoints of the scattering sum (see above): one row per slot
+    double *sx;  // [slot][n_chan] macroscopic reaction-channel cross sections (null without channels)
     double *x, *y, *z, *u, *v, *w, *E, *wt, *Sa, *Ss, *track;
     int32_t *mat, *cell, *ncoll, *ncross;
     uint8_t *flags, *inside, *event;
@@ -132,6 +138,8 @@ struct TallyDev {
     double *coll;   // [rows][n_bins] collision estimator
     double *glob;   // [rows][N_GLOBAL]
     double *mesh_tl, *mesh_coll;  // [n_bins] mesh tallies (atomic accumulation)
+    double *chan;   // [rows][n_mat * n_chan] track-length reaction rates (null without channels)
+    int32_t n_chan, chan_bins;
     int32_t n_bins, rows;
     int32_t enabled;  // 0: inactive batch, binned flux tallies off
 };
@@ -237,7 +245,7 @@ template <int ILP>
 __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__restrict__ mnuc,
                                             const uint32_t *h, int32_t nk, int32_t q, int32_t cnt, double e,
                                             double (&dens)[ILP], uint32_t (&ix)[ILP], double (&sc)[ILP],
-                                            double (&ss)[ILP])
+                                            double (&ss)[ILP], double (&fr)[ILP], uint32_t (&pt)[ILP])
 {
     uint32_t lo[ILP], hi[ILP], off[ILP], len[ILP];
 #pragma unroll
@@ -301,6 +309,40 @@ __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__res
         const double f = (e - e0[k]) / (e1[k] - e0[k]);
         sc[k] = x0[k].x + f * (x1[k].x - x0[k].x);
         ss[k] = x0[k].y + f * (x1[k].y - x0[k].y);
+        fr[k] = f;
+        pt[k] = off[k] + ix[k];
+    }
+}
+
+// The same without the interpolation fraction and table position.
+template <int ILP>
+__device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__restrict__ mnuc,
+                                            const uint32_t *h, int32_t nk, int32_t q, int32_t cnt, double e,
+                                            double (&dens)[ILP], uint32_t (&ix)[ILP], double (&sc)[ILP],
+                                            double (&ss)[ILP])
+{
+    double fr[ILP];
+    uint32_t pt[ILP];
+    micro_group<ILP>(xs, mnuc, h, nk, q, cnt, e, dens, ix, sc, ss, fr, pt);
+}
+
+// Adds density * (channel x of point pt interpolated with fraction f) into
+// acc[x] for the nuclides k < cnt of a group, in material order.
+template <int ILP>
+__device__ __forceinline__ void channel_group(const XsDev &xs, int32_t cnt, const double (&dens)[ILP],
+                                              const double (&fr)[ILP], const uint32_t (&pt)[ILP],
+                                              double (&acc)[MAX_CHAN])
+{
+    const int32_t K = xs.n_chan;
+#pragma unroll
+    for (int k = 0; k < ILP; ++k) {
+        if (k < cnt) {
+            const double *r0 = xs.xc + (size_t)pt[k] * (size_t)K;
+            const double *r1 = r0 + K;
+#pragma unroll
+            for (int x = 0; x < MAX_CHAN; ++x)
+                if (x < K) acc[x] = acc[x] + dens[k] * (r0[x] + fr[k] * (r1[x] - r0[x]));
+        }
     }
 }
 

@@ -25,6 +25,7 @@ struct LookupLaunch {
     unsigned long long *nuc_count = nullptr;
     int32_t ilp = 4;  // nuclides looked up in lockstep per lane (1, 2 or 4)
     double *cp = nullptr;     // scattering-sum checkpoints [slot][CP_MAX] (transport lookups only)
+    double *sx = nullptr;     // reaction channels [p][n_chan] (when the tables have channels)
 };
 
 hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st);

@@ -467,13 +467,16 @@ struct LookupArgs {
     double *sc_out, *ss_out;  // nullable, per nuclide
     unsigned long long *nuc_count;  // nullable: adds sum of nk over the queue
     double *cp;               // nullable: scattering-sum checkpoints [slot][CP_MAX]
+    double *sx;               // reaction channels [p][n_chan] (the CHAN kernels)
 };
 
 constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
 
 // DIAG: the per-nuclide outputs (idx_out, sc_out, ss_out) may be set; the
-// transport's lookups run without them, in fewer registers.
-template <int ILP, bool DIAG>
+// transport's lookups run without them, in fewer registers.  CHAN: the
+// reaction channels are assembled in the same pass (same index and fraction
+// per nuclide) into sx.
+template <int ILP, bool DIAG, bool CHAN>
 __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 {
     __shared__ uint32_t sh[LDS_HASH_WORDS];
@@ -526,6 +529,8 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     if (m < 0 || m >= xs.n_mat) {  // not a material: no table access, NaN out
         if (a.Sa) a.Sa[p] = NAN;
         if (a.Ss) a.Ss[p] = NAN;
+        if (CHAN)
+            for (int32_t x = 0; x < xs.n_chan; ++x) a.sx[(size_t)p * xs.n_chan + x] = NAN;
         m = -1;
     }
     if (m >= 0) {
@@ -535,13 +540,19 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     const MatNuc *mnuc = xs.mnuc + q0;
     const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
     const int32_t cp_mask = (1 << cp_sh) - 1;
+    double acc[MAX_CHAN];
+    if (CHAN) {
+#pragma unroll
+        for (int x = 0; x < MAX_CHAN; ++x) acc[x] = 0.0;
+    }
     // the nuclide loop, once with the brackets in LDS and once in global memory
     auto nuclides = [&](const uint32_t *h0) {
         for (int32_t q = 0; q < nk; q += ILP) {
             const int32_t cnt = nk - q < ILP ? nk - q : ILP;
-            double dens[ILP], c[ILP], s[ILP];
-            uint32_t ix[ILP];
-            micro_group<ILP>(xs, mnuc, h0, nk, q, cnt, e, dens, ix, c, s);
+            double dens[ILP], c[ILP], s[ILP], fr[ILP];
+            uint32_t ix[ILP], pt[ILP];
+            micro_group<ILP>(xs, mnuc, h0, nk, q, cnt, e, dens, ix, c, s, fr, pt);
+            if (CHAN) channel_group<ILP>(xs, cnt, dens, fr, pt, acc);
             // the sum runs in material order, one nuclide after the other
 #pragma unroll
             for (int k = 0; k < ILP; ++k) {
@@ -563,6 +574,11 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     else nuclides(hash_row(xs, m, b, nk));
     if (a.Sa) a.Sa[p] = sa;
     if (a.Ss) a.Ss[p] = ss;
+    if (CHAN) {
+#pragma unroll
+        for (int x = 0; x < MAX_CHAN; ++x)
+            if (x < xs.n_chan) a.sx[(size_t)p * xs.n_chan + x] = acc[x];
+    }
     if (a.flags) a.flags[p] = F_ALIVE;
     nk_done = nk;
     }
@@ -587,6 +603,8 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
     const uint32_t i = i0 + threadIdx.x;
     StepScore sc;
     clear_score(sc);
+    int32_t flight_mat = -1;              // material of this lane's flight (-1: none)
+    const double *sx_row = b.sx;
     if (i < n) {
         const uint32_t s = b.A[i];
         if ((int64_t)b.ncoll[s] + b.ncross[s] >= max_events) {
@@ -594,6 +612,8 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
         } else {
             Particle p = load_particle(b, s);
             const double x0 = p.x;
+            flight_mat = p.mat;
+            if (tal.chan) sx_row = b.sx + (size_t)s * tal.n_chan;
             do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on != 0, sc);
             if (W.imp_nx) imp_enter(W, s, x0, p.x, p.E, p.wt);
             b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
@@ -604,6 +624,9 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
     }
     if (tal.enabled && g.tally_kind != TALLY_MESH)
         wg_bin_add(sc.tl_bin, sc.tl_val, slab, tal.n_bins, tal.tl + (size_t)blockIdx.x * tal.n_bins);
+    if (tal.enabled && tal.chan)
+        wg_chan_add(flight_mat, sc.g[G_TRACK], sx_row, tal.n_chan, slab, tal.chan_bins,
+                    tal.chan + (size_t)blockIdx.x * tal.chan_bins);
     wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
 }
 
@@ -805,15 +828,20 @@ struct TileRows {
     double *mesh_tl, *mesh_coll;
     int32_t n_bins;
     bool enabled;              // binned flux tallies on
+    double *chan;              // reaction-rate row (chan_bins doubles; the CHAN tiles)
+    int32_t chan_bins, n_chan;
 };
 
 // ILP: nuclides per lane in lockstep in the lookup and the collision's walk
 // (the tail runs few particles per compute unit: latency, not registers,
 // bounds it, so it takes more).
-template <int ILP>
+// CHAN: the lookups also assemble the reaction channels into sx_row and the
+// flights score their reaction rates.
+template <int ILP, bool CHAN>
 __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev &xs, const GeomDev &g,
                                 const TileRows &r, uint64_t seed, int64_t max_events, HistLog *log,
-                                uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl)
+                                uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl,
+                                double *sx_row)
 {
     const bool binned = r.enabled && g.tally_kind != TALLY_MESH;
     const bool log_on = log != nullptr;
@@ -822,16 +850,19 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         clear_score(sc);
         int32_t fate = 0;
         if (alive && need) {
-            do_lookup<ILP>(p, xs);
+            do_lookup<ILP, CHAN>(p, xs, sx_row);
             need = false;
         }
+        int32_t flight_mat = -1;
         if (alive && (int64_t)p.ncoll + p.ncross >= max_events) {
             fate = FATE_LOST;
             atomicAdd(lost, 1ull);
         } else if (alive) {
+            flight_mat = p.mat;
             do_advance(p, g, seed, r.enabled, r.mesh_tl, log_on, sc);
         }
         if (binned) wg_bin_add(sc.tl_bin, sc.tl_val, slab, r.n_bins, r.tl);
+        if (CHAN && r.enabled) wg_chan_add(flight_mat, sc.g[G_TRACK], sx_row, r.n_chan, slab, r.chan_bins, r.chan);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
                 fate = do_collide<ILP>(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr);
@@ -856,6 +887,7 @@ constexpr int TAIL_ILP = 4;
 // one launch finishes them (workgroup row = blockIdx.x); the histories are
 // the ones the event kernels would give.  Analog transport only: with weight
 // windows a history's copies run in parallel in the event kernels.
+template <bool CHAN>
 __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, TallyDev tal, const Counters *ctr,
                                              uint64_t seed, int64_t max_events, HistLog *log, uint64_t first_pid,
                                              unsigned long long *lost)
@@ -883,7 +915,11 @@ __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, Tal
     r.mesh_coll = tal.mesh_coll;
     r.n_bins = tal.n_bins;
     r.enabled = tal.enabled != 0;
-    run_tile<TAIL_ILP>(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl);
+    r.chan = CHAN ? tal.chan + (size_t)blockIdx.x * tal.chan_bins : nullptr;
+    r.chan_bins = tal.chan_bins;
+    r.n_chan = tal.n_chan;
+    double *sx_row = CHAN ? b.sx + (size_t)s * tal.n_chan : nullptr;
+    run_tile<TAIL_ILP, CHAN>(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl, sx_row);
     if (i < n) b.flags[s] = 0;
 }
 
@@ -958,9 +994,11 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
             r.mesh_coll = nullptr;
             r.n_bins = P.g.n_bins;
             r.enabled = true;
+            r.chan = nullptr;
+            r.chan_bins = r.n_chan = 0;
             HistLog *log = set.log ? set.log + P.log_off : nullptr;
-            run_tile<DEFAULT_LOOKUP_ILP>(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid, set.lost, slab,
-                                         gl);
+            run_tile<DEFAULT_LOOKUP_ILP, false>(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid,
+                                                set.lost, slab, gl, nullptr);
         }
     }
 }
@@ -1036,10 +1074,13 @@ static inline unsigned blocks_for(size_t n, size_t per) { return (unsigned)((n +
 
 // LDS of the per-wave tally slabs (none when the binned tallies are off or
 // use the mesh path)
+// LDS of the tally slabs: the binned flux tally's and the reaction rates'.
 static inline size_t slab_bytes(const GeomDev &g, const TallyDev &t)
 {
-    if (!t.enabled || g.tally_kind == TALLY_MESH) return 0;
-    return (size_t)WAVES * (size_t)t.n_bins * sizeof(double);
+    if (!t.enabled) return 0;
+    size_t bins = g.tally_kind == TALLY_MESH ? 0 : (size_t)t.n_bins;
+    if (t.chan && (size_t)t.chan_bins > bins) bins = (size_t)t.chan_bins;
+    return (size_t)WAVES * bins * sizeof(double);
 }
 
 hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t st)
@@ -1151,18 +1192,22 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     a.ss_out = l.ss_out;
     a.nuc_count = l.nuc_count;
     a.cp = l.cp;
+    a.sx = l.sx;
     const dim3 grid(blocks_for(l.n_bound, WG));
-    if (a.idx_out || a.sc_out || a.ss_out) {
+    if (a.sx && l.xs.n_chan > 0) {  // channels: at most two nuclides in lockstep (registers)
+        if (l.ilp == 1) hipLaunchKernelGGL((k_lookup<1, false, true>), grid, dim3(WG), 0, st, a);
+        else hipLaunchKernelGGL((k_lookup<2, false, true>), grid, dim3(WG), 0, st, a);
+    } else if (a.idx_out || a.sc_out || a.ss_out) {
         switch (l.ilp) {
-        case 1: hipLaunchKernelGGL((k_lookup<1, true>), grid, dim3(WG), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_lookup<2, true>), grid, dim3(WG), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_lookup<4, true>), grid, dim3(WG), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_lookup<1, true, false>), grid, dim3(WG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_lookup<2, true, false>), grid, dim3(WG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_lookup<4, true, false>), grid, dim3(WG), 0, st, a); break;
         }
     } else {
         switch (l.ilp) {
-        case 1: hipLaunchKernelGGL((k_lookup<1, false>), grid, dim3(WG), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_lookup<2, false>), grid, dim3(WG), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_lookup<4, false>), grid, dim3(WG), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_lookup<1, false, false>), grid, dim3(WG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_lookup<2, false, false>), grid, dim3(WG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_lookup<4, false, false>), grid, dim3(WG), 0, st, a); break;
         }
     }
     return hipGetLastError();
@@ -1237,8 +1282,12 @@ hipError_t launch_tail(const BankDev &b, const XsDev &xs, const GeomDev &g, cons
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    hipLaunchKernelGGL(k_tail, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed, max_events,
-                       log, first_pid, lost);
+    if (t.chan)
+        hipLaunchKernelGGL(k_tail<true>, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed,
+                           max_events, log, first_pid, lost);
+    else
+        hipLaunchKernelGGL(k_tail<false>, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, xs, g, t, ctr, seed,
+                           max_events, log, first_pid, lost);
     return hipGetLastError();
 }
 

@@ -195,24 +195,62 @@ __device__ inline void wg_glob_add(const double (&val)[N_GLOBAL], double *lds, d
     __syncthreads();
 }
 
+// Adds each lane's track-length reaction rates wd * sx[x] (x < K) into the
+// workgroup's row [n_mat][K] at its flight's material (mat < 0: no flight).
+// Every thread must call it; slab holds WAVES * nb doubles, nb = n_mat * K.
+__device__ inline void wg_chan_add(int32_t mat, double wd, const double *sx, int32_t K, double *slab, int32_t nb,
+                                   double *row)
+{
+    for (int32_t t = threadIdx.x; t < WAVES * nb; t += WG) slab[t] = 0.0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    bool active = mat >= 0;
+    uint64_t mask = __ballot(active);
+    while (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        const int32_t M = __shfl(mat, leader, 64);
+        const bool mine = active && mat == M;
+        for (int32_t x = 0; x < K; ++x) {
+            const double s = wave_sum(mine ? wd * sx[x] : 0.0);
+            if (lane_id() == leader) slab[wave * nb + M * K + x] += s;
+        }
+        active = active && !mine;
+        mask = __ballot(active);
+    }
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < nb; t += WG) {
+        double s = 0.0;
+        for (int w = 0; w < WAVES; ++w) s = s + slab[w * nb + t];
+        if (s != 0.0) row[t] = row[t] + s;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // the steps
 // ---------------------------------------------------------------------------
 constexpr int DEFAULT_LOOKUP_ILP = 2;
 
 // Macroscopic cross sections of the particle's material at its energy
-// (hash brackets read from global memory).
-template <int ILP>
-__device__ inline void do_lookup(Particle &p, const XsDev &xs)
+// (hash brackets read from global memory); CHAN: also the reaction channels
+// into sx_row.
+template <int ILP, bool CHAN = false>
+__device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = nullptr)
 {
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
     const uint32_t *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
     double sa = 0.0, ss = 0.0;
+    double acc[MAX_CHAN];
+    if (CHAN) {
+#pragma unroll
+        for (int x = 0; x < MAX_CHAN; ++x) acc[x] = 0.0;
+    }
     for (int32_t q = 0; q < nk; q += ILP) {
         const int32_t cnt = nk - q < ILP ? nk - q : ILP;
-        double dens[ILP], c[ILP], s[ILP];
-        uint32_t ix[ILP];
-        micro_group<ILP>(xs, xs.mnuc + q0, h, nk, q, cnt, p.E, dens, ix, c, s);
+        double dens[ILP], c[ILP], s[ILP], fr[ILP];
+        uint32_t ix[ILP], pt[ILP];
+        micro_group<ILP>(xs, xs.mnuc + q0, h, nk, q, cnt, p.E, dens, ix, c, s, fr, pt);
+        if (CHAN) channel_group<ILP>(xs, cnt, dens, fr, pt, acc);
 #pragma unroll
         for (int k = 0; k < ILP; ++k) {
             if (k < cnt) {
@@ -223,6 +261,11 @@ __device__ inline void do_lookup(Particle &p, const XsDev &xs)
     }
     p.Sa = sa;
     p.Ss = ss;
+    if (CHAN) {
+#pragma unroll
+        for (int x = 0; x < MAX_CHAN; ++x)
+            if (x < xs.n_chan) sx_row[x] = acc[x];
+    }
 }
 
 // Flight: distance to collision -ln(xi)/Sigma_t (one draw), distance to the

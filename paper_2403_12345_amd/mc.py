@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libmc.so")
 MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST, MC_ESTATE, MC_ENODEV = 0, -1, -2, -3, -4, -5, -6
 MC_GEOM_INFINITE, MC_GEOM_LATTICE, MC_GEOM_SLAB = 0, 1, 2
 MC_TALLY_ENERGY, MC_TALLY_PIN, MC_TALLY_MESH, MC_TALLY_SLAB = 0, 1, 2, 3
-MC_T_FLUX_TRACK, MC_T_FLUX_COLLISION, MC_T_GLOBAL = 0, 1, 2
+MC_T_FLUX_TRACK, MC_T_FLUX_COLLISION, MC_T_GLOBAL, MC_T_REACTION = 0, 1, 2, 3
+MC_MAX_CHANNELS = 16
 (MC_G_TRACK, MC_G_COLL_EST, MC_G_ABSORB, MC_G_CUTOFF, MC_G_LEAK, MC_G_TRACK_ABS, MC_G_NCOLL,
  MC_G_NCROSS, MC_G_LEAK_XHI, MC_G_LEAK_XHI_UNC, MC_G_SPLIT, MC_G_ROULETTE, MC_N_GLOBAL) = range(13)
 MC_FATE_ABSORBED, MC_FATE_CUTOFF, MC_FATE_LEAKED, MC_FATE_LOST, MC_FATE_ROULETTE = 1, 2, 3, 4, 5
@@ -142,6 +143,8 @@ def load():
         "mc_reset_tallies": ([V], C.c_int),
         "mc_get_stats": ([V, P(mc_stats)], C.c_int),
         "mc_lookup_macro": ([V, SZ, V, V, V, V, I32], C.c_int),
+        "mc_init_channels": ([V, I32, P(P(D))], C.c_int),
+        "mc_lookup_channels": ([V, SZ, V, V, V, V, V], C.c_int),
         "mc_lookup_nuclides": ([V, I32, SZ, V, V, V, V], C.c_int),
         "mc_sort_queue": ([V, SZ, V, V, V, V], C.c_int),
         "mc_hash_bounds": ([P(D), I32, D, D, I32, P(I32)], C.c_int),
@@ -285,6 +288,25 @@ def mc_lookup_macro(ctx, E, mat, sig_a, sig_s, sorted_: bool = False):
     n = E.numel() if hasattr(E, "numel") else int(E)
     _check(ctx, load().mc_lookup_macro(ctx, n, _ptr(E), _ptr(mat), _ptr(sig_a), _ptr(sig_s),
                                        1 if sorted_ else 0))
+
+
+def mc_init_channels(ctx, channels):
+    """Reaction channels: one [grid points, n_chan] float64 array per nuclide
+    (None or [] removes them)."""
+    if not channels:
+        _check(ctx, load().mc_init_channels(ctx, 0, None))
+        return
+    arrs = [np.ascontiguousarray(c, np.float64) for c in channels]
+    k = arrs[0].shape[1]
+    if any(a.ndim != 2 or a.shape[1] != k for a in arrs):
+        raise ValueError("every nuclide needs a [points, n_chan] array with the same n_chan")
+    ptrs = (C.POINTER(C.c_double) * len(arrs))(*[_dp(a) for a in arrs])
+    _check(ctx, load().mc_init_channels(ctx, k, ptrs))
+
+
+def mc_lookup_channels(ctx, E, mat, out, sig_a=None, sig_s=None):
+    n = E.numel() if hasattr(E, "numel") else int(E)
+    _check(ctx, load().mc_lookup_channels(ctx, n, _ptr(E), _ptr(mat), _ptr(out), _ptr(sig_a), _ptr(sig_s)))
 
 
 def mc_lookup_nuclides(ctx, mat: int, E, idx=None, sig_c=None, sig_s=None):

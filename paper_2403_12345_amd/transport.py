@@ -78,10 +78,14 @@ class Transport:
             mc.mc_init_geometry(self.ctx, desc)
             del keep
             self.set_weight_windows(getattr(prob, "ww", None), getattr(prob, "imp", None))
+            chans = getattr(prob, "channels", None)
+            if chans:
+                mc.mc_init_channels(self.ctx, chans)
         except Exception:
             mc.mc_destroy(self.ctx)
             raise
         self.n_bins = prob.n_bins
+        self.n_reaction = len(prob.materials) * (chans[0].shape[1] if chans else 0)
 
     def set_weight_windows(self, ww=None, imp=None):
         """Weight windows (an object with the attributes of mcsynth.WeightWindows)
@@ -107,7 +111,7 @@ class Transport:
         mc.mc_run_batch(self.ctx, seed, first_pid, n, run_opts(**opts))
 
     def tallies(self, tally_id):
-        nb = mc.MC_N_GLOBAL if tally_id == mc.MC_T_GLOBAL else self.n_bins
+        nb = {mc.MC_T_GLOBAL: mc.MC_N_GLOBAL, mc.MC_T_REACTION: self.n_reaction}.get(tally_id, self.n_bins)
         mean, se, meta = mc.mc_get_tallies(self.ctx, tally_id, nb)
         return mean, se, meta
 

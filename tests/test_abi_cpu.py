@@ -46,8 +46,10 @@ def _header_enum(name):
 def test_binding_constants_match_header_and_oracle():
     import oracle
     for k in ("MC_G_LEAK_XHI", "MC_G_SPLIT", "MC_G_ROULETTE", "MC_N_GLOBAL", "MC_MLP_NPAR", "MC_FATE_ROULETTE",
-              "MC_WW_LINEAR", "MC_WW_MLP"):
+              "MC_WW_LINEAR", "MC_WW_MLP", "MC_T_REACTION"):
         assert getattr(mc, k) == _header_enum(k), k
+    src = open(os.path.join(ROOT, "include", "mc.h")).read()
+    assert mc.MC_MAX_CHANNELS == int(re.search(r"#define MC_MAX_CHANNELS (\d+)", src).group(1))
     assert mc.MC_N_GLOBAL == oracle.N_GLOBAL
     assert mc.MC_G_SPLIT == oracle.G_SPLIT and mc.MC_G_ROULETTE == oracle.G_ROULETTE
     from oracle import mlp
