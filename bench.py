@@ -134,6 +134,40 @@ def c3_transport(tuning_cache: str, histories: int = 20_000_000, tune_histories:
             "mesh_track_sum": float(mesh.sum()), "total_track": float(glob[0]), "tuning": tuning}
 
 
+def c3_channels(tuning: dict, n_chan: int = 10, histories: int = 20_000_000, prob=None):
+    """The 300-nuclide lattice with n_chan reaction channels per nuclide (the
+    per-nuclide reaction data of a depletion tally; ~2.6 GB of tables for 10):
+    every lookup assembles them, every flight scores per-material
+    track-length reaction rates.  One batch of 2e7 histories with the launch
+    shapes tuned for the same lattice without channels."""
+    import mcsynth
+    from paper_2403_12345_amd import mc
+    from paper_2403_12345_amd.transport import Transport
+
+    prob = prob if prob is not None else mcsynth.c3_problem()
+    prob = mcsynth.with_channels(prob, n_chan)
+    table_bytes = prob.data_bytes()
+    try:
+        with Transport(prob, device=0) as t:
+            mc.mc_set_tuning(t.ctx, **tuning)
+            t.run_batch(prob.seed, 0, histories, time_kernels=True)
+            s = t.stats()
+            rr, _, _ = t.tallies(mc.MC_T_REACTION)
+    finally:
+        prob.channels = None
+    sec = s["batch_ms"] / 1e3
+    lk = s["lookup_ms"] / 1e3
+    gbs = s["lookup_bytes"] / lk / 1e9 if lk > 0 else 0.0
+    return {"workload": f"the 300-nuclide lattice with {n_chan} reaction channels per nuclide "
+                        f"({table_bytes / 1e9:.2f} GB of tables), per-material track-length reaction "
+                        f"rates, 2e7 histories per batch",
+            "xs_bytes": table_bytes,
+            "n_chan": n_chan, "histories": histories, "particles_per_s": histories / sec, "batch_s": sec,
+            "lookups_per_s_insitu": s["lookups"] / sec, "bytes_per_lookup": 36 + 8 * n_chan + (56 + 16 * n_chan) * 300,
+            "lookup_kernel_s": lk, "lookup_GBs": gbs, "lookup_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "reaction_rates_per_source": [float(x) for x in rr], "tuning": tuning}
+
+
 def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(2,), prob=None):
     """Stand-alone lookup of n (energy, material) pairs on the 300-nuclide
     material (grids of 20k-150k points, ~0.6 GB of tables, far above the
@@ -318,7 +352,9 @@ def main():
         print(json.dumps({"fom": fom_bench()}), flush=True)
         return
     if args.mode == "c3":
-        print(json.dumps({"c3_transport": c3_transport(args.tuning_cache)}), flush=True)
+        c3 = mcsynth.c3_problem()
+        plain = c3_transport(args.tuning_cache, prob=c3)
+        print(json.dumps({"c3_transport": plain, "c3_channels": c3_channels(plain["tuning"], prob=c3)}), flush=True)
         return
     from paper_2403_12345_amd import mc
 
@@ -404,6 +440,7 @@ def main():
         line["lookup_microbench"] = lookup_microbench(prob=c3)
     if not args.no_c3:
         line["c3_transport"] = c3_transport(args.tuning_cache, prob=c3)
+        line["c3_channels"] = c3_channels(line["c3_transport"]["tuning"], prob=c3)
     if not args.no_problem_set:
         line["problem_set"] = problem_set_bench()
     if not args.no_fom:

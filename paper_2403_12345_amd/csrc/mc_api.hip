@@ -1607,7 +1607,9 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
 {
     if (!ctx || n == 0) return MC_EINVAL;
     if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "mc_autotune: materials and geometry first");
-    const std::string sig = sig_text(ctx, "single", fnv(ctx->geom_sig, &n, sizeof(n)));
+    uint64_t key = fnv(ctx->geom_sig, &n, sizeof(n));
+    if (ctx->n_chan) key = fnv(key, &ctx->n_chan, sizeof(ctx->n_chan));  // channels change the lookup kernel
+    const std::string sig = sig_text(ctx, "single", key);
     mc_tuning t = ctx->tune;
     if (cache_lookup(cache_path, sig, t)) {
         ctx->tune = t;
