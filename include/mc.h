@@ -376,6 +376,17 @@ int mc_hash_bounds(const double *E, int32_t N, double emin, double emax, int32_t
  *                  the collision's re-gathers) when at least this many
  *                  particles are alive (0: the lookup queue's sort_min;
  *                  2^30: never)
+ *   loops          event loops run at once in mc_run_batch (0 or 1: one;
+ *                  at most 8): loop l takes the l-th contiguous share of the
+ *                  batch's pids on its own stream and host thread, with its
+ *                  own bank of in_flight slots, sharing the tables; the
+ *                  batch tallies sum the loops' rows in loop order, so the
+ *                  histories are the same for any count and the tallies
+ *                  differ only by summation order (reruns with the same count
+ *                  are bitwise identical).  The paper runs several ranks per
+ *                  GPU for the same overlap (section 2, "GPU Streams").
+ *                  Analog batches only (one loop with weight windows or an
+ *                  importance grid), and at least 4096 histories per loop.
  */
 typedef struct mc_tuning {
     int32_t lookup_ilp;
@@ -385,7 +396,7 @@ typedef struct mc_tuning {
     int32_t set_tile_histories;
     int32_t set_grid;
     int32_t collide_sort_min;
-    int32_t reserved;
+    int32_t loops;
 } mc_tuning;
 
 /* Set (mc_set_tuning) or read (mc_get_tuning) the context's launch shapes.
@@ -399,8 +410,8 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
  * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
  * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}
  * in_flight {n/4, n/2, 2^20, 2^22, n} (each at most n and 2^24; the
- * search starts from min(n, 2^22)) and collide_sort_min {0, never}, keeps the
- * fastest in the
+ * search starts from min(n, 2^22)), collide_sort_min {0, never} and loops
+ * {1, 2, 3, 4}, keeps the fastest in the
  * context (mc_set_tuning) and returns it in *best.  The tallies are reset afterwards.  cache_path (nullable) names a
  * text file of one line per tuned problem: when it holds the signature of
  * this problem and device, the stored setting is used without timing; else

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mc.h"
@@ -89,6 +90,19 @@ struct mc_ctx {
 
     std::vector<hipEvent_t> ev_a, ev_b;
     hipEvent_t ev_batch0 = nullptr, ev_batch1 = nullptr;
+
+    // concurrent event loops (tuning field loops > 1): each a worker context
+    // with its own stream, bank and counters, sharing this context's tables;
+    // their tally rows are slices of one array so the batch sums them in order
+    std::vector<mc_ctx *> workers;
+    bool owns_stream = false;
+    Buffers loop_bufs;
+    TallyDev loop_tal{};         // [loops * rows] rows (mesh arrays shared)
+    int32_t loop_n = 0, loop_rows = 0, loop_bins = -1, loop_chan_bins = -1;
+    bool loop_mesh = false;
+    double *loop_partial = nullptr;
+    hipEvent_t ev_loop_start = nullptr;
+    std::vector<hipEvent_t> ev_loop_done;
     mc_stats stats{};
     bool timing = false;  // time the stand-alone lookups (mc_set_timing)
     mc_tuning tune{};      // launch shapes (0 = default)
@@ -260,8 +274,13 @@ int mc_create(mc_ctx **out, int device, void *hip_stream)
 void mc_destroy(mc_ctx *ctx)
 {
     if (!ctx) return;
+    for (mc_ctx *w : ctx->workers) mc_destroy(w);
+    ctx->workers.clear();
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    ctx->loop_bufs.release();
+    if (ctx->ev_loop_start) (void)hipEventDestroy(ctx->ev_loop_start);
+    for (hipEvent_t e : ctx->ev_loop_done) (void)hipEventDestroy(e);
     ctx->mat_bufs.release();
     ctx->geom_bufs.release();
     ctx->bank_bufs.release();
@@ -282,6 +301,7 @@ void mc_destroy(mc_ctx *ctx)
     for (hipEvent_t e : ctx->ev_b) (void)hipEventDestroy(e);
     if (ctx->ev_batch0) (void)hipEventDestroy(ctx->ev_batch0);
     if (ctx->ev_batch1) (void)hipEventDestroy(ctx->ev_batch1);
+    if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
 
@@ -915,14 +935,13 @@ static int ensure_ww(mc_ctx *ctx, uint32_t cap)
     return MC_OK;
 }
 
-int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const mc_run_opts *opts_in)
+// One event loop over histories [first_pid, first_pid + n) on the context's
+// stream.  view == nullptr: the context's own tally rows, zeroed here, and the
+// batch statistics at the end.  view != nullptr (a worker of concurrent
+// loops): the rows of the view, zeroed by the caller, and no statistics.
+static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const mc_run_opts &opts,
+                    const TallyDev *view)
 {
-    if (!ctx) return MC_EINVAL;
-    if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "mc_run_batch: materials and geometry first");
-    if (n == 0) return fail(ctx, MC_EINVAL, "mc_run_batch: n must be >= 1");
-    HIPCHK(hipSetDevice(ctx->device));
-    mc_run_opts opts{};
-    if (opts_in) opts = *opts_in;
     const bool windows = ctx->ww_desc.kind != MC_WW_OFF;
     uint64_t cap64 = opts.in_flight ? opts.in_flight
                                     : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight
@@ -944,7 +963,7 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     hipStream_t st = ctx->stream;
     BankDev &b = ctx->bank;
     const WwDev &W = ctx->ww;
-    TallyDev tal = ctx->tal;
+    TallyDev tal = view ? *view : ctx->tal;
     tal.enabled = opts.no_tally ? 0 : 1;
     const GeomDev &g = ctx->geom;
     const bool mesh = g.tally_kind == TALLY_MESH;
@@ -952,13 +971,15 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     // reset per-batch state
     HIPCHK(launch_fill_u8(b.flags, cap, 0, st));
     const size_t row_bins = mesh ? 1 : (size_t)ctx->n_bins;
-    HIPCHK(launch_fill_f64(tal.tl, (size_t)tal.rows * row_bins, 0.0, st));
-    HIPCHK(launch_fill_f64(tal.coll, (size_t)tal.rows * row_bins, 0.0, st));
-    HIPCHK(launch_fill_f64(tal.glob, (size_t)tal.rows * N_GLOBAL, 0.0, st));
-    if (tal.chan) HIPCHK(launch_fill_f64(tal.chan, (size_t)tal.rows * (size_t)tal.chan_bins, 0.0, st));
-    if (mesh) {
-        HIPCHK(launch_fill_f64(tal.mesh_tl, (size_t)ctx->n_bins, 0.0, st));
-        HIPCHK(launch_fill_f64(tal.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
+    if (!view) {
+        HIPCHK(launch_fill_f64(tal.tl, (size_t)tal.rows * row_bins, 0.0, st));
+        HIPCHK(launch_fill_f64(tal.coll, (size_t)tal.rows * row_bins, 0.0, st));
+        HIPCHK(launch_fill_f64(tal.glob, (size_t)tal.rows * N_GLOBAL, 0.0, st));
+        if (tal.chan) HIPCHK(launch_fill_f64(tal.chan, (size_t)tal.rows * (size_t)tal.chan_bins, 0.0, st));
+        if (mesh) {
+            HIPCHK(launch_fill_f64(tal.mesh_tl, (size_t)ctx->n_bins, 0.0, st));
+            HIPCHK(launch_fill_f64(tal.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
+        }
     }
     HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->ctr), 2 * sizeof(Counters) / 4, 0u, st));
     // with windows, copies add into their history's record: it starts zeroed
@@ -1051,6 +1072,22 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
         HIPCHK(launch_collide(b, qc, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
         if (W.kind != WW_OFF) HIPCHK(launch_ww_flush(b, W, dc, st));
     }
+    if (view) {  // a worker of concurrent loops: its caller forms the statistics
+        HIPCHK(hipEventRecord(ctx->ev_batch1, st));
+        unsigned long long dstat[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(dstat, ctx->dstat, sizeof(dstat), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t k = 0; k < n_timed; ++k) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ctx->ev_a[k], ctx->ev_b[k]));
+            s.lookup_ms += t;
+        }
+        s.iterations = it;
+        s.nuclide_lookups = dstat[0];
+        s.lost = dstat[1];
+        ctx->stats = s;
+        return MC_OK;
+    }
     // batch statistics: per-workgroup rows summed in a fixed order
     const double inv_n = 1.0 / (double)n;
     if (mesh) {
@@ -1093,6 +1130,216 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     if (s.lost > opts.max_lost)
         return fail(ctx, MC_ELOST, std::to_string(s.lost) + " particles lost (event cap reached)");
     return MC_OK;
+}
+
+// Worker contexts of concurrent loops: own stream (default priority), bank,
+// counters and events; the tables and tallies of ctx, refreshed per batch.
+static int ensure_workers(mc_ctx *ctx, int L)
+{
+    while ((int)ctx->workers.size() < L) {
+        hipStream_t st = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        mc_ctx *w = nullptr;
+        const int rc = mc_create(&w, ctx->device, st);
+        if (rc) {
+            (void)hipStreamDestroy(st);
+            return fail(ctx, rc, "concurrent loops: worker context");
+        }
+        w->owns_stream = true;
+        ctx->workers.push_back(w);
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->ev_loop_done.push_back(e);
+    }
+    if (!ctx->ev_loop_start) HIPCHK(hipEventCreateWithFlags(&ctx->ev_loop_start, hipEventDisableTiming));
+    for (int l = 0; l < L; ++l) {
+        mc_ctx *w = ctx->workers[l];
+        w->have_mat = w->have_geom = true;
+        w->xs = ctx->xs;
+        w->geom = ctx->geom;
+        w->n_bins = ctx->n_bins;
+        w->n_mat = ctx->n_mat;
+        w->n_nuc = ctx->n_nuc;
+        w->n_keys = ctx->n_keys;
+        w->n_chan = ctx->n_chan;
+        w->tune = ctx->tune;
+        w->tune.loops = 1;
+        w->ww_desc = mc_ww_desc{};
+        w->ww_desc.kind = MC_WW_OFF;
+    }
+    return MC_OK;
+}
+
+// Tally rows of L concurrent loops of R rows each (and the shared mesh
+// arrays), laid out so that the batch statistics read them as one array.
+static int ensure_loop_rows(mc_ctx *ctx, int L, int32_t R)
+{
+    const bool mesh = ctx->geom.tally_kind == TALLY_MESH;
+    const int32_t chan_bins = ctx->n_chan ? ctx->n_mat * ctx->n_chan : 0;
+    if (ctx->loop_n == L && ctx->loop_rows >= R && ctx->loop_bins == ctx->n_bins && ctx->loop_mesh == mesh &&
+        ctx->loop_chan_bins == chan_bins)
+        return MC_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->loop_bufs.release();
+    ctx->loop_n = 0;
+    Buffers &B = ctx->loop_bufs;
+    TallyDev t{};
+    t.n_bins = ctx->n_bins;
+    t.rows = L * R;
+    t.n_chan = ctx->n_chan;
+    t.chan_bins = chan_bins;
+    const size_t row_bins = mesh ? 1 : (size_t)ctx->n_bins;
+    int rc = dalloc(ctx, B, &t.tl, (size_t)t.rows * row_bins);
+    if (!rc) rc = dalloc(ctx, B, &t.coll, (size_t)t.rows * row_bins);
+    if (!rc) rc = dalloc(ctx, B, &t.glob, (size_t)t.rows * N_GLOBAL);
+    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins);
+    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins);
+    if (!rc && chan_bins) rc = dalloc(ctx, B, &t.chan, (size_t)t.rows * (size_t)chan_bins);
+    const size_t part_bins = std::max<size_t>(std::max<size_t>(ctx->n_bins, N_GLOBAL), (size_t)chan_bins);
+    if (!rc) rc = dalloc(ctx, B, &ctx->loop_partial, (size_t)64 * part_bins);
+    if (rc) {
+        B.release();
+        return rc;
+    }
+    ctx->loop_tal = t;
+    ctx->loop_n = L;
+    ctx->loop_rows = R;
+    ctx->loop_bins = ctx->n_bins;
+    ctx->loop_mesh = mesh;
+    ctx->loop_chan_bins = chan_bins;
+    return MC_OK;
+}
+
+// L event loops at once (the paper runs several ranks per GPU for the same
+// effect): loop l takes the l-th contiguous share of the pids on its own
+// stream, driven by its own host thread; the batch statistics sum the rows of
+// loop 0, then loop 1, ... (fixed order: reruns are bitwise identical).
+static int run_concurrent(mc_ctx *ctx, int L, uint64_t seed, uint64_t first_pid, uint64_t n,
+                          const mc_run_opts &opts)
+{
+    int rc = ensure_workers(ctx, L);
+    if (rc) return rc;
+    const uint64_t per_max = (n + (uint64_t)L - 1) / (uint64_t)L;
+    uint64_t cap = opts.in_flight ? opts.in_flight
+                                  : (ctx->tune.in_flight > 0 ? (uint64_t)ctx->tune.in_flight : kDefaultInFlight);
+    cap = std::min(cap, per_max);
+    if (cap > (1ull << 30)) return fail(ctx, MC_EINVAL, "in_flight above 2^30");
+    const int32_t R = (int32_t)((cap + WG - 1) / WG);
+    rc = ensure_loop_rows(ctx, L, R);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    const bool mesh = ctx->geom.tally_kind == TALLY_MESH;
+    TallyDev all = ctx->loop_tal;
+    all.enabled = opts.no_tally ? 0 : 1;
+    const size_t row_bins = mesh ? 1 : (size_t)ctx->n_bins;
+    HIPCHK(hipEventRecord(ctx->ev_batch0, st));
+    HIPCHK(launch_fill_f64(all.tl, (size_t)all.rows * row_bins, 0.0, st));
+    HIPCHK(launch_fill_f64(all.coll, (size_t)all.rows * row_bins, 0.0, st));
+    HIPCHK(launch_fill_f64(all.glob, (size_t)all.rows * N_GLOBAL, 0.0, st));
+    if (all.chan) HIPCHK(launch_fill_f64(all.chan, (size_t)all.rows * (size_t)all.chan_bins, 0.0, st));
+    if (mesh) {
+        HIPCHK(launch_fill_f64(all.mesh_tl, (size_t)ctx->n_bins, 0.0, st));
+        HIPCHK(launch_fill_f64(all.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
+    }
+    HIPCHK(hipEventRecord(ctx->ev_loop_start, st));
+    std::vector<TallyDev> views(L);
+    std::vector<mc_run_opts> wopts(L, opts);
+    std::vector<uint64_t> first(L), count(L);
+    uint64_t next = first_pid;
+    for (int l = 0; l < L; ++l) {
+        count[l] = n / (uint64_t)L + ((uint64_t)l < n % (uint64_t)L ? 1 : 0);
+        first[l] = next;
+        next += count[l];
+        TallyDev v = all;
+        v.rows = R;
+        v.tl = all.tl + (size_t)l * R * row_bins;
+        v.coll = all.coll + (size_t)l * R * row_bins;
+        v.glob = all.glob + (size_t)l * R * N_GLOBAL;
+        if (all.chan) v.chan = all.chan + (size_t)l * R * (size_t)all.chan_bins;
+        views[l] = v;
+        wopts[l].in_flight = std::min<uint64_t>(cap, count[l]);
+        wopts[l].max_lost = UINT64_MAX;  // counted over all loops below
+        if (opts.history_log)
+            wopts[l].history_log = static_cast<HistLog *>(opts.history_log) + (first[l] - first_pid);
+        HIPCHK(hipStreamWaitEvent(ctx->workers[l]->stream, ctx->ev_loop_start, 0));
+    }
+    std::vector<int> wrc(L, MC_OK);
+    auto body = [&](int l) {
+        mc_ctx *w = ctx->workers[l];
+        if (hipSetDevice(w->device) != hipSuccess) {
+            wrc[l] = fail(w, MC_EHIP, "hipSetDevice");
+            return;
+        }
+        wrc[l] = run_loop(w, seed, first[l], count[l], wopts[l], &views[l]);
+    };
+    std::vector<std::thread> threads;
+    for (int l = 1; l < L; ++l) threads.emplace_back(body, l);
+    body(0);
+    for (std::thread &t : threads) t.join();
+    for (int l = 0; l < L; ++l) {
+        if (wrc[l]) {
+            HIPCHK(hipDeviceSynchronize());
+            return fail(ctx, wrc[l], "concurrent loop " + std::to_string(l) + ": " + ctx->workers[l]->err);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        HIPCHK(hipEventRecord(ctx->ev_loop_done[l], ctx->workers[l]->stream));
+        HIPCHK(hipStreamWaitEvent(st, ctx->ev_loop_done[l], 0));
+    }
+    const double inv_n = 1.0 / (double)n;
+    double *part = ctx->loop_partial;
+    if (mesh) {
+        HIPCHK(launch_batch_stats(nullptr, 0, ctx->n_bins, all.mesh_tl, part, inv_n, ctx->S1[0], ctx->S2[0], st));
+        HIPCHK(launch_batch_stats(nullptr, 0, ctx->n_bins, all.mesh_coll, part, inv_n, ctx->S1[1], ctx->S2[1], st));
+    } else {
+        HIPCHK(launch_batch_stats(all.tl, all.rows, ctx->n_bins, nullptr, part, inv_n, ctx->S1[0], ctx->S2[0], st));
+        HIPCHK(launch_batch_stats(all.coll, all.rows, ctx->n_bins, nullptr, part, inv_n, ctx->S1[1], ctx->S2[1], st));
+    }
+    HIPCHK(launch_batch_stats(all.glob, all.rows, N_GLOBAL, nullptr, part, inv_n, ctx->S1[2], ctx->S2[2], st));
+    if (all.chan)
+        HIPCHK(launch_batch_stats(all.chan, all.rows, all.chan_bins, nullptr, part, inv_n, ctx->S1[3], ctx->S2[3],
+                                  st));
+    HIPCHK(hipEventRecord(ctx->ev_batch1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_batch0, ctx->ev_batch1));
+    mc_stats s{};
+    for (int l = 0; l < L; ++l) {
+        const mc_stats &q = ctx->workers[l]->stats;
+        s.lookups += q.lookups;
+        s.nuclide_lookups += q.nuclide_lookups;
+        s.lookup_launches += q.lookup_launches;
+        s.sorted_lookups += q.sorted_lookups;
+        s.lookup_ms += q.lookup_ms;
+        s.tail_particles += q.tail_particles;
+        s.lost += q.lost;
+        s.iterations = std::max(s.iterations, q.iterations);
+    }
+    s.batch_ms = ms;
+    s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +
+                     (56ull + 16ull * (uint64_t)ctx->n_chan) * s.nuclide_lookups;
+    ctx->stats = s;
+    ctx->n_batches += 1;
+    ctx->histories += n;
+    if (s.lost > opts.max_lost)
+        return fail(ctx, MC_ELOST, std::to_string(s.lost) + " particles lost (event cap reached)");
+    return MC_OK;
+}
+
+int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const mc_run_opts *opts_in)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "mc_run_batch: materials and geometry first");
+    if (n == 0) return fail(ctx, MC_EINVAL, "mc_run_batch: n must be >= 1");
+    HIPCHK(hipSetDevice(ctx->device));
+    mc_run_opts opts{};
+    if (opts_in) opts = *opts_in;
+    // concurrent loops: analog batches of at least 4096 histories per loop
+    int L = ctx->tune.loops > 1 ? ctx->tune.loops : 1;
+    if (ctx->ww_desc.kind != MC_WW_OFF || ctx->ww_desc.imp_nx > 0) L = 1;
+    while (L > 1 && n / (uint64_t)L < 4096) --L;
+    if (L > 1) return run_concurrent(ctx, L, seed, first_pid, n, opts);
+    return run_loop(ctx, seed, first_pid, n, opts, nullptr);
 }
 
 int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_, size_t n_bins,
@@ -1140,6 +1387,7 @@ int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t)
     if (t->tail_particles < -1) return fail(ctx, MC_EINVAL, "tail_particles must be >= -1");
     if (t->sort_min < 0 || t->in_flight < 0 || t->set_grid < 0 || t->collide_sort_min < 0)
         return fail(ctx, MC_EINVAL, "negative tuning value");
+    if (t->loops < 0 || t->loops > 8) return fail(ctx, MC_EINVAL, "loops must be in [0, 8]");
     if (t->set_tile_histories < 0 || t->set_tile_histories % WG != 0)
         return fail(ctx, MC_EINVAL, "set_tile_histories must be a multiple of 256");
     ctx->tune = *t;
@@ -1154,6 +1402,7 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t)
     t->tail_particles = (int32_t)tail_particles(ctx);
     if (!t->sort_min) t->sort_min = (int32_t)kDefaultSortMin;
     if (!t->collide_sort_min) t->collide_sort_min = t->sort_min;
+    if (!t->loops) t->loops = 1;
     if (!t->in_flight) t->in_flight = (int32_t)kDefaultInFlight;
     if (!t->set_tile_histories) t->set_tile_histories = WG;
     if (!t->set_grid) t->set_grid = 2 * ctx->n_cu;
@@ -1580,11 +1829,12 @@ static bool cache_lookup(const char *path, const std::string &sig, mc_tuning &t)
         mc_tuning r{};
         double ms = 0.0;
         // fields: signature, lookup_ilp, tail, sort_min, in_flight, set tile,
-        // set grid, best ms, collide_sort_min (absent in older lines: 0)
-        const int got = std::sscanf(line, "%199s %d %d %d %d %d %d %lf %d", s, &r.lookup_ilp, &r.tail_particles,
+        // set grid, best ms, collide_sort_min, loops (the last two absent in
+        // older lines: 0)
+        const int got = std::sscanf(line, "%199s %d %d %d %d %d %d %lf %d %d", s, &r.lookup_ilp, &r.tail_particles,
                                     &r.sort_min, &r.in_flight, &r.set_tile_histories, &r.set_grid, &ms,
-                                    &r.collide_sort_min);
-        if ((got == 8 || got == 9) && sig == s) {
+                                    &r.collide_sort_min, &r.loops);
+        if (got >= 8 && sig == s) {
             t = r;
             found = true;
         }
@@ -1598,8 +1848,8 @@ static void cache_store(const char *path, const std::string &sig, const mc_tunin
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %.4f %d\n", sig.c_str(), t.lookup_ilp, t.tail_particles, t.sort_min,
-                 t.in_flight, t.set_tile_histories, t.set_grid, ms, t.collide_sort_min);
+    std::fprintf(f, "%s %d %d %d %d %d %d %.4f %d %d\n", sig.c_str(), t.lookup_ilp, t.tail_particles, t.sort_min,
+                 t.in_flight, t.set_tile_histories, t.set_grid, ms, t.collide_sort_min, t.loops);
     std::fclose(f);
 }
 
@@ -1637,10 +1887,11 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t sorts[] = {4096, 16384, 65536, 262144, (int32_t)kSortNever};
     const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), 1 << 20, 1 << 22, n_cap};
     const int32_t csorts[] = {0, (int32_t)kSortNever};
-    const int32_t *axes[] = {tails, sorts, ilps, flights, csorts};
-    const int counts[] = {4, 5, 3, 5, 2};
+    const int32_t loops[] = {1, 2, 3, 4};
+    const int32_t *axes[] = {tails, sorts, ilps, flights, csorts, loops};
+    const int counts[] = {4, 5, 3, 5, 2, 4};
     for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
-        for (int axis = 0; axis < 5 && !rc; ++axis) {
+        for (int axis = 0; axis < 6 && !rc; ++axis) {
             for (int k = 0; k < counts[axis] && !rc; ++k) {
                 mc_tuning c = cur;
                 const int32_t v = axes[axis][k];
@@ -1649,6 +1900,7 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
                 if (axis == 2) c.lookup_ilp = v;
                 if (axis == 3) c.in_flight = std::min(v, n_cap);
                 if (axis == 4) c.collide_sort_min = v;
+                if (axis == 5) c.loops = v;
                 if (std::memcmp(&c, &cur, sizeof c) == 0) continue;
                 double ms = 0.0;
                 rc = trial(c, ms);

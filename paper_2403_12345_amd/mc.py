@@ -70,9 +70,9 @@ class mc_stats(C.Structure):
 class mc_tuning(C.Structure):
     _fields_ = [("lookup_ilp", C.c_int32), ("tail_particles", C.c_int32), ("sort_min", C.c_int32),
                 ("in_flight", C.c_int32), ("set_tile_histories", C.c_int32), ("set_grid", C.c_int32),
-                ("collide_sort_min", C.c_int32), ("reserved", C.c_int32)]
+                ("collide_sort_min", C.c_int32), ("loops", C.c_int32)]
     KEYS = ("lookup_ilp", "tail_particles", "sort_min", "in_flight", "set_tile_histories", "set_grid",
-            "collide_sort_min")
+            "collide_sort_min", "loops")
 
     def as_dict(self):
         return {k: getattr(self, k) for k in self.KEYS}

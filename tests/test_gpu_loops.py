@@ -1,0 +1,115 @@
+"""Concurrent event loops (tuning field loops): the batch's pids split into
+contiguous shares, each run by its own event loop on its own stream.
+
+* A history depends only on (seed, pid), so the C1 histories with three loops
+  are the oracle's, record for record (the history log is shared).
+* Lattice tallies with two loops equal the one-loop tallies up to summation
+  order, and reruns with two loops are bitwise identical.
+* Mesh tallies (shared atomic arrays) and reaction rates take part.
+* Windowed batches and small batches fall back to one loop; bad counts are
+  rejected.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import mcsynth
+import oracle
+from paper_2403_12345_amd import mc
+from paper_2403_12345_amd.transport import Transport
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch
+
+
+def _tallies(t, ids=(mc.MC_T_FLUX_TRACK, mc.MC_T_FLUX_COLLISION, mc.MC_T_GLOBAL)):
+    return [t.tallies(k)[0] for k in ids]
+
+
+@pytest.mark.parametrize("loops", [2, 3])
+def test_c1_histories_identical_to_oracle_with_loops(torch_cuda, loops):
+    torch = torch_cuda
+    prob = mcsynth.c1_problem()
+    n = 10_000
+    _say(f"c1 loops={loops}")
+    with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, loops=loops)
+        log = torch.zeros(n * mc.HISTORY_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        t.run_batch(1, 0, n, history_log=log)
+        torch.cuda.synchronize()
+        g = log.cpu().numpy().view(mc.HISTORY_DTYPE)
+    o = oracle.run(oracle.OracleProblem(prob), 1, 0, n, history=True).history
+    for k in ("fate", "n_coll", "n_cross", "n_draws", "E_final"):
+        assert np.array_equal(g[k], o[k]), k
+    np.testing.assert_allclose(g["track"], o["track"], rtol=1e-12)
+
+
+def test_c2_two_loops_match_one_loop_and_rerun_bitwise(torch_cuda):
+    prob = mcsynth.c2_problem()
+    _say("c2 loops")
+    res = {}
+    for loops in (1, 2, 2):
+        with Transport(prob) as t:
+            mc.mc_set_tuning(t.ctx, loops=loops, in_flight=60_000)
+            for b in range(3):
+                t.run_batch(2, b * 100_000, 100_000)
+            res.setdefault(loops, []).append(_tallies(t))
+    one, two_a, two_b = res[1][0], res[2][0], res[2][1]
+    for a, b in zip(two_a, two_b):
+        assert np.array_equal(a, b)
+    for a, b in zip(one, two_a):
+        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-300)
+
+
+def test_mesh_and_reaction_rates_with_loops(torch_cuda):
+    c2 = mcsynth.c2_problem(histories=1000)
+    prob = mcsynth.lattice_homogeneous_problem(c2.nuclides, c2.materials[0], n=5, seed=6)
+    L = 5 * mcsynth.PIN_PITCH
+    prob.tally = mcsynth.Tally(mcsynth.TALLY_MESH, mesh_dims=(10, 10, 2), mesh_box=(0.0, L, 0.0, L, 0.0, 1.0))
+    prob = mcsynth.with_channels(prob, 3)
+    ids = (mc.MC_T_FLUX_TRACK, mc.MC_T_GLOBAL, mc.MC_T_REACTION)
+    out = {}
+    for loops in (1, 4):
+        with Transport(prob) as t:
+            mc.mc_set_tuning(t.ctx, loops=loops)
+            for b in range(2):
+                t.run_batch(6, b * 40_000, 40_000)
+            out[loops] = _tallies(t, ids)
+    for a, b in zip(out[1], out[4]):
+        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-300)
+
+
+def test_loops_fall_back_and_reject_bad_counts(torch_cuda):
+    prob = mcsynth.slab_problem(sigma_t=(0.1, 0.3, 0.1), thickness=(20.0, 20.0, 20.0),
+                                scatter_ratio=(0.8, 0.6, 0.8), awr=12.0)
+    prob.ww = mcsynth.WeightWindows(kind=mcsynth.WW_LINEAR, lin=(0.0, 4.0, 0.0), length=60.0)
+    with Transport(prob) as t:
+        base = None
+        for loops in (1, 3):
+            mc.mc_set_tuning(t.ctx, loops=loops)
+            t.reset()
+            t.run_batch(8, 0, 20_000)   # windows: one loop either way
+            g = t.tallies(mc.MC_T_GLOBAL)[0]
+            if base is None:
+                base = g
+            else:
+                assert np.array_equal(base, g)
+        with pytest.raises(mc.MCError, match="MC_EINVAL"):
+            mc.mc_set_tuning(t.ctx, loops=9)
+    prob = mcsynth.c1_problem()
+    with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, loops=4)
+        t.run_batch(1, 0, 5000)          # fewer than 4096 per loop: fewer loops
+        assert t.tallies(mc.MC_T_GLOBAL)[2].n_batches == 1
