@@ -365,21 +365,31 @@ def main():
     # launch shapes from the library's autotuner (from its cache when this
     # problem was tuned on this device kind, else timed on batches of other pids)
     tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n, args.tuning_cache)
-    for w in range(args.warmup):
-        t.run_batch(seed, w * n, n)
+    if args.warmup:
+        t.run_batches(seed, 0, n, args.warmup)
     t.reset()
-    tot = {"lookup_ms": 0.0, "lookup_bytes": 0, "lookup_launches": 0, "lookups": 0,
-           "nuclide_lookups": 0, "iterations": 0, "sorted_lookups": 0}
+    # the K steps: K batches through mc_run_batches (with the tuned number of
+    # event loops, consecutive batches overlap), every lookup launch timed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        t.run_batch(seed, (args.warmup + k) * n, n, time_kernels=True)
-        s = t.stats()
-        for key in tot:
-            tot[key] += s[key]
+    t.run_batches(seed, args.warmup * n, n, args.steps, time_kernels=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    tot = t.stats()
     value = args.steps * n / elapsed
+
+    # the lookup kernel on one event loop (no other loop's kernels beside it)
+    single_loop = None
+    if tuning.get("loops", 1) > 1:
+        mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
+        t.run_batch(seed, (args.warmup + args.steps) * n, n, time_kernels=True)
+        s1 = t.stats()
+        mc.mc_set_tuning(t.ctx, **tuning)
+        l1 = max(s1["lookup_launches"], 1)
+        us1 = s1["lookup_ms"] * 1e3 / l1
+        a1 = s1["lookup_bytes"] / l1 / (us1 / 1e6) / 1e9
+        single_loop = {"batch_ms": s1["batch_ms"], "particles_per_s": n / (s1["batch_ms"] / 1e3),
+                       "avg_launch_us": us1, "achieved": a1, "frac": a1 / HBM_PEAK_GBS}
 
     inactive = None
     if not args.no_inactive:
@@ -433,6 +443,7 @@ def main():
         "lookups_per_s_insitu": tot["lookups"] / elapsed,
         "nuclide_lookups_per_lookup": tot["nuclide_lookups"] / max(tot["lookups"], 1),
         "iterations_per_step": tot["iterations"] / args.steps,
+        "lookup_one_loop": single_loop,
         "inactive_particles_per_s": inactive,
     }
     c3 = mcsynth.c3_problem() if not (args.no_lookup_bench and args.no_c3) else None

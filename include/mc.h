@@ -247,6 +247,22 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n,
                  const mc_run_opts *opts);
 
 /*
+ * n_batches batches of n histories each, batch b holding pids [first_pid +
+ * b n, first_pid + (b + 1) n): the same tallies, bit for bit, as n_batches
+ * calls of mc_run_batch (each batch's value is formed from its own rows and
+ * the statistics take the values in batch order).  With the tuning field
+ * loops = L > 1 (analog transport) up to L batches run at once, each whole
+ * batch on its own event loop (stream, host thread and bank), the next batch
+ * to the first loop free -- the overlap the paper gets from several ranks per
+ * GPU (section 2, "GPU Streams"): one batch's sparse tail runs beside another
+ * batch's full queues.  mc_get_stats then describes the whole call (batch_ms:
+ * its wall time; the counters summed).  history_log (opts) holds n_batches * n
+ * records.  At most 2^20 batches per call.  Errors as mc_run_batch.
+ */
+int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, uint64_t n_batches,
+                 const mc_run_opts *opts);
+
+/*
  * Batch statistics of tally `tally_id` (MC_T_*) over every batch since the
  * last reset: mean[b] = S1/B and stderr_[b] = sqrt((S2/B - mean^2)/(B - 1))
  * of the per-source-particle batch values (stderr_ is 0 when B < 2).
@@ -405,8 +421,9 @@ int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t);
 int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
 
 /*
- * Autotuner of the single-problem path: times one batch of n histories
- * (pids first_pid .. first_pid + n - 1, key seed) per candidate, searching one
+ * Autotuner of the single-problem path: times mc_run_batches of n histories
+ * per batch (pids from first_pid, key seed; 4 batches, 2 when n >= 2^22) per
+ * candidate, per batch, searching one
  * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
  * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}
  * in_flight {n/4, n/2, 2^20, 2^22, n} (each at most n and 2^24; the

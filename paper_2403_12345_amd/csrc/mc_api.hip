@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <atomic>
+#include <chrono>
 #include <thread>
 #include <vector>
 
@@ -103,6 +105,9 @@ struct mc_ctx {
     double *loop_partial = nullptr;
     hipEvent_t ev_loop_start = nullptr;
     std::vector<hipEvent_t> ev_loop_done;
+    Buffers batch_bufs;            // per-batch values of mc_run_batches
+    double *batch_vals = nullptr;
+    size_t batch_vals_n = 0;
     mc_stats stats{};
     bool timing = false;  // time the stand-alone lookups (mc_set_timing)
     mc_tuning tune{};      // launch shapes (0 = default)
@@ -279,6 +284,7 @@ void mc_destroy(mc_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->loop_bufs.release();
+    ctx->batch_bufs.release();
     if (ctx->ev_loop_start) (void)hipEventDestroy(ctx->ev_loop_start);
     for (hipEvent_t e : ctx->ev_loop_done) (void)hipEventDestroy(e);
     ctx->mat_bufs.release();
@@ -936,11 +942,11 @@ static int ensure_ww(mc_ctx *ctx, uint32_t cap)
 }
 
 // One event loop over histories [first_pid, first_pid + n) on the context's
-// stream.  view == nullptr: the context's own tally rows, zeroed here, and the
-// batch statistics at the end.  view != nullptr (a worker of concurrent
-// loops): the rows of the view, zeroed by the caller, and no statistics.
+// stream, into the context's own tally rows (view == nullptr) or the rows of
+// a view; zero_rows: clear them first; stats: add the batch statistics (and
+// count the batch) at the end.
 static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, const mc_run_opts &opts,
-                    const TallyDev *view)
+                    const TallyDev *view, bool zero_rows, bool stats)
 {
     const bool windows = ctx->ww_desc.kind != MC_WW_OFF;
     uint64_t cap64 = opts.in_flight ? opts.in_flight
@@ -971,7 +977,7 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
     // reset per-batch state
     HIPCHK(launch_fill_u8(b.flags, cap, 0, st));
     const size_t row_bins = mesh ? 1 : (size_t)ctx->n_bins;
-    if (!view) {
+    if (zero_rows) {
         HIPCHK(launch_fill_f64(tal.tl, (size_t)tal.rows * row_bins, 0.0, st));
         HIPCHK(launch_fill_f64(tal.coll, (size_t)tal.rows * row_bins, 0.0, st));
         HIPCHK(launch_fill_f64(tal.glob, (size_t)tal.rows * N_GLOBAL, 0.0, st));
@@ -1072,7 +1078,7 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
         HIPCHK(launch_collide(b, qc, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
         if (W.kind != WW_OFF) HIPCHK(launch_ww_flush(b, W, dc, st));
     }
-    if (view) {  // a worker of concurrent loops: its caller forms the statistics
+    if (!stats) {  // a worker of concurrent loops or batches: its caller forms the statistics
         HIPCHK(hipEventRecord(ctx->ev_batch1, st));
         unsigned long long dstat[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(dstat, ctx->dstat, sizeof(dstat), hipMemcpyDeviceToHost, st));
@@ -1270,7 +1276,7 @@ static int run_concurrent(mc_ctx *ctx, int L, uint64_t seed, uint64_t first_pid,
             wrc[l] = fail(w, MC_EHIP, "hipSetDevice");
             return;
         }
-        wrc[l] = run_loop(w, seed, first[l], count[l], wopts[l], &views[l]);
+        wrc[l] = run_loop(w, seed, first[l], count[l], wopts[l], &views[l], false, false);
     };
     std::vector<std::thread> threads;
     for (int l = 1; l < L; ++l) threads.emplace_back(body, l);
@@ -1339,7 +1345,176 @@ int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, con
     if (ctx->ww_desc.kind != MC_WW_OFF || ctx->ww_desc.imp_nx > 0) L = 1;
     while (L > 1 && n / (uint64_t)L < 4096) --L;
     if (L > 1) return run_concurrent(ctx, L, seed, first_pid, n, opts);
-    return run_loop(ctx, seed, first_pid, n, opts, nullptr);
+    return run_loop(ctx, seed, first_pid, n, opts, nullptr, true, true);
+}
+
+// Batches b = 0 .. n_batches-1 of pids [first_pid + b n, first_pid + (b+1) n),
+// up to `loops` of them at once, each whole batch on one worker (its own
+// stream, bank and rows; the next batch goes to the first worker free).
+// Every batch's value is formed from its own rows exactly as mc_run_batch
+// forms it, and the statistics take the values in batch order: the tallies
+// equal those of n_batches mc_run_batch calls bit for bit.
+int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, uint64_t n_batches,
+                   const mc_run_opts *opts_in)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "mc_run_batches: materials and geometry first");
+    if (n == 0 || n_batches == 0) return fail(ctx, MC_EINVAL, "mc_run_batches: n and n_batches must be >= 1");
+    if (n_batches > (1u << 20)) return fail(ctx, MC_EINVAL, "mc_run_batches: at most 2^20 batches per call");
+    HIPCHK(hipSetDevice(ctx->device));
+    mc_run_opts opts{};
+    if (opts_in) opts = *opts_in;
+    int L = ctx->tune.loops > 1 ? ctx->tune.loops : 1;
+    if (ctx->ww_desc.kind != MC_WW_OFF || ctx->ww_desc.imp_nx > 0) L = 1;
+    if ((uint64_t)L > n_batches) L = (int)n_batches;
+    if (L <= 1) {
+        mc_stats tot{};
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint64_t b = 0; b < n_batches; ++b) {
+            mc_run_opts o = opts;
+            if (opts.history_log) o.history_log = static_cast<HistLog *>(opts.history_log) + b * n;
+            const int rc = mc_run_batch(ctx, seed, first_pid + b * n, n, &o);
+            if (rc) return rc;
+            const mc_stats &q = ctx->stats;
+            tot.iterations += q.iterations;
+            tot.lookups += q.lookups;
+            tot.nuclide_lookups += q.nuclide_lookups;
+            tot.lookup_launches += q.lookup_launches;
+            tot.sorted_lookups += q.sorted_lookups;
+            tot.lost += q.lost;
+            tot.lookup_bytes += q.lookup_bytes;
+            tot.lookup_ms += q.lookup_ms;
+            tot.tail_particles += q.tail_particles;
+        }
+        tot.batch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ctx->stats = tot;
+        return MC_OK;
+    }
+    int rc = ensure_workers(ctx, L);
+    if (rc) return rc;
+    const bool mesh = ctx->geom.tally_kind == TALLY_MESH;
+    const int32_t nb_t = ctx->n_bins, nb_r = ctx->n_chan ? ctx->n_mat * ctx->n_chan : 0;
+    const size_t cols = 2 * (size_t)nb_t + N_GLOBAL + (size_t)nb_r;  // tl, coll, glob, reaction
+    if (ctx->batch_vals_n < n_batches * cols) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->batch_bufs.release();
+        ctx->batch_vals_n = 0;
+        rc = dalloc(ctx, ctx->batch_bufs, &ctx->batch_vals, n_batches * cols);
+        if (rc) return rc;
+        ctx->batch_vals_n = n_batches * cols;
+    }
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipEventRecord(ctx->ev_batch0, st));
+    HIPCHK(hipEventRecord(ctx->ev_loop_start, st));
+    for (int l = 0; l < L; ++l) HIPCHK(hipStreamWaitEvent(ctx->workers[l]->stream, ctx->ev_loop_start, 0));
+    std::atomic<uint64_t> next{0};
+    std::atomic<bool> failed{false};
+    std::vector<int> wrc(L, MC_OK);
+    std::vector<mc_stats> tot(L);
+    const double inv_n = 1.0 / (double)n;
+    auto body = [&](int l) {
+        mc_ctx *w = ctx->workers[l];
+        if (hipSetDevice(w->device) != hipSuccess) {
+            wrc[l] = fail(w, MC_EHIP, "hipSetDevice");
+            failed = true;
+            return;
+        }
+        for (;;) {
+            const uint64_t b = next++;
+            if (b >= n_batches || failed) return;
+            mc_run_opts o = opts;
+            o.max_lost = UINT64_MAX;  // counted over all batches below
+            if (opts.history_log) o.history_log = static_cast<HistLog *>(opts.history_log) + b * n;
+            int r = run_loop(w, seed, first_pid + b * n, n, o, nullptr, true, false);
+            // the batch's value from its rows, as mc_run_batch forms it
+            const TallyDev &t = w->tal;
+            double *T = ctx->batch_vals + b * cols;
+            hipStream_t ws = w->stream;
+            if (!r) {
+                hipError_t e = hipSuccess;
+                if (mesh) {
+                    e = launch_batch_stats(nullptr, 0, nb_t, t.mesh_tl, w->partial, inv_n, T, nullptr, ws);
+                    if (e == hipSuccess)
+                        e = launch_batch_stats(nullptr, 0, nb_t, t.mesh_coll, w->partial, inv_n, T + nb_t, nullptr, ws);
+                } else {
+                    e = launch_batch_stats(t.tl, t.rows, nb_t, nullptr, w->partial, inv_n, T, nullptr, ws);
+                    if (e == hipSuccess)
+                        e = launch_batch_stats(t.coll, t.rows, nb_t, nullptr, w->partial, inv_n, T + nb_t, nullptr, ws);
+                }
+                if (e == hipSuccess)
+                    e = launch_batch_stats(t.glob, t.rows, N_GLOBAL, nullptr, w->partial, inv_n, T + 2 * nb_t,
+                                           nullptr, ws);
+                if (e == hipSuccess && t.chan)
+                    e = launch_batch_stats(t.chan, t.rows, nb_r, nullptr, w->partial, inv_n,
+                                           T + 2 * nb_t + N_GLOBAL, nullptr, ws);
+                if (e != hipSuccess) r = fail(w, MC_EHIP, hipGetErrorString(e));
+            }
+            if (r) {
+                wrc[l] = r;
+                failed = true;
+                return;
+            }
+            const mc_stats &q = w->stats;
+            mc_stats &a = tot[l];
+            a.iterations += q.iterations;
+            a.lookups += q.lookups;
+            a.nuclide_lookups += q.nuclide_lookups;
+            a.lookup_launches += q.lookup_launches;
+            a.sorted_lookups += q.sorted_lookups;
+            a.lost += q.lost;
+            a.lookup_ms += q.lookup_ms;
+            a.tail_particles += q.tail_particles;
+        }
+    };
+    std::vector<std::thread> threads;
+    for (int l = 1; l < L; ++l) threads.emplace_back(body, l);
+    body(0);
+    for (std::thread &t : threads) t.join();
+    for (int l = 0; l < L; ++l) {
+        if (wrc[l]) {
+            HIPCHK(hipDeviceSynchronize());
+            return fail(ctx, wrc[l], "concurrent batches, loop " + std::to_string(l) + ": " + ctx->workers[l]->err);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        HIPCHK(hipEventRecord(ctx->ev_loop_done[l], ctx->workers[l]->stream));
+        HIPCHK(hipStreamWaitEvent(st, ctx->ev_loop_done[l], 0));
+    }
+    // the statistics, batch by batch in order (columns of one tally are
+    // contiguous in every batch's value row: accumulate per tally)
+    const int32_t nbk = (int32_t)n_batches;
+    const double *V = ctx->batch_vals;
+    // values are rows of `cols`; gather each tally's columns with its stride
+    HIPCHK(launch_batch_accum_strided(V, nbk, (int32_t)cols, 0, nb_t, ctx->S1[0], ctx->S2[0], st));
+    HIPCHK(launch_batch_accum_strided(V, nbk, (int32_t)cols, nb_t, nb_t, ctx->S1[1], ctx->S2[1], st));
+    HIPCHK(launch_batch_accum_strided(V, nbk, (int32_t)cols, 2 * nb_t, N_GLOBAL, ctx->S1[2], ctx->S2[2], st));
+    if (nb_r)
+        HIPCHK(launch_batch_accum_strided(V, nbk, (int32_t)cols, 2 * nb_t + N_GLOBAL, nb_r, ctx->S1[3], ctx->S2[3],
+                                          st));
+    HIPCHK(hipEventRecord(ctx->ev_batch1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_batch0, ctx->ev_batch1));
+    mc_stats s{};
+    for (const mc_stats &a : tot) {
+        s.iterations += a.iterations;
+        s.lookups += a.lookups;
+        s.nuclide_lookups += a.nuclide_lookups;
+        s.lookup_launches += a.lookup_launches;
+        s.sorted_lookups += a.sorted_lookups;
+        s.lost += a.lost;
+        s.lookup_ms += a.lookup_ms;
+        s.tail_particles += a.tail_particles;
+    }
+    s.batch_ms = ms;
+    s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +
+                     (56ull + 16ull * (uint64_t)ctx->n_chan) * s.nuclide_lookups;
+    ctx->stats = s;
+    ctx->n_batches += n_batches;
+    ctx->histories += n * n_batches;
+    if (s.lost > opts.max_lost)
+        return fail(ctx, MC_ELOST, std::to_string(s.lost) + " particles lost (event cap reached)");
+    return MC_OK;
 }
 
 int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_, size_t n_bins,
@@ -1872,10 +2047,13 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kMaxTunedInFlight);
     cur.in_flight = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
     cur.collide_sort_min = 0;  // follows sort_min unless the search turns it off
+    // each trial: a few batches through mc_run_batches (so that loops > 1
+    // shows its overlap of consecutive batches), timed per batch
+    const uint64_t trial_batches = n >= (1ull << 22) ? 2 : 4;
     auto trial = [&](const mc_tuning &c, double &ms) -> int {
         ctx->tune = c;
-        const int r = mc_run_batch(ctx, seed, first_pid, n, nullptr);
-        ms = ctx->stats.batch_ms;
+        const int r = mc_run_batches(ctx, seed, first_pid, n, trial_batches, nullptr);
+        ms = ctx->stats.batch_ms / (double)trial_batches;
         return r;
     };
     double best_ms = 0.0;

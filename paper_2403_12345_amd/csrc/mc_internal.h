@@ -120,6 +120,9 @@ struct ImpSampleArgs {
     float *range_out;                // [2] smallest and largest target
 };
 hipError_t launch_imp_samples(const ImpSampleArgs &a, hipStream_t st);
+// S1 += T_b, S2 += T_b^2 over the batch values T[b * stride + off + k], b in order.
+hipError_t launch_batch_accum_strided(const double *T, int32_t n_b, int32_t stride, int32_t off, int32_t n_cols,
+                                      double *S1, double *S2, hipStream_t st);
 hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols, const double *direct,
                               double *partial, double inv_n, double *S1, double *S2, hipStream_t st);
 

@@ -1050,7 +1050,7 @@ __global__ void __launch_bounds__(WG) k_rows_partial(const double *rows, int32_t
 }
 
 // T = (sum of the partials in chunk order, or the atomic accumulator) / n;
-// S1 += T; S2 += T^2.
+// S1 += T; S2 += T^2 (S2 == nullptr: S1 = T, the batch value alone).
 __global__ void __launch_bounds__(WG) k_batch_stats(const double *partial, const double *direct,
                                                     int32_t n_cols, double inv_n, double *S1, double *S2)
 {
@@ -1063,8 +1063,29 @@ __global__ void __launch_bounds__(WG) k_batch_stats(const double *partial, const
         for (int c = 0; c < RED_CHUNKS; ++c) s = s + partial[(size_t)c * n_cols + k];
     }
     const double T = s * inv_n;
+    if (!S2) {
+        S1[k] = T;
+        return;
+    }
     S1[k] = S1[k] + T;
     S2[k] = S2[k] + T * T;
+}
+
+// S1 += T_b, S2 += T_b^2 for the batch values T[b * stride + off + k],
+// b = 0 .. n_b-1 in order (as n_b batch-statistics updates would).
+__global__ void __launch_bounds__(WG) k_batch_accum(const double *T, int32_t n_b, int32_t stride, int32_t off,
+                                                    int32_t n_cols, double *S1, double *S2)
+{
+    const int32_t k = blockIdx.x * WG + threadIdx.x;
+    if (k >= n_cols) return;
+    double s1 = S1[k], s2 = S2[k];
+    for (int32_t b = 0; b < n_b; ++b) {
+        const double t = T[(size_t)b * stride + off + k];
+        s1 = s1 + t;
+        s2 = s2 + t * t;
+    }
+    S1[k] = s1;
+    S2[k] = s2;
 }
 
 // ---------------------------------------------------------------------------
@@ -1417,6 +1438,15 @@ hipError_t launch_batch_stats(const double *rows, int32_t n_rows, int32_t n_cols
     }
     hipLaunchKernelGGL(k_batch_stats, dim3(blocks_for(n_cols, WG)), dim3(WG), 0, st, partial, direct,
                        n_cols, inv_n, S1, S2);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_accum_strided(const double *T, int32_t n_b, int32_t stride, int32_t off, int32_t n_cols,
+                                      double *S1, double *S2, hipStream_t st)
+{
+    if (n_cols == 0 || n_b == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_accum, dim3(blocks_for(n_cols, WG)), dim3(WG), 0, st, T, n_b, stride, off, n_cols,
+                       S1, S2);
     return hipGetLastError();
 }
 

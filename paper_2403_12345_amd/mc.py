@@ -139,6 +139,7 @@ def load():
                                P(D), I32], C.c_int),
         "mc_init_geometry": ([V, P(mc_geometry_desc)], C.c_int),
         "mc_run_batch": ([V, U64, U64, U64, P(mc_run_opts)], C.c_int),
+        "mc_run_batches": ([V, U64, U64, U64, U64, P(mc_run_opts)], C.c_int),
         "mc_get_tallies": ([V, I32, P(D), P(D), SZ, P(mc_tally_meta)], C.c_int),
         "mc_reset_tallies": ([V], C.c_int),
         "mc_get_stats": ([V, P(mc_stats)], C.c_int),
@@ -263,6 +264,11 @@ def mc_init_geometry(ctx, desc: mc_geometry_desc):
 
 def mc_run_batch(ctx, seed: int, first_pid: int, n: int, opts: mc_run_opts | None = None):
     rc = load().mc_run_batch(ctx, seed, first_pid, n, C.byref(opts) if opts is not None else None)
+    _check(ctx, rc)
+
+
+def mc_run_batches(ctx, seed: int, first_pid: int, n: int, n_batches: int, opts: mc_run_opts | None = None):
+    rc = load().mc_run_batches(ctx, seed, first_pid, n, n_batches, C.byref(opts) if opts is not None else None)
     _check(ctx, rc)
 
 

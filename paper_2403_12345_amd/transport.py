@@ -110,6 +110,9 @@ class Transport:
     def run_batch(self, seed, first_pid, n, **opts):
         mc.mc_run_batch(self.ctx, seed, first_pid, n, run_opts(**opts))
 
+    def run_batches(self, seed, first_pid, n, n_batches, **opts):
+        mc.mc_run_batches(self.ctx, seed, first_pid, n, n_batches, run_opts(**opts))
+
     def tallies(self, tally_id):
         nb = {mc.MC_T_GLOBAL: mc.MC_N_GLOBAL, mc.MC_T_REACTION: self.n_reaction}.get(tally_id, self.n_bins)
         mean, se, meta = mc.mc_get_tallies(self.ctx, tally_id, nb)

@@ -113,3 +113,47 @@ def test_loops_fall_back_and_reject_bad_counts(torch_cuda):
         mc.mc_set_tuning(t.ctx, loops=4)
         t.run_batch(1, 0, 5000)          # fewer than 4096 per loop: fewer loops
         assert t.tallies(mc.MC_T_GLOBAL)[2].n_batches == 1
+
+
+def _all_tallies(t):
+    return [t.tallies(k)[:2] for k in (mc.MC_T_FLUX_TRACK, mc.MC_T_FLUX_COLLISION, mc.MC_T_GLOBAL)]
+
+
+@pytest.mark.parametrize("loops", [1, 2, 3])
+def test_run_batches_equal_sequential_batches_bitwise(torch_cuda, loops):
+    """mc_run_batches with several loops forms each batch's value from its own
+    rows and takes the values in batch order: the tallies (means and standard
+    errors) equal those of one mc_run_batch per batch, bit for bit."""
+    prob = mcsynth.c2_problem()
+    n, nb = 40_000, 5
+    with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, in_flight=25_000, loops=1)
+        for b in range(nb):
+            t.run_batch(2, 1000 + b * n, n)
+        ref = _all_tallies(t)
+    with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, in_flight=25_000, loops=loops)
+        t.run_batches(2, 1000, n, nb)
+        got = _all_tallies(t)
+        st = t.stats()
+        assert t.tallies(mc.MC_T_GLOBAL)[2].n_batches == nb
+    assert st["lookups"] > 0 and st["batch_ms"] > 0
+    for (m0, s0), (m1, s1) in zip(ref, got):
+        assert np.array_equal(m0, m1) and np.array_equal(s0, s1)
+
+
+def test_run_batches_history_log_and_errors(torch_cuda):
+    torch = torch_cuda
+    prob = mcsynth.c1_problem()
+    n, nb = 5000, 3
+    with Transport(prob) as t:
+        mc.mc_set_tuning(t.ctx, loops=3)
+        log = torch.zeros(n * nb * mc.HISTORY_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        t.run_batches(1, 0, n, nb, history_log=log)
+        torch.cuda.synchronize()
+        g = log.cpu().numpy().view(mc.HISTORY_DTYPE)
+        with pytest.raises(mc.MCError, match="MC_EINVAL"):
+            t.run_batches(1, 0, n, 0)
+    o = oracle.run(oracle.OracleProblem(prob), 1, 0, n * nb, history=True).history
+    for k in ("fate", "n_coll", "n_cross", "n_draws", "E_final"):
+        assert np.array_equal(g[k], o[k]), k
