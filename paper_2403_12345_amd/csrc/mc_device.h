@@ -65,6 +65,17 @@ struct XsDev {
 
 constexpr int MAX_CHAN = 16;  // most reaction channels
 
+// Mesh tallies accumulate in 64-bit fixed point, 2^-32 per unit (weight * cm):
+// integer additions commute, so the sums do not depend on the order in which
+// the atomics land and reruns are bitwise identical.  A bin holds up to 2^32
+// units per batch; a contribution is rounded to the nearest 2^-32.
+constexpr double MESH_FIX_SCALE = 4294967296.0;        // 2^32
+constexpr double MESH_FIX_INV = 1.0 / 4294967296.0;    // 2^-32
+__device__ __forceinline__ void mesh_add(double *acc, int32_t idx, double v)
+{
+    atomicAdd(reinterpret_cast<unsigned long long *>(acc) + idx, (unsigned long long)__double2ull_rn(v * MESH_FIX_SCALE));
+}
+
 struct GeomDev {
     int32_t kind, inf_mat;
     int32_t nx, ny;
@@ -137,7 +148,7 @@ struct TallyDev {
     double *tl;     // [rows][n_bins] track-length flux (lattice / energy / slab)
     double *coll;   // [rows][n_bins] collision estimator
     double *glob;   // [rows][N_GLOBAL]
-    double *mesh_tl, *mesh_coll;  // [n_bins] mesh tallies (atomic accumulation)
+    double *mesh_tl, *mesh_coll;  // [n_bins] mesh tallies (64-bit fixed point, integer atomics; see mesh_add)
     double *chan;   // [rows][n_mat * n_chan] track-length reaction rates (null without channels)
     int32_t n_chan, chan_bins;
     int32_t n_bins, rows;

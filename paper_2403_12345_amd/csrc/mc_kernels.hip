@@ -1049,8 +1049,9 @@ __global__ void __launch_bounds__(WG) k_rows_partial(const double *rows, int32_t
     partial[(size_t)c * n_cols + k] = s;
 }
 
-// T = (sum of the partials in chunk order, or the atomic accumulator) / n;
-// S1 += T; S2 += T^2 (S2 == nullptr: S1 = T, the batch value alone).
+// T = (sum of the partials in chunk order, or the fixed-point mesh
+// accumulator `direct`) / n; S1 += T; S2 += T^2 (S2 == nullptr: S1 = T, the
+// batch value alone).
 __global__ void __launch_bounds__(WG) k_batch_stats(const double *partial, const double *direct,
                                                     int32_t n_cols, double inv_n, double *S1, double *S2)
 {
@@ -1058,7 +1059,7 @@ __global__ void __launch_bounds__(WG) k_batch_stats(const double *partial, const
     if (k >= n_cols) return;
     double s = 0.0;
     if (direct) {
-        s = direct[k];
+        s = (double)reinterpret_cast<const unsigned long long *>(direct)[k] * MESH_FIX_INV;
     } else {
         for (int c = 0; c < RED_CHUNKS; ++c) s = s + partial[(size_t)c * n_cols + k];
     }

@@ -133,7 +133,7 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
         const double t1 = fmin(fmax(tnext[k], t), d);
         if (t1 > t) {
             const int32_t idx = (c[2] * g.mesh_dims[1] + c[1]) * g.mesh_dims[0] + c[0];
-            atomicAdd(acc + idx, wt * (t1 - t));
+            mesh_add(acc, idx, wt * (t1 - t));
         }
         t = t1;
         if (t >= d) break;
@@ -396,7 +396,7 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
         case TALLY_SLAB: sc.c_bin = p.cell; break;
         case TALLY_MESH: {
             const int32_t c = mesh_index(g, p.x, p.y, p.z);
-            if (c >= 0) atomicAdd(mesh_coll + c, p.wt / st);
+            if (c >= 0) mesh_add(mesh_coll, c, p.wt / st);
         } break;
         }
         sc.c_val = p.wt / st;

@@ -42,3 +42,21 @@ def test_mesh_tally_on_gpu(torch_cuda):
     st = oracle.run_batches(oracle.OracleProblem(prob), 5, 20, 5000)
     n_fail, allowed, z = three_sigma(gm, gs, st.mean["tl"], st.stderr["tl"])
     assert n_fail <= allowed, (n_fail, allowed, z)
+
+
+def test_mesh_tally_rerun_is_bitwise_identical(torch_cuda):
+    """The mesh sums are 64-bit fixed point, so the order in which the atomic
+    additions land does not matter: two runs (and one split over three
+    concurrent event loops) give the same bits."""
+    prob = mesh_problem()
+    out = []
+    for loops in (1, 1, 3):
+        with Transport(prob) as t:
+            mc.mc_set_tuning(t.ctx, loops=loops)
+            for b in range(3):
+                t.run_batch(41, b * 20_000, 20_000)
+            out.append((t.tallies(mc.MC_T_FLUX_TRACK)[0], t.tallies(mc.MC_T_FLUX_COLLISION)[0]))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0], out[2]):
+        assert np.array_equal(a, b)
