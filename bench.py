@@ -168,6 +168,52 @@ def c3_channels(tuning: dict, n_chan: int = 10, histories: int = 20_000_000, pro
             "reaction_rates_per_source": [float(x) for x in rr], "tuning": tuning}
 
 
+def c2_union(tuning: dict, steps: int = 5, n_lookups: int = 10_000_000):
+    """What the hash grid gives up against unionized grids on the 17x17
+    lattice: the C2 transport (same tuning, 1e6 histories per batch) and 1e7
+    stand-alone lookups on the 30-nuclide fuel, with per-nuclide hash searches
+    and with one union-grid search per lookup (same results bit for bit)."""
+    import numpy as np
+    import torch
+
+    import mcsynth
+    from paper_2403_12345_amd import mc
+    from paper_2403_12345_amd.transport import Transport
+
+    prob = mcsynth.c2_problem()
+    n = prob.histories
+    out = {"workload": "17x17 lattice transport (1e6 histories per batch) and 1e7 log-uniform lookups on its "
+                       "30-nuclide fuel, hash-grid against unionized-grid search"}
+    rng = np.random.default_rng(4321)
+    E = torch.from_numpy(mcsynth.lookup_energies(rng, n_lookups)).cuda()
+    M = torch.zeros(n_lookups, dtype=torch.int32, device="cuda")
+    Sa = torch.empty(n_lookups, dtype=torch.float64, device="cuda")
+    Ss = torch.empty(n_lookups, dtype=torch.float64, device="cuda")
+    with Transport(prob, device=0) as t:
+        mc.mc_set_tuning(t.ctx, **tuning)
+        for mode in ("hash", "union"):
+            if mode == "union":
+                out["union_table_bytes"] = mc.mc_set_union_grid(t.ctx, True)
+            t.run_batches(prob.seed, 0, n, 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t.run_batches(prob.seed, n, n, steps)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            r = {"particles_per_s": steps * n / sec}
+            for srt in (False, True):
+                mc.mc_lookup_macro(t.ctx, E, M, Sa, Ss, srt)
+                mc.mc_set_timing(t.ctx, True)
+                for _ in range(3):
+                    mc.mc_lookup_macro(t.ctx, E, M, Sa, Ss, srt)
+                s = t.stats()
+                mc.mc_set_timing(t.ctx, False)
+                r["sorted_lookups_per_s" if srt else "unsorted_lookups_per_s"] = s["lookups"] / (s["lookup_ms"] / 1e3)
+            out[mode] = r
+        mc.mc_set_union_grid(t.ctx, False)
+    return out
+
+
 def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(2,), prob=None):
     """Stand-alone lookup of n (energy, material) pairs on the 300-nuclide
     material (grids of 20k-150k points, ~0.6 GB of tables, far above the
@@ -325,7 +371,8 @@ def main():
     ap.add_argument("--no-fom", action="store_true", help="skip the learned-importance figure-of-merit benchmark")
     ap.add_argument("--no-c3", action="store_true", help="skip the 300-nuclide lattice transport batch")
     ap.add_argument("--tuning-cache", default=TUNING_CACHE, help="autotuner cache file")
-    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom", "c3"), default="full",
+    ap.add_argument("--no-union", action="store_true", help="skip the hash-grid against union-grid comparison")
+    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom", "c3", "union"), default="full",
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -350,6 +397,13 @@ def main():
         return
     if args.mode == "fom":
         print(json.dumps({"fom": fom_bench()}), flush=True)
+        return
+    if args.mode == "union":
+        from paper_2403_12345_amd import mc
+        p = mcsynth.c2_problem()
+        with Transport(p, device=0) as t:
+            tuning = mc.mc_autotune(t.ctx, p.seed, 1 << 40, p.histories, args.tuning_cache)
+        print(json.dumps({"c2_union": c2_union(tuning)}), flush=True)
         return
     if args.mode == "c3":
         c3 = mcsynth.c3_problem()
@@ -452,6 +506,8 @@ def main():
     if not args.no_c3:
         line["c3_transport"] = c3_transport(args.tuning_cache, prob=c3)
         line["c3_channels"] = c3_channels(line["c3_transport"]["tuning"], prob=c3)
+    if not args.no_union:
+        line["c2_union"] = c2_union(tuning)
     if not args.no_problem_set:
         line["problem_set"] = problem_set_bench()
     if not args.no_fom:

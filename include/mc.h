@@ -311,6 +311,26 @@ int mc_set_timing(mc_ctx *ctx, int32_t on);
 int mc_init_channels(mc_ctx *ctx, int32_t n_chan, const double *const *sig_x);
 
 /*
+ * Unionized-grid lookups (the alternative to per-nuclide searches the paper
+ * names among the lookup accelerations, section 3): per material, the sorted
+ * union U of its nuclides' energy grids with its own hash bounds, and per
+ * union point u a row of every nuclide's interval at U_u (4 B per union point
+ * and nuclide).  A lookup then searches the union grid once and reads each
+ * nuclide's interval from the row instead of searching it: the same
+ * intervals, interpolation and sums, so the same results bit for bit.
+ *   on      1: build the tables (host work, then device memory) and use them
+ *           for every macroscopic lookup of the context (transport and
+ *           mc_lookup_macro; the per-nuclide outputs of mc_lookup_nuclides,
+ *           the reaction channels and the collision's re-gathers keep the
+ *           hash search); 0: free them.
+ *   bytes   (nullable) device bytes of the tables
+ * mc_init_materials removes them.  Errors: MC_ESTATE (no materials), MC_EINVAL
+ * (a material's union grid above 2^32 points or 2^34 row entries),
+ * MC_ENOMEM.
+ */
+int mc_set_union_grid(mc_ctx *ctx, int32_t on, uint64_t *bytes);
+
+/*
  * The channel lookup on its own: for n (energy, material) pairs, out[i *
  * n_chan + x] = sum over the material's nuclides of density * channel x
  * (device, n * n_chan fp64), and, when non-null, sig_a / sig_s as in

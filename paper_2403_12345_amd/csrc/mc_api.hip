@@ -55,6 +55,11 @@ struct mc_ctx {
     uint32_t n_keys = 0;  // n_mat * M sort keys
     std::vector<int32_t> nuc_glen;   // grid points per nuclide
     std::vector<uint32_t> nuc_goff;  // first point of each nuclide in the tables
+    std::vector<int32_t> mat_nuc_host;  // nuclide ids of the materials, in order
+    double emin = 0.0, emax = 0.0;   // energy range of the hash grid
+    int32_t M = 0;                   // hash bins
+    Buffers union_bufs;              // unionized grids (mc_set_union_grid)
+    uint64_t union_bytes = 0;
 
     // reaction channels (tables, and the reaction-rate tally's batch sums)
     int32_t n_chan = 0;
@@ -285,6 +290,7 @@ void mc_destroy(mc_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     ctx->loop_bufs.release();
     ctx->batch_bufs.release();
+    ctx->union_bufs.release();
     if (ctx->ev_loop_start) (void)hipEventDestroy(ctx->ev_loop_start);
     for (hipEvent_t e : ctx->ev_loop_done) (void)hipEventDestroy(e);
     ctx->mat_bufs.release();
@@ -484,6 +490,8 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->mat_bufs.release();
     ctx->chan_bufs.release();  // new tables: no reaction channels until mc_init_channels
+    ctx->union_bufs.release();  // ... and no unionized grids until mc_set_union_grid
+    ctx->union_bytes = 0;
     ctx->n_chan = 0;
     ctx->S1[3] = ctx->S2[3] = nullptr;
     ctx->have_mat = false;
@@ -503,7 +511,92 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     ctx->mat_len.assign(mat_len, mat_len + n_mat);
     ctx->nuc_glen = H.glen;
     ctx->nuc_goff = H.goff;
+    ctx->mat_nuc_host = H.mnucid;
+    ctx->emin = H.emin;
+    ctx->emax = H.emax;
+    ctx->M = n_hash_bins;
     ctx->have_mat = true;
+    return MC_OK;
+}
+
+int mc_set_union_grid(mc_ctx *ctx, int32_t on, uint64_t *bytes)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mat) return fail(ctx, MC_ESTATE, "mc_set_union_grid: materials first");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->union_bufs.release();
+    ctx->union_bytes = 0;
+    ctx->xs.um = nullptr;
+    ctx->xs.ug = nullptr;
+    ctx->xs.uh = nullptr;
+    ctx->xs.ui = nullptr;
+    if (bytes) *bytes = 0;
+    if (!on) return MC_OK;
+    // the nuclide grids, back from the device
+    const size_t pts = ctx->nuc_goff.back() + (size_t)ctx->nuc_glen.back();
+    std::vector<double> Eg(pts);
+    HIPCHK(hipMemcpy(Eg.data(), ctx->xs.Eg, pts * sizeof(double), hipMemcpyDeviceToHost));
+    const int32_t M = ctx->M;
+    const double delta = std::log(ctx->emax / ctx->emin) / (double)M;
+    std::vector<UnionMat> um(ctx->n_mat);
+    std::vector<double> ug;
+    std::vector<uint32_t> uh, ui;
+    size_t q_base = 0;
+    for (int32_t m = 0; m < ctx->n_mat; ++m) {
+        const int32_t nk = ctx->mat_len[m];
+        std::vector<double> U;
+        for (int32_t q = 0; q < nk; ++q) {
+            const int32_t k = ctx->mat_nuc_host[q_base + q];
+            const double *g = Eg.data() + ctx->nuc_goff[k];
+            U.insert(U.end(), g, g + ctx->nuc_glen[k]);
+        }
+        std::sort(U.begin(), U.end());
+        U.erase(std::unique(U.begin(), U.end()), U.end());
+        const size_t NU = U.size();
+        if (NU * (size_t)nk > (size_t)1 << 34 || NU >= (1ull << 32))
+            return fail(ctx, MC_EINVAL, "mc_set_union_grid: union grid of material " + std::to_string(m) + " too large");
+        um[m].g_off = ug.size();
+        um[m].i_off = ui.size();
+        um[m].n = (uint32_t)NU;
+        um[m].h_off = (uint32_t)uh.size();
+        for (int32_t b = 0; b < M; ++b)
+            uh.push_back((uint32_t)host_grid_index(U.data(), (int32_t)NU, ctx->emin * std::exp((double)b * delta)));
+        uh.push_back((uint32_t)(NU - 2));
+        // rows: i_q(U_u) = max{j : E_j <= U_u} clamped to [0, N - 2], one walk per nuclide
+        const size_t base = ui.size();
+        ui.resize(base + NU * (size_t)nk);
+        for (int32_t q = 0; q < nk; ++q) {
+            const int32_t k = ctx->mat_nuc_host[q_base + q];
+            const double *g = Eg.data() + ctx->nuc_goff[k];
+            const int32_t N = ctx->nuc_glen[k];
+            int32_t j = 0;
+            for (size_t u = 0; u < NU; ++u) {
+                while (j + 1 < N && g[j + 1] <= U[u]) ++j;
+                ui[base + u * (size_t)nk + q] = (uint32_t)std::min(j, N - 2);
+            }
+        }
+        ug.insert(ug.end(), U.begin(), U.end());
+        q_base += (size_t)nk;
+    }
+    UnionMat *d_um = nullptr;
+    double *d_ug = nullptr;
+    uint32_t *d_uh = nullptr, *d_ui = nullptr;
+    Buffers &B = ctx->union_bufs;
+    int rc = upload(ctx, B, &d_um, um.data(), um.size());
+    if (!rc) rc = upload(ctx, B, &d_ug, ug.data(), ug.size());
+    if (!rc) rc = upload(ctx, B, &d_uh, uh.data(), uh.size());
+    if (!rc) rc = upload(ctx, B, &d_ui, ui.data(), ui.size());
+    if (rc) {
+        B.release();
+        return rc;
+    }
+    ctx->xs.um = d_um;
+    ctx->xs.ug = d_ug;
+    ctx->xs.uh = d_uh;
+    ctx->xs.ui = d_ui;
+    ctx->union_bytes = ug.size() * sizeof(double) + (uh.size() + ui.size()) * sizeof(uint32_t);
+    if (bytes) *bytes = ctx->union_bytes;
     return MC_OK;
 }
 

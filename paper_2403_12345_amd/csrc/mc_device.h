@@ -61,6 +61,22 @@ struct XsDev {
     // reaction channels: n_chan values per grid point, point p's at xc[p * n_chan]
     int32_t n_chan;
     const double *xc;
+    // unionized grids (null: the per-nuclide hash search only)
+    const struct UnionMat *um;
+    const double *ug;      // union grids of all materials
+    const uint32_t *uh;    // their hash bounds, M + 1 per material
+    const uint32_t *ui;    // index rows: nuclide intervals at each union point
+};
+
+// Unionized grid of one material: the sorted union U of its nuclides' grids
+// (ug[g_off .. g_off + n)), hash bounds uh[h_off + b] = the union index of the
+// bin's lower edge (b = 0 .. M), and per union point u the row
+// ui[i_off + u * nk + q] = i_q(U_u), the interval of nuclide position q at U_u.
+// No nuclide has a grid point strictly between U_u and U_(u+1), so for U_u <= E <
+// U_(u+1) that row holds each nuclide's own interval of E.
+struct UnionMat {
+    uint64_t g_off, i_off;
+    uint32_t n, h_off;
 };
 
 constexpr int MAX_CHAN = 16;  // most reaction channels

@@ -589,6 +589,94 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     }
 }
 
+// Lookup on the unionized grid of the particle's material: one search in the
+// union grid (hash bracket, bisection, walk), then each nuclide's interval is
+// read from the union point's index row instead of searched.  Same intervals,
+// same interpolation and sums in material order as k_lookup, so the same
+// results bit for bit (scattering-sum checkpoints included).
+template <int ILP>
+__global__ void __launch_bounds__(WG) k_lookup_union(LookupArgs a)
+{
+    const XsDev &xs = a.xs;
+    const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
+    const uint32_t i = blockIdx.x * WG + threadIdx.x;
+    int32_t nk_done = 0;
+    if (i < n) {
+        const uint32_t p = a.list ? a.list[i] : i;
+        const double e = a.E[p];
+        int32_t m, b;
+        if (a.keys) {
+            const uint32_t key = a.keys[i];
+            m = (int32_t)(key / (uint32_t)xs.M);
+            b = (int32_t)(key % (uint32_t)xs.M);
+        } else {
+            m = a.mat[p];
+            b = hash_bin(xs, e);
+        }
+        if (m < 0 || m >= xs.n_mat) {
+            if (a.Sa) a.Sa[p] = NAN;
+            if (a.Ss) a.Ss[p] = NAN;
+        } else {
+            const UnionMat um = xs.um[m];
+            const double *U = xs.ug + um.g_off;
+            const uint32_t last = um.n - 1u;
+            uint32_t lo = xs.uh[um.h_off + b], hi = xs.uh[um.h_off + b + 1] + 1u;
+            hi = hi < last ? hi : last;
+            lo = lo < hi ? lo : hi;
+            while (lo < hi) {  // largest u in [lo, hi] with U_u <= E
+                const uint32_t mid = (lo + hi + 1u) >> 1;
+                if (U[mid] <= e) lo = mid; else hi = mid - 1u;
+            }
+            uint32_t u = lo;  // a bin computed one off: walk to the defined point
+            while (u > 0u && e < U[u]) --u;
+            while (u < last && e >= U[u + 1u]) ++u;
+            const int32_t q0 = xs.mat_off[m];
+            const int32_t nk = xs.mat_off[m + 1] - q0;
+            const uint32_t *row = xs.ui + um.i_off + (uint64_t)u * (uint64_t)nk;
+            const MatNuc *mnuc = xs.mnuc + q0;
+            const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;
+            const int32_t cp_mask = (1 << cp_sh) - 1;
+            double sa = 0.0, ss = 0.0;
+            for (int32_t q = 0; q < nk; q += ILP) {
+                const int32_t cnt = nk - q < ILP ? nk - q : ILP;
+                double dens[ILP], e0[ILP], e1[ILP];
+                double2 x0[ILP], x1[ILP];
+#pragma unroll
+                for (int k = 0; k < ILP; ++k) {
+                    const int32_t qk = q + (k < cnt ? k : 0);
+                    const MatNuc mn = mnuc[qk];
+                    const uint32_t pt = mn.off + row[qk];
+                    dens[k] = mn.dens;
+                    e0[k] = xs.Eg[pt];
+                    e1[k] = xs.Eg[pt + 1u];
+                    x0[k] = xs.xs[pt];
+                    x1[k] = xs.xs[pt + 1u];
+                }
+#pragma unroll
+                for (int k = 0; k < ILP; ++k) {
+                    if (k < cnt) {
+                        const double f = (e - e0[k]) / (e1[k] - e0[k]);
+                        const double c = x0[k].x + f * (x1[k].x - x0[k].x);
+                        const double s = x0[k].y + f * (x1[k].y - x0[k].y);
+                        sa = sa + dens[k] * c;
+                        ss = ss + dens[k] * s;
+                        const int32_t done = q + k + 1;
+                        if ((done & cp_mask) == 0) a.cp[(size_t)p * CP_MAX + ((done >> cp_sh) - 1)] = ss;
+                    }
+                }
+            }
+            if (a.Sa) a.Sa[p] = sa;
+            if (a.Ss) a.Ss[p] = ss;
+            if (a.flags) a.flags[p] = F_ALIVE;
+            nk_done = nk;
+        }
+    }
+    if (a.nuc_count) {
+        const uint32_t c = wave_sum_u32((uint32_t)nk_done);
+        if (lane_id() == 0 && c) atomicAdd(a.nuc_count, (unsigned long long)c);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // advance: sample the flight, move, score track length
 // ---------------------------------------------------------------------------
@@ -1216,7 +1304,13 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
     a.cp = l.cp;
     a.sx = l.sx;
     const dim3 grid(blocks_for(l.n_bound, WG));
-    if (a.sx && l.xs.n_chan > 0) {  // channels: at most two nuclides in lockstep (registers)
+    if (l.xs.um && !(a.sx && l.xs.n_chan > 0) && !(a.idx_out || a.sc_out || a.ss_out)) {
+        switch (l.ilp) {  // unionized grid
+        case 1: hipLaunchKernelGGL(k_lookup_union<1>, grid, dim3(WG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_lookup_union<2>, grid, dim3(WG), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_lookup_union<4>, grid, dim3(WG), 0, st, a); break;
+        }
+    } else if (a.sx && l.xs.n_chan > 0) {  // channels: at most two nuclides in lockstep (registers)
         if (l.ilp == 1) hipLaunchKernelGGL((k_lookup<1, false, true>), grid, dim3(WG), 0, st, a);
         else hipLaunchKernelGGL((k_lookup<2, false, true>), grid, dim3(WG), 0, st, a);
     } else if (a.idx_out || a.sc_out || a.ss_out) {

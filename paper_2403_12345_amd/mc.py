@@ -145,6 +145,7 @@ def load():
         "mc_get_stats": ([V, P(mc_stats)], C.c_int),
         "mc_lookup_macro": ([V, SZ, V, V, V, V, I32], C.c_int),
         "mc_init_channels": ([V, I32, P(P(D))], C.c_int),
+        "mc_set_union_grid": ([V, I32, P(U64)], C.c_int),
         "mc_lookup_channels": ([V, SZ, V, V, V, V, V], C.c_int),
         "mc_lookup_nuclides": ([V, I32, SZ, V, V, V, V], C.c_int),
         "mc_sort_queue": ([V, SZ, V, V, V, V], C.c_int),
@@ -308,6 +309,13 @@ def mc_init_channels(ctx, channels):
         raise ValueError("every nuclide needs a [points, n_chan] array with the same n_chan")
     ptrs = (C.POINTER(C.c_double) * len(arrs))(*[_dp(a) for a in arrs])
     _check(ctx, load().mc_init_channels(ctx, k, ptrs))
+
+
+def mc_set_union_grid(ctx, on: bool = True) -> int:
+    """Unionized-grid lookups on (device bytes of the tables) or off."""
+    b = C.c_uint64(0)
+    _check(ctx, load().mc_set_union_grid(ctx, 1 if on else 0, C.byref(b)))
+    return int(b.value)
 
 
 def mc_lookup_channels(ctx, E, mat, out, sig_a=None, sig_s=None):
