@@ -260,6 +260,65 @@ def with_channels(prob: "Problem", n_chan: int, data_seed: int = 9009) -> "Probl
     return prob
 
 
+@dataclass
+class MultipoleNuclide:
+    """Windowed-multipole data of one nuclide (u = sqrt(E)): poles (Im < 0),
+    capture and scattering residues, [n_windows, 2] pole ranges of the even
+    windows over [u_lo, u_hi], and per window background coefficients of
+    u^-1, u^0, u^1."""
+    poles: np.ndarray   # complex128 [P], sorted by real part
+    res_c: np.ndarray   # complex128 [P]
+    res_s: np.ndarray   # complex128 [P]
+    u_lo: float
+    u_hi: float
+    win: np.ndarray     # int32 [W, 2]
+    bg_c: np.ndarray    # float64 [W, 3]
+    bg_s: np.ndarray    # float64 [W, 3]
+    awr: float
+
+
+def make_multipole_nuclide(rng, awr: float, n_res: int = 20, n_windows: int = 1024,
+                           reach: float = 2.0) -> MultipoleNuclide:
+    """Synthetic multipole nuclide: resonances E_r ~ logU[1, 1e5] eV with
+    widths Gamma = E_r 10^U[-3, -1.5] become poles sqrt(E_r) - i Gamma / (4
+    sqrt(E_r)); a residue h gamma E_r gives a resonance of peak h barns (capture
+    heights logU[10, 1e4] b with real residues, scattering heights logU[10, 1e3] b
+    with a phase of up to 0.2 rad); background 1/v capture b_c sqrt(0.0253 / E)
+    and constant potential scattering a_s.  Window w holds the poles within
+    reach + 1/2 window widths of its centre."""
+    e_r = np.sort(_log_uniform(rng, 1.0, 1.0e5, n_res))
+    gam_e = e_r * 10.0 ** rng.uniform(-3.0, -1.5, n_res)
+    a = np.sqrt(e_r)
+    g = gam_e / (4.0 * a)
+    poles = a - 1j * g
+    h_c = _log_uniform(rng, 10.0, 1.0e4, n_res)
+    h_s = _log_uniform(rng, 10.0, 1.0e3, n_res)
+    res_c = (h_c * g * e_r).astype(np.complex128)
+    res_s = h_s * g * e_r * np.exp(1j * rng.uniform(-0.2, 0.2, n_res))
+    u_lo, u_hi = np.sqrt(EMIN), np.sqrt(EMAX)
+    du = (u_hi - u_lo) / n_windows
+    centre = u_lo + (np.arange(n_windows) + 0.5) * du
+    lo = np.searchsorted(a, centre - (reach + 0.5) * du, side="left")
+    hi = np.searchsorted(a, centre + (reach + 0.5) * du, side="right")
+    win = np.stack([lo, hi], 1).astype(np.int32)
+    b_c = _log_uniform(rng, 0.1, 100.0) * np.sqrt(E_THERMAL)
+    a_s = rng.uniform(2.0, 20.0)
+    bg_c = np.tile([b_c, 0.0, 0.0], (n_windows, 1))
+    bg_s = np.tile([0.0, a_s, 0.0], (n_windows, 1))
+    return MultipoleNuclide(poles=poles, res_c=res_c, res_s=res_s, u_lo=float(u_lo), u_hi=float(u_hi), win=win,
+                            bg_c=bg_c, bg_s=bg_s, awr=float(awr))
+
+
+def multipole_material(n_nuclides: int = 300, data_seed: int = 7007):
+    """n_nuclides synthetic multipole nuclides (A = 1 first, then U[2, 240])
+    and densities log-uniform in [1e-6, 1e-2] atoms/(b cm)."""
+    rng = np.random.default_rng(data_seed)
+    awr = np.concatenate([[1.0], rng.uniform(2.0, 240.0, n_nuclides - 1)])
+    nucs = [make_multipole_nuclide(rng, a) for a in awr]
+    dens = _log_uniform(rng, 1e-6, 1e-2, n_nuclides)
+    return nucs, np.arange(n_nuclides, dtype=np.int32), dens
+
+
 def constant_nuclide(sig_c: float, sig_s: float, awr: float, n_points: int = 2000) -> Nuclide:
     """A nuclide whose tabulated cross sections are constant (closed-form tests)."""
     E = log_uniform_grid(n_points)

@@ -109,11 +109,24 @@ def lib():
         _lib.orc_micro_xs_many.argtypes = [P(_Problem), C.c_int32, C.c_int64, P(D), P(C.c_int64), P(D), P(D)]
         _lib.orc_macro_xs_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D), P(D)]
         _lib.orc_macro_channels_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D)]
+        _lib.orc_faddeeva_init.argtypes = []
+        _lib.orc_faddeeva_many.argtypes = [C.c_int64, P(D), P(D), P(D), P(D)]
+        _lib.orc_mp_macro_many.argtypes = [P(_MpNuclide), P(D), C.c_int32, P(C.c_int32), P(D), D, C.c_int64,
+                                           P(D), P(D), P(D)]
+        _lib.orc_faddeeva_init()
     return _lib
 
 
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class _MpNuclide(C.Structure):
+    _fields_ = [("n_poles", C.c_int32), ("n_windows", C.c_int32), ("n_bg", C.c_int32), ("pad", C.c_int32),
+                ("u_lo", C.c_double), ("u_hi", C.c_double),
+                ("poles", C.POINTER(C.c_double)), ("res_c", C.POINTER(C.c_double)),
+                ("res_s", C.POINTER(C.c_double)), ("win", C.POINTER(C.c_int32)),
+                ("bg_c", C.POINTER(C.c_double)), ("bg_s", C.POINTER(C.c_double))]
 
 
 def _iptr(a):
@@ -247,6 +260,46 @@ def macro_channels(op: OracleProblem, mats, energies):
     out = np.empty((e.size, op.n_chan))
     lib().orc_macro_channels_many(op.ref(), e.size, _iptr(m), _dptr(e), _dptr(out))
     return out
+
+
+def faddeeva(z):
+    """w(z) for Im z > 0 (the oracle's rational series)."""
+    z = np.ascontiguousarray(np.asarray(z, np.complex128).ravel())
+    zr, zi = np.ascontiguousarray(z.real), np.ascontiguousarray(z.imag)
+    wr, wi = np.empty(z.size), np.empty(z.size)
+    lib().orc_faddeeva_many(z.size, _dptr(zr), _dptr(zi), _dptr(wr), _dptr(wi))
+    return wr + 1j * wi
+
+
+def multipole_macro(nucs, mat_ids, dens, T: float, energies):
+    """(Sigma_a, Sigma_s) of a material of multipole nuclides (a list of
+    mcsynth.MultipoleNuclide; the material's ids and densities) at temperature
+    T (K) for each energy."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a
+
+    cs = (_MpNuclide * len(nucs))()
+    for c, nd in zip(cs, nucs):
+        c.n_poles, c.n_windows, c.n_bg = nd.poles.size, nd.win.shape[0], nd.bg_c.shape[1]
+        c.u_lo, c.u_hi = nd.u_lo, nd.u_hi
+        c.poles = _dptr(arr(nd.poles.view(np.float64), np.float64))
+        c.res_c = _dptr(arr(nd.res_c.view(np.float64), np.float64))
+        c.res_s = _dptr(arr(nd.res_s.view(np.float64), np.float64))
+        c.win = _iptr(arr(nd.win, np.int32))
+        c.bg_c = _dptr(arr(nd.bg_c, np.float64))
+        c.bg_s = _dptr(arr(nd.bg_s, np.float64))
+    awr = arr([nd.awr for nd in nucs], np.float64)
+    ids = arr(mat_ids, np.int32)
+    d = arr(dens, np.float64)
+    e = arr(np.ravel(energies), np.float64)
+    Sa, Ss = np.empty(e.size), np.empty(e.size)
+    lib().orc_mp_macro_many(cs, _dptr(awr), ids.size, _iptr(ids), _dptr(d), float(T), e.size, _dptr(e),
+                            _dptr(Sa), _dptr(Ss))
+    return Sa, Ss
 
 
 def elastic(A: float, E: float, mu_cm: float):

@@ -995,3 +995,133 @@ void orc_macro_xs_many(const orc_problem *p, int64_t n, const int32_t *mat, cons
 #endif
     for (int64_t i = 0; i < n; ++i) orc_macro_xs(p, mat[i], e[i], Sa + i, Ss + i);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Windowed multipole cross sections with Doppler broadening on the fly      */
+/* (the compute-bound alternative to tabulated data the paper points to in   */
+/* section 4.1; Josey, Forget and Smith, J. Comput. Phys. 2016).  In u =     */
+/* sqrt(E) a nuclide's cross section is a sum over poles p_j (Im p_j < 0)   */
+/* with residues r_j, plus a smooth background:                              */
+/*   sigma_x(E, T) = (1/E) sum_j Re[ r_x,j c_j(u) ] + sum_n b_x,n u^(n-1)     */
+/*   c_j(u) = sqrt(pi) beta w(beta (u - p_j)),  beta = sqrt(A / (k_B T)),     */
+/* w the Faddeeva function; as T -> 0, c_j -> i / (u - p_j).  Only the poles */
+/* of the window holding u enter (the windows split [u_lo, u_hi] evenly).    */
+/* ------------------------------------------------------------------------ */
+
+/* Faddeeva function w(z) = exp(-z^2) erfc(-i z) for Im z > 0 by Weideman's  */
+/* rational series (SIAM J. Numer. Anal. 31, 1994): with L = (N / sqrt 2)^(1/2)*/
+/* and Z = (L + i z) / (L - i z),                                            */
+/*   w(z) = 2 sum_{n=1..N} a_n Z^(n-1) / (L - i z)^2 + pi^(-1/2) / (L - i z), */
+/* a_n the cosine coefficients of f(t) = exp(-t^2) (L^2 + t^2) on the map     */
+/* t = L tan(theta / 2), sampled at theta_k = k pi / M, M = 2N.              */
+#define ORC_WN 32
+static double orc_wa[ORC_WN + 1], orc_wL = 0.0;
+
+void orc_faddeeva_init(void)
+{
+    const int N = ORC_WN, M = 2 * N;
+    const double L = sqrt(sqrt((double)N * (double)N / 2.0));
+    for (int n = 1; n <= N; ++n) {
+        double s = 0.0;
+        for (int k = -M + 1; k <= M - 1; ++k) {
+            const double th = (double)k * M_PI / (double)M;
+            const double t = L * tan(th / 2.0);
+            const double f = exp(-t * t) * (L * L + t * t);
+            s += f * cos(M_PI * (double)n * (double)k / (double)M);
+        }
+        orc_wa[n] = s / (2.0 * (double)M);
+    }
+    orc_wL = L;
+}
+
+void orc_faddeeva(double zr, double zi, double *wr, double *wi)
+{
+    const double L = orc_wL;
+    /* d = L - i z = (L + zi) - i zr;  Z = (L + i z) / d = ((L - zi) + i zr) / d */
+    const double dr = L + zi, di = -zr;
+    const double nr = L - zi, ni = zr;
+    const double dd = dr * dr + di * di;
+    const double Zr = (nr * dr + ni * di) / dd, Zi = (ni * dr - nr * di) / dd;
+    double pr = orc_wa[ORC_WN], pi_ = 0.0; /* Horner from a_N down to a_1 */
+    for (int n = ORC_WN - 1; n >= 1; --n) {
+        const double tr = pr * Zr - pi_ * Zi + orc_wa[n];
+        const double ti = pr * Zi + pi_ * Zr;
+        pr = tr;
+        pi_ = ti;
+    }
+    /* 1/d and 1/d^2 */
+    const double ir = dr / dd, ii = -di / dd;
+    const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
+    const double sp = 0.56418958354775628695; /* 1 / sqrt(pi) */
+    *wr = 2.0 * (pr * i2r - pi_ * i2i) + sp * ir;
+    *wi = 2.0 * (pr * i2i + pi_ * i2r) + sp * ii;
+}
+
+typedef struct {
+    int32_t n_poles, n_windows, n_bg, pad;
+    double u_lo, u_hi;
+    const double *poles;  /* [n_poles][2] (re, im) */
+    const double *res_c;  /* [n_poles][2] */
+    const double *res_s;  /* [n_poles][2] */
+    const int32_t *win;   /* [n_windows][2] pole range [start, end) */
+    const double *bg_c;   /* [n_windows][n_bg] */
+    const double *bg_s;
+} orc_mp_nuclide;
+
+#define ORC_KB 8.617333262e-5 /* Boltzmann constant, eV / K */
+
+/* Microscopic capture and scattering cross sections of a multipole nuclide of
+ * mass ratio A at E (eV) and temperature T (K, > 0). */
+void orc_mp_micro(const orc_mp_nuclide *nd, double A, double T, double e, double *sc, double *ss)
+{
+    const double u = sqrt(e);
+    const double beta = sqrt(A / (ORC_KB * T));
+    const double du = (nd->u_hi - nd->u_lo) / (double)nd->n_windows;
+    int32_t w = (int32_t)floor((u - nd->u_lo) / du);
+    if (w < 0) w = 0;
+    if (w > nd->n_windows - 1) w = nd->n_windows - 1;
+    double c = 0.0, s = 0.0;
+    const double spb = 1.7724538509055160273 * beta; /* sqrt(pi) beta */
+    for (int32_t j = nd->win[2 * w]; j < nd->win[2 * w + 1]; ++j) {
+        const double zr = beta * (u - nd->poles[2 * j]), zi = -beta * nd->poles[2 * j + 1];
+        double wr, wi;
+        orc_faddeeva(zr, zi, &wr, &wi);
+        const double cr = spb * wr, ci = spb * wi;
+        c += nd->res_c[2 * j] * cr - nd->res_c[2 * j + 1] * ci;
+        s += nd->res_s[2 * j] * cr - nd->res_s[2 * j + 1] * ci;
+    }
+    c = c / e;
+    s = s / e;
+    /* background: sum_n b_n u^(n-1) */
+    double up = 1.0 / u;
+    for (int32_t n = 0; n < nd->n_bg; ++n) {
+        c += nd->bg_c[w * nd->n_bg + n] * up;
+        s += nd->bg_s[w * nd->n_bg + n] * up;
+        up *= u;
+    }
+    *sc = c;
+    *ss = s;
+}
+
+/* Macroscopic values of a material (nuclides ids[0..nk), densities dens) at
+ * temperature T: sums in material order. */
+void orc_mp_macro_many(const orc_mp_nuclide *nucs, const double *awr, int32_t nk, const int32_t *ids,
+                       const double *dens, double T, int64_t n, const double *e, double *Sa, double *Ss)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double a = 0.0, s = 0.0;
+        for (int32_t q = 0; q < nk; ++q) {
+            double sc, ss;
+            orc_mp_micro(&nucs[ids[q]], awr[ids[q]], T, e[i], &sc, &ss);
+            a = a + dens[q] * sc;
+            s = s + dens[q] * ss;
+        }
+        Sa[i] = a;
+        Ss[i] = s;
+    }
+}
+
+void orc_faddeeva_many(int64_t n, const double *zr, const double *zi, double *wr, double *wi)
+{
+    for (int64_t i = 0; i < n; ++i) orc_faddeeva(zr[i], zi[i], wr + i, wi + i);
+}
