@@ -214,6 +214,47 @@ def c2_union(tuning: dict, steps: int = 5, n_lookups: int = 10_000_000):
     return out
 
 
+FLOPS_PER_POLE = 280  # fp64 operations of one pole term (Faddeeva series of 32 terms, residues)
+
+
+def multipole_microbench(n: int = 1_000_000, reps: int = 3):
+    """Windowed-multipole lookups with Doppler broadening on the fly: 300
+    synthetic nuclides of 200 resonances (poles) each, 1024 windows in
+    sqrt(E), one material at 600 K, 1e6 log-uniform energies.  Bound by fp64
+    arithmetic: FLOPS_PER_POLE per pole term summed against the 78.6 TFLOP/s
+    fp64 vector peak."""
+    import numpy as np
+    import torch
+
+    import mcsynth
+    from paper_2403_12345_amd import mc
+
+    nucs, ids, dens = mcsynth.multipole_material()
+    rng = np.random.default_rng(99)
+    E = torch.from_numpy(mcsynth.lookup_energies(rng, n)).cuda()
+    M = torch.zeros(n, dtype=torch.int32, device="cuda")
+    Sa = torch.empty(n, dtype=torch.float64, device="cuda")
+    Ss = torch.empty(n, dtype=torch.float64, device="cuda")
+    c = mc.mc_create(0)
+    try:
+        mc.mc_init_multipole(c, nucs, [len(ids)], ids, dens, [600.0])
+        poles = mc.mc_lookup_multipole(c, E, M, Sa, Ss, count_poles=True)
+        mc.mc_set_timing(c, True)
+        for _ in range(reps):
+            mc.mc_lookup_multipole(c, E, M, Sa, Ss)
+        s = mc.mc_get_stats(c).as_dict()
+        mc.mc_set_timing(c, False)
+    finally:
+        mc.mc_destroy(c)
+    sec = s["lookup_ms"] / 1e3 / s["lookup_launches"]
+    tflops = poles * FLOPS_PER_POLE / sec / 1e12
+    return {"workload": "1e6 log-uniform energies, one material of 300 multipole nuclides (200 poles, 1024 windows "
+                        "each) at 600 K", "lookups_per_s": n / sec, "pole_terms_per_lookup": poles / n,
+            "launch_ms": sec * 1e3, "roofline": {"bound": "alu", "achieved": tflops, "peak": 78.6,
+                                                  "unit": "TFLOP/s", "frac": tflops / 78.6,
+                                                  "flops_per_pole": FLOPS_PER_POLE}}
+
+
 def lookup_microbench(n: int = 10_000_000, reps: int = 3, ilps=(2,), prob=None):
     """Stand-alone lookup of n (energy, material) pairs on the 300-nuclide
     material (grids of 20k-150k points, ~0.6 GB of tables, far above the
@@ -372,7 +413,9 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 300-nuclide lattice transport batch")
     ap.add_argument("--tuning-cache", default=TUNING_CACHE, help="autotuner cache file")
     ap.add_argument("--no-union", action="store_true", help="skip the hash-grid against union-grid comparison")
-    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom", "c3", "union"), default="full",
+    ap.add_argument("--no-multipole", action="store_true", help="skip the windowed-multipole lookup benchmark")
+    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom", "c3", "union", "multipole"),
+                    default="full",
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -397,6 +440,9 @@ def main():
         return
     if args.mode == "fom":
         print(json.dumps({"fom": fom_bench()}), flush=True)
+        return
+    if args.mode == "multipole":
+        print(json.dumps({"multipole": multipole_microbench()}), flush=True)
         return
     if args.mode == "union":
         from paper_2403_12345_amd import mc
@@ -508,6 +554,8 @@ def main():
         line["c3_channels"] = c3_channels(line["c3_transport"]["tuning"], prob=c3)
     if not args.no_union:
         line["c2_union"] = c2_union(tuning)
+    if not args.no_multipole:
+        line["multipole"] = multipole_microbench()
     if not args.no_problem_set:
         line["problem_set"] = problem_set_bench()
     if not args.no_fom:

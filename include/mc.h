@@ -311,6 +311,56 @@ int mc_set_timing(mc_ctx *ctx, int32_t on);
 int mc_init_channels(mc_ctx *ctx, int32_t n_chan, const double *const *sig_x);
 
 /*
+ * Windowed-multipole cross sections with Doppler broadening computed on the
+ * fly (the compute-bound alternative to tabulated data that the paper points
+ * to in section 4.1).  In u = sqrt(E) (eV^1/2) a nuclide's microscopic
+ * capture / scattering cross section at temperature T is
+ *   sigma_x(E, T) = (1/E) sum_j Re[ r_x,j sqrt(pi) beta w(beta (u - p_j)) ]
+ *                   + sum_n b_x,w,n u^(n-1),     beta = sqrt(A / (k_B T)),
+ * w the Faddeeva function (evaluated by Weideman's rational series, 32 terms),
+ * the sum over the poles of the window w holding u (windows split [u_lo,
+ * u_hi] evenly; u outside clamps to the first / last window).  As T -> 0 each
+ * pole term tends to Re[r i / (u - p)] / E.  These data stand apart from the
+ * tabulated materials (their own nuclides and materials).
+ */
+typedef struct mc_mp_nuclide {
+    int32_t n_poles;      /* >= 0 */
+    int32_t n_windows;    /* >= 1 */
+    int32_t n_bg;         /* background coefficients per window, 0 .. 8 */
+    int32_t reserved;
+    double u_lo, u_hi;    /* window range in sqrt(eV), 0 < u_lo < u_hi */
+    const double *poles;  /* host, [n_poles][2] (re, im), Im < 0 */
+    const double *res_c;  /* host, [n_poles][2] capture residues (barn eV) */
+    const double *res_s;  /* host, [n_poles][2] scattering residues */
+    const int32_t *win;   /* host, [n_windows][2] pole ranges [start, end) */
+    const double *bg_c;   /* host, [n_windows][n_bg] coefficients of u^-1, u^0, ... */
+    const double *bg_s;
+} mc_mp_nuclide;
+
+/*
+ * Load multipole nuclides (copied during the call) and materials of them:
+ * mat_len / mat_nuc / mat_dens as in mc_init_materials, mat_temp[m] the
+ * temperature of material m in kelvin (> 0).  Replaces earlier multipole
+ * data.  Errors: MC_EINVAL (counts, ranges, Im p >= 0, non-finite data, ids,
+ * densities, temperatures), MC_ENOMEM.
+ */
+int mc_init_multipole(mc_ctx *ctx, int32_t n_nuc, const mc_mp_nuclide *nucs, const double *awr, int32_t n_mat,
+                      const int32_t *mat_len, const int32_t *mat_nuc, const double *mat_dens,
+                      const double *mat_temp);
+
+/*
+ * Macroscopic multipole cross sections of n (energy, material) pairs: sig_a /
+ * sig_s (device, n fp64) = sum over the material's nuclides, in material
+ * order, of density * sigma_c / sigma_s at the material's temperature.
+ * E, mat device inputs (n each).  poles_evaluated (nullable, host): the
+ * number of pole terms summed (synchronizes the stream).  Timed like
+ * mc_lookup_macro when mc_set_timing is on (lookups, launches, ms).  Errors:
+ * MC_ESTATE (no multipole data), MC_EINVAL.
+ */
+int mc_lookup_multipole(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *sig_a, double *sig_s,
+                        uint64_t *poles_evaluated);
+
+/*
  * Unionized-grid lookups (the alternative to per-nuclide searches the paper
  * names among the lookup accelerations, section 3): per material, the sorted
  * union U of its nuclides' energy grids with its own hash bounds, and per

@@ -309,12 +309,13 @@ def make_multipole_nuclide(rng, awr: float, n_res: int = 20, n_windows: int = 10
                             bg_c=bg_c, bg_s=bg_s, awr=float(awr))
 
 
-def multipole_material(n_nuclides: int = 300, data_seed: int = 7007):
-    """n_nuclides synthetic multipole nuclides (A = 1 first, then U[2, 240])
-    and densities log-uniform in [1e-6, 1e-2] atoms/(b cm)."""
+def multipole_material(n_nuclides: int = 300, data_seed: int = 7007, n_res: int = 200):
+    """n_nuclides synthetic multipole nuclides of n_res resonances each (A = 1
+    first, then U[2, 240]) and densities log-uniform in [1e-6, 1e-2]
+    atoms/(b cm)."""
     rng = np.random.default_rng(data_seed)
     awr = np.concatenate([[1.0], rng.uniform(2.0, 240.0, n_nuclides - 1)])
-    nucs = [make_multipole_nuclide(rng, a) for a in awr]
+    nucs = [make_multipole_nuclide(rng, a, n_res=n_res) for a in awr]
     dens = _log_uniform(rng, 1e-6, 1e-2, n_nuclides)
     return nucs, np.arange(n_nuclides, dtype=np.int32), dens
 

@@ -61,6 +61,11 @@ struct mc_ctx {
     Buffers union_bufs;              // unionized grids (mc_set_union_grid)
     uint64_t union_bytes = 0;
 
+    // windowed multipole data (mc_init_multipole)
+    Buffers mp_bufs;
+    MpDev mp{};
+    bool have_mp = false;
+
     // reaction channels (tables, and the reaction-rate tally's batch sums)
     int32_t n_chan = 0;
     Buffers chan_bufs;
@@ -291,6 +296,7 @@ void mc_destroy(mc_ctx *ctx)
     ctx->loop_bufs.release();
     ctx->batch_bufs.release();
     ctx->union_bufs.release();
+    ctx->mp_bufs.release();
     if (ctx->ev_loop_start) (void)hipEventDestroy(ctx->ev_loop_start);
     for (hipEvent_t e : ctx->ev_loop_done) (void)hipEventDestroy(e);
     ctx->mat_bufs.release();
@@ -516,6 +522,171 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     ctx->emax = H.emax;
     ctx->M = n_hash_bins;
     ctx->have_mat = true;
+    return MC_OK;
+}
+
+static int timing_event_pair(mc_ctx *ctx, size_t k);
+
+// Coefficients a_1 .. a_N of the rational Faddeeva series (Weideman 1994):
+// the cosine coefficients of f(t) = exp(-t^2) (L^2 + t^2) on t = L tan(theta/2),
+// by a plain sum over theta_k = k pi / M, k = -M+1 .. M-1, M = 2N,
+// L = sqrt(N / sqrt 2).
+static void faddeeva_coefficients(double *a, double &L)
+{
+    const int N = FAD_N, M = 2 * N;
+    L = std::sqrt(std::sqrt((double)N * (double)N / 2.0));
+    const double pi = 3.14159265358979323846;
+    for (int n = 1; n <= N; ++n) {
+        double s = 0.0;
+        for (int k = -M + 1; k <= M - 1; ++k) {
+            const double t = L * std::tan((double)k * pi / (double)M / 2.0);
+            s += std::exp(-t * t) * (L * L + t * t) * std::cos(pi * (double)n * (double)k / (double)M);
+        }
+        a[n - 1] = s / (2.0 * (double)M);
+    }
+}
+
+int mc_init_multipole(mc_ctx *ctx, int32_t n_nuc, const mc_mp_nuclide *nucs, const double *awr, int32_t n_mat,
+                      const int32_t *mat_len, const int32_t *mat_nuc, const double *mat_dens, const double *mat_temp)
+{
+    if (!ctx) return MC_EINVAL;
+    if (n_nuc < 1 || !nucs || !awr || n_mat < 1 || !mat_len || !mat_nuc || !mat_dens || !mat_temp)
+        return fail(ctx, MC_EINVAL, "mc_init_multipole: missing array or non-positive count");
+    std::vector<MpNuc> nd(n_nuc);
+    std::vector<double> poles, rc, rs, bgc, bgs;
+    std::vector<int32_t> win;
+    for (int32_t k = 0; k < n_nuc; ++k) {
+        const mc_mp_nuclide &x = nucs[k];
+        const std::string who = "mc_init_multipole: nuclide " + std::to_string(k) + ": ";
+        if (x.n_poles < 0 || x.n_windows < 1 || x.n_bg < 0 || x.n_bg > 8) return fail(ctx, MC_EINVAL, who + "counts");
+        if (!(x.u_lo > 0.0) || !(x.u_hi > x.u_lo)) return fail(ctx, MC_EINVAL, who + "window range");
+        if (!(awr[k] > 0.0)) return fail(ctx, MC_EINVAL, who + "awr must be > 0");
+        if (!x.win || (x.n_poles > 0 && (!x.poles || !x.res_c || !x.res_s)) || (x.n_bg > 0 && (!x.bg_c || !x.bg_s)))
+            return fail(ctx, MC_EINVAL, who + "missing array");
+        for (int32_t w = 0; w < x.n_windows; ++w)
+            if (x.win[2 * w] < 0 || x.win[2 * w] > x.win[2 * w + 1] || x.win[2 * w + 1] > x.n_poles)
+                return fail(ctx, MC_EINVAL, who + "window " + std::to_string(w) + " pole range");
+        for (int32_t j = 0; j < 2 * x.n_poles; ++j)
+            if (!std::isfinite(x.poles[j]) || !std::isfinite(x.res_c[j]) || !std::isfinite(x.res_s[j]))
+                return fail(ctx, MC_EINVAL, who + "non-finite pole data");
+        for (int32_t j = 0; j < x.n_poles; ++j)
+            if (!(x.poles[2 * j + 1] < 0.0)) return fail(ctx, MC_EINVAL, who + "poles need Im p < 0");
+        nd[k].p_off = (uint32_t)(poles.size() / 2);
+        nd[k].w_off = (uint32_t)(win.size() / 2);
+        nd[k].bg_off = (uint32_t)bgc.size();
+        nd[k].n_windows = x.n_windows;
+        nd[k].n_bg = x.n_bg;
+        nd[k].u_lo = x.u_lo;
+        nd[k].du = (x.u_hi - x.u_lo) / (double)x.n_windows;
+        poles.insert(poles.end(), x.poles, x.poles + 2 * x.n_poles);
+        rc.insert(rc.end(), x.res_c, x.res_c + 2 * x.n_poles);
+        rs.insert(rs.end(), x.res_s, x.res_s + 2 * x.n_poles);
+        win.insert(win.end(), x.win, x.win + 2 * x.n_windows);
+        bgc.insert(bgc.end(), x.bg_c, x.bg_c + (size_t)x.n_windows * x.n_bg);
+        bgs.insert(bgs.end(), x.bg_s, x.bg_s + (size_t)x.n_windows * x.n_bg);
+    }
+    std::vector<int32_t> moff{0};
+    std::vector<double> beta;
+    constexpr double kB = 8.617333262e-5;  // eV / K
+    for (int32_t m = 0; m < n_mat; ++m) {
+        if (mat_len[m] < 1) return fail(ctx, MC_EINVAL, "mc_init_multipole: empty material");
+        if (!(mat_temp[m] > 0.0)) return fail(ctx, MC_EINVAL, "mc_init_multipole: temperatures must be > 0 K");
+        for (int32_t q = 0; q < mat_len[m]; ++q) {
+            const int32_t i = moff.back() + q, k = mat_nuc[i];
+            if (k < 0 || k >= n_nuc) return fail(ctx, MC_EINVAL, "mc_init_multipole: unknown nuclide id");
+            if (!(mat_dens[i] > 0.0)) return fail(ctx, MC_EINVAL, "mc_init_multipole: densities must be > 0");
+            beta.push_back(std::sqrt(awr[k] / (kB * mat_temp[m])));
+        }
+        moff.push_back(moff.back() + mat_len[m]);
+    }
+    double fa[FAD_N], fL = 0.0;
+    faddeeva_coefficients(fa, fL);
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->mp_bufs.release();
+    ctx->have_mp = false;
+    Buffers &B = ctx->mp_bufs;
+    MpDev d{};
+    MpNuc *d_nd = nullptr;
+    double2 *d_p = nullptr, *d_rc = nullptr, *d_rs = nullptr;
+    int2 *d_w = nullptr;
+    double *d_bgc = nullptr, *d_bgs = nullptr, *d_dens = nullptr, *d_beta = nullptr, *d_fa = nullptr;
+    int32_t *d_moff = nullptr, *d_mnuc = nullptr;
+    const size_t np = std::max<size_t>(poles.size() / 2, 1);
+    poles.resize(2 * np, -1.0);
+    rc.resize(2 * np, 0.0);
+    rs.resize(2 * np, 0.0);
+    if (bgc.empty()) {
+        bgc.push_back(0.0);
+        bgs.push_back(0.0);
+    }
+    int rc_ = upload(ctx, B, &d_nd, nd.data(), nd.size());
+    if (!rc_) rc_ = upload(ctx, B, &d_p, reinterpret_cast<const double2 *>(poles.data()), np);
+    if (!rc_) rc_ = upload(ctx, B, &d_rc, reinterpret_cast<const double2 *>(rc.data()), np);
+    if (!rc_) rc_ = upload(ctx, B, &d_rs, reinterpret_cast<const double2 *>(rs.data()), np);
+    if (!rc_) rc_ = upload(ctx, B, &d_w, reinterpret_cast<const int2 *>(win.data()), win.size() / 2);
+    if (!rc_) rc_ = upload(ctx, B, &d_bgc, bgc.data(), bgc.size());
+    if (!rc_) rc_ = upload(ctx, B, &d_bgs, bgs.data(), bgs.size());
+    if (!rc_) rc_ = upload(ctx, B, &d_moff, moff.data(), moff.size());
+    if (!rc_) rc_ = upload(ctx, B, &d_mnuc, mat_nuc, (size_t)moff.back());
+    if (!rc_) rc_ = upload(ctx, B, &d_dens, mat_dens, (size_t)moff.back());
+    if (!rc_) rc_ = upload(ctx, B, &d_beta, beta.data(), beta.size());
+    if (!rc_) rc_ = upload(ctx, B, &d_fa, fa, (size_t)FAD_N);
+    if (rc_) {
+        B.release();
+        return rc_;
+    }
+    d.nuc = d_nd;
+    d.poles = d_p;
+    d.rc = d_rc;
+    d.rs = d_rs;
+    d.win = d_w;
+    d.bgc = d_bgc;
+    d.bgs = d_bgs;
+    d.mat_off = d_moff;
+    d.mat_nuc = d_mnuc;
+    d.mat_dens = d_dens;
+    d.mat_beta = d_beta;
+    d.fa = d_fa;
+    d.fL = fL;
+    d.n_mat = n_mat;
+    ctx->mp = d;
+    ctx->have_mp = true;
+    return MC_OK;
+}
+
+int mc_lookup_multipole(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *sig_a, double *sig_s,
+                        uint64_t *poles_evaluated)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mp) return fail(ctx, MC_ESTATE, "mc_lookup_multipole: no multipole data");
+    if (n == 0) return MC_OK;
+    if (n >= (1ull << 31) || !E || !mat || !sig_a || !sig_s)
+        return fail(ctx, MC_EINVAL, "mc_lookup_multipole: bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    unsigned long long *cnt = poles_evaluated ? ctx->dstat + 2 : nullptr;
+    if (cnt) HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(cnt), 2, 0u, ctx->stream));
+    if (ctx->timing) {
+        int rc = timing_event_pair(ctx, 0);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(ctx->ev_a[0], ctx->stream));
+    }
+    HIPCHK(launch_lookup_mp(ctx->mp, (uint32_t)n, E, mat, sig_a, sig_s, cnt, ctx->stream));
+    if (ctx->timing) {
+        HIPCHK(hipEventRecord(ctx->ev_b[0], ctx->stream));
+        HIPCHK(hipEventSynchronize(ctx->ev_b[0]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_a[0], ctx->ev_b[0]));
+        ctx->stats.lookups += n;
+        ctx->stats.lookup_launches += 1;
+        ctx->stats.lookup_ms += ms;
+    }
+    if (cnt) {
+        unsigned long long c = 0;
+        HIPCHK(hipMemcpyAsync(&c, cnt, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        *poles_evaluated = c;
+    }
     return MC_OK;
 }
 

@@ -526,3 +526,53 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 }  // namespace mc
+
+namespace mc {
+// ---------------------------------------------------------------------------
+// windowed multipole data (on-the-fly Doppler broadening)
+// ---------------------------------------------------------------------------
+constexpr int FAD_N = 32;  // terms of the rational Faddeeva series
+
+struct MpNuc {
+    uint32_t p_off, w_off, bg_off;  // first pole, window, background row
+    int32_t n_windows, n_bg, pad;
+    double u_lo, du;                // windows [u_lo + w du, u_lo + (w + 1) du)
+};
+
+struct MpDev {
+    const MpNuc *nuc;
+    const double2 *poles, *rc, *rs;  // per pole (re, im)
+    const int2 *win;                 // per window [start, end) poles
+    const double *bgc, *bgs;         // per window n_bg coefficients of u^-1, u^0, ...
+    const int32_t *mat_off, *mat_nuc;
+    const double *mat_dens, *mat_beta;  // per (material, position): density, sqrt(A / (k_B T))
+    const double *fa;                // a_1 .. a_N of the Faddeeva series (fa[n - 1])
+    double fL;                       // its L
+    int32_t n_mat;
+};
+
+// Faddeeva function w(z) for Im z > 0 by the rational series of Weideman
+// (1994): with d = L - i z and Z = (L + i z) / d,
+//   w = 2 sum_{n=1..N} a_n Z^(n-1) / d^2 + pi^(-1/2) / d.
+__device__ __forceinline__ void faddeeva(const MpDev &mp, double zr, double zi, double &wr, double &wi)
+{
+    const double L = mp.fL;
+    const double dr = L + zi, di = -zr;
+    const double nr = L - zi, ni = zr;
+    const double dd = dr * dr + di * di;
+    const double Zr = (nr * dr + ni * di) / dd, Zi = (ni * dr - nr * di) / dd;
+    double pr = mp.fa[FAD_N - 1], pi_ = 0.0;
+#pragma unroll 8
+    for (int n = FAD_N - 2; n >= 0; --n) {
+        const double tr = pr * Zr - pi_ * Zi + mp.fa[n];
+        const double ti = pr * Zi + pi_ * Zr;
+        pr = tr;
+        pi_ = ti;
+    }
+    const double ir = dr / dd, ii = -di / dd;
+    const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
+    const double sp = 0.56418958354775628695;  // 1 / sqrt(pi)
+    wr = 2.0 * (pr * i2r - pi_ * i2i) + sp * ir;
+    wi = 2.0 * (pr * i2i + pi_ * i2r) + sp * ii;
+}
+}  // namespace mc

@@ -41,6 +41,9 @@ struct SortBufs {
     uint32_t *chunk_total = nullptr;  // [chunks][256], kept zero between sorts
     uint32_t *chunk_off = nullptr;    // [chunks][256]
 };
+// Windowed-multipole macroscopic cross sections of n (energy, material) pairs.
+hipError_t launch_lookup_mp(const MpDev &mp, uint32_t n, const double *E, const int32_t *mat, double *Sa,
+                            double *Ss, unsigned long long *pole_count, hipStream_t st);
 size_t sort_tile_count(size_t n);
 size_t sort_chunk_count(size_t n);
 // Stable sort of the n (<= n_bound) items list[i] (or i) by key = mat * M + hash bin of E;

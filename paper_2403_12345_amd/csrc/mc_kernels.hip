@@ -677,6 +677,66 @@ __global__ void __launch_bounds__(WG) k_lookup_union(LookupArgs a)
     }
 }
 
+// Windowed-multipole macroscopic cross sections: per nuclide of the
+// material, u = sqrt(E), the window holding u, its poles' terms
+// Re[r sqrt(pi) beta w(beta (u - p))] / E and the background polynomial in u;
+// sums in material order.  pole_count (nullable) adds the poles evaluated.
+__global__ void __launch_bounds__(WG) k_lookup_mp(MpDev mp, uint32_t n, const double *E, const int32_t *mat,
+                                                  double *Sa, double *Ss, unsigned long long *pole_count)
+{
+    const uint32_t i = blockIdx.x * WG + threadIdx.x;
+    uint32_t poles = 0;
+    if (i < n) {
+        const double e = E[i];
+        const int32_t m = mat[i];
+        if (m < 0 || m >= mp.n_mat) {
+            Sa[i] = NAN;
+            Ss[i] = NAN;
+        } else {
+            const double u = sqrt(e);
+            const double spi = 1.7724538509055160273;  // sqrt(pi)
+            double sa = 0.0, ss = 0.0;
+            for (int32_t q = mp.mat_off[m]; q < mp.mat_off[m + 1]; ++q) {
+                const MpNuc nd = mp.nuc[mp.mat_nuc[q]];
+                const double beta = mp.mat_beta[q];
+                int32_t w = (int32_t)floor((u - nd.u_lo) / nd.du);
+                w = w < 0 ? 0 : (w > nd.n_windows - 1 ? nd.n_windows - 1 : w);
+                const int2 rg = mp.win[nd.w_off + w];
+                const double spb = spi * beta;
+                double c = 0.0, s = 0.0;
+                for (int32_t j = rg.x; j < rg.y; ++j) {
+                    const double2 p = mp.poles[nd.p_off + j];
+                    double wr, wi;
+                    faddeeva(mp, beta * (u - p.x), -beta * p.y, wr, wi);
+                    const double cr = spb * wr, ci = spb * wi;
+                    const double2 a = mp.rc[nd.p_off + j], b = mp.rs[nd.p_off + j];
+                    c += a.x * cr - a.y * ci;
+                    s += b.x * cr - b.y * ci;
+                }
+                poles += (uint32_t)(rg.y - rg.x);
+                c = c / e;
+                s = s / e;
+                double up = 1.0 / u;
+                const double *bc = mp.bgc + nd.bg_off + (size_t)w * nd.n_bg;
+                const double *bs = mp.bgs + nd.bg_off + (size_t)w * nd.n_bg;
+                for (int32_t k = 0; k < nd.n_bg; ++k) {
+                    c += bc[k] * up;
+                    s += bs[k] * up;
+                    up *= u;
+                }
+                sa = sa + mp.mat_dens[q] * c;
+                ss = ss + mp.mat_dens[q] * s;
+            }
+            Sa[i] = sa;
+            Ss[i] = ss;
+        }
+    }
+    if (pole_count) {
+        const uint32_t t = wave_sum_u32(poles);
+        if (lane_id() == 0 && t) atomicAdd(pole_count, (unsigned long long)t);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // advance: sample the flight, move, score track length
 // ---------------------------------------------------------------------------
@@ -1276,6 +1336,14 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
         hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(WG), 0, st, sb.chunk_total, sb.chunk_off, chunks);
         hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(WG), 0, st, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup_mp(const MpDev &mp, uint32_t n, const double *E, const int32_t *mat, double *Sa,
+                            double *Ss, unsigned long long *pole_count, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lookup_mp, dim3(blocks_for(n, WG)), dim3(WG), 0, st, mp, n, E, mat, Sa, Ss, pole_count);
     return hipGetLastError();
 }
 

@@ -146,6 +146,8 @@ def load():
         "mc_lookup_macro": ([V, SZ, V, V, V, V, I32], C.c_int),
         "mc_init_channels": ([V, I32, P(P(D))], C.c_int),
         "mc_set_union_grid": ([V, I32, P(U64)], C.c_int),
+        "mc_init_multipole": ([V, I32, V, P(D), I32, P(I32), P(I32), P(D), P(D)], C.c_int),
+        "mc_lookup_multipole": ([V, SZ, V, V, V, V, P(U64)], C.c_int),
         "mc_lookup_channels": ([V, SZ, V, V, V, V, V], C.c_int),
         "mc_lookup_nuclides": ([V, I32, SZ, V, V, V, V], C.c_int),
         "mc_sort_queue": ([V, SZ, V, V, V, V], C.c_int),
@@ -309,6 +311,49 @@ def mc_init_channels(ctx, channels):
         raise ValueError("every nuclide needs a [points, n_chan] array with the same n_chan")
     ptrs = (C.POINTER(C.c_double) * len(arrs))(*[_dp(a) for a in arrs])
     _check(ctx, load().mc_init_channels(ctx, k, ptrs))
+
+
+class mc_mp_nuclide(C.Structure):
+    _fields_ = [("n_poles", C.c_int32), ("n_windows", C.c_int32), ("n_bg", C.c_int32), ("reserved", C.c_int32),
+                ("u_lo", C.c_double), ("u_hi", C.c_double),
+                ("poles", C.POINTER(C.c_double)), ("res_c", C.POINTER(C.c_double)),
+                ("res_s", C.POINTER(C.c_double)), ("win", C.POINTER(C.c_int32)),
+                ("bg_c", C.POINTER(C.c_double)), ("bg_s", C.POINTER(C.c_double))]
+
+
+def mc_init_multipole(ctx, nucs, mat_len, mat_nuc, mat_dens, mat_temp):
+    """Multipole nuclides (objects with poles / res_c / res_s complex arrays,
+    u_lo, u_hi, win [W, 2], bg_c / bg_s [W, n_bg], awr) and their materials."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a
+
+    cs = (mc_mp_nuclide * len(nucs))()
+    for c, nd in zip(cs, nucs):
+        c.n_poles, c.n_windows, c.n_bg = int(np.size(nd.poles)), int(nd.win.shape[0]), int(nd.bg_c.shape[1])
+        c.u_lo, c.u_hi = nd.u_lo, nd.u_hi
+        c.poles = _dp(arr(np.asarray(nd.poles, np.complex128).view(np.float64), np.float64))
+        c.res_c = _dp(arr(np.asarray(nd.res_c, np.complex128).view(np.float64), np.float64))
+        c.res_s = _dp(arr(np.asarray(nd.res_s, np.complex128).view(np.float64), np.float64))
+        c.win = _ip(arr(nd.win, np.int32))
+        c.bg_c = _dp(arr(nd.bg_c, np.float64))
+        c.bg_s = _dp(arr(nd.bg_s, np.float64))
+    awr = arr([nd.awr for nd in nucs], np.float64)
+    ml, mn = arr(mat_len, np.int32), arr(mat_nuc, np.int32)
+    md, mt = arr(mat_dens, np.float64), arr(mat_temp, np.float64)
+    _check(ctx, load().mc_init_multipole(ctx, len(nucs), C.cast(cs, C.c_void_p), _dp(awr), ml.size, _ip(ml), _ip(mn),
+                                         _dp(md), _dp(mt)))
+
+
+def mc_lookup_multipole(ctx, E, mat, sig_a, sig_s, count_poles: bool = False):
+    n = E.numel()
+    cnt = C.c_uint64(0)
+    _check(ctx, load().mc_lookup_multipole(ctx, n, _ptr(E), _ptr(mat), _ptr(sig_a), _ptr(sig_s),
+                                           C.byref(cnt) if count_poles else None))
+    return int(cnt.value) if count_poles else None
 
 
 def mc_set_union_grid(ctx, on: bool = True) -> int:
