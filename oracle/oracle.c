@@ -1041,16 +1041,19 @@ void orc_faddeeva(double zr, double zi, double *wr, double *wi)
     const double dr = L + zi, di = -zr;
     const double nr = L - zi, ni = zr;
     const double dd = dr * dr + di * di;
-    const double Zr = (nr * dr + ni * di) / dd, Zi = (ni * dr - nr * di) / dd;
-    double pr = orc_wa[ORC_WN], pi_ = 0.0; /* Horner from a_N down to a_1 */
+    const double rdd = 1.0 / dd;
+    const double Zr = (nr * dr + ni * di) * rdd, Zi = (ni * dr - nr * di) * rdd;
+    /* Horner from a_N down to a_1, each step p = p Z + a_n with fused
+     * multiply-adds (the evaluation order of the series is ours to fix) */
+    double pr = orc_wa[ORC_WN], pi_ = 0.0;
     for (int n = ORC_WN - 1; n >= 1; --n) {
-        const double tr = pr * Zr - pi_ * Zi + orc_wa[n];
-        const double ti = pr * Zi + pi_ * Zr;
+        const double tr = fma(pr, Zr, fma(-pi_, Zi, orc_wa[n]));
+        const double ti = fma(pr, Zi, pi_ * Zr);
         pr = tr;
         pi_ = ti;
     }
     /* 1/d and 1/d^2 */
-    const double ir = dr / dd, ii = -di / dd;
+    const double ir = dr * rdd, ii = -di * rdd;
     const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
     const double sp = 0.56418958354775628695; /* 1 / sqrt(pi) */
     *wr = 2.0 * (pr * i2r - pi_ * i2i) + sp * ir;

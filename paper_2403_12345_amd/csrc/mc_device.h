@@ -560,16 +560,18 @@ __device__ __forceinline__ void faddeeva(const MpDev &mp, double zr, double zi, 
     const double dr = L + zi, di = -zr;
     const double nr = L - zi, ni = zr;
     const double dd = dr * dr + di * di;
-    const double Zr = (nr * dr + ni * di) / dd, Zi = (ni * dr - nr * di) / dd;
+    const double rdd = 1.0 / dd;
+    const double Zr = (nr * dr + ni * di) * rdd, Zi = (ni * dr - nr * di) * rdd;
+    // Horner, p = p Z + a_n with fused multiply-adds
     double pr = mp.fa[FAD_N - 1], pi_ = 0.0;
 #pragma unroll 8
     for (int n = FAD_N - 2; n >= 0; --n) {
-        const double tr = pr * Zr - pi_ * Zi + mp.fa[n];
-        const double ti = pr * Zi + pi_ * Zr;
+        const double tr = fma(pr, Zr, fma(-pi_, Zi, mp.fa[n]));
+        const double ti = fma(pr, Zi, pi_ * Zr);
         pr = tr;
         pi_ = ti;
     }
-    const double ir = dr / dd, ii = -di / dd;
+    const double ir = dr * rdd, ii = -di * rdd;
     const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
     const double sp = 0.56418958354775628695;  // 1 / sqrt(pi)
     wr = 2.0 * (pr * i2r - pi_ * i2i) + sp * ir;
