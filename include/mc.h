@@ -492,7 +492,7 @@ int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
 
 /*
  * Autotuner of the single-problem path: times mc_run_batches of n histories
- * per batch (pids from first_pid, key seed; 4 batches, 2 when n >= 2^22) per
+ * per batch (pids from first_pid, key seed; 12 batches, 2 when n >= 2^22) per
  * candidate, per batch, searching one
  * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
  * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}

@@ -2313,7 +2313,7 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     cur.collide_sort_min = 0;  // follows sort_min unless the search turns it off
     // each trial: a few batches through mc_run_batches (so that loops > 1
     // shows its overlap of consecutive batches), timed per batch
-    const uint64_t trial_batches = n >= (1ull << 22) ? 2 : 4;
+    const uint64_t trial_batches = n >= (1ull << 22) ? 2 : 12;  // 12: whole rounds for 1 to 4 loops
     auto trial = [&](const mc_tuning &c, double &ms) -> int {
         ctx->tune = c;
         const int r = mc_run_batches(ctx, seed, first_pid, n, trial_batches, nullptr);
@@ -2330,19 +2330,20 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), 1 << 20, 1 << 22, n_cap};
     const int32_t csorts[] = {0, (int32_t)kSortNever};
     const int32_t loops[] = {1, 2, 3, 4};
-    const int32_t *axes[] = {tails, sorts, ilps, flights, csorts, loops};
-    const int counts[] = {4, 5, 3, 5, 2, 4};
+    // the loop count first: whether a sort pays depends on what overlaps it
+    const int32_t *axes[] = {loops, tails, sorts, ilps, flights, csorts};
+    const int counts[] = {4, 4, 5, 3, 5, 2};
     for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
         for (int axis = 0; axis < 6 && !rc; ++axis) {
             for (int k = 0; k < counts[axis] && !rc; ++k) {
                 mc_tuning c = cur;
                 const int32_t v = axes[axis][k];
-                if (axis == 0) c.tail_particles = v;
-                if (axis == 1) c.sort_min = v;
-                if (axis == 2) c.lookup_ilp = v;
-                if (axis == 3) c.in_flight = std::min(v, n_cap);
-                if (axis == 4) c.collide_sort_min = v;
-                if (axis == 5) c.loops = v;
+                if (axis == 0) c.loops = v;
+                if (axis == 1) c.tail_particles = v;
+                if (axis == 2) c.sort_min = v;
+                if (axis == 3) c.lookup_ilp = v;
+                if (axis == 4) c.in_flight = std::min(v, n_cap);
+                if (axis == 5) c.collide_sort_min = v;
                 if (std::memcmp(&c, &cur, sizeof c) == 0) continue;
                 double ms = 0.0;
                 rc = trial(c, ms);
