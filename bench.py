@@ -420,8 +420,8 @@ def main():
                     help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
-              "(sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X and has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 """FP64 oracle of the importance network -- TEST INFRASTRUCTURE.
 
-The learned importance map is an addition of this build, not part of the
-paper: a 4 -> 64 -> 64 -> 1 multilayer perceptron with SiLU hidden
+The learned importance map is an addition to the paper's method, not part
+of the paper: a 4 -> 64 -> 64 -> 1 multilayer perceptron with SiLU hidden
 activations that predicts ln I(x, y, z, ln E).  Its kernels on the GPU keep
 the weight matrices in BF16, feed BF16 operands to the matrix cores and
 accumulate in FP32.  This oracle computes the same network in float64 with

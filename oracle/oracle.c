@@ -149,7 +149,7 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
  * pid_lo, pid_hi), key = (seed_lo, seed_hi); the even draw takes output words
  * (1:0), the odd draw words (3:2), as a 64-bit integer x; u = ((x >> 12) + 0.5)
  * * 2^-52, exact in fp64 and strictly inside (0, 1).  (Counter layout and conversion
- * are this build's reading; the paper does not fix them.) */
+ * are a reading of ours; the paper does not fix them.) */
 double orc_uniform(uint64_t seed, uint32_t lineage, uint64_t pid, uint64_t n)
 {
     uint32_t ctr[4] = {(uint32_t)(n >> 1), lineage, (uint32_t)pid, (uint32_t)(pid >> 32)};

@@ -19,7 +19,7 @@ matrix-core training, windows from the network).  The sequence:
 The production windows then come from the network, its ln I clamped to the
 span of the training targets (outside the cells it was fitted on the network
 extrapolates, and an unbounded map could split without limit); analog
-transport remains the unbiased judge of its estimate.
+transport remains the unbiased reference for its estimate.
 """
 from __future__ import annotations
 

@@ -122,8 +122,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; "
-                          f"g.build()') -- there is no CPU fallback")
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'from paper_2403_12345_amd.build "
+                          f"import build_library; build_library()') -- there is no CPU fallback")
     # The library is handed PyTorch's device pointers and streams, so it must
     # run on the HIP runtime PyTorch loaded: load that first.
     import torch  # noqa: F401

@@ -36,6 +36,8 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(mc.mc_stats) == 8 * 10
     assert ctypes.sizeof(mc.mc_ww_desc) == 6 * 4 + 10 * 8
     assert ctypes.sizeof(mc.mc_train_opts) == 48
+    assert ctypes.sizeof(mc.mc_mp_nuclide) == 4 * 4 + 2 * 8 + 6 * 8
+    assert ctypes.sizeof(mc.mc_tuning) == 8 * 4
 
 
 def _header_enum(name):
