@@ -558,6 +558,17 @@ def main():
     if not args.no_c3:
         line["c3_transport"] = c3_transport(args.tuning_cache, prob=c3)
         line["c3_channels"] = c3_channels(line["c3_transport"]["tuning"], prob=c3)
+    if not (args.no_c3 and args.no_lookup_bench):
+        # the lookup rates quoted against the measured copy bandwidth too
+        cal = copy_calibration()
+        line["copy_GBs"] = cal["copy_GBs"]
+        if not args.no_c3:
+            for k in ("c3_transport", "c3_channels"):
+                line[k]["lookup_frac_of_copy_bw"] = line[k]["lookup_GBs"] / cal["copy_GBs"]
+        if not args.no_lookup_bench:
+            for k, v in line["lookup_microbench"].items():
+                if isinstance(v, dict) and "achieved_GBs" in v:
+                    v["frac_of_copy_bw"] = v["achieved_GBs"] / cal["copy_GBs"]
     if not args.no_union:
         line["c2_union"] = c2_union(tuning)
     if not args.no_multipole:
