@@ -427,13 +427,13 @@ static int finish_xs(mc_ctx *ctx, HostXs &H, int32_t M)
     const size_t n_nuc = H.glen.size();
     std::vector<int32_t> lo(n_nuc * (size_t)(M + 1));
     for (size_t k = 0; k < n_nuc; ++k) build_bounds(H.grids[k], H.glen[k], H.emin, H.emax, M, &lo[k * (M + 1)]);
-    uint64_t words = 0;
+    uint64_t pairs = 0;  // brackets (lo_b, lo_b+1) per material, bin and nuclide
     H.hoff.resize(n_mat);
     for (size_t m = 0; m < n_mat; ++m) {
-        H.hoff[m] = words;
-        words += (uint64_t)(M + 1) * (uint64_t)H.mat_len[m];
+        H.hoff[m] = pairs;
+        pairs += (uint64_t)M * (uint64_t)H.mat_len[m];
     }
-    H.hash.assign(words, 0u);
+    H.hash.assign(2 * pairs, 0u);
     for (size_t m = 0; m < n_mat; ++m) {
         const int32_t nk = H.mat_len[m];
         for (int32_t q = 0; q < nk; ++q) {
@@ -441,7 +441,11 @@ static int finish_xs(mc_ctx *ctx, HostXs &H, int32_t M)
             MatNuc &mn = H.mnuc[H.moff[m] + q];
             mn.off = H.goff[k];
             mn.len = (uint32_t)H.glen[k];
-            for (int32_t b = 0; b <= M; ++b) H.hash[H.hoff[m] + (uint64_t)b * nk + q] = (uint32_t)lo[(size_t)k * (M + 1) + b];
+            for (int32_t b = 0; b < M; ++b) {
+                const uint64_t at = 2 * (H.hoff[m] + (uint64_t)b * nk + q);
+                H.hash[at] = (uint32_t)lo[(size_t)k * (M + 1) + b];
+                H.hash[at + 1] = (uint32_t)lo[(size_t)k * (M + 1) + b + 1];
+            }
         }
     }
     return MC_OK;
@@ -453,7 +457,7 @@ static int upload_xs(mc_ctx *ctx, const HostXs &H, int32_t M, Buffers &B, XsDev 
     double2 *d_xs;
     int32_t *d_moff, *d_mnucid;
     MatNuc *d_mnuc;
-    uint32_t *d_hash;
+    uint2 *d_hash;
     uint64_t *d_hoff;
     int rc = upload(ctx, B, &d_Eg, H.Eg.data(), H.Eg.size());
     if (!rc) rc = upload(ctx, B, &d_xs, reinterpret_cast<const double2 *>(H.xs.data()), H.Eg.size());
@@ -461,7 +465,7 @@ static int upload_xs(mc_ctx *ctx, const HostXs &H, int32_t M, Buffers &B, XsDev 
     if (!rc) rc = upload(ctx, B, &d_moff, H.moff.data(), H.moff.size());
     if (!rc) rc = upload(ctx, B, &d_mnucid, H.mnucid.data(), H.mnucid.size());
     if (!rc) rc = upload(ctx, B, &d_mnuc, H.mnuc.data(), H.mnuc.size());
-    if (!rc) rc = upload(ctx, B, &d_hash, H.hash.data(), H.hash.size());
+    if (!rc) rc = upload(ctx, B, &d_hash, reinterpret_cast<const uint2 *>(H.hash.data()), H.hash.size() / 2);
     if (!rc) rc = upload(ctx, B, &d_hoff, H.hoff.data(), H.hoff.size());
     if (rc) return rc;
     x = XsDev{};

@@ -43,9 +43,10 @@ struct MatNuc {
 // Cross-section tables in HBM.
 //   Eg[p]      fp64 grid energies of every nuclide, concatenated
 //   xs[p]      {sigma_c, sigma_s} at the same point (16 B, one load per point)
-//   hash       per material m: (M + 1) rows of n_k uint32 bounds, row b holding
-//              i_q(E_b) for the material's nuclides q (bin-major so that one
-//              particle's bounds for all its nuclides are contiguous)
+//   hash       per material m: M rows of n_k uint2 brackets, row b holding
+//              (i_q(E_b), i_q(E_b+1)) for the material's nuclides q (bin-major
+//              so that one particle's brackets for all its nuclides are
+//              contiguous; one 8-byte load per nuclide)
 struct XsDev {
     const double *Eg;
     const double2 *xs;
@@ -53,7 +54,7 @@ struct XsDev {
     const int32_t *mat_off;    // [n_mat + 1] into mat_nuc / mnuc
     const int32_t *mat_nuc;    // nuclide ids in material order
     const MatNuc *mnuc;        // per (material, position)
-    const uint32_t *hash;
+    const uint2 *hash;
     const uint64_t *hash_off;  // [n_mat] start of material m's rows
     int32_t n_mat;
     int32_t M;                 // hash bins
@@ -268,9 +269,14 @@ __device__ __forceinline__ void lerp_xs(const XsDev &xs, uint32_t off, uint32_t 
 // logarithms rounding differently at a bin edge) does a lane walk to the
 // defined index and reload.  Each nuclide's result is exactly that of
 // grid_find + lerp_xs.
+// Two consecutive grid energies, 8-byte aligned (one 16-byte load).
+struct __attribute__((aligned(8))) EPair {
+    double a, b;
+};
+
 template <int ILP>
 __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__restrict__ mnuc,
-                                            const uint32_t *h, int32_t nk, int32_t q, int32_t cnt, double e,
+                                            const uint2 *h, int32_t nk, int32_t q, int32_t cnt, double e,
                                             double (&dens)[ILP], uint32_t (&ix)[ILP], double (&sc)[ILP],
                                             double (&ss)[ILP], double (&fr)[ILP], uint32_t (&pt)[ILP])
 {
@@ -280,7 +286,8 @@ __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__res
         const bool act = k < cnt;
         const int32_t qk = q + (act ? k : 0);  // inactive slots repeat nuclide q, in bounds
         const MatNuc mn = mnuc[qk];
-        const uint32_t a = h[qk], b = h[nk + qk];
+        const uint2 br = h[qk];
+        const uint32_t a = br.x, b = br.y;
         off[k] = mn.off;
         len[k] = mn.len;
         dens[k] = act ? mn.dens : 0.0;
@@ -310,8 +317,9 @@ __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__res
     double2 x0[ILP], x1[ILP];
 #pragma unroll
     for (int k = 0; k < ILP; ++k) {
-        e0[k] = xs.Eg[off[k] + lo[k]];
-        e1[k] = xs.Eg[off[k] + lo[k] + 1u];
+        const EPair ep = *reinterpret_cast<const EPair *>(xs.Eg + off[k] + lo[k]);  // E_i, E_i+1 in one load
+        e0[k] = ep.a;
+        e1[k] = ep.b;
         x0[k] = xs.xs[off[k] + lo[k]];
         x1[k] = xs.xs[off[k] + lo[k] + 1u];
     }
@@ -344,7 +352,7 @@ __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__res
 // The same without the interpolation fraction and table position.
 template <int ILP>
 __device__ __forceinline__ void micro_group(const XsDev &xs, const MatNuc *__restrict__ mnuc,
-                                            const uint32_t *h, int32_t nk, int32_t q, int32_t cnt, double e,
+                                            const uint2 *h, int32_t nk, int32_t q, int32_t cnt, double e,
                                             double (&dens)[ILP], uint32_t (&ix)[ILP], double (&sc)[ILP],
                                             double (&ss)[ILP])
 {
@@ -374,7 +382,7 @@ __device__ __forceinline__ void channel_group(const XsDev &xs, int32_t cnt, cons
 }
 
 // Hash row pointer of bin b of material m (global memory).
-__device__ __forceinline__ const uint32_t *hash_row(const XsDev &xs, int32_t m, int32_t b, int32_t nk)
+__device__ __forceinline__ const uint2 *hash_row(const XsDev &xs, int32_t m, int32_t b, int32_t nk)
 {
     return xs.hash + xs.hash_off[m] + (uint64_t)b * (uint64_t)nk;
 }
@@ -384,8 +392,8 @@ __device__ __forceinline__ double micro_scatter(const XsDev &xs, int32_t m, int3
                                                 int32_t b, double e)
 {
     const MatNuc mn = xs.mnuc[xs.mat_off[m] + q];
-    const uint32_t *h = hash_row(xs, m, b, nk);
-    const uint32_t i = grid_find(xs.Eg + mn.off, mn.len, h[q], h[nk + q], e);
+    const uint2 *h = hash_row(xs, m, b, nk);
+    const uint32_t i = grid_find(xs.Eg + mn.off, mn.len, h[q].x, h[q].y, e);
     double sc, ss;
     lerp_xs(xs, mn.off, i, e, sc, ss);
     return ss;

@@ -470,7 +470,7 @@ struct LookupArgs {
     double *sx;               // reaction channels [p][n_chan] (the CHAN kernels)
 };
 
-constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
+constexpr int LDS_HASH_PAIRS = 2048;  // 16 KiB of staged hash brackets
 
 // DIAG: the per-nuclide outputs (idx_out, sc_out, ss_out) may be set; the
 // transport's lookups run without them, in fewer registers.  CHAN: the
@@ -479,7 +479,7 @@ constexpr int LDS_HASH_WORDS = 4096;  // 16 KiB of staged hash bounds
 template <int ILP, bool DIAG, bool CHAN>
 __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 {
-    __shared__ uint32_t sh[LDS_HASH_WORDS];
+    __shared__ uint2 sh[LDS_HASH_PAIRS];
     __shared__ int32_t s_info[4];
     const XsDev &xs = a.xs;
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
@@ -498,8 +498,8 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
             if (m0 == m1) {
                 const int32_t nk = xs.mat_off[m0 + 1] - xs.mat_off[m0];
                 b0 = (int32_t)(k0 % (uint32_t)xs.M);
-                nrow = (int32_t)(k1 % (uint32_t)xs.M) - b0 + 2;
-                if (nrow * nk <= LDS_HASH_WORDS) { staged = 1; m = m0; }
+                nrow = (int32_t)(k1 % (uint32_t)xs.M) - b0 + 1;
+                if (nrow * nk <= LDS_HASH_PAIRS) { staged = 1; m = m0; }
             }
         }
         s_info[0] = staged; s_info[1] = m; s_info[2] = b0; s_info[3] = nrow;
@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     if (staged) {
         const int32_t m = s_info[1], b0 = s_info[2], nrow = s_info[3];
         const int32_t nk = xs.mat_off[m + 1] - xs.mat_off[m];
-        const uint32_t *src = hash_row(xs, m, b0, nk);
+        const uint2 *src = hash_row(xs, m, b0, nk);
         for (int32_t t = threadIdx.x; t < nrow * nk; t += WG) sh[t] = src[t];
         __syncthreads();
     }
@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
         for (int x = 0; x < MAX_CHAN; ++x) acc[x] = 0.0;
     }
     // the nuclide loop, once with the brackets in LDS and once in global memory
-    auto nuclides = [&](const uint32_t *h0) {
+    auto nuclides = [&](const uint2 *h0) {
         for (int32_t q = 0; q < nk; q += ILP) {
             const int32_t cnt = nk - q < ILP ? nk - q : ILP;
             double dens[ILP], c[ILP], s[ILP], fr[ILP];

@@ -238,7 +238,7 @@ template <int ILP, bool CHAN = false>
 __device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = nullptr)
 {
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
-    const uint32_t *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
+    const uint2 *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
     double sa = 0.0, ss = 0.0;
     double acc[MAX_CHAN];
     if (CHAN) {
@@ -409,7 +409,7 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
     }
     const double target = rng.next() * p.Ss;
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
-    const uint32_t *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
+    const uint2 *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
     double cum = 0.0;
     int32_t pick = -1, qstart = 0;
     const int32_t ncp = cp ? cp_count(nk) : 0;
