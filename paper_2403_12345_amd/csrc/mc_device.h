@@ -54,8 +54,8 @@ struct XsDev {
     const int32_t *mat_off;    // [n_mat + 1] into mat_nuc / mnuc
     const int32_t *mat_nuc;    // nuclide ids in material order
     const MatNuc *mnuc;        // per (material, position)
-    const uint2 *hash;
-    const uint64_t *hash_off;  // [n_mat] start of material m's rows
+    const uint2 *hash;         // [hash_off[m] + b * nk + q] = (lo_q(E_b), lo_q(E_b+1)): bin b's bracket
+    const uint64_t *hash_off;  // [n_mat] start of material m's rows (in pairs)
     int32_t n_mat;
     int32_t M;                 // hash bins
     double ln_emin, inv_delta; // bin b = floor((ln E - ln emin) * inv_delta)
@@ -261,7 +261,7 @@ __device__ __forceinline__ void lerp_xs(const XsDev &xs, uint32_t off, uint32_t 
 }
 
 // Micro cross sections of up to ILP nuclides (positions q .. q+cnt-1 of a
-// material whose entries start at mnuc, hash brackets h[q], h[nk + q]) at E.
+// material whose entries start at mnuc, hash bracket pairs h[q]) at E.
 // The bisections run in lockstep with their probe loads issued together, so a
 // wave keeps ILP independent gathers in flight per step instead of one.  The
 // interval found is checked against the energies loaded for the

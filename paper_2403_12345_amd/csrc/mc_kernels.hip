@@ -122,7 +122,7 @@ __device__ __forceinline__ void tile_prefix3(const uint32_t *cnt, uint32_t n_til
 }
 
 // ---------------------------------------------------------------------------
-// queue building over the slots (one tile of 4096 slots per workgroup)
+// queue building over the slots (one tile of TILE slots per workgroup)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(WG) k_slots_count(BankDev bank)
 {
