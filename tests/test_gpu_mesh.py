@@ -1,4 +1,4 @@
-"""GPU mesh track-length tally (3-D walk through the mesh, FP64 atomics)
+"""GPU mesh track-length tally (3-D walk through the mesh, 64-bit fixed-point atomics)
 against the oracle and the closed forms of a homogeneous reflected box:
 the pieces of every flight add up to the total track length, the flux is flat,
 and GPU and oracle cell tallies agree within 3 sigma (independent seeds)."""
