@@ -120,9 +120,11 @@ struct GeomDev {
 // leaves at most CP_MAX of them.  The collision starts its walk for the
 // sampled nuclide at the checkpoint before the target instead of at nuclide
 // 0: the same partial sums, far fewer gathers.  (The rows are written by
-// scattered 8-byte stores, so a few checkpoints per lookup, not one per
-// nuclide: each store can cost the lookup a partial-line write-back.)
-constexpr int CP_MAX = 16, CP_MIN_NUC = 16;
+// scattered stores, two checkpoints at a time, so a few checkpoints per
+// lookup, not one per nuclide: each store can cost the lookup a partial-line
+// write-back.  For 300 nuclides a stride of 16 (18 checkpoints) beats both 32
+// and 8.)
+constexpr int CP_MAX = 32, CP_MIN_NUC = 16;
 __host__ __device__ __forceinline__ int32_t cp_shift(int32_t nk)
 {
     int32_t sh = 3;
@@ -133,6 +135,23 @@ __host__ __device__ __forceinline__ int32_t cp_count(int32_t nk)
 {
     return nk > CP_MIN_NUC ? nk >> cp_shift(nk) : 0;
 }
+
+// The lookup writes a row's checkpoints two at a time (one 16-byte store for
+// checkpoints 2i and 2i+1): half as many scattered partial-line writes.
+struct CpPairs {
+    double *row;  // the particle's row of CP_MAX (16-byte aligned)
+    double pend;  // checkpoint 2i, waiting for 2i+1
+    __device__ __forceinline__ void put(int32_t j, double v)
+    {
+        if (j & 1) *reinterpret_cast<double2 *>(row + (j - 1)) = make_double2(pend, v);
+        else pend = v;
+    }
+    // after the last of count checkpoints
+    __device__ __forceinline__ void finish(int32_t count)
+    {
+        if (count & 1) row[count - 1] = pend;
+    }
+};
 
 struct BankDev {
     double *cp;  // [slot][CP_MAX] checkpoints of the scattering sum (see above): one row per slot

@@ -540,6 +540,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     const MatNuc *mnuc = xs.mnuc + q0;
     const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
     const int32_t cp_mask = (1 << cp_sh) - 1;
+    CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
     double acc[MAX_CHAN];
     if (CHAN) {
 #pragma unroll
@@ -560,7 +561,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
                     sa = sa + dens[k] * c[k];
                     ss = ss + dens[k] * s[k];
                     const int32_t done = q + k + 1;  // a checkpoint of the scattering sum
-                    if ((done & cp_mask) == 0) a.cp[(size_t)p * CP_MAX + ((done >> cp_sh) - 1)] = ss;
+                    if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
                     if (DIAG) {
                         if (a.idx_out) a.idx_out[(size_t)p * nk + q + k] = (int32_t)ix[k];
                         if (a.sc_out) a.sc_out[(size_t)p * nk + q + k] = c[k];
@@ -572,6 +573,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     };
     if (staged) nuclides(sh + (b - s_info[2]) * nk);
     else nuclides(hash_row(xs, m, b, nk));
+    if (cp_sh != 30) cpw.finish(nk >> cp_sh);
     if (a.Sa) a.Sa[p] = sa;
     if (a.Ss) a.Ss[p] = ss;
     if (CHAN) {
@@ -636,6 +638,7 @@ __global__ void __launch_bounds__(WG) k_lookup_union(LookupArgs a)
             const MatNuc *mnuc = xs.mnuc + q0;
             const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;
             const int32_t cp_mask = (1 << cp_sh) - 1;
+            CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
             double sa = 0.0, ss = 0.0;
             for (int32_t q = 0; q < nk; q += ILP) {
                 const int32_t cnt = nk - q < ILP ? nk - q : ILP;
@@ -661,10 +664,11 @@ __global__ void __launch_bounds__(WG) k_lookup_union(LookupArgs a)
                         sa = sa + dens[k] * c;
                         ss = ss + dens[k] * s;
                         const int32_t done = q + k + 1;
-                        if ((done & cp_mask) == 0) a.cp[(size_t)p * CP_MAX + ((done >> cp_sh) - 1)] = ss;
+                        if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
                     }
                 }
             }
+            if (cp_sh != 30) cpw.finish(nk >> cp_sh);
             if (a.Sa) a.Sa[p] = sa;
             if (a.Ss) a.Ss[p] = ss;
             if (a.flags) a.flags[p] = F_ALIVE;
@@ -989,7 +993,7 @@ template <int ILP, bool CHAN>
 __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev &xs, const GeomDev &g,
                                 const TileRows &r, uint64_t seed, int64_t max_events, HistLog *log,
                                 uint64_t log_first_pid, unsigned long long *lost, double *slab, double *gl,
-                                double *sx_row)
+                                double *sx_row, double *cp_row)
 {
     const bool binned = r.enabled && g.tally_kind != TALLY_MESH;
     const bool log_on = log != nullptr;
@@ -998,7 +1002,7 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         clear_score(sc);
         int32_t fate = 0;
         if (alive && need) {
-            do_lookup<ILP, CHAN>(p, xs, sx_row);
+            do_lookup<ILP, CHAN>(p, xs, sx_row, cp_row);
             need = false;
         }
         int32_t flight_mat = -1;
@@ -1013,7 +1017,7 @@ __device__ inline void run_tile(Particle &p, bool alive, bool need, const XsDev 
         if (CHAN && r.enabled) wg_chan_add(flight_mat, sc.g[G_TRACK], sx_row, r.n_chan, slab, r.chan_bins, r.chan);
         if (alive && fate == 0) {
             if (p.ev == EV_COLLIDE) {
-                fate = do_collide<ILP>(p, xs, g, seed, r.enabled, r.mesh_coll, sc, nullptr);
+                fate = do_collide<ILP>(p, xs, g, seed, r.enabled, r.mesh_coll, sc, cp_row);
                 need = fate == 0;
             } else {
                 bool leak_xhi;
@@ -1067,7 +1071,11 @@ __global__ void __launch_bounds__(WG) k_tail(BankDev b, XsDev xs, GeomDev g, Tal
     r.chan_bins = tal.chan_bins;
     r.n_chan = tal.n_chan;
     double *sx_row = CHAN ? b.sx + (size_t)s * tal.n_chan : nullptr;
-    run_tile<TAIL_ILP, CHAN>(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl, sx_row);
+    // the slot's checkpoint row: written by the lookups of the event loop and
+    // of this kernel, read by the collisions of both
+    double *cp_row = b.cp ? b.cp + (size_t)s * CP_MAX : nullptr;
+    run_tile<TAIL_ILP, CHAN>(p, alive, need, xs, g, r, seed, max_events, log, first_pid, lost, slab, gl, sx_row,
+                             cp_row);
     if (i < n) b.flags[s] = 0;
 }
 
@@ -1146,7 +1154,7 @@ __global__ void __launch_bounds__(WG) k_problem_set(SetDev set, XsDev xs, int64_
             r.chan_bins = r.n_chan = 0;
             HistLog *log = set.log ? set.log + P.log_off : nullptr;
             run_tile<DEFAULT_LOOKUP_ILP, false>(p, alive, true, xs, P.g, r, P.seed, max_events, log, first_pid,
-                                                set.lost, slab, gl, nullptr);
+                                                set.lost, slab, gl, nullptr, nullptr);
         }
     }
 }

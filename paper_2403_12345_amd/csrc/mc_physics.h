@@ -233,13 +233,17 @@ constexpr int DEFAULT_LOOKUP_ILP = 2;
 
 // Macroscopic cross sections of the particle's material at its energy
 // (hash brackets read from global memory); CHAN: also the reaction channels
-// into sx_row.
+// into sx_row; cp_row (nullable): the scattering-sum checkpoints, as the
+// event-loop lookup writes them.
 template <int ILP, bool CHAN = false>
-__device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = nullptr)
+__device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = nullptr, double *cp_row = nullptr)
 {
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
     const uint2 *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
     double sa = 0.0, ss = 0.0;
+    const int32_t cp_sh = cp_row && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
+    const int32_t cp_mask = (1 << cp_sh) - 1;
+    CpPairs cpw{cp_row, 0.0};
     double acc[MAX_CHAN];
     if (CHAN) {
 #pragma unroll
@@ -256,9 +260,12 @@ __device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = 
             if (k < cnt) {
                 sa = sa + dens[k] * c[k];
                 ss = ss + dens[k] * s[k];
+                const int32_t done = q + k + 1;
+                if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
             }
         }
     }
+    if (cp_sh != 30) cpw.finish(nk >> cp_sh);
     p.Sa = sa;
     p.Ss = ss;
     if (CHAN) {
