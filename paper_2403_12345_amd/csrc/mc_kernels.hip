@@ -472,15 +472,126 @@ struct LookupArgs {
 
 constexpr int LDS_HASH_PAIRS = 2048;  // 16 KiB of staged hash brackets
 
+// Grid points a wave stages per nuclide for a sorted queue (see window_lookups).
+constexpr int WIN_PTS = 64;
+
+// Orders a wave's LDS writes before its reads of them (and reads before the
+// next writes): LDS instructions of one wave execute in program order, so only
+// the compiler has to be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lookups of a staged workgroup of a sorted queue: one material, hash bins
+// ascending through the workgroup, bracket rows b0 .. in LDS (sh).  Per
+// nuclide the lanes of a wave need grid points only from the bracket start of
+// the wave's lowest bin to one past the bracket end of its highest.  When that
+// window holds at most WIN_PTS points the wave reads it (energies and cross
+// sections) with one coalesced load each into LDS, and every lane bisects its
+// own bracket there and interpolates from there; a wider window falls back to
+// each lane searching global memory.  Per nuclide a wave then issues two
+// vector loads instead of one per bracket, probe and interval point.  Same
+// interval (with the one-off-bin walk), interpolation and sums in material
+// order as micro_group: the results bit for bit.  Returns the nuclides looked
+// up for this lane.
+__device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uint2 *sh, const int32_t *s_info,
+                                                  uint32_t i, bool valid, double *we, double2 *wx)
+{
+    const XsDev &xs = a.xs;
+    const uint64_t vmask = __ballot(valid);
+    if (!vmask) return 0;
+    const int32_t m = __builtin_amdgcn_readfirstlane(s_info[1]);
+    const int32_t b0 = __builtin_amdgcn_readfirstlane(s_info[2]);
+    const int32_t q0 = __builtin_amdgcn_readfirstlane(xs.mat_off[m]);
+    const int32_t nk = __builtin_amdgcn_readfirstlane(xs.mat_off[m + 1]) - q0;
+    uint32_t p = 0;
+    double e = 0.0;
+    int32_t b = 0;
+    if (valid) {
+        p = a.list ? a.list[i] : i;
+        e = a.E[p];
+        b = (int32_t)(a.keys[i] % (uint32_t)xs.M);
+    }
+    const int32_t bmin = __builtin_amdgcn_readfirstlane(__shfl(b, __ffsll((long long)vmask) - 1, 64));
+    const int32_t bmax = __builtin_amdgcn_readfirstlane(__shfl(b, 63 - __clzll((long long)vmask), 64));
+    const uint2 *hmin = sh + (bmin - b0) * nk, *hmax = sh + (bmax - b0) * nk, *hown = sh + (b - b0) * nk;
+    const uint32_t lane = (uint32_t)lane_id();
+    double *E_w = we + (threadIdx.x & ~63u);
+    double2 *X_w = wx + (threadIdx.x & ~63u);
+    const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
+    const int32_t cp_mask = (1 << cp_sh) - 1;
+    CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
+    double sa = 0.0, ss = 0.0;
+    for (int32_t q = 0; q < nk; ++q) {
+        const MatNuc mn = xs.mnuc[q0 + q];
+        const double *g = xs.Eg + mn.off;
+        const double2 *x = xs.xs + mn.off;
+        const uint32_t wlo = __builtin_amdgcn_readfirstlane(hmin[q].x);
+        const uint32_t wn = __builtin_amdgcn_readfirstlane(hmax[q].y) + 2u - wlo;  // points wlo .. wlo + wn - 1
+        double c = 0.0, sg = 0.0;
+        if (wn <= (uint32_t)WIN_PTS) {
+            if (lane < wn) {
+                E_w[lane] = g[wlo + lane];
+                X_w[lane] = x[wlo + lane];
+            }
+            wave_lds_sync();
+            if (valid) {
+                uint32_t lo = hown[q].x, hi = hown[q].y;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1u) >> 1;
+                    if (E_w[mid - wlo] <= e) lo = mid; else hi = mid - 1u;
+                }
+                uint32_t ii = lo;
+                double e0 = E_w[ii - wlo], e1 = E_w[ii + 1u - wlo];
+                double2 x0 = X_w[ii - wlo], x1 = X_w[ii + 1u - wlo];
+                if ((e < e0 && ii > 0u) || (e >= e1 && ii + 2u < mn.len)) {
+                    // hash bin computed one off: walk to the defined index
+                    while (ii > 0u && e < g[ii]) --ii;
+                    while (ii + 2u < mn.len && e >= g[ii + 1u]) ++ii;
+                    e0 = g[ii];
+                    e1 = g[ii + 1u];
+                    x0 = x[ii];
+                    x1 = x[ii + 1u];
+                }
+                const double f = (e - e0) / (e1 - e0);
+                c = x0.x + f * (x1.x - x0.x);
+                sg = x0.y + f * (x1.y - x0.y);
+            }
+            wave_lds_sync();
+        } else if (valid) {
+            const uint32_t ii = grid_find(g, mn.len, hown[q].x, hown[q].y, e);
+            lerp_xs(xs, mn.off, ii, e, c, sg);
+        }
+        if (valid) {
+            sa = sa + mn.dens * c;
+            ss = ss + mn.dens * sg;
+            const int32_t done = q + 1;
+            if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
+        }
+    }
+    if (!valid) return 0;
+    if (cp_sh != 30) cpw.finish(nk >> cp_sh);
+    if (a.Sa) a.Sa[p] = sa;
+    if (a.Ss) a.Ss[p] = ss;
+    if (a.flags) a.flags[p] = F_ALIVE;
+    return nk;
+}
+
 // DIAG: the per-nuclide outputs (idx_out, sc_out, ss_out) may be set; the
 // transport's lookups run without them, in fewer registers.  CHAN: the
 // reaction channels are assembled in the same pass (same index and fraction
 // per nuclide) into sx.
-template <int ILP, bool DIAG, bool CHAN>
+// WIN: sorted queues take window_lookups in staged workgroups.
+template <int ILP, bool DIAG, bool CHAN, bool WIN = false>
 __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 {
     __shared__ uint2 sh[LDS_HASH_PAIRS];
     __shared__ int32_t s_info[4];
+    __shared__ double s_we[WIN ? WG : 1];
+    __shared__ double2 s_wx[WIN ? WG : 1];
     const XsDev &xs = a.xs;
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
     const uint32_t i0 = blockIdx.x * WG;
@@ -514,7 +625,9 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
         __syncthreads();
     }
     int32_t nk_done = 0;
-    if (valid) {
+    if (WIN && staged) {
+        nk_done = window_lookups(a, sh, s_info, i, valid, s_we, s_wx);
+    } else if (valid) {
     const uint32_t p = a.list ? a.list[i] : i;
     const double e = a.E[p];
     int32_t m, b;
@@ -1396,10 +1509,14 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
         default: hipLaunchKernelGGL((k_lookup<4, true, false>), grid, dim3(WG), 0, st, a); break;
         }
     } else {
-        switch (l.ilp) {
-        case 1: hipLaunchKernelGGL((k_lookup<1, false, false>), grid, dim3(WG), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_lookup<2, false, false>), grid, dim3(WG), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_lookup<4, false, false>), grid, dim3(WG), 0, st, a); break;
+        if (a.keys) {  // sorted: staged workgroups read shared grid windows
+            hipLaunchKernelGGL((k_lookup<2, false, false, true>), grid, dim3(WG), 0, st, a);
+        } else {
+            switch (l.ilp) {
+            case 1: hipLaunchKernelGGL((k_lookup<1, false, false>), grid, dim3(WG), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_lookup<2, false, false>), grid, dim3(WG), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_lookup<4, false, false>), grid, dim3(WG), 0, st, a); break;
+            }
         }
     }
     return hipGetLastError();

@@ -176,5 +176,36 @@ def test_c3_scale_lookup_sampled(torch_cuda):
         ra, rs = oracle.macro_xs(op, m[sel], e[sel])
         ga, gs = Sa.cpu().numpy()[sel], Ss.cpu().numpy()[sel]
         assert np.max(np.abs(ga - ra) / ra) <= REL and np.max(np.abs(gs - rs) / rs) <= REL
+        # sorted queues read shared grid windows; unsorted ones search per lane:
+        # the same values bit for bit, all 1e6 of them
+        Sa2 = torch.empty(n, dtype=torch.float64, device="cuda")
+        Ss2 = torch.empty(n, dtype=torch.float64, device="cuda")
+        mc.mc_lookup_macro(t.ctx, torch.from_numpy(e).cuda(), torch.from_numpy(m).cuda(), Sa2, Ss2, False)
+        torch.cuda.synchronize()
+        assert torch.equal(Sa, Sa2) and torch.equal(Ss, Ss2)
     finally:
         t.close()
+
+
+def test_sorted_lookups_at_grid_points_and_bin_edges(c2, torch_cuda):
+    """Sorted queues dense in energy (every lane of a wave in one or two hash
+    bins): the fuel's grid points, their neighbours one ulp away and the hash
+    bin edges one ulp either side, each energy many times over, in all three
+    materials; equal to the oracle bit for bit."""
+    torch = torch_cuda
+    prob, t, op = c2
+    fuel = prob.materials[0].nuclides[:3]
+    pts = np.concatenate([prob.nuclides[k].E for k in fuel])
+    pts = pts[(pts > mcsynth.EMIN) & (pts < mcsynth.EMAX)][::7]
+    edges = mcsynth.EMIN * np.exp(np.arange(1, 8192) * np.log(mcsynth.EMAX / mcsynth.EMIN) / 8192)
+    base = np.concatenate([pts, np.nextafter(pts, 0), np.nextafter(pts, np.inf),
+                           np.nextafter(edges, 0), edges, np.nextafter(edges, np.inf)])
+    e = np.repeat(base, 3)
+    m = (np.arange(e.size) % 3).astype(np.int32)
+    _say(f"sorted edge lookups n={e.size}")
+    Sa = torch.empty(e.size, dtype=torch.float64, device="cuda")
+    Ss = torch.empty(e.size, dtype=torch.float64, device="cuda")
+    mc.mc_lookup_macro(t.ctx, torch.from_numpy(e).cuda(), torch.from_numpy(m).cuda(), Sa, Ss, True)
+    torch.cuda.synchronize()
+    ra, rs = oracle.macro_xs(op, m, e)
+    assert np.array_equal(Sa.cpu().numpy(), ra) and np.array_equal(Ss.cpu().numpy(), rs)
