@@ -491,14 +491,15 @@ int mc_set_tuning(mc_ctx *ctx, const mc_tuning *t);
 int mc_get_tuning(mc_ctx *ctx, mc_tuning *t);
 
 /*
- * Autotuner of the single-problem path: times mc_run_batches of n histories
- * per batch (pids from first_pid, key seed; 12 batches, 2 when n >= 2^22) per
- * candidate, per batch, searching one
- * parameter at a time (two sweeps) over tail_particles {8192, 32768, 131072,
- * 262144}, sort_min {4096, 16384, 65536, 262144, never}, lookup_ilp {1, 2, 4}
- * in_flight {n/4, n/2, 2^20, 2^22, n} (each at most n and 2^24; the
- * search starts from min(n, 2^22)), collide_sort_min {0, never} and loops
- * {1, 2, 3, 4}, keeps the fastest in the
+ * Autotuner of the single-problem path: times batches of n histories (pids
+ * from first_pid, key seed) per candidate, per batch: 12 through
+ * mc_run_batches, or for n >= 2^22 two single batches through mc_run_batch
+ * (how such batches run: one at a time, split over the loops), searching one
+ * parameter at a time (two sweeps, in this order) over loops {1, 2, 3, 4},
+ * tail_particles {8192, 32768, 131072, 262144}, sort_min {4096, 16384,
+ * 65536, 262144, never}, lookup_ilp {1, 2, 4}, in_flight {n/4, n/3, n/2,
+ * 2^20, 2^22, n} (each at most n and 2^24; the search starts from
+ * min(n, 2^22)) and collide_sort_min {0, never}, keeps the fastest in the
  * context (mc_set_tuning) and returns it in *best.  The tallies are reset afterwards.  cache_path (nullable) names a
  * text file of one line per tuned problem: when it holds the signature of
  * this problem and device, the stored setting is used without timing; else

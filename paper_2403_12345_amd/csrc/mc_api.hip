@@ -2315,13 +2315,25 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kMaxTunedInFlight);
     cur.in_flight = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
     cur.collide_sort_min = 0;  // follows sort_min unless the search turns it off
-    // each trial: a few batches through mc_run_batches (so that loops > 1
-    // shows its overlap of consecutive batches), timed per batch
-    const uint64_t trial_batches = n >= (1ull << 22) ? 2 : 12;  // 12: whole rounds for 1 to 4 loops
+    // each trial, timed per batch: 12 batches through mc_run_batches (whole
+    // rounds for 1 to 4 loops, so that loops > 1 shows its overlap of
+    // consecutive batches); batches of 2^22 histories or more are run one at
+    // a time, as mc_run_batch runs them (split over the loops), twice
+    const bool single = n >= (1ull << 22);
     auto trial = [&](const mc_tuning &c, double &ms) -> int {
         ctx->tune = c;
-        const int r = mc_run_batches(ctx, seed, first_pid, n, trial_batches, nullptr);
-        ms = ctx->stats.batch_ms / (double)trial_batches;
+        if (single) {
+            double tot = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                const int r = mc_run_batch(ctx, seed, first_pid, n, nullptr);
+                if (r) return r;
+                tot += ctx->stats.batch_ms;
+            }
+            ms = tot / 2.0;
+            return MC_OK;
+        }
+        const int r = mc_run_batches(ctx, seed, first_pid, n, 12, nullptr);
+        ms = ctx->stats.batch_ms / 12.0;
         return r;
     };
     double best_ms = 0.0;
@@ -2331,12 +2343,15 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t ilps[] = {1, 2, 4};
     const int32_t tails[] = {8192, 32768, 131072, 262144};
     const int32_t sorts[] = {4096, 16384, 65536, 262144, (int32_t)kSortNever};
-    const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 2), 1 << 20, 1 << 22, n_cap};
+    // per loop: a quarter, a third or half of the batch (so 4, 3 or 2 loops
+    // hold it all in flight at once), fixed sizes, the whole batch
+    const int32_t flights[] = {std::max(1024, n_cap / 4), std::max(1024, n_cap / 3), std::max(1024, n_cap / 2),
+                               1 << 20, 1 << 22, n_cap};
     const int32_t csorts[] = {0, (int32_t)kSortNever};
     const int32_t loops[] = {1, 2, 3, 4};
     // the loop count first: whether a sort pays depends on what overlaps it
     const int32_t *axes[] = {loops, tails, sorts, ilps, flights, csorts};
-    const int counts[] = {4, 4, 5, 3, 5, 2};
+    const int counts[] = {4, 4, 5, 3, 6, 2};
     for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
         for (int axis = 0; axis < 6 && !rc; ++axis) {
             for (int k = 0; k < counts[axis] && !rc; ++k) {
