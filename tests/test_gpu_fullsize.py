@@ -3,9 +3,9 @@ the oracle can afford one by one and on properties that hold at any size.
 
 * 17x17 lattice: one batch of 1e6 histories through the batched entry point
   (mc_run_batches) with the autotuner's shapes from the committed cache
-  (several event loops of 250k particles in flight, the one-launch tail).
+  (several event loops running consecutive batches, the one-launch tail).
 * 300-nuclide 255x255 lattice: one batch of 2e7 histories with its tuned
-  shapes (8M in flight, sorted lookup queues), mesh flux tally.
+  shapes (millions in flight, sorted lookup queues), mesh flux tally.
 * Sampled pids at the start, middle and end of each batch against the
   oracle's histories of the same pids: fate, draws and final energy equal for
   at least 90 % (with geometry the device and host logarithms may differ in
