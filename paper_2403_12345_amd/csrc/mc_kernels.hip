@@ -525,17 +525,39 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     const int32_t cp_mask = (1 << cp_sh) - 1;
     CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
     double sa = 0.0, ss = 0.0;
+    // nuclide q's window: first point and count (wave-uniform), and this
+    // lane's point of it, loaded one nuclide ahead so that the loads of the
+    // next window are in flight while the lanes search the current one
+    MatNuc mn_n = xs.mnuc[q0];
+    uint32_t wlo_n = __builtin_amdgcn_readfirstlane(hmin[0].x);
+    uint32_t wn_n = __builtin_amdgcn_readfirstlane(hmax[0].y) + 2u - wlo_n;  // points wlo .. wlo + wn - 1
+    double pe = 0.0;
+    double2 px = make_double2(0.0, 0.0);
+    if (wn_n <= (uint32_t)WIN_PTS && lane < wn_n) {
+        pe = xs.Eg[mn_n.off + wlo_n + lane];
+        px = xs.xs[mn_n.off + wlo_n + lane];
+    }
     for (int32_t q = 0; q < nk; ++q) {
-        const MatNuc mn = xs.mnuc[q0 + q];
+        const MatNuc mn = mn_n;
+        const uint32_t wlo = wlo_n, wn = wn_n;
+        const double ce = pe;
+        const double2 cx = px;
+        if (q + 1 < nk) {
+            mn_n = xs.mnuc[q0 + q + 1];
+            wlo_n = __builtin_amdgcn_readfirstlane(hmin[q + 1].x);
+            wn_n = __builtin_amdgcn_readfirstlane(hmax[q + 1].y) + 2u - wlo_n;
+            if (wn_n <= (uint32_t)WIN_PTS && lane < wn_n) {
+                pe = xs.Eg[mn_n.off + wlo_n + lane];
+                px = xs.xs[mn_n.off + wlo_n + lane];
+            }
+        }
         const double *g = xs.Eg + mn.off;
         const double2 *x = xs.xs + mn.off;
-        const uint32_t wlo = __builtin_amdgcn_readfirstlane(hmin[q].x);
-        const uint32_t wn = __builtin_amdgcn_readfirstlane(hmax[q].y) + 2u - wlo;  // points wlo .. wlo + wn - 1
         double c = 0.0, sg = 0.0;
         if (wn <= (uint32_t)WIN_PTS) {
             if (lane < wn) {
-                E_w[lane] = g[wlo + lane];
-                X_w[lane] = x[wlo + lane];
+                E_w[lane] = ce;
+                X_w[lane] = cx;
             }
             wave_lds_sync();
             if (valid) {
