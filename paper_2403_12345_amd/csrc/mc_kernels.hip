@@ -495,8 +495,10 @@ __device__ __forceinline__ void wave_lds_sync()
 // each lane searching global memory.  Per nuclide a wave then issues two
 // vector loads instead of one per bracket, probe and interval point.  Same
 // interval (with the one-off-bin walk), interpolation and sums in material
-// order as micro_group: the results bit for bit.  Returns the nuclides looked
-// up for this lane.
+// order as micro_group: the results bit for bit.  CHAN: the reaction
+// channels are assembled from the interval found (rows read per lane), as
+// channel_group does.  Returns the nuclides looked up for this lane.
+template <bool CHAN>
 __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uint2 *sh, const int32_t *s_info,
                                                   uint32_t i, bool valid, double *we, double2 *wx)
 {
@@ -525,6 +527,11 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     const int32_t cp_mask = (1 << cp_sh) - 1;
     CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
     double sa = 0.0, ss = 0.0;
+    double acc[MAX_CHAN];
+    if (CHAN) {
+#pragma unroll
+        for (int xc = 0; xc < MAX_CHAN; ++xc) acc[xc] = 0.0;
+    }
     // nuclide q's window: first point and count (wave-uniform), and this
     // lane's point of it, loaded one nuclide ahead so that the loads of the
     // next window are in flight while the lanes search the current one
@@ -553,7 +560,8 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
         }
         const double *g = xs.Eg + mn.off;
         const double2 *x = xs.xs + mn.off;
-        double c = 0.0, sg = 0.0;
+        double c = 0.0, sg = 0.0, f = 0.0;
+        uint32_t ii = 0;
         if (wn <= (uint32_t)WIN_PTS) {
             if (lane < wn) {
                 E_w[lane] = ce;
@@ -566,7 +574,7 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                     const uint32_t mid = (lo + hi + 1u) >> 1;
                     if (E_w[mid - wlo] <= e) lo = mid; else hi = mid - 1u;
                 }
-                uint32_t ii = lo;
+                ii = lo;
                 double e0 = E_w[ii - wlo], e1 = E_w[ii + 1u - wlo];
                 double2 x0 = X_w[ii - wlo], x1 = X_w[ii + 1u - wlo];
                 if ((e < e0 && ii > 0u) || (e >= e1 && ii + 2u < mn.len)) {
@@ -578,16 +586,28 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                     x0 = x[ii];
                     x1 = x[ii + 1u];
                 }
-                const double f = (e - e0) / (e1 - e0);
+                f = (e - e0) / (e1 - e0);
                 c = x0.x + f * (x1.x - x0.x);
                 sg = x0.y + f * (x1.y - x0.y);
             }
             wave_lds_sync();
         } else if (valid) {
-            const uint32_t ii = grid_find(g, mn.len, hown[q].x, hown[q].y, e);
-            lerp_xs(xs, mn.off, ii, e, c, sg);
+            ii = grid_find(g, mn.len, hown[q].x, hown[q].y, e);
+            const double e0 = g[ii], e1 = g[ii + 1u];
+            const double2 x0 = x[ii], x1 = x[ii + 1u];
+            f = (e - e0) / (e1 - e0);
+            c = x0.x + f * (x1.x - x0.x);
+            sg = x0.y + f * (x1.y - x0.y);
         }
         if (valid) {
+            if (CHAN) {
+                const int32_t K = xs.n_chan;
+                const double *r0 = xs.xc + (size_t)(mn.off + ii) * (size_t)K;
+                const double *r1 = r0 + K;
+#pragma unroll
+                for (int xc = 0; xc < MAX_CHAN; ++xc)
+                    if (xc < K) acc[xc] = acc[xc] + mn.dens * (r0[xc] + f * (r1[xc] - r0[xc]));
+            }
             sa = sa + mn.dens * c;
             ss = ss + mn.dens * sg;
             const int32_t done = q + 1;
@@ -598,6 +618,11 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     if (cp_sh != 30) cpw.finish(nk >> cp_sh);
     if (a.Sa) a.Sa[p] = sa;
     if (a.Ss) a.Ss[p] = ss;
+    if (CHAN) {
+#pragma unroll
+        for (int xc = 0; xc < MAX_CHAN; ++xc)
+            if (xc < xs.n_chan) a.sx[(size_t)p * xs.n_chan + xc] = acc[xc];
+    }
     if (a.flags) a.flags[p] = F_ALIVE;
     return nk;
 }
@@ -648,7 +673,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     }
     int32_t nk_done = 0;
     if (WIN && staged) {
-        nk_done = window_lookups(a, sh, s_info, i, valid, s_we, s_wx);
+        nk_done = window_lookups<CHAN>(a, sh, s_info, i, valid, s_we, s_wx);
     } else if (valid) {
     const uint32_t p = a.list ? a.list[i] : i;
     const double e = a.E[p];
@@ -1522,7 +1547,8 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
         default: hipLaunchKernelGGL(k_lookup_union<4>, grid, dim3(WG), 0, st, a); break;
         }
     } else if (a.sx && l.xs.n_chan > 0) {  // channels: at most two nuclides in lockstep (registers)
-        if (l.ilp == 1) hipLaunchKernelGGL((k_lookup<1, false, true>), grid, dim3(WG), 0, st, a);
+        if (a.keys) hipLaunchKernelGGL((k_lookup<2, false, true, true>), grid, dim3(WG), 0, st, a);
+        else if (l.ilp == 1) hipLaunchKernelGGL((k_lookup<1, false, true>), grid, dim3(WG), 0, st, a);
         else hipLaunchKernelGGL((k_lookup<2, false, true>), grid, dim3(WG), 0, st, a);
     } else if (a.idx_out || a.sc_out || a.ss_out) {
         switch (l.ilp) {
