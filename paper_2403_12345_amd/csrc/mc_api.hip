@@ -1020,7 +1020,7 @@ static int alloc_sort(mc_ctx *ctx, Buffers &B, SortBufs &sb, size_t n)
     const size_t tiles = sort_tile_count(n), chunks = sort_chunk_count(n);
     if (!rc) rc = dalloc(ctx, B, &sb.tile_hist, tiles * 256);
     if (!rc) rc = dalloc(ctx, B, &sb.chunk_total, chunks * 256);
-    if (!rc) rc = dalloc(ctx, B, &sb.chunk_off, chunks * 256);
+    if (!rc) rc = dalloc(ctx, B, &sb.chunk_off, (chunks + 1) * 256);  // + the digit bases
     if (!rc) HIPCHK(hipMemset(sb.chunk_total, 0, chunks * 256 * sizeof(uint32_t)));
     return rc;
 }

@@ -39,7 +39,7 @@ struct SortBufs {
     uint32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr;
     uint32_t *tile_hist = nullptr;    // [tiles][256]
     uint32_t *chunk_total = nullptr;  // [chunks][256], kept zero between sorts
-    uint32_t *chunk_off = nullptr;    // [chunks][256]
+    uint32_t *chunk_off = nullptr;    // [chunks + 1][256]: per-chunk offsets, then the digit bases
 };
 // Windowed-multipole macroscopic cross sections of n (energy, material) pairs.
 hipError_t launch_lookup_mp(const MpDev &mp, uint32_t n, const double *E, const int32_t *mat, double *Sa,

@@ -328,7 +328,7 @@ struct SortPassArgs {
     uint32_t *keys_out, *vals_out;
     uint32_t *tile_hist;       // [tiles][256]
     uint32_t *chunk_total;     // [chunks][256], zero on entry of a count
-    const uint32_t *chunk_off; // [chunks][256]
+    const uint32_t *chunk_off; // [chunks + 1][256] (see k_radix_scan)
 };
 
 __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
@@ -361,13 +361,15 @@ __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
     if (c) atomicAdd(&a.chunk_total[(blockIdx.x / a.chunk) * 256 + threadIdx.x], c);
 }
 
-// chunk_off[c][d] = (items with digit < d) + (items of digit d in chunks < c);
-// resets chunk_total for the next pass.  One workgroup, thread = digit.
+// chunk_off[c][d] = items of digit d in chunks < c, and in the row after the
+// last chunk, chunk_off[n_chunks][d] = items with digit < d (the scatter adds
+// the two); resets chunk_total for the next pass.  One workgroup, thread =
+// digit, one pass over the chunk totals.
 __global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32_t *chunk_off, uint32_t n_chunks)
 {
     __shared__ uint32_t tot[256];
     const uint32_t d = threadIdx.x;
-    constexpr uint32_t B = 8;  // chunk totals loaded together (independent loads in flight)
+    constexpr uint32_t B = 16;  // chunk totals loaded together (independent loads in flight)
     uint32_t run = 0;
     for (uint32_t c0 = 0; c0 < n_chunks; c0 += B) {
         uint32_t v[B];
@@ -391,15 +393,7 @@ __global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32
         tot[d] += v;
         __syncthreads();
     }
-    const uint32_t base = tot[d] - run;
-    for (uint32_t c0 = 0; c0 < n_chunks; c0 += B) {
-        uint32_t v[B];
-#pragma unroll
-        for (uint32_t k = 0; k < B; ++k) v[k] = c0 + k < n_chunks ? chunk_off[(c0 + k) * 256 + d] : 0u;
-#pragma unroll
-        for (uint32_t k = 0; k < B; ++k)
-            if (c0 + k < n_chunks) chunk_off[(c0 + k) * 256 + d] = v[k] + base;
-    }
+    chunk_off[n_chunks * 256 + d] = tot[d] - run;
 }
 
 __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
@@ -411,8 +405,16 @@ __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
     if (base >= n) return;
     const uint32_t t = blockIdx.x, c0 = (t / a.chunk) * a.chunk;
     {
-        uint32_t o = a.chunk_off[(t / a.chunk) * 256 + threadIdx.x];
-        for (uint32_t u = c0; u < t; ++u) o += a.tile_hist[u * 256 + threadIdx.x];
+        const uint32_t n_chunks = (gridDim.x + a.chunk - 1) / a.chunk;
+        uint32_t o = a.chunk_off[(t / a.chunk) * 256 + threadIdx.x] + a.chunk_off[n_chunks * 256 + threadIdx.x];
+        // the chunk's earlier tiles, their histograms loaded 8 at a time
+        for (uint32_t u0 = c0; u0 < t; u0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) v[k] = u0 + k < t ? a.tile_hist[(u0 + k) * 256 + threadIdx.x] : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) o += v[k];
+        }
         off[threadIdx.x] = o;
     }
     const int wave = threadIdx.x >> 6;
