@@ -474,8 +474,10 @@ struct LookupArgs {
 
 constexpr int LDS_HASH_PAIRS = 2048;  // 16 KiB of staged hash brackets
 
-// Grid points a wave stages per nuclide for a sorted queue (see window_lookups).
+// Grid points a wave stages per nuclide for a sorted queue (see window_lookups),
+// and reaction-channel values (window points * channels).
 constexpr int WIN_PTS = 64;
+constexpr int WIN_CHAN = 512;
 
 // Orders a wave's LDS writes before its reads of them (and reads before the
 // next writes): LDS instructions of one wave execute in program order, so only
@@ -498,11 +500,23 @@ __device__ __forceinline__ void wave_lds_sync()
 // vector loads instead of one per bracket, probe and interval point.  Same
 // interval (with the one-off-bin walk), interpolation and sums in material
 // order as micro_group: the results bit for bit.  CHAN: the reaction
-// channels are assembled from the interval found (rows read per lane), as
-// channel_group does.  Returns the nuclides looked up for this lane.
+// channels are assembled from the interval found, as channel_group does; the
+// window's channel rows are staged in LDS too when they fit in WIN_CHAN
+// values, else each lane reads its two rows.  Returns the nuclides looked up
+// for this lane.
+template <bool CHAN>
+__device__ __forceinline__ void window_channels(const double *r0, int32_t K, double dens, double f,
+                                                double (&acc)[MAX_CHAN])
+{
+    const double *r1 = r0 + K;
+#pragma unroll
+    for (int xc = 0; xc < MAX_CHAN; ++xc)
+        if (xc < K) acc[xc] = acc[xc] + dens * (r0[xc] + f * (r1[xc] - r0[xc]));
+}
+
 template <bool CHAN>
 __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uint2 *sh, const int32_t *s_info,
-                                                  uint32_t i, bool valid, double *we, double2 *wx)
+                                                  uint32_t i, bool valid, double *we, double2 *wx, double *wc)
 {
     const XsDev &xs = a.xs;
     const uint64_t vmask = __ballot(valid);
@@ -525,6 +539,8 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     const uint32_t lane = (uint32_t)lane_id();
     double *E_w = we + (threadIdx.x & ~63u);
     double2 *X_w = wx + (threadIdx.x & ~63u);
+    double *C_w = wc + (CHAN ? (threadIdx.x >> 6) * WIN_CHAN : 0);
+    const int32_t K = CHAN ? xs.n_chan : 0;
     const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
     const int32_t cp_mask = (1 << cp_sh) - 1;
     CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
@@ -565,6 +581,24 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
         double c = 0.0, sg = 0.0, f = 0.0;
         uint32_t ii = 0;
         if (wn <= (uint32_t)WIN_PTS) {
+            const uint32_t nc = CHAN ? wn * (uint32_t)K : 0u;
+            const bool cwin = CHAN && nc <= (uint32_t)WIN_CHAN;
+            if (cwin) {  // the window's channel rows: contiguous, 4 loads per lane at a time
+                const double *src = xs.xc + (size_t)(mn.off + wlo) * (size_t)K;
+                for (uint32_t j0 = 0; j0 < nc; j0 += 256u) {
+                    double v[4];
+#pragma unroll
+                    for (uint32_t r = 0; r < 4; ++r) {
+                        const uint32_t j = j0 + r * 64u + lane;
+                        v[r] = j < nc ? src[j] : 0.0;
+                    }
+#pragma unroll
+                    for (uint32_t r = 0; r < 4; ++r) {
+                        const uint32_t j = j0 + r * 64u + lane;
+                        if (j < nc) C_w[j] = v[r];
+                    }
+                }
+            }
             if (lane < wn) {
                 E_w[lane] = ce;
                 X_w[lane] = cx;
@@ -591,6 +625,12 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                 f = (e - e0) / (e1 - e0);
                 c = x0.x + f * (x1.x - x0.x);
                 sg = x0.y + f * (x1.y - x0.y);
+                if (CHAN) {
+                    if (cwin && ii >= wlo && ii + 1u < wlo + wn)
+                        window_channels<CHAN>(C_w + (size_t)(ii - wlo) * (size_t)K, K, mn.dens, f, acc);
+                    else
+                        window_channels<CHAN>(xs.xc + (size_t)(mn.off + ii) * (size_t)K, K, mn.dens, f, acc);
+                }
             }
             wave_lds_sync();
         } else if (valid) {
@@ -600,16 +640,9 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
             f = (e - e0) / (e1 - e0);
             c = x0.x + f * (x1.x - x0.x);
             sg = x0.y + f * (x1.y - x0.y);
+            if (CHAN) window_channels<CHAN>(xs.xc + (size_t)(mn.off + ii) * (size_t)K, K, mn.dens, f, acc);
         }
         if (valid) {
-            if (CHAN) {
-                const int32_t K = xs.n_chan;
-                const double *r0 = xs.xc + (size_t)(mn.off + ii) * (size_t)K;
-                const double *r1 = r0 + K;
-#pragma unroll
-                for (int xc = 0; xc < MAX_CHAN; ++xc)
-                    if (xc < K) acc[xc] = acc[xc] + mn.dens * (r0[xc] + f * (r1[xc] - r0[xc]));
-            }
             sa = sa + mn.dens * c;
             ss = ss + mn.dens * sg;
             const int32_t done = q + 1;
@@ -641,6 +674,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     __shared__ int32_t s_info[4];
     __shared__ double s_we[WIN ? WG : 1];
     __shared__ double2 s_wx[WIN ? WG : 1];
+    __shared__ double s_wc[(WIN && CHAN) ? WAVES * WIN_CHAN : 1];
     const XsDev &xs = a.xs;
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
     const uint32_t i0 = blockIdx.x * WG;
@@ -675,7 +709,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     }
     int32_t nk_done = 0;
     if (WIN && staged) {
-        nk_done = window_lookups<CHAN>(a, sh, s_info, i, valid, s_we, s_wx);
+        nk_done = window_lookups<CHAN>(a, sh, s_info, i, valid, s_we, s_wx, s_wc);
     } else if (valid) {
     const uint32_t p = a.list ? a.list[i] : i;
     const double e = a.E[p];
