@@ -147,10 +147,25 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
 // deterministic workgroup accumulation (no atomics)
 // ---------------------------------------------------------------------------
 // Adds val into bin `bin` (< 0: nothing) of the workgroup's row.  Each wave
-// peels off one distinct bin at a time: the lanes holding it are summed by the
-// butterfly and the first of them adds the sum into the wave's LDS slab; the
-// slabs are then added in wave order into the row.  Every thread of the
+// peels off one distinct bin at a time: the values of the lanes holding it
+// are added in lane order when they are few (cheaper than a butterfly over
+// all 64), by the butterfly when they are many, and the first of them adds
+// the sum into the wave's LDS slab;
+// the slabs are then added in wave order into the row.  Every thread of the
 // workgroup must call it.
+__device__ __forceinline__ double lanes_sum(double v, uint64_t lanes)
+{
+    // many lanes (a material's rates, one bin per wave): the butterfly
+    if (__popcll(lanes) > 8) return wave_sum(((lanes >> lane_id()) & 1ull) ? v : 0.0);
+    double s = 0.0;
+    while (lanes) {
+        const int j = __ffsll((long long)lanes) - 1;
+        s = s + __shfl(v, j, 64);
+        lanes &= lanes - 1ull;
+    }
+    return s;
+}
+
 __device__ inline void wg_bin_add(int32_t bin, double val, double *slab, int32_t nbins, double *row)
 {
     for (int32_t t = threadIdx.x; t < WAVES * nbins; t += WG) slab[t] = 0.0;
@@ -162,7 +177,7 @@ __device__ inline void wg_bin_add(int32_t bin, double val, double *slab, int32_t
         const int leader = __ffsll((long long)mask) - 1;
         const int32_t B = __shfl(bin, leader, 64);
         const bool mine = active && bin == B;
-        const double s = wave_sum(mine ? val : 0.0);
+        const double s = lanes_sum(val, __ballot(mine));
         if (lane_id() == leader) slab[wave * nbins + B] += s;
         active = active && !mine;
         mask = __ballot(active);
@@ -210,8 +225,9 @@ __device__ inline void wg_chan_add(int32_t mat, double wd, const double *sx, int
         const int leader = __ffsll((long long)mask) - 1;
         const int32_t M = __shfl(mat, leader, 64);
         const bool mine = active && mat == M;
+        const uint64_t lanes = __ballot(mine);
         for (int32_t x = 0; x < K; ++x) {
-            const double s = wave_sum(mine ? wd * sx[x] : 0.0);
+            const double s = lanes_sum(wd * sx[x], lanes);
             if (lane_id() == leader) slab[wave * nb + M * K + x] += s;
         }
         active = active && !mine;
