@@ -536,11 +536,35 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // Butterfly sum over the wave: every lane ends with the same bits, because at
 // each stage partners add the same two values (commutativity).
+// Lane j's value (j the same in every lane) in every lane.
+__device__ __forceinline__ double lane_f64(double v, int j)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), j),
+                            __builtin_amdgcn_readlane(__double2loint(v), j));
+}
+
+// One DPP step on a double: lane i receives the value the control selects
+// (0 where the row/bank mask or the pattern gives it none).
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, BANKS, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, BANKS, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a converged wave, the same value in every lane: a
+// fixed tree of DPP steps (quad sums, rows, then rows 0+1 and 2+3 into lane
+// 63), read from lane 63.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = v + __shfl_xor(v, o, 64);
-    return v;
+    v = v + dpp_f64<0xb1, 0xf, 0xf>(v);   // quad_perm 1,0,3,2
+    v = v + dpp_f64<0x4e, 0xf, 0xf>(v);   // quad_perm 2,3,0,1: quad sums
+    v = v + dpp_f64<0x114, 0xf, 0xe>(v);  // row_shr 4 into banks 1-3
+    v = v + dpp_f64<0x118, 0xf, 0xc>(v);  // row_shr 8 into banks 2-3: row sum in lane 15 of each row
+    v = v + dpp_f64<0x142, 0xa, 0xf>(v);  // row_bcast 15 into rows 1, 3
+    v = v + dpp_f64<0x143, 0xc, 0xf>(v);  // row_bcast 31 into rows 2, 3: the sum in lane 63
+    return lane_f64(v, 63);
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)

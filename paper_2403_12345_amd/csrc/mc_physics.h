@@ -160,7 +160,7 @@ __device__ __forceinline__ double lanes_sum(double v, uint64_t lanes)
     double s = 0.0;
     while (lanes) {
         const int j = __ffsll((long long)lanes) - 1;
-        s = s + __shfl(v, j, 64);
+        s = s + lane_f64(v, j);
         lanes &= lanes - 1ull;
     }
     return s;
