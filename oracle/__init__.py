@@ -105,12 +105,15 @@ def lib():
         _lib.orc_ln_importance_source.argtypes = [P(_Problem)]
         _lib.orc_ln_importance_source.restype = D
         _lib.orc_run.restype = C.c_int
+        _lib.orc_run_scatter_stats.argtypes = [P(_Problem), C.c_uint64, C.c_uint64, C.c_uint64, P(D), C.c_int]
+        _lib.orc_run_scatter_stats.restype = C.c_int
         _lib.orc_max_threads.restype = C.c_int
         _lib.orc_micro_xs_many.argtypes = [P(_Problem), C.c_int32, C.c_int64, P(D), P(C.c_int64), P(D), P(D)]
         _lib.orc_macro_xs_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D), P(D)]
         _lib.orc_macro_channels_many.argtypes = [P(_Problem), C.c_int64, P(C.c_int32), P(D), P(D)]
         _lib.orc_faddeeva_init.argtypes = []
         _lib.orc_faddeeva_many.argtypes = [C.c_int64, P(D), P(D), P(D), P(D)]
+        _lib.orc_faddeeva_coeffs.argtypes = [P(D), P(D)]
         _lib.orc_mp_macro_many.argtypes = [P(_MpNuclide), P(D), C.c_int32, P(C.c_int32), P(D), D, C.c_int64,
                                            P(D), P(D), P(D)]
         _lib.orc_faddeeva_init()
@@ -201,6 +204,7 @@ class OracleProblem:
         c.n_chan = self.n_chan
         c.chan = _dptr(self.chan)
         self.n_mat = len(mats)
+        self.n_nuc = len(nucs)
         self.c = c
         self.n_cells = prob.imp.cells
         self.n_bins = prob.n_bins
@@ -269,6 +273,15 @@ def faddeeva(z):
     wr, wi = np.empty(z.size), np.empty(z.size)
     lib().orc_faddeeva_many(z.size, _dptr(zr), _dptr(zi), _dptr(wr), _dptr(wi))
     return wr + 1j * wi
+
+
+def faddeeva_coeffs():
+    """(L, a[0..N-1]) of the oracle's rational series for w(z): the constants a
+    rounding bound of a pole term needs."""
+    L = C.c_double()
+    a = np.empty(32)
+    lib().orc_faddeeva_coeffs(C.byref(L), _dptr(a))
+    return float(L.value), a
 
 
 def multipole_macro(nucs, mat_ids, dens, T: float, energies):
@@ -344,6 +357,17 @@ def run(op: OracleProblem, seed: int, first_pid: int, n: int, history: bool = Fa
     return RunResult(n=n, tl=tl, coll=coll, glob=glob, history=hist,
                      imp=imp.reshape(3, -1) if imp is not None else None,
                      rr=rr.reshape(op.n_mat, op.n_chan) if rr is not None else None)
+
+
+def scatter_stats(op: OracleProblem, seed: int, first_pid: int, n: int, threads: int = 0) -> np.ndarray:
+    """Per target nuclide k of the collisions of histories [first_pid,
+    first_pid + n): row k = (scatterings on k, sum of ln(E / E') over them).
+    Test statistics of the target selection; the tallies are discarded."""
+    ns = np.zeros(2 * op.n_nuc)
+    rc = lib().orc_run_scatter_stats(op.ref(), seed, first_pid, n, _dptr(ns), threads)
+    if rc != 0:
+        raise MemoryError("oracle run failed")
+    return ns.reshape(-1, 2)
 
 
 def bf16(x: float) -> float:

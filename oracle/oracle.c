@@ -24,6 +24,7 @@
  *
  * Exported functions use the prefix orc_.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -679,6 +680,8 @@ typedef struct {
 typedef struct {
     double *tl, *coll, *glob, *imp; /* imp: num[nc], den[nc], cnt[nc] */
     double *rr;                     /* reaction rates [n_mat][n_chan] (track length) */
+    double *ns;                     /* test statistics per target nuclide [n_nuc][2]:
+                                       scatterings, sum of ln(E / E') (nullable) */
 } scores;
 
 static int64_t imp_cell(const orc_problem *p, double x, double E)
@@ -852,11 +855,21 @@ static void track_history(const orc_problem *p, uint64_t seed, uint64_t pid, sco
                 if (term > 0.0) nuc = p->mat_nuc[qq];
                 if (cum >= target && term > 0.0) break;
             }
+            if (nuc < 0) {
+                /* no nuclide scatters although the particle was not captured:
+                 * Sigma_s = 0 and Sigma_a = 0 at once; the history cannot go on */
+                fate = FATE_LOST;
+                goto dead;
+            }
             double mu_cm = 2.0 * next_u(&c.rs) - 1.0;
             double phi = 2.0 * M_PI * next_u(&c.rs);
             double e_out, mu_lab;
             orc_elastic(p->awr[nuc], c.q.E, mu_cm, &e_out, &mu_lab);
             orc_rotate(c.q.d, mu_lab, phi);
+            if (sc.ns) {
+                sc.ns[2 * nuc] += 1.0;
+                sc.ns[2 * nuc + 1] += log(c.q.E / e_out);
+            }
             c.q.E = e_out;
         }
         if (c.q.E < p->e_cut) {
@@ -927,8 +940,9 @@ double orc_ln_importance_source(const orc_problem *p)
  * The pids are split into at most 64 contiguous blocks, each tracked in pid
  * order by one thread and summed in block order, so the result does not
  * depend on the thread count.  hist (nullable) receives one record per pid. */
-int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *tl,
-            double *coll, double *glob, double *imp, double *rr, orc_history *hist, int n_threads)
+static int run_blocks(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *tl,
+                      double *coll, double *glob, double *imp, double *rr, double *ns, orc_history *hist,
+                      int n_threads)
 {
     int64_t nb = tally_bins(p);
     int64_t ni = imp ? 3 * imp_cells(p) : 0;
@@ -938,7 +952,8 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n,
     if (p->ww_kind && (p->ww_depth > WW_MAX_DEPTH || p->ww_depth < 0)) return -2;
     int64_t n_blocks = n < 64 ? (int64_t)n : 64;
     if (n_blocks == 0) return 0;
-    int64_t stride = nb * 2 + N_GLOBAL + ni + nr;
+    int64_t nn = ns ? 2 * (int64_t)p->n_nuc : 0;
+    int64_t stride = nb * 2 + N_GLOBAL + ni + nr + nn;
     double *part = (double *)calloc((size_t)(n_blocks * stride), sizeof(double));
     if (!part) return -1;
     const double ln_src = p->ww_kind ? orc_ln_importance_source(p) : 0.0;
@@ -951,7 +966,7 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n,
         uint64_t hi = (uint64_t)(b + 1) * n / (uint64_t)n_blocks;
         double *t = part + b * stride;
         scores sc = {t, t + nb, t + 2 * nb, imp ? t + 2 * nb + N_GLOBAL : NULL,
-                     nr ? t + 2 * nb + N_GLOBAL + ni : NULL};
+                     nr ? t + 2 * nb + N_GLOBAL + ni : NULL, nn ? t + 2 * nb + N_GLOBAL + ni + nr : NULL};
         for (uint64_t i = lo; i < hi; ++i) track_history(p, seed, first_pid + i, sc, ln_src, hist ? hist + i : NULL);
     }
     for (int64_t b = 0; b < n_blocks; ++b) {
@@ -960,9 +975,31 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n,
         for (int k = 0; k < N_GLOBAL; ++k) glob[k] += t[2 * nb + k];
         for (int64_t k = 0; k < ni; ++k) imp[k] += t[2 * nb + N_GLOBAL + k];
         for (int64_t k = 0; k < nr; ++k) rr[k] += t[2 * nb + N_GLOBAL + ni + k];
+        for (int64_t k = 0; k < nn; ++k) ns[k] += t[2 * nb + N_GLOBAL + ni + nr + k];
     }
     free(part);
     return 0;
+}
+
+int orc_run(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *tl,
+            double *coll, double *glob, double *imp, double *rr, orc_history *hist, int n_threads)
+{
+    return run_blocks(p, seed, first_pid, n, tl, coll, glob, imp, rr, NULL, hist, n_threads);
+}
+
+/* Test statistics of the collision's target selection and kinematics: the
+ * same run as orc_run (scores discarded), adding per target nuclide k the
+ * number of scatterings ns[2k] and the sum of their lethargy gains
+ * ln(E / E') into ns[2k + 1]. */
+int orc_run_scatter_stats(const orc_problem *p, uint64_t seed, uint64_t first_pid, uint64_t n, double *ns,
+                          int n_threads)
+{
+    int64_t nb = tally_bins(p);
+    double *tl = (double *)calloc((size_t)(2 * nb + N_GLOBAL + 1), sizeof(double));
+    if (!tl) return -1;
+    int rc = run_blocks(p, seed, first_pid, n, tl, tl + nb, tl + 2 * nb, NULL, NULL, ns, NULL, n_threads);
+    free(tl);
+    return rc;
 }
 
 int orc_max_threads(void)
@@ -1036,28 +1073,26 @@ void orc_faddeeva_init(void)
 
 void orc_faddeeva(double zr, double zi, double *wr, double *wi)
 {
-    const double L = orc_wL;
-    /* d = L - i z = (L + zi) - i zr;  Z = (L + i z) / d = ((L - zi) + i zr) / d */
-    const double dr = L + zi, di = -zr;
-    const double nr = L - zi, ni = zr;
-    const double dd = dr * dr + di * di;
-    const double rdd = 1.0 / dd;
-    const double Zr = (nr * dr + ni * di) * rdd, Zi = (ni * dr - nr * di) * rdd;
-    /* Horner from a_N down to a_1, each step p = p Z + a_n with fused
-     * multiply-adds (the evaluation order of the series is ours to fix) */
-    double pr = orc_wa[ORC_WN], pi_ = 0.0;
-    for (int n = ORC_WN - 1; n >= 1; --n) {
-        const double tr = fma(pr, Zr, fma(-pi_, Zi, orc_wa[n]));
-        const double ti = fma(pr, Zi, pi_ * Zr);
-        pr = tr;
-        pi_ = ti;
+    /* the series as written, in complex arithmetic: powers Z^(n-1) built up
+     * from n = 1 and the terms added in that order */
+    const double complex z = CMPLX(zr, zi);
+    const double complex d = orc_wL - I * z;          /* L - i z */
+    const double complex Z = (orc_wL + I * z) / d;    /* (L + i z) / (L - i z) */
+    double complex s = 0.0, Zp = 1.0;                 /* Zp = Z^(n-1) */
+    for (int n = 1; n <= ORC_WN; ++n) {
+        s = s + orc_wa[n] * Zp;
+        Zp = Zp * Z;
     }
-    /* 1/d and 1/d^2 */
-    const double ir = dr * rdd, ii = -di * rdd;
-    const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
-    const double sp = 0.56418958354775628695; /* 1 / sqrt(pi) */
-    *wr = 2.0 * (pr * i2r - pi_ * i2i) + sp * ir;
-    *wi = 2.0 * (pr * i2i + pi_ * i2r) + sp * ii;
+    const double complex w = 2.0 * s / (d * d) + (1.0 / sqrt(M_PI)) / d;
+    *wr = creal(w);
+    *wi = cimag(w);
+}
+
+/* Weideman's constants (L and a_1..a_N) for the tests' rounding bound. */
+void orc_faddeeva_coeffs(double *L, double *a)
+{
+    *L = orc_wL;
+    for (int n = 1; n <= ORC_WN; ++n) a[n - 1] = orc_wa[n];
 }
 
 typedef struct {
@@ -1084,14 +1119,15 @@ void orc_mp_micro(const orc_mp_nuclide *nd, double A, double T, double e, double
     if (w < 0) w = 0;
     if (w > nd->n_windows - 1) w = nd->n_windows - 1;
     double c = 0.0, s = 0.0;
-    const double spb = 1.7724538509055160273 * beta; /* sqrt(pi) beta */
     for (int32_t j = nd->win[2 * w]; j < nd->win[2 * w + 1]; ++j) {
-        const double zr = beta * (u - nd->poles[2 * j]), zi = -beta * nd->poles[2 * j + 1];
+        const double complex pole = CMPLX(nd->poles[2 * j], nd->poles[2 * j + 1]);
+        const double complex zz = beta * (u - pole);
         double wr, wi;
-        orc_faddeeva(zr, zi, &wr, &wi);
-        const double cr = spb * wr, ci = spb * wi;
-        c += nd->res_c[2 * j] * cr - nd->res_c[2 * j + 1] * ci;
-        s += nd->res_s[2 * j] * cr - nd->res_s[2 * j + 1] * ci;
+        orc_faddeeva(creal(zz), cimag(zz), &wr, &wi);
+        /* c_j = sqrt(pi) beta w(beta (u - p_j)) */
+        const double complex cj = sqrt(M_PI) * beta * CMPLX(wr, wi);
+        c = c + creal(CMPLX(nd->res_c[2 * j], nd->res_c[2 * j + 1]) * cj);
+        s = s + creal(CMPLX(nd->res_s[2 * j], nd->res_s[2 * j + 1]) * cj);
     }
     c = c / e;
     s = s / e;

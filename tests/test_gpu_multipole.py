@@ -2,9 +2,15 @@
 broadening) against the oracle, through the C ABI.
 
 * Macroscopic capture and scattering cross sections of two materials at 300 K
-  and 1200 K agree with the oracle to 1e-12 relative on log-uniform energies
-  and on energies packed around resonances (where the Faddeeva arguments are
-  small and the broadening matters).
+  and 1200 K agree with the oracle on log-uniform energies and on energies
+  packed around resonances (where the Faddeeva arguments are small and the
+  broadening matters).  The oracle sums the rational series for w(z) in its
+  own order (powers of Z built up, complex division) and the kernel by
+  Horner's rule with fused multiply-adds, so they agree to rounding: within
+  K u S, u = 2^-53, S the sum of the magnitudes of every term (each pole
+  term bounded through |Z| <= 1 in the upper half plane and |L - i z|, each
+  background term, times the densities), K = 128 covering the 32-term series,
+  the complex products and the sums over poles and nuclides.
 * The number of pole terms evaluated is the sum of the window sizes.
 * Invalid data are rejected.
 """
@@ -34,6 +40,40 @@ def _energies(nucs, rng, n=20_000):
         u = a[k] + g[k] * rng.normal(0, 3, 400)
         E.append(np.clip(u, 1e-3, None) ** 2)
     return np.concatenate(E)
+
+
+KB = 8.617333262e-5
+
+
+def _rounding_scale(nucs, mats, E, M):
+    """S(E): the sum over the material's nuclides of N_k times the magnitudes
+    of every term of sigma_c and sigma_s (pole terms bounded by |r| sqrt(pi)
+    beta (2 sum|a_n| / |d|^2 + 1 / (sqrt(pi) |d|)) / E with d = L - i z, the
+    background terms by |b_n| u^(n-1))."""
+    L, a = oracle.faddeeva_coeffs()
+    A1 = np.sum(np.abs(a))
+    S = np.zeros(E.size)
+    for m, (mi, md, T) in enumerate(mats):
+        sel = np.nonzero(M == m)[0]
+        u = np.sqrt(E[sel])
+        for q, dq in zip(mi, md):
+            nd = nucs[q]
+            beta = np.sqrt(nd.awr / (KB * T))
+            du = (nd.u_hi - nd.u_lo) / nd.win.shape[0]
+            w = np.clip(np.floor((u - nd.u_lo) / du), 0, nd.win.shape[0] - 1).astype(int)
+            acc = np.zeros(sel.size)
+            for i in range(sel.size):
+                j0, j1 = nd.win[w[i]]
+                if j1 > j0:
+                    z = beta * (u[i] - nd.poles[j0:j1])
+                    dabs = np.abs(L - 1j * z)
+                    wb = 2 * A1 / dabs ** 2 + 1 / (np.sqrt(np.pi) * dabs)
+                    r = np.abs(nd.res_c[j0:j1]) + np.abs(nd.res_s[j0:j1])
+                    acc[i] = np.sum(r * np.sqrt(np.pi) * beta * wb) / E[sel[i]]
+            bg = np.abs(nd.bg_c[w]) + np.abs(nd.bg_s[w])
+            acc += np.sum(bg * u[:, None] ** (np.arange(bg.shape[1])[None, :] - 1.0), axis=1)
+            S[sel] += dq * acc
+    return S
 
 
 def test_multipole_lookups_match_oracle(torch_cuda):
@@ -69,9 +109,12 @@ def test_multipole_lookups_match_oracle(torch_cuda):
         mc.mc_destroy(c)
     ga, gs = Sa.cpu().numpy(), Ss.cpu().numpy()
     assert np.all(ref_a > 0)
-    np.testing.assert_allclose(ga, ref_a, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(gs, ref_s, rtol=1e-12, atol=0)
-    print(f"multipole: {np.mean(ga == ref_a):.3f} of capture values bitwise equal; {n_poles} pole terms", flush=True)
+    bound = 128 * 2.0 ** -53 * _rounding_scale(nucs, mats, E, M)
+    err = np.maximum(np.abs(ga - ref_a), np.abs(gs - ref_s))
+    assert np.all(err <= bound), (np.max(err / bound), np.argmax(err / bound))
+    rel = np.max(np.abs(ga - ref_a) / ref_a)
+    print(f"multipole: largest error {np.max(err / bound):.3g} of the bound, capture rel {rel:.2e}, "
+          f"{np.mean(ga == ref_a):.3f} bitwise equal; {n_poles} pole terms", flush=True)
     assert n_poles == expect_poles
 
 
