@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the transport hot path on one MI355X.
 
-Workload: the 17x17 pin lattice (three materials of 30/3/5 synthetic
-nuclides on 10k-60k point grids, 8192-bin hash grid, reflective faces), one
-batch of 1,000,000 histories per step, event-based, per-pin flux tallies on
-(an active batch).  value = active particles/s over the timed steps.
+Workload (one step): one batch of 2e7 histories of the lookup-bound scale
+case -- a 255x255 pin lattice (15x15 assemblies of 17x17 pins, reflective
+faces), one material of 300 synthetic nuclides on 20k-150k point grids
+(605 MB of tables), 8192-bin hash grid, uniform 2 MeV source, event-based,
+100x100x10 mesh flux tally on (an active batch).  value = active particles/s
+over the timed steps (inputs resident in HBM, no per-launch timing inside the
+timed region).
 
 The lookup kernel, the dominant one, is timed with HIP events on the stream it
-runs on; its roofline entry prices its algorithmic bytes (36 + 56 n_nuclides
-per macroscopic lookup) against the HBM peak.  The oracle (plain C,
-history-based) is timed on the host on a bounded sample of the same workload.
+runs on, in a separate batch on one event loop.  Its roofline entry prices the
+bytes it moves from DRAM per lookup (rocprofv3 counters, committed under
+profiles/ for this kernel source) against the HBM peak; the algorithmic
+gather rate (36 + 56 n_nuclides bytes per macroscopic lookup, which neighbours
+in a sorted queue share through the caches) is reported beside it.  The
+oracle (plain C, history-based) is timed on the host on a bounded sample of
+the same workload.
 
 Prints one JSON line.
 """
@@ -27,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "active particles/s and macro-XS lookups/s (HBM GB/s % peak); FOM learned vs analog"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lookup_traffic_c2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lookup_traffic_c3.json")
 # launch shapes found by the library's autotuner on an MI355X (its cache format:
 # one line per problem signature); missing or stale entries are tuned afresh
 TUNING_CACHE = os.path.join(ROOT, "paper_2403_12345_amd", "tuning_cache.txt")
@@ -41,9 +48,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launches: int):
-    """HBM bytes per lookup launch from the committed rocprofv3 counter runs,
-    valid only for the kernel source they were taken on."""
+def measured_traffic():
+    """DRAM bytes per macroscopic lookup of the transport's lookup kernel (read
+    and written, from the committed rocprofv3 counter runs), valid only for
+    the kernel source they were taken on; None otherwise."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -51,14 +59,26 @@ def measured_traffic(launches: int):
         return None
     if d.get("kernel_digest") != kernel_source_digest():
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
-def cpu_baseline(prob, seed: int, target_s: float = 12.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, seed: int, target_s: float = 15.0, n1: int = 2000):
+    """The oracle on the host: the first pids of the same batch, sized to
+    about target_s seconds."""
     import oracle
     op = oracle.OracleProblem(prob)
     threads = oracle.max_threads()
-    n1 = 20_000
     t0 = time.perf_counter()
     oracle.run(op, seed, 0, n1)
     t1 = time.perf_counter() - t0
@@ -67,37 +87,38 @@ def cpu_baseline(prob, seed: int, target_s: float = 12.0):
     oracle.run(op, seed, 0, n2)
     t2 = time.perf_counter() - t0
     return {"value": n2 / t2, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"histories [0, {n2}) of one batch of the same problem, seed {seed}, "
                       f"history-based OpenMP over {threads} threads, {t2:.1f} s",
             "per_core": n2 / t2 / threads}
 
 
-def cpu_oracle_extra(c2, c3, target_s: float = 6.0):
-    """The oracle's other rates on the host: the 300-nuclide lattice on the
-    first pids of its batch (the full 2e7 would take hours) and macroscopic
-    lookups/s on log-uniform energies for the 30-nuclide fuel and the
-    300-nuclide material."""
+def cpu_oracle_extra(c2, c3, target_s: float = 5.0):
+    """The oracle's other rates on the host: the 17x17 lattice on the first
+    pids of its batch and macroscopic lookups/s on log-uniform energies for
+    the 30-nuclide fuel and the 300-nuclide material."""
     import numpy as np
 
     import mcsynth
     import oracle
     threads = oracle.max_threads()
-    op3 = oracle.OracleProblem(c3)
-    n1 = 2000
+    op2 = oracle.OracleProblem(c2)
+    n1 = 20_000
     t0 = time.perf_counter()
-    oracle.run(op3, c3.seed, 0, n1)
+    oracle.run(op2, c2.seed, 0, n1)
     t1 = time.perf_counter() - t0
-    n2 = int(max(n1, n1 * target_s / max(t1, 1e-3)))
+    n2 = int(min(c2.histories, max(n1, n1 * target_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
-    oracle.run(op3, c3.seed, 0, n2)
+    oracle.run(op2, c2.seed, 0, n2)
     t2 = time.perf_counter() - t0
     rng = np.random.default_rng(12345)
-    out = {"cores": threads, "kind": "oracle",
-           "c3_subset": {"particles_per_s": n2 / t2, "per_core": n2 / t2 / threads,
-                         "sample": f"histories [0, {n2}) of the 300-nuclide lattice batch, seed {c3.seed}, "
+    out = {"cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "c2_subset": {"particles_per_s": n2 / t2, "per_core": n2 / t2 / threads,
+                         "sample": f"histories [0, {n2}) of the 17x17 lattice batch, seed {c2.seed}, "
                                    f"{t2:.1f} s"}}
+    op3 = oracle.OracleProblem(c3)
     for name, prob, n in (("c2_fuel_lookups_per_s", c2, 200_000), ("c3_lookups_per_s", c3, 20_000)):
-        op = op3 if prob is c3 else oracle.OracleProblem(prob)
+        op = op3 if prob is c3 else op2
         E = mcsynth.lookup_energies(rng, n)
         t0 = time.perf_counter()
         oracle.macro_xs(op, np.zeros(n, np.int32), E)
@@ -105,48 +126,47 @@ def cpu_oracle_extra(c2, c3, target_s: float = 6.0):
     return out
 
 
-def c3_transport(tuning_cache: str, histories: int = 20_000_000, tune_histories: int = 20_000_000, prob=None):
-    """One batch of the lookup-bound scale case: 15x15 assemblies of 17x17 pins
-    (255x255 lattice), one material of 300 nuclides (605 MB of tables), 2e7
-    histories, 100x100x10 mesh flux tally; launch shapes (particles in flight
-    among them) from the autotuner, tuned on batches of the same size."""
+def c2_transport(tuning_cache: str, prob=None, warmup: int = 3, steps: int = 12):
+    """The 17x17 pin lattice (materials of 30/3/5 nuclides, 28 MB of tables
+    that sit in the on-chip caches): batches of 1e6 histories through
+    mc_run_batches with the tuned event loops, then one batch on one loop with
+    its lookup launches timed."""
+    import torch
+
     import mcsynth
     from paper_2403_12345_amd import mc
     from paper_2403_12345_amd.transport import Transport
 
-    prob = prob if prob is not None else mcsynth.c3_problem()
-    one = None
+    prob = prob if prob is not None else mcsynth.c2_problem()
+    n, seed = prob.histories, prob.seed
     with Transport(prob, device=0) as t:
-        tuning = mc.mc_autotune(t.ctx, prob.seed, 1 << 40, tune_histories, tuning_cache)
-        t.run_batch(prob.seed, 0, histories, time_kernels=True)
-        s = t.stats()
-        mesh, _, _ = t.tallies(mc.MC_T_FLUX_TRACK)
-        glob, _, _ = t.tallies(mc.MC_T_GLOBAL)
-        if tuning["loops"] > 1:
-            # with several loops their lookup launches overlap and the summed
-            # kernel time counts the overlap twice: the kernel's own rate comes
-            # from the same batch on one loop
-            mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
-            t.run_batch(prob.seed, 0, histories, time_kernels=True)
-            s1 = t.stats()
-            mc.mc_set_tuning(t.ctx, **tuning)
-            lk1 = s1["lookup_ms"] / 1e3
-            g1 = s1["lookup_bytes"] / lk1 / 1e9 if lk1 > 0 else 0.0
-            one = {"particles_per_s": histories / (s1["batch_ms"] / 1e3), "lookup_kernel_s": lk1,
-                   "lookup_GBs": g1, "lookup_frac_of_hbm_peak": g1 / HBM_PEAK_GBS}
-    sec = s["batch_ms"] / 1e3
-    lk = s["lookup_ms"] / 1e3
-    gbs = s["lookup_bytes"] / lk / 1e9 if lk > 0 else 0.0
-    return {"workload": "255x255 pin lattice (15x15 assemblies of 17x17), one material of 300 synthetic nuclides "
-                        "(grids of 20k-150k points, 605 MB), uniform 2 MeV source, 2e7 histories per batch, "
-                        "100x100x10 mesh flux tally",
-            "histories": histories, "particles_per_s": histories / sec, "batch_s": sec,
-            "lookups": s["lookups"], "lookups_per_s_insitu": s["lookups"] / sec,
-            "lookup_kernel_s": lk, "lookup_GBs": gbs, "lookup_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
-            "sorted_lookups": s["sorted_lookups"], "iterations": s["iterations"],
-            "mesh_track_sum": float(mesh.sum()), "total_track": float(glob[0]), "tuning": tuning,
-            "lookup_time_note": "summed over the launches of all loops (overlapping when loops > 1)",
-            "one_loop": one}
+        tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n, tuning_cache)
+        t.run_batches(seed, 0, n, warmup)
+        t.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.run_batches(seed, warmup * n, n, steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tot = t.stats()
+        mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
+        t.run_batch(seed, (warmup + steps) * n, n, time_kernels=True)
+        one = t.stats()
+    launches = max(one["lookup_launches"], 1)
+    avg_s = one["lookup_ms"] / 1e3 / launches
+    gbs = one["lookup_bytes"] / launches / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {"workload": "17x17 pin lattice (r 0.41, pitch 1.26, h 1 cm, reflective), materials of 30/3/5 "
+                        "synthetic nuclides on 10k-60k point fp64 grids (28 MB, cache-resident), 8192 hash "
+                        "bins, uniform 2 MeV source, 1e6 histories per batch, per-pin flux tally",
+            "particles_per_s": steps * n / elapsed, "ms_per_batch": elapsed / steps * 1e3,
+            "warmup": warmup, "steps": steps, "tuning": tuning,
+            "lookups_per_s_insitu": tot["lookups"] / elapsed,
+            "nuclide_lookups_per_lookup": tot["nuclide_lookups"] / max(tot["lookups"], 1),
+            "iterations_per_batch": tot["iterations"] / steps,
+            "one_loop_batch_ms": one["batch_ms"],
+            "lookup": {"avg_launch_us": avg_s * 1e6, "launches": one["lookup_launches"],
+                       "effective_gather_GBs": gbs, "effective_gather_frac": gbs / HBM_PEAK_GBS,
+                       "bound": "on-chip caches (tables in the Infinity Cache), not HBM"}}
 
 
 def c3_channels(tuning: dict, n_chan: int = 10, histories: int = 20_000_000, prob=None):
@@ -420,22 +440,28 @@ def copy_calibration(n_doubles: int = 1 << 28, reps: int = 5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
-    ap.add_argument("--warmup", type=int, default=3, help="untimed batches first (3: one round of up to 3 loops)")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1, help="untimed batches first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-inactive", action="store_true", help="skip the tally-off contrast batch")
     ap.add_argument("--no-lookup-bench", action="store_true", help="skip the 300-nuclide lookup benchmark")
     ap.add_argument("--no-problem-set", action="store_true", help="skip the 64-problem batching benchmark")
     ap.add_argument("--no-fom", action="store_true", help="skip the learned-importance figure-of-merit benchmark")
-    ap.add_argument("--no-c3", action="store_true", help="skip the 300-nuclide lattice transport batch")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 17x17 lattice transport batches")
+    ap.add_argument("--no-channels", action="store_true", help="skip the 300-nuclide lattice with reaction channels")
     ap.add_argument("--tuning-cache", default=TUNING_CACHE, help="autotuner cache file")
     ap.add_argument("--no-union", action="store_true", help="skip the hash-grid against union-grid comparison")
     ap.add_argument("--no-multipole", action="store_true", help="skip the windowed-multipole lookup benchmark")
     ap.add_argument("--loops", type=int, default=0, help="event loops of the timed steps (0: the tuned count)")
-    ap.add_argument("--mode", choices=("full", "lookup", "copy", "set", "fom", "c3", "union", "multipole"),
+    ap.add_argument("--mode", choices=("full", "c3", "lookup", "copy", "set", "fom", "c2", "union", "multipole"),
                     default="full",
-                    help="lookup: only the 300-nuclide lookup benchmark; copy: only the copy calibration")
+                    help="c3: the headline steps only (no other benchmark, no CPU baseline); lookup: only the "
+                         "300-nuclide lookup benchmark; copy: only the copy calibration")
     args = ap.parse_args()
+    if args.mode == "c3":
+        for k in ("no_cpu_baseline", "no_inactive", "no_lookup_bench", "no_problem_set", "no_fom", "no_c2",
+                  "no_channels", "no_union", "no_multipole"):
+            setattr(args, k, True)
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X and has no multi-GPU path",
               file=sys.stderr)
@@ -469,14 +495,12 @@ def main():
             tuning = mc.mc_autotune(t.ctx, p.seed, 1 << 40, p.histories, args.tuning_cache)
         print(json.dumps({"c2_union": c2_union(tuning)}), flush=True)
         return
-    if args.mode == "c3":
-        c3 = mcsynth.c3_problem()
-        plain = c3_transport(args.tuning_cache, prob=c3)
-        print(json.dumps({"c3_transport": plain, "c3_channels": c3_channels(plain["tuning"], prob=c3)}), flush=True)
+    if args.mode == "c2":
+        print(json.dumps({"c2_transport": c2_transport(args.tuning_cache)}), flush=True)
         return
     from paper_2403_12345_amd import mc
 
-    prob = mcsynth.c2_problem()
+    prob = mcsynth.c3_problem()
     n = prob.histories
     seed = prob.seed
     t = Transport(prob, device=0)
@@ -489,23 +513,20 @@ def main():
     if args.warmup:
         t.run_batches(seed, 0, n, args.warmup)
     t.reset()
-    # the K steps: K batches through mc_run_batches (with the tuned number of
-    # event loops, consecutive batches overlap)
+    # the K steps: K batches through mc_run_batches, no per-launch timing
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t.run_batches(seed, args.warmup * n, n, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps * n / elapsed
-    # the same K batches again with every lookup launch bracketed by HIP
-    # events on its loop's stream (kept out of the timed steps above)
-    t.reset()
-    t.run_batches(seed, args.warmup * n, n, args.steps, time_kernels=True)
-    tot = t.stats()
+    steps_stats = t.stats()
+    mesh, _, _ = t.tallies(mc.MC_T_FLUX_TRACK)
+    glob, _, _ = t.tallies(mc.MC_T_GLOBAL)
 
-    # the roofline of the lookup kernel: one batch on one event loop (with
-    # several loops each launch shares the GPU with the other loops' kernels,
-    # and its duration says little about the kernel itself)
+    # the roofline of the lookup kernel: one more batch on one event loop with
+    # every lookup launch bracketed by HIP events on its stream (with several
+    # loops a launch shares the GPU with the other loops' kernels)
     mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
     t.run_batch(seed, (args.warmup + args.steps) * n, n, time_kernels=True)
     one = t.stats()
@@ -515,18 +536,47 @@ def main():
     if not args.no_inactive:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        t.run_batch(seed, (args.warmup + args.steps) * n, n, no_tally=True)
+        t.run_batch(seed, (args.warmup + args.steps + 1) * n, n, no_tally=True)
         torch.cuda.synchronize()
         inactive = n / (time.perf_counter() - t1)
     t.close()
 
     launches = max(one["lookup_launches"], 1)
     avg_launch_s = one["lookup_ms"] / 1e3 / launches
-    bytes_per_launch = one["lookup_bytes"] / launches
-    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    t_launches = max(tot["lookup_launches"], 1)
-    t_avg_s = tot["lookup_ms"] / 1e3 / t_launches
-    t_ach = tot["lookup_bytes"] / t_launches / t_avg_s / 1e9 if t_avg_s > 0 else 0.0
+    lookups_per_launch = one["lookups"] / launches
+    alg_bytes_per_launch = one["lookup_bytes"] / launches
+    alg_gbs = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    traffic = measured_traffic()
+    if traffic is not None:
+        dram_per_launch = traffic["dram_bytes_per_lookup"] * lookups_per_launch
+        achieved = dram_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+        roof_bytes = "DRAM bytes per lookup from the committed counter runs x lookups per launch"
+    else:
+        dram_per_launch = None
+        achieved = None
+        roof_bytes = "no counter data for this kernel source: DRAM traffic unmeasured"
+    roofline = {
+        "kernel": "k_lookup (sorted-queue window path)",
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
+        "traffic": dram_per_launch,
+        "bytes": roof_bytes,
+        "avg_launch_us": avg_launch_s * 1e6,
+        "launches": one["lookup_launches"],
+        "lookups_per_launch": lookups_per_launch,
+        "measured_on": "one batch on one event loop, every lookup launch timed with HIP events",
+        "algorithmic_bytes_per_launch": alg_bytes_per_launch,
+        "effective_gather_GBs": alg_gbs,
+        "effective_gather_frac": alg_gbs / HBM_PEAK_GBS,
+    }
+    if traffic is not None:
+        roofline["counter_profile"] = traffic.get("source")
+        roofline["l2_hit"] = traffic.get("l2_hit")
+        if traffic.get("valu_insts_per_nuclide_wave") is not None:
+            roofline["valu_insts_per_nuclide_wave"] = traffic["valu_insts_per_nuclide_wave"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -541,58 +591,47 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "17x17 pin lattice (r 0.41, pitch 1.26, h 1 cm, reflective), materials of "
-                        "30/3/5 synthetic nuclides on 10k-60k point fp64 grids, 8192 hash bins, "
-                        "uniform 2 MeV source, 1e6 histories per batch event-based, per-pin flux tally",
+            "workload": "255x255 pin lattice (15x15 assemblies of 17x17 pins, r 0.41, pitch 1.26, h 1 cm, "
+                        "reflective), one material of 300 synthetic nuclides on 20k-150k point fp64 grids "
+                        "(605 MB of tables), 8192 hash bins, uniform 2 MeV source, 2e7 histories per batch "
+                        "event-based, 100x100x10 mesh flux tally",
             "histories_per_step": n,
             "in_flight": tuning["in_flight"],
             "tuning": tuning,
             "nuclides": len(prob.nuclides),
             "xs_bytes": prob.data_bytes(),
         },
-        "roofline": {
-            "kernel": "k_lookup",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(launches),
-            "avg_launch_us": avg_launch_s * 1e6,
-            "bytes_per_launch": bytes_per_launch,
-            "launches": one["lookup_launches"],
-            "measured_on": "one batch on one event loop",
-        },
-        "lookup_concurrent_loops": {"loops": tuning.get("loops", 1), "avg_launch_us": t_avg_s * 1e6,
-                                    "launches": tot["lookup_launches"], "achieved_GBs": t_ach,
-                                    "frac": t_ach / HBM_PEAK_GBS,
-                                    "measured_on": "the K steps' batches rerun with every lookup launch timed"},
+        "roofline": roofline,
         "one_loop_batch_ms": one["batch_ms"],
-        "lookups_per_s_kernel": tot["lookups"] / (tot["lookup_ms"] / 1e3) if tot["lookup_ms"] else None,
-        "lookups_per_s_insitu": tot["lookups"] / elapsed,
-        "nuclide_lookups_per_lookup": tot["nuclide_lookups"] / max(tot["lookups"], 1),
-        "iterations_per_step": tot["iterations"] / args.steps,
+        "one_loop_particles_per_s": n / (one["batch_ms"] / 1e3),
+        "lookups_per_s_kernel": one["lookups"] / (one["lookup_ms"] / 1e3) if one["lookup_ms"] else None,
+        "lookups_per_s_insitu": steps_stats["lookups"] / elapsed,
+        "lookup_kernel_share_one_loop": one["lookup_ms"] / one["batch_ms"] if one["batch_ms"] else None,
+        "iterations_per_step": steps_stats["iterations"] / args.steps,
+        "mesh_track_sum": float(mesh.sum()),
+        "total_track": float(glob[mc.MC_G_TRACK]),
+        "mesh_underflow": steps_stats["mesh_underflow"],
         "inactive_particles_per_s": inactive,
     }
-    c3 = mcsynth.c3_problem() if not (args.no_lookup_bench and args.no_c3) else None
+    c2 = mcsynth.c2_problem()
+    if not args.no_c2:
+        line["c2_transport"] = c2_transport(args.tuning_cache, prob=c2)
     if not args.no_lookup_bench:
-        line["lookup_microbench"] = lookup_microbench(prob=c3)
-    if not args.no_c3:
-        line["c3_transport"] = c3_transport(args.tuning_cache, prob=c3)
-        line["c3_channels"] = c3_channels(line["c3_transport"]["tuning"], prob=c3)
-    if not (args.no_c3 and args.no_lookup_bench):
-        # the lookup rates quoted against the measured copy bandwidth too
-        cal = copy_calibration()
+        line["lookup_microbench"] = lookup_microbench(prob=prob)
+    if not args.no_channels:
+        line["c3_channels"] = c3_channels(tuning, prob=prob)
+    # rates quoted against the measured copy bandwidth too
+    cal = copy_calibration() if args.mode != "c3" else None
+    if cal is not None:
         line["copy_GBs"] = cal["copy_GBs"]
-        if not args.no_c3:
-            for k in ("c3_transport", "c3_channels"):
-                line[k]["lookup_frac_of_copy_bw"] = line[k]["lookup_GBs"] / cal["copy_GBs"]
-        if not args.no_lookup_bench:
-            for k, v in line["lookup_microbench"].items():
-                if isinstance(v, dict) and "achieved_GBs" in v:
-                    v["frac_of_copy_bw"] = v["achieved_GBs"] / cal["copy_GBs"]
+        line["roofline"]["effective_gather_frac_of_copy_bw"] = alg_gbs / cal["copy_GBs"]
+    if not args.no_lookup_bench:
+        for k, v in line["lookup_microbench"].items():
+            if isinstance(v, dict) and "achieved_GBs" in v:
+                v["frac_of_copy_bw"] = v["achieved_GBs"] / cal["copy_GBs"]
     if not args.no_union:
-        line["c2_union"] = c2_union(tuning)
+        c2_tuning = line["c2_transport"]["tuning"] if "c2_transport" in line else {}
+        line["c2_union"] = c2_union(c2_tuning)
     if not args.no_multipole:
         line["multipole"] = multipole_microbench()
     if not args.no_problem_set:
@@ -601,7 +640,7 @@ def main():
         line["fom"] = fom_bench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, seed)
-        line["cpu_oracle"] = cpu_oracle_extra(prob, c3 if c3 is not None else mcsynth.c3_problem())
+        line["cpu_oracle"] = cpu_oracle_extra(c2, prob)
     print(json.dumps(line), flush=True)
 
 

@@ -42,7 +42,8 @@ typedef enum mc_status {
     MC_EHIP = -3,    /* a HIP runtime call failed (text in mc_last_error) */
     MC_ELOST = -4,   /* more lost particles than mc_run_opts.max_lost */
     MC_ESTATE = -5,  /* call order: materials before geometry before runs */
-    MC_ENODEV = -6   /* no usable gfx950 device */
+    MC_ENODEV = -6,  /* no usable gfx950 device */
+    MC_ERANGE = -7   /* a fixed-point mesh tally's range bound failed (see mc_run_batch) */
 } mc_status;
 
 typedef struct mc_ctx mc_ctx; /* opaque */
@@ -180,22 +181,50 @@ typedef struct mc_stats {
                                    later lookups are not in the counters above; the
                                    tail runs analog batches without an importance
                                    grid only) */
+    uint64_t mesh_underflow;    /* mesh-tally contributions (track length and
+                                   collision estimator) that were positive but
+                                   below the fixed-point resolution 2^-33 weight*cm
+                                   and so added nothing */
 } mc_stats;
 
-/* Batch statistics of one tally bin range (mc_get_tallies). */
+/* Batch statistics of one tally (mc_get_tallies).  s1 and s2 are set by the
+ * caller: when non-null they must hold n_bins doubles (host) and receive the
+ * raw batch sums S1 = sum_b T_b and S2 = sum_b T_b^2 of the per-source-particle
+ * batch values T_b -- with n_batches and histories, the state that
+ * mc_set_tallies restores (checkpoint and resume between batches). */
 typedef struct mc_tally_meta {
     uint64_t n_batches;
     uint64_t n_bins;
     uint64_t histories;    /* histories summed over all batches */
+    double *s1, *s2;       /* caller-owned host arrays (nullable), filled by the call */
 } mc_tally_meta;
+
+/*
+ * Device memory of a context: when given to mc_create, every device buffer
+ * the library needs (tables, particle bank, queues, tallies, scratch) comes
+ * from alloc and goes back through release; without it the library calls
+ * hipMalloc / hipFree.  alloc(user, bytes, device, stream) returns device
+ * memory of `device` usable on `stream` (the context's, or one of its event
+ * loops' streams) or NULL (the call then fails with MC_ENOMEM); release(user,
+ * ptr, device, stream) is called for each such pointer once no work that uses
+ * it remains (the library synchronizes first).  Both may be called from the
+ * library's event-loop threads.  The PyTorch binding passes its caching
+ * allocator here.
+ */
+typedef struct mc_alloc {
+    void *(*alloc)(void *user, size_t bytes, int device, void *stream);
+    void (*release)(void *user, void *ptr, int device, void *stream);
+    void *user;
+} mc_alloc;
 
 /*
  * Create a context on HIP device `device` (must be gfx950) that enqueues its
  * work on `hip_stream` (a hipStream_t; NULL = the device's null stream).
- * *out receives the context; on failure *out is NULL and the return value
- * says why (MC_ENODEV, MC_EHIP).
+ * alloc (nullable, copied) supplies the context's device memory (see
+ * mc_alloc).  *out receives the context; on failure *out is NULL and the
+ * return value says why (MC_ENODEV, MC_EHIP, MC_ENOMEM).
  */
-int mc_create(mc_ctx **out, int device, void *hip_stream);
+int mc_create(mc_ctx **out, int device, void *hip_stream, const mc_alloc *alloc);
 
 /* Free every device buffer of the context (synchronizes its stream). */
 void mc_destroy(mc_ctx *ctx);
@@ -231,17 +260,30 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len,
                       const int32_t *mat_len, const int32_t *mat_nuc, const double *mat_dens,
                       int32_t n_hash_bins);
 
-/* Geometry, source and tally (see mc_geometry_desc).  Requires materials.
+/* Geometry, source and tally (see mc_geometry_desc): the constructive solid
+ * geometry the particles are ray-traced through, surface by surface (paper
+ * section 3: surface tracking; the lattice of pins of section 4.1), where
+ * the source particles start, and what is tallied.  Requires materials.
  * Resets the tallies.  Errors: MC_EINVAL, MC_ESTATE. */
 int mc_init_geometry(mc_ctx *ctx, const mc_geometry_desc *desc);
 
 /*
  * Track histories with particle ids [first_pid, first_pid + n) to death and
- * add them to the tallies as one batch.  Particle pid draws its random
+ * add them to the tallies as one batch.  The histories run event by event
+ * over the whole bank of particles in flight (paper section 2, "Event-Based
+ * Parallelism": lookup, flight, crossing and collision kernels chosen from
+ * event queues), the lookup queue sorted by material and energy (section 2,
+ * "Sorting"), dead slots refilled from the batch until every history has
+ * started (section 2, "In-Flight Particles").  Particle pid draws its random
  * numbers from the Philox4x32-10 stream keyed by `seed` with counter
  * (draw/2, lineage, pid), so a history does not depend on what else runs.
  * opts may be NULL (defaults).  Synchronizes the stream at the end.
- * Errors: MC_ESTATE (no geometry), MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST.
+ * Mesh tallies accumulate each batch in fixed point (2^-32 weight*cm); a batch
+ * whose total weighted track length reaches 2^31 could wrap a bin, and then
+ * the call returns MC_ERANGE (its values are already in the sums: reset or
+ * restore the tallies, and run smaller batches).
+ * Errors: MC_ESTATE (no geometry), MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST,
+ * MC_ERANGE.
  */
 int mc_run_batch(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n,
                  const mc_run_opts *opts);
@@ -264,14 +306,29 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
 
 /*
  * Batch statistics of tally `tally_id` (MC_T_*) over every batch since the
- * last reset: mean[b] = S1/B and stderr_[b] = sqrt((S2/B - mean^2)/(B - 1))
- * of the per-source-particle batch values (stderr_ is 0 when B < 2).
+ * last reset (paper section 2, "Tallying": tallies are scored in active
+ * batches): mean[b] = S1/B and stderr_[b] = sqrt((S2/B - mean^2)/(B - 1)) of
+ * the per-source-particle batch values (stderr_ is 0 when B < 2).
  * mean and stderr_ are host arrays of n_bins entries (n_bins must equal the
  * tally's bin count: MC_N_GLOBAL for MC_T_GLOBAL); either may be NULL; meta
- * may be NULL.
+ * may be NULL (and receives the raw sums when meta->s1 / meta->s2 are set).
  */
 int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_, size_t n_bins,
                    mc_tally_meta *meta);
+
+/*
+ * Restore tally `tally_id` to raw batch sums read by mc_get_tallies (s1, s2:
+ * host, n_bins doubles each, n_bins the tally's bin count) and set the
+ * context's batch count and history total to n_batches and histories (shared
+ * by all tallies: restore every tally with the same values).  Later batches
+ * then add to the restored sums exactly as they would have added to the
+ * originals, so a run stopped between batches and resumed in a new context
+ * gives the same tallies bit for bit.  Errors: MC_ESTATE (no geometry; no
+ * reaction channels for MC_T_REACTION), MC_EINVAL (id, n_bins, NULL arrays,
+ * non-finite values, histories < n_batches).
+ */
+int mc_set_tallies(mc_ctx *ctx, int32_t tally_id, const double *s1, const double *s2, size_t n_bins,
+                   uint64_t n_batches, uint64_t histories);
 
 /* Zero every tally's batch sums. */
 int mc_reset_tallies(mc_ctx *ctx);
@@ -669,6 +726,15 @@ typedef struct {
  * field; MC_ESTATE from mc_run_batch when MC_WW_MLP is set and no network is
  * loaded. */
 int mc_set_weight_windows(mc_ctx *ctx, const mc_ww_desc *desc);
+
+/* The bootstrap importance map of a deep-penetration problem from an analog
+ * pilot: with R0 the mean of the MC_T_GLOBAL bin MC_G_LEAK_XHI (weight
+ * leaking through the x+ face per source particle) over the context's
+ * batches and N their histories, *slope = -ln(max(R0, 1/N)): the linear map
+ * ln I = slope * f_x makes the importance of the far face relative to the
+ * source that of the pilot's response (or of one history in N when none
+ * scored).  Errors: MC_ESTATE (no geometry or no batch). */
+int mc_ww_bootstrap_slope(mc_ctx *ctx, double *slope);
 
 /* Importance sums since the last mc_set_weight_windows / tally reset, into
  * host arrays of n_cells = imp_nx * imp_ne doubles (each may be NULL).

@@ -30,21 +30,22 @@ constexpr uint64_t kSortNever = 1ull << 30;  // no queue is that long: never sor
 constexpr int64_t kDefaultMaxEvents = 100000;
 constexpr int64_t kDefaultTailParticles = 131072;
 
+}  // namespace
+
+// Device buffers of one part of a context, released together; they come from
+// the context's allocator (mc_alloc) when it has one, else from hipMalloc.
 struct Buffers {
     std::vector<void *> ptrs;
-    void release()
-    {
-        for (void *p : ptrs) (void)hipFree(p);
-        ptrs.clear();
-    }
+    const mc_ctx *owner = nullptr;  // set by the first dalloc
+    void release();
 };
-
-}  // namespace
 
 struct mc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    bool has_alloc = false;  // device memory from `alloc` (mc_create), else hipMalloc
+    mc_alloc alloc{};
 
     // materials
     bool have_mat = false;
@@ -77,6 +78,7 @@ struct mc_ctx {
     int32_t n_bins = 0;
     double *S1[4] = {nullptr, nullptr, nullptr, nullptr}, *S2[4] = {nullptr, nullptr, nullptr, nullptr};
     uint64_t n_batches = 0, histories = 0;
+    double track_s1 = 0.0;  // host copy of S1 of the global track-length bin (mesh range check)
 
     // particle bank and per-workgroup tally rows
     Buffers bank_bufs;
@@ -166,6 +168,17 @@ struct mc_ctx {
     float *imp_range = nullptr;
 };
 
+void Buffers::release()
+{
+    for (void *p : ptrs) {
+        if (owner && owner->has_alloc)
+            owner->alloc.release(owner->alloc.user, p, owner->device, owner->stream);
+        else
+            (void)hipFree(p);
+    }
+    ptrs.clear();
+}
+
 static MlpDev mlp_dev(const mc_ctx *ctx)
 {
     MlpDev m;
@@ -202,8 +215,14 @@ static int dalloc(mc_ctx *ctx, Buffers &b, T **p, size_t count)
     *p = nullptr;
     if (count == 0) count = 1;
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
-    if (e != hipSuccess) return fail(ctx, MC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    b.owner = ctx;
+    if (ctx->has_alloc) {
+        q = ctx->alloc.alloc(ctx->alloc.user, count * sizeof(T), ctx->device, ctx->stream);
+        if (!q) return fail(ctx, MC_ENOMEM, "allocator: " + std::to_string(count * sizeof(T)) + " bytes refused");
+    } else {
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) return fail(ctx, MC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
     b.ptrs.push_back(q);
     *p = static_cast<T *>(q);
     return MC_OK;
@@ -256,10 +275,11 @@ extern "C" {
 
 const char *mc_version(void) { return "mc355 0.1 (gfx950)"; }
 
-int mc_create(mc_ctx **out, int device, void *hip_stream)
+int mc_create(mc_ctx **out, int device, void *hip_stream, const mc_alloc *alloc)
 {
     if (!out) return MC_EINVAL;
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->release)) return MC_EINVAL;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || device < 0 || device >= n) return MC_ENODEV;
     hipDeviceProp_t prop;
@@ -270,6 +290,10 @@ int mc_create(mc_ctx **out, int device, void *hip_stream)
     if (!ctx) return MC_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    if (alloc) {
+        ctx->has_alloc = true;
+        ctx->alloc = *alloc;
+    }
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     ctx->arch = prop.gcnArchName;
     int rc = dalloc(ctx, ctx->misc_bufs, &ctx->ctr, 2);
@@ -843,6 +867,7 @@ static int reset_tallies(mc_ctx *ctx)
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->n_batches = 0;
     ctx->histories = 0;
+    ctx->track_s1 = 0.0;
     return MC_OK;
 }
 
@@ -1067,8 +1092,8 @@ static int ensure_bank(mc_ctx *ctx, uint32_t cap)
     if (!rc) rc = dalloc(ctx, B, &t.tl, (size_t)t.rows * row_bins);
     if (!rc) rc = dalloc(ctx, B, &t.coll, (size_t)t.rows * row_bins);
     if (!rc) rc = dalloc(ctx, B, &t.glob, (size_t)t.rows * N_GLOBAL);
-    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins);
-    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins);
+    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins + 1);    // + underflow count
+    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins + 1);
     t.n_chan = ctx->n_chan;
     t.chan_bins = chan_bins;
     if (!rc && chan_bins) rc = dalloc(ctx, B, &t.chan, (size_t)t.rows * (size_t)chan_bins);
@@ -1209,6 +1234,36 @@ static int ensure_ww(mc_ctx *ctx, uint32_t cap)
     return MC_OK;
 }
 
+// Mesh tallies of one batch: the contributions that fell below the fixed-point
+// resolution (the word after the bins of each array), read after the batch.
+static int mesh_underflow(mc_ctx *ctx, const TallyDev &t, uint64_t *out)
+{
+    uint64_t u[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&u[0], t.mesh_tl + ctx->n_bins, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(&u[1], t.mesh_coll + ctx->n_bins, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = u[0] + u[1];
+    return MC_OK;
+}
+
+// Range bound of the fixed-point mesh tallies (see mesh_add): every bin of a
+// batch stays below 2^32 T_b + 2^62 units for a batch with weighted track
+// total T_b, so T_b < 2^31 rules out a wrapped bin.  T_b is read from the
+// global track-length sum the batch added to S1.
+static int mesh_range_check(mc_ctx *ctx, uint64_t n)
+{
+    double s1 = 0.0;
+    HIPCHK(hipMemcpyAsync(&s1, ctx->S1[2] + MC_G_TRACK, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double Tb = (s1 - ctx->track_s1) * (double)n;
+    ctx->track_s1 = s1;
+    if (!(Tb < MESH_TRACK_LIMIT))
+        return fail(ctx, MC_ERANGE,
+                    "mesh tally: the batch's weighted track length " + std::to_string(Tb) +
+                        " reaches 2^31, where a fixed-point bin could wrap; reset the tallies and run smaller batches");
+    return MC_OK;
+}
+
 // One event loop over histories [first_pid, first_pid + n) on the context's
 // stream, into the context's own tally rows (view == nullptr) or the rows of
 // a view; zero_rows: clear them first; stats: add the batch statistics (and
@@ -1251,8 +1306,8 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
         HIPCHK(launch_fill_f64(tal.glob, (size_t)tal.rows * N_GLOBAL, 0.0, st));
         if (tal.chan) HIPCHK(launch_fill_f64(tal.chan, (size_t)tal.rows * (size_t)tal.chan_bins, 0.0, st));
         if (mesh) {
-            HIPCHK(launch_fill_f64(tal.mesh_tl, (size_t)ctx->n_bins, 0.0, st));
-            HIPCHK(launch_fill_f64(tal.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
+            HIPCHK(launch_fill_f64(tal.mesh_tl, (size_t)ctx->n_bins + 1, 0.0, st));
+            HIPCHK(launch_fill_f64(tal.mesh_coll, (size_t)ctx->n_bins + 1, 0.0, st));
         }
     }
     HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->ctr), 2 * sizeof(Counters) / 4, 0u, st));
@@ -1359,6 +1414,10 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
         s.iterations = it;
         s.nuclide_lookups = dstat[0];
         s.lost = dstat[1];
+        if (mesh && !view) {  // own mesh arrays (with a view the caller reads the shared ones)
+            rc = mesh_underflow(ctx, tal, &s.mesh_underflow);
+            if (rc) return rc;
+        }
         ctx->stats = s;
         return MC_OK;
     }
@@ -1398,9 +1457,17 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
     // per lookup 36 B (+ 8 B per channel written), per nuclide 56 B (+ 16 B per channel)
     s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +
                      (56ull + 16ull * (uint64_t)ctx->n_chan) * s.nuclide_lookups;
+    if (mesh) {
+        rc = mesh_underflow(ctx, tal, &s.mesh_underflow);
+        if (rc) return rc;
+    }
     ctx->stats = s;
     ctx->n_batches += 1;
     ctx->histories += n;
+    if (mesh) {
+        rc = mesh_range_check(ctx, n);
+        if (rc) return rc;
+    }
     if (s.lost > opts.max_lost)
         return fail(ctx, MC_ELOST, std::to_string(s.lost) + " particles lost (event cap reached)");
     return MC_OK;
@@ -1414,7 +1481,7 @@ static int ensure_workers(mc_ctx *ctx, int L)
         hipStream_t st = nullptr;
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
         mc_ctx *w = nullptr;
-        const int rc = mc_create(&w, ctx->device, st);
+        const int rc = mc_create(&w, ctx->device, st, ctx->has_alloc ? &ctx->alloc : nullptr);
         if (rc) {
             (void)hipStreamDestroy(st);
             return fail(ctx, rc, "concurrent loops: worker context");
@@ -1466,8 +1533,8 @@ static int ensure_loop_rows(mc_ctx *ctx, int L, int32_t R)
     int rc = dalloc(ctx, B, &t.tl, (size_t)t.rows * row_bins);
     if (!rc) rc = dalloc(ctx, B, &t.coll, (size_t)t.rows * row_bins);
     if (!rc) rc = dalloc(ctx, B, &t.glob, (size_t)t.rows * N_GLOBAL);
-    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins);
-    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins);
+    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_tl, (size_t)ctx->n_bins + 1);    // + underflow count
+    if (!rc && mesh) rc = dalloc(ctx, B, &t.mesh_coll, (size_t)ctx->n_bins + 1);
     if (!rc && chan_bins) rc = dalloc(ctx, B, &t.chan, (size_t)t.rows * (size_t)chan_bins);
     const size_t part_bins = std::max<size_t>(std::max<size_t>(ctx->n_bins, N_GLOBAL), (size_t)chan_bins);
     if (!rc) rc = dalloc(ctx, B, &ctx->loop_partial, (size_t)64 * part_bins);
@@ -1512,8 +1579,8 @@ static int run_concurrent(mc_ctx *ctx, int L, uint64_t seed, uint64_t first_pid,
     HIPCHK(launch_fill_f64(all.glob, (size_t)all.rows * N_GLOBAL, 0.0, st));
     if (all.chan) HIPCHK(launch_fill_f64(all.chan, (size_t)all.rows * (size_t)all.chan_bins, 0.0, st));
     if (mesh) {
-        HIPCHK(launch_fill_f64(all.mesh_tl, (size_t)ctx->n_bins, 0.0, st));
-        HIPCHK(launch_fill_f64(all.mesh_coll, (size_t)ctx->n_bins, 0.0, st));
+        HIPCHK(launch_fill_f64(all.mesh_tl, (size_t)ctx->n_bins + 1, 0.0, st));
+        HIPCHK(launch_fill_f64(all.mesh_coll, (size_t)ctx->n_bins + 1, 0.0, st));
     }
     HIPCHK(hipEventRecord(ctx->ev_loop_start, st));
     std::vector<TallyDev> views(L);
@@ -1592,9 +1659,17 @@ static int run_concurrent(mc_ctx *ctx, int L, uint64_t seed, uint64_t first_pid,
     s.batch_ms = ms;
     s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +
                      (56ull + 16ull * (uint64_t)ctx->n_chan) * s.nuclide_lookups;
+    if (mesh) {
+        rc = mesh_underflow(ctx, all, &s.mesh_underflow);
+        if (rc) return rc;
+    }
     ctx->stats = s;
     ctx->n_batches += 1;
     ctx->histories += n;
+    if (mesh) {
+        rc = mesh_range_check(ctx, n);
+        if (rc) return rc;
+    }
     if (s.lost > opts.max_lost)
         return fail(ctx, MC_ELOST, std::to_string(s.lost) + " particles lost (event cap reached)");
     return MC_OK;
@@ -1653,6 +1728,7 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
             tot.lookup_bytes += q.lookup_bytes;
             tot.lookup_ms += q.lookup_ms;
             tot.tail_particles += q.tail_particles;
+            tot.mesh_underflow += q.mesh_underflow;
         }
         tot.batch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         ctx->stats = tot;
@@ -1732,6 +1808,7 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
             a.lost += q.lost;
             a.lookup_ms += q.lookup_ms;
             a.tail_particles += q.tail_particles;
+            a.mesh_underflow += q.mesh_underflow;
         }
     };
     std::vector<std::thread> threads;
@@ -1773,6 +1850,7 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
         s.lost += a.lost;
         s.lookup_ms += a.lookup_ms;
         s.tail_particles += a.tail_particles;
+        s.mesh_underflow += a.mesh_underflow;
     }
     s.batch_ms = ms;
     s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +
@@ -1780,6 +1858,21 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
     ctx->stats = s;
     ctx->n_batches += n_batches;
     ctx->histories += n * n_batches;
+    if (mesh) {
+        // every batch's weighted track total (its per-source value times n)
+        std::vector<double> tb(n_batches);
+        HIPCHK(hipMemcpy2DAsync(tb.data(), sizeof(double), ctx->batch_vals + 2 * (size_t)nb_t + MC_G_TRACK,
+                                cols * sizeof(double), sizeof(double), n_batches, hipMemcpyDeviceToHost, st));
+        double s1 = 0.0;
+        HIPCHK(hipMemcpyAsync(&s1, ctx->S1[2] + MC_G_TRACK, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->track_s1 = s1;
+        for (uint64_t b = 0; b < n_batches; ++b)
+            if (!(tb[b] * (double)n < MESH_TRACK_LIMIT))
+                return fail(ctx, MC_ERANGE,
+                            "mesh tally: batch " + std::to_string(b) + "'s weighted track length reaches 2^31, "
+                            "where a fixed-point bin could wrap; reset the tallies and run smaller batches");
+    }
     if (s.lost > opts.max_lost)
         return fail(ctx, MC_ELOST, std::to_string(s.lost) + " particles lost (event cap reached)");
     return MC_OK;
@@ -1811,7 +1904,50 @@ int mc_get_tallies(mc_ctx *ctx, int32_t tally_id, double *mean, double *stderr_,
         meta->n_batches = ctx->n_batches;
         meta->n_bins = nb;
         meta->histories = ctx->histories;
+        if (meta->s1) std::memcpy(meta->s1, s1.data(), nb * sizeof(double));
+        if (meta->s2) std::memcpy(meta->s2, s2.data(), nb * sizeof(double));
     }
+    return MC_OK;
+}
+
+int mc_set_tallies(mc_ctx *ctx, int32_t tally_id, const double *s1, const double *s2, size_t n_bins,
+                   uint64_t n_batches, uint64_t histories)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "no geometry");
+    if (tally_id < 0 || tally_id > 3) return fail(ctx, MC_EINVAL, "unknown tally id");
+    if (tally_id == MC_T_REACTION && !ctx->n_chan) return fail(ctx, MC_ESTATE, "no reaction channels");
+    if (!s1 || !s2) return fail(ctx, MC_EINVAL, "mc_set_tallies: s1 and s2 are required");
+    const size_t nb = (tally_id == MC_T_GLOBAL)     ? (size_t)N_GLOBAL
+                      : (tally_id == MC_T_REACTION) ? (size_t)ctx->n_mat * (size_t)ctx->n_chan
+                                                    : (size_t)ctx->n_bins;
+    if (n_bins != nb) return fail(ctx, MC_EINVAL, "n_bins does not match the tally (" + std::to_string(nb) + ")");
+    if (histories < n_batches) return fail(ctx, MC_EINVAL, "mc_set_tallies: fewer histories than batches");
+    for (size_t k = 0; k < nb; ++k)
+        if (!std::isfinite(s1[k]) || !std::isfinite(s2[k]) || s2[k] < 0.0)
+            return fail(ctx, MC_EINVAL, "mc_set_tallies: bin " + std::to_string(k) + " is not a valid sum");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMemcpyAsync(ctx->S1[tally_id], s1, nb * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->S2[tally_id], s2, nb * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->n_batches = n_batches;
+    ctx->histories = histories;
+    if (tally_id == MC_T_GLOBAL) ctx->track_s1 = s1[MC_G_TRACK];
+    return MC_OK;
+}
+
+int mc_ww_bootstrap_slope(mc_ctx *ctx, double *slope)
+{
+    if (!ctx || !slope) return MC_EINVAL;
+    if (!ctx->have_geom) return fail(ctx, MC_ESTATE, "no geometry");
+    if (ctx->n_batches == 0 || ctx->histories == 0) return fail(ctx, MC_ESTATE, "mc_ww_bootstrap_slope: no batch run");
+    double mean[N_GLOBAL];
+    const int rc = mc_get_tallies(ctx, MC_T_GLOBAL, mean, nullptr, N_GLOBAL, nullptr);
+    if (rc) return rc;
+    // the far face's importance relative to the source: the pilot's response,
+    // floored at one history in the pilot when none scored
+    const double r0 = std::max(mean[MC_G_LEAK_XHI], 1.0 / (double)ctx->histories);
+    *slope = -std::log(r0);
     return MC_OK;
 }
 

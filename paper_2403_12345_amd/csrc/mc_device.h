@@ -84,13 +84,23 @@ constexpr int MAX_CHAN = 16;  // most reaction channels
 
 // Mesh tallies accumulate in 64-bit fixed point, 2^-32 per unit (weight * cm):
 // integer additions commute, so the sums do not depend on the order in which
-// the atomics land and reruns are bitwise identical.  A bin holds up to 2^32
-// units per batch; a contribution is rounded to the nearest 2^-32.
+// the atomics land and reruns are bitwise identical.  A contribution v is
+// rounded to the nearest 2^-32 (absolute error at most 2^-33 per
+// contribution).  Range: a bin holds at most 2^64 units, and no bin can
+// exceed 2^32 times the batch's total weighted track length plus half a unit
+// per contribution, so a batch whose global track total stays below 2^31
+// cannot wrap any bin; the host checks that bound after every batch
+// (MC_ERANGE).  The array has n_bins bins and one more word: the number of
+// positive contributions that rounded to zero (below the resolution).
 constexpr double MESH_FIX_SCALE = 4294967296.0;        // 2^32
 constexpr double MESH_FIX_INV = 1.0 / 4294967296.0;    // 2^-32
-__device__ __forceinline__ void mesh_add(double *acc, int32_t idx, double v)
+constexpr double MESH_TRACK_LIMIT = 2147483648.0;      // 2^31 weight * cm per batch
+__device__ __forceinline__ void mesh_add(double *acc, int32_t idx, double v, int32_t n_bins)
 {
-    atomicAdd(reinterpret_cast<unsigned long long *>(acc) + idx, (unsigned long long)__double2ull_rn(v * MESH_FIX_SCALE));
+    unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
+    const unsigned long long q = __double2ull_rn(v * MESH_FIX_SCALE);
+    if (q) atomicAdd(a + idx, q);
+    else if (v > 0.0) atomicAdd(a + n_bins, 1ull);
 }
 
 struct GeomDev {

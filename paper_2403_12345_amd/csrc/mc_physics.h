@@ -96,19 +96,36 @@ __device__ __forceinline__ int32_t mesh_index(const GeomDev &g, double x, double
     return (c[2] * g.mesh_dims[1] + c[1]) * g.mesh_dims[0] + c[0];
 }
 
-// Track-length score of a straight flight through the mesh: walk the cells it
-// crosses (3-D digital differential analyser), adding w * length per cell.
+// Track-length score of a straight flight through the mesh: the part of the
+// flight inside the mesh box (slab intersection: the entry and exit of the
+// flight through each pair of box planes), walked cell by cell by a 3-D
+// digital differential analyser, adding w * length per cell.  Track outside
+// the box scores nothing.
 __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, double y, double z, double u,
                                    double v, double w, double d, double wt)
 {
     const double r0[3] = {x, y, z}, dir[3] = {u, v, w};
+    // [t_in, t_out): the flight's parameter range inside the box
+    double t_in = 0.0, t_out = d;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (dir[k] == 0.0) {
+            if (r0[k] < g.mesh_lo[k] || r0[k] > g.mesh_hi[k]) return;
+        } else {
+            const double ta = (g.mesh_lo[k] - r0[k]) / dir[k], tb = (g.mesh_hi[k] - r0[k]) / dir[k];
+            t_in = fmax(t_in, fmin(ta, tb));
+            t_out = fmin(t_out, fmax(ta, tb));
+        }
+    }
+    if (!(t_out > t_in)) return;
     double h[3], tnext[3], tdelta[3];
     int32_t c[3], step[3];
-    // start cell: the one holding the flight's first point (nudged along the
-    // flight by a hair so a start on a mesh plane picks the cell ahead)
+    // first cell: the one holding the clipped flight's first point (nudged
+    // along the flight by a hair so a start on a mesh plane picks the cell ahead)
+    const double tq = t_in + fmin(t_out - t_in, 1e-9) * 0.5;
     for (int k = 0; k < 3; ++k) {
         h[k] = (g.mesh_hi[k] - g.mesh_lo[k]) / g.mesh_dims[k];
-        double q = r0[k] + dir[k] * fmin(d, 1e-9) * 0.5;
+        const double q = r0[k] + dir[k] * tq;
         int32_t v0 = (int32_t)floor((q - g.mesh_lo[k]) / h[k]);
         c[k] = v0 < 0 ? 0 : (v0 > g.mesh_dims[k] - 1 ? g.mesh_dims[k] - 1 : v0);
         if (dir[k] > 0.0) {
@@ -125,18 +142,18 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
             tdelta[k] = INFINITY;
         }
     }
-    double t = 0.0;
-    for (int guard = 0; guard < 100000 && t < d; ++guard) {
+    double t = t_in;
+    for (int guard = 0; guard < 100000 && t < t_out; ++guard) {
         int k = 0;
         if (tnext[1] < tnext[k]) k = 1;
         if (tnext[2] < tnext[k]) k = 2;
-        const double t1 = fmin(fmax(tnext[k], t), d);
+        const double t1 = fmin(fmax(tnext[k], t), t_out);
         if (t1 > t) {
             const int32_t idx = (c[2] * g.mesh_dims[1] + c[1]) * g.mesh_dims[0] + c[0];
-            mesh_add(acc, idx, wt * (t1 - t));
+            mesh_add(acc, idx, wt * (t1 - t), g.n_bins);
         }
         t = t1;
-        if (t >= d) break;
+        if (t >= t_out) break;
         c[k] += step[k];
         if (c[k] < 0 || c[k] >= g.mesh_dims[k]) break;
         tnext[k] += tdelta[k];
@@ -419,7 +436,7 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
         case TALLY_SLAB: sc.c_bin = p.cell; break;
         case TALLY_MESH: {
             const int32_t c = mesh_index(g, p.x, p.y, p.z);
-            if (c >= 0) mesh_add(mesh_coll, c, p.wt / st);
+            if (c >= 0) mesh_add(mesh_coll, c, p.wt / st, g.n_bins);
         } break;
         }
         sc.c_val = p.wt / st;

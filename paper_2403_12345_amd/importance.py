@@ -63,8 +63,8 @@ def learn(t, seed: int, pilot: int = 1_000_000, boot: int = 1_000_000, nx: int =
     t.reset()
     t.run_batch(seed, first_pid, pilot)
     r0 = float(t.tallies(mc.MC_T_GLOBAL)[0][mc.MC_G_LEAK_XHI])
+    slope = mc.mc_ww_bootstrap_slope(ctx)
     sec["pilot"] = time.perf_counter() - tic
-    slope = -math.log(max(r0, 1.0 / pilot))
     # 2. bootstrap windows with the importance grid
     tic = time.perf_counter()
     grid = dict(imp_nx=nx, imp_ne=ne, imp_x0=x0, imp_x1=x1)

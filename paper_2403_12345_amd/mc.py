@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmc.so")
 
-MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST, MC_ESTATE, MC_ENODEV = 0, -1, -2, -3, -4, -5, -6
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ELOST, MC_ESTATE, MC_ENODEV, MC_ERANGE = 0, -1, -2, -3, -4, -5, -6, -7
 MC_GEOM_INFINITE, MC_GEOM_LATTICE, MC_GEOM_SLAB = 0, 1, 2
 MC_TALLY_ENERGY, MC_TALLY_PIN, MC_TALLY_MESH, MC_TALLY_SLAB = 0, 1, 2, 3
 MC_T_FLUX_TRACK, MC_T_FLUX_COLLISION, MC_T_GLOBAL, MC_T_REACTION = 0, 1, 2, 3
@@ -27,7 +27,7 @@ MC_FATE_ABSORBED, MC_FATE_CUTOFF, MC_FATE_LEAKED, MC_FATE_LOST, MC_FATE_ROULETTE
 MC_WW_OFF, MC_WW_LINEAR, MC_WW_MLP = 0, 1, 2
 
 _STATUS = {MC_EINVAL: "MC_EINVAL", MC_ENOMEM: "MC_ENOMEM", MC_EHIP: "MC_EHIP", MC_ELOST: "MC_ELOST",
-           MC_ESTATE: "MC_ESTATE", MC_ENODEV: "MC_ENODEV"}
+           MC_ESTATE: "MC_ESTATE", MC_ENODEV: "MC_ENODEV", MC_ERANGE: "MC_ERANGE"}
 
 
 class MCError(RuntimeError):
@@ -61,7 +61,7 @@ class mc_stats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("lookups", C.c_uint64), ("nuclide_lookups", C.c_uint64),
                 ("lookup_launches", C.c_uint64), ("sorted_lookups", C.c_uint64), ("lost", C.c_uint64),
                 ("lookup_bytes", C.c_uint64), ("lookup_ms", C.c_double), ("batch_ms", C.c_double),
-                ("tail_particles", C.c_uint64)]
+                ("tail_particles", C.c_uint64), ("mesh_underflow", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -106,7 +106,34 @@ class mc_train_opts(C.Structure):
 
 
 class mc_tally_meta(C.Structure):
-    _fields_ = [("n_batches", C.c_uint64), ("n_bins", C.c_uint64), ("histories", C.c_uint64)]
+    _fields_ = [("n_batches", C.c_uint64), ("n_bins", C.c_uint64), ("histories", C.c_uint64),
+                ("s1", C.POINTER(C.c_double)), ("s2", C.POINTER(C.c_double))]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p)
+
+
+class mc_alloc(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("user", C.c_void_p)]
+
+
+def _torch_alloc(user, nbytes, device, stream):
+    # device memory from PyTorch's caching allocator (NULL -> MC_ENOMEM)
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_release(user, ptr, device, stream):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# one allocator description for every context (the callbacks must outlive them)
+_TORCH_ALLOC = mc_alloc(_ALLOC_FN(_torch_alloc), _RELEASE_FN(_torch_release), None)
 
 
 HISTORY_DTYPE = np.dtype([("fate", np.int32), ("n_coll", np.int32), ("n_cross", np.int32),
@@ -131,7 +158,7 @@ def load():
     P, V, D, I32, U64, SZ = C.POINTER, C.c_void_p, C.c_double, C.c_int32, C.c_uint64, C.c_size_t
     sig = {
         "mc_version": ([], C.c_char_p),
-        "mc_create": ([P(V), C.c_int, V], C.c_int),
+        "mc_create": ([P(V), C.c_int, V, P(mc_alloc)], C.c_int),
         "mc_destroy": ([V], None),
         "mc_last_error": ([V], C.c_char_p),
         "mc_set_stream": ([V, V], C.c_int),
@@ -141,6 +168,8 @@ def load():
         "mc_run_batch": ([V, U64, U64, U64, P(mc_run_opts)], C.c_int),
         "mc_run_batches": ([V, U64, U64, U64, U64, P(mc_run_opts)], C.c_int),
         "mc_get_tallies": ([V, I32, P(D), P(D), SZ, P(mc_tally_meta)], C.c_int),
+        "mc_set_tallies": ([V, I32, P(D), P(D), SZ, U64, U64], C.c_int),
+        "mc_ww_bootstrap_slope": ([V, P(D)], C.c_int),
         "mc_reset_tallies": ([V], C.c_int),
         "mc_get_stats": ([V, P(mc_stats)], C.c_int),
         "mc_lookup_macro": ([V, SZ, V, V, V, V, I32], C.c_int),
@@ -221,9 +250,15 @@ def mc_version() -> str:
     return load().mc_version().decode()
 
 
-def mc_create(device: int = 0, stream=None):
+def mc_create(device: int = 0, stream=None, allocator: str | None = "torch"):
+    """A context on `device` enqueuing on `stream` (torch's current stream by
+    default); allocator "torch": its device memory comes from PyTorch's caching
+    allocator, None: from hipMalloc."""
     ctx = C.c_void_p()
-    rc = load().mc_create(C.byref(ctx), device, _stream_handle(stream))
+    if allocator not in ("torch", None):
+        raise ValueError(f"allocator must be 'torch' or None, not {allocator!r}")
+    al = C.byref(_TORCH_ALLOC) if allocator == "torch" else None
+    rc = load().mc_create(C.byref(ctx), device, _stream_handle(stream), al)
     _check(None, rc)
     return ctx
 
@@ -275,12 +310,33 @@ def mc_run_batches(ctx, seed: int, first_pid: int, n: int, n_batches: int, opts:
     _check(ctx, rc)
 
 
-def mc_get_tallies(ctx, tally_id: int, n_bins: int):
+def mc_get_tallies(ctx, tally_id: int, n_bins: int, raw: bool = False):
+    """(mean, stderr, meta); with raw=True also the raw batch sums (S1, S2)."""
     mean = np.zeros(n_bins)
     se = np.zeros(n_bins)
     meta = mc_tally_meta()
+    s1 = s2 = None
+    if raw:
+        s1, s2 = np.zeros(n_bins), np.zeros(n_bins)
+        meta.s1, meta.s2 = _dp(s1), _dp(s2)
     _check(ctx, load().mc_get_tallies(ctx, tally_id, _dp(mean), _dp(se), n_bins, C.byref(meta)))
+    if raw:
+        return mean, se, meta, s1, s2
     return mean, se, meta
+
+
+def mc_set_tallies(ctx, tally_id: int, s1, s2, n_batches: int, histories: int):
+    s1 = np.ascontiguousarray(s1, np.float64)
+    s2 = np.ascontiguousarray(s2, np.float64)
+    if s1.shape != s2.shape:
+        raise ValueError("s1 and s2 differ in size")
+    _check(ctx, load().mc_set_tallies(ctx, tally_id, _dp(s1), _dp(s2), s1.size, int(n_batches), int(histories)))
+
+
+def mc_ww_bootstrap_slope(ctx) -> float:
+    a = C.c_double()
+    _check(ctx, load().mc_ww_bootstrap_slope(ctx, C.byref(a)))
+    return float(a.value)
 
 
 def mc_reset_tallies(ctx):

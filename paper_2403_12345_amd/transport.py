@@ -66,9 +66,9 @@ def run_opts(in_flight=0, sort_min=0, no_tally=False, time_kernels=False, max_ev
 class Transport:
     """One library context holding one problem."""
 
-    def __init__(self, prob, device: int = 0, stream=None):
+    def __init__(self, prob, device: int = 0, stream=None, allocator: str | None = "torch"):
         self.prob = prob
-        self.ctx = mc.mc_create(device, stream)
+        self.ctx = mc.mc_create(device, stream, allocator)
         try:
             mc.mc_init_materials(self.ctx, [n.E for n in prob.nuclides], [n.sig_c for n in prob.nuclides],
                                  [n.sig_s for n in prob.nuclides], [n.awr for n in prob.nuclides],
@@ -113,10 +113,29 @@ class Transport:
     def run_batches(self, seed, first_pid, n, n_batches, **opts):
         mc.mc_run_batches(self.ctx, seed, first_pid, n, n_batches, run_opts(**opts))
 
+    def _bins(self, tally_id):
+        return {mc.MC_T_GLOBAL: mc.MC_N_GLOBAL, mc.MC_T_REACTION: self.n_reaction}.get(tally_id, self.n_bins)
+
     def tallies(self, tally_id):
-        nb = {mc.MC_T_GLOBAL: mc.MC_N_GLOBAL, mc.MC_T_REACTION: self.n_reaction}.get(tally_id, self.n_bins)
-        mean, se, meta = mc.mc_get_tallies(self.ctx, tally_id, nb)
+        mean, se, meta = mc.mc_get_tallies(self.ctx, tally_id, self._bins(tally_id))
         return mean, se, meta
+
+    def checkpoint(self) -> dict:
+        """Raw batch sums of every tally, the batch count and history total:
+        what restore() needs to resume between batches."""
+        ids = [mc.MC_T_FLUX_TRACK, mc.MC_T_FLUX_COLLISION, mc.MC_T_GLOBAL]
+        if self.n_reaction:
+            ids.append(mc.MC_T_REACTION)
+        out = {"tallies": {}}
+        for k in ids:
+            _, _, meta, s1, s2 = mc.mc_get_tallies(self.ctx, k, self._bins(k), raw=True)
+            out["tallies"][k] = (s1, s2)
+            out["n_batches"], out["histories"] = int(meta.n_batches), int(meta.histories)
+        return out
+
+    def restore(self, state: dict):
+        for k, (s1, s2) in state["tallies"].items():
+            mc.mc_set_tallies(self.ctx, k, s1, s2, state["n_batches"], state["histories"])
 
     def reset(self):
         mc.mc_reset_tallies(self.ctx)

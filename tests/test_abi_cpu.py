@@ -33,7 +33,9 @@ def test_struct_sizes_match_header_layout():
     # mc_history is 48 bytes (4 int32, 1 uint64, 3 double); the run options 48
     assert mc.HISTORY_DTYPE.itemsize == 48
     assert ctypes.sizeof(mc.mc_run_opts) == 48
-    assert ctypes.sizeof(mc.mc_stats) == 8 * 10
+    assert ctypes.sizeof(mc.mc_stats) == 8 * 11
+    assert ctypes.sizeof(mc.mc_tally_meta) == 8 * 5
+    assert ctypes.sizeof(mc.mc_alloc) == 8 * 3
     assert ctypes.sizeof(mc.mc_ww_desc) == 6 * 4 + 10 * 8
     assert ctypes.sizeof(mc.mc_train_opts) == 48
     assert ctypes.sizeof(mc.mc_mp_nuclide) == 4 * 4 + 2 * 8 + 6 * 8
@@ -42,13 +44,14 @@ def test_struct_sizes_match_header_layout():
 
 def _header_enum(name):
     src = open(os.path.join(ROOT, "include", "mc.h")).read()
-    return int(re.search(r"\b" + name + r"\s*=\s*(\d+)", src).group(1))
+    return int(re.search(r"\b" + name + r"\s*=\s*(-?\d+)", src).group(1))
 
 
 def test_binding_constants_match_header_and_oracle():
     import oracle
     for k in ("MC_G_LEAK_XHI", "MC_G_SPLIT", "MC_G_ROULETTE", "MC_N_GLOBAL", "MC_MLP_NPAR", "MC_FATE_ROULETTE",
-              "MC_WW_LINEAR", "MC_WW_MLP", "MC_T_REACTION"):
+              "MC_WW_LINEAR", "MC_WW_MLP", "MC_T_REACTION", "MC_EINVAL", "MC_ENOMEM", "MC_EHIP",
+              "MC_ELOST", "MC_ESTATE", "MC_ENODEV", "MC_ERANGE"):
         assert getattr(mc, k) == _header_enum(k), k
     src = open(os.path.join(ROOT, "include", "mc.h")).read()
     assert mc.MC_MAX_CHANNELS == int(re.search(r"#define MC_MAX_CHANNELS (\d+)", src).group(1))

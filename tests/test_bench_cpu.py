@@ -1,7 +1,8 @@
 """Host-side pieces of bench.py and the committed measurement files (no GPU).
 
-* The HBM traffic entry is taken from the committed counter file only while
-  its kernel digest matches the kernel sources; otherwise it is null.
+* The DRAM traffic of the lookup kernel is taken from the committed counter
+  file only while its kernel digest matches the kernel sources; otherwise
+  the roofline has no measured bytes.
 * --gpus other than 1 exits with a message before anything touches a GPU.
 * The committed autotuner cache holds well-formed lines (signature, launch
   shapes in range, best time).
@@ -21,24 +22,28 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_traffic_follows_the_kernel_digest(tmp_path, monkeypatch):
     f = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.measured_traffic(10) is None  # no file
-    f.write_text(json.dumps({"kernel_digest": bench.kernel_source_digest(), "bytes_per_launch": 123.0}))
-    assert bench.measured_traffic(10) == 123.0
-    f.write_text(json.dumps({"kernel_digest": "0" * 16, "bytes_per_launch": 123.0}))
-    assert bench.measured_traffic(10) is None
+    assert bench.measured_traffic() is None  # no file
+    f.write_text(json.dumps({"kernel_digest": bench.kernel_source_digest(), "dram_bytes_per_lookup": 123.0}))
+    assert bench.measured_traffic()["dram_bytes_per_lookup"] == 123.0
+    f.write_text(json.dumps({"kernel_digest": "0" * 16, "dram_bytes_per_lookup": 123.0}))
+    assert bench.measured_traffic() is None
     f.write_text("not json")
-    assert bench.measured_traffic(10) is None
+    assert bench.measured_traffic() is None
 
 
 def test_committed_traffic_file_is_well_formed():
-    with open(os.path.join(ROOT, "profiles", "lookup_traffic_c2.json")) as fh:
+    path = os.path.join(ROOT, "profiles", "lookup_traffic_c3.json")
+    if not os.path.exists(path):
+        pytest.skip("no counter file committed yet")
+    with open(path) as fh:
         d = json.load(fh)
     assert len(d["kernel_digest"]) == 16
-    assert d["bytes_per_launch"] > 0
-    # the scales are stored rounded to three decimals
-    assert d["bytes_per_launch"] == pytest.approx(
-        (d["fetch_kib_per_launch"] * d["fetch_scale"] + d["write_kib_per_launch"] * d["write_scale"]) * 1024,
-        rel=1e-3)
+    # DRAM bytes per lookup: read bytes by request size (from the DRAM side
+    # only) plus written bytes, over the lookups of the profiled launches
+    assert d["dram_bytes_per_lookup"] == pytest.approx(
+        (d["dram_read_bytes"] + d["write_bytes"]) / d["lookups"], rel=1e-6)
+    assert 0 < d["dram_bytes_per_lookup"] < 36 + 56 * 300 * 8
+    assert os.path.exists(os.path.join(ROOT, d["source"]))
 
 
 def test_more_than_one_gpu_is_refused():

@@ -36,3 +36,19 @@ def test_mesh_flux_is_flat_in_a_homogeneous_reflected_box():
     truth = np.full(32, 10.0 / 32)  # 1/Sigma_a = 10 cm per source particle, equal cell volumes
     n_fail, allowed, z = three_sigma(st.mean["tl"], st.stderr["tl"], truth=truth)
     assert n_fail <= allowed, (n_fail, allowed, z)
+
+
+def test_partial_mesh_scores_only_inside_its_box():
+    """A mesh box over part of the homogeneous reflected lattice: cell c
+    expects (1/Sigma_a) V_c / V_geometry, and the cells together hold the
+    box's share of the track length, not the whole of it."""
+    prob = mesh_problem(dims=(3, 4, 2))
+    prob.tally = mcsynth.Tally(mcsynth.TALLY_MESH, mesh_dims=(3, 4, 2), mesh_box=(1.0, 4.0, 0.5, 6.3, 0.25, 0.75))
+    st = oracle.run_batches(oracle.OracleProblem(prob), 7, 20, 5000)
+    v_cell = (3.0 / 3) * (5.8 / 4) * (0.5 / 2)
+    truth = np.full(24, 10.0 * v_cell / (6.3 * 6.3 * 1.0))
+    for k in ("tl", "coll"):
+        n_fail, allowed, z = three_sigma(st.mean[k], st.stderr[k], truth=truth)
+        assert n_fail <= allowed, (k, n_fail, allowed, z)
+    share = 3.0 * 5.8 * 0.5 / (6.3 * 6.3)
+    assert abs(st.mean["tl"].sum() - 10.0 * share) < 3 * np.sqrt(np.sum(st.stderr["tl"] ** 2))
