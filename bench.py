@@ -437,6 +437,111 @@ def copy_calibration(n_doubles: int = 1 << 28, reps: int = 5):
             "copy_GBs": 2 * n_doubles * 8 / sec / 1e9}
 
 
+def pmc_per_dispatch(dirs, kernel_regex: str):
+    """Counter values of the dispatches whose kernel name matches kernel_regex,
+    from rocprofv3 --pmc CSV output (every *counter_collection.csv under the
+    given directories): {counter: [value per dispatch]}, dispatches in id order."""
+    import csv
+    import glob
+    import re
+    pat = re.compile(kernel_regex)
+    per = {}
+    for d in dirs:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            with open(f, newline="") as fh:
+                for row in csv.DictReader(fh):
+                    if not pat.search(row.get("Kernel_Name", "")):
+                        continue
+                    key = (f, int(row.get("Dispatch_Id", 0)))
+                    per.setdefault(row["Counter_Name"], {})
+                    per[row["Counter_Name"]][key] = per[row["Counter_Name"]].get(key, 0.0) + float(row["Counter_Value"])
+    return {c: [v[k] for k in sorted(v)] for c, v in per.items()}
+
+
+def traffic_summary(lookup_dirs, copy_dirs, roof_json: str, out_path: str):
+    """Bytes the lookup kernel moves between L2 and memory, per macroscopic
+    lookup, from rocprofv3 counter runs of the roofline batch (bench.py --mode
+    c3roof, whose JSON line gives the batch's lookups), and the same counters
+    on the copy calibration (bench.py --mode copy: 2 GiB read + 2 GiB written
+    per launch) as the scale check.  Read bytes by request size: 32 B x
+    TCC_EA0_RDREQ_32B + 64 B x _64B + 128 B x _128B; bytes to DRAM: 32 B x
+    TCC_EA0_RDREQ_DRAM_32B (a 64-byte request counts 2, a 128-byte one 4) and
+    32 B x TCC_EA0_WRREQ_WRITE_DRAM_32B; FETCH_SIZE and WRITE_SIZE (KiB) as
+    the counter definitions compute them, with the copy's ratio of true to
+    counted bytes."""
+    with open(roof_json) as f:
+        roof = json.loads(f.read().strip().splitlines()[-1])["c3_roofline_batch"]
+    lk = pmc_per_dispatch(lookup_dirs, r"k_lookup")
+    cp = pmc_per_dispatch(copy_dirs, r"(?i)copy|elementwise") if copy_dirs else {}
+
+    def tot(d, c):
+        return float(sum(d.get(c, []))) if c in d else None
+
+    n_lookups = roof["lookups"]
+    launches = roof["lookup_launches"]
+    out = {"kernel_digest": roof["kernel_digest"], "lookups": n_lookups, "launches": launches,
+           "dispatches_counted": {c: len(v) for c, v in lk.items()}}
+    rd = {b: tot(lk, f"TCC_EA0_RDREQ_{b}B_sum") for b in (32, 64, 128)}
+    if all(v is not None for v in rd.values()):
+        rbytes = 32 * rd[32] + 64 * rd[64] + 128 * rd[128]
+        out["read_requests"] = {f"{b}B": rd[b] for b in rd}
+        out["read_bytes_per_lookup"] = rbytes / n_lookups
+    dram = tot(lk, "TCC_EA0_RDREQ_DRAM_32B_sum")
+    dramw = tot(lk, "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum")
+    if dram is not None:
+        out["dram_read_bytes_per_lookup"] = 32 * dram / n_lookups
+    if dramw is not None:
+        out["dram_write_bytes_per_lookup"] = 32 * dramw / n_lookups
+    if dram is not None and dramw is not None:
+        out["dram_bytes_per_lookup"] = 32 * (dram + dramw) / n_lookups
+    hit, miss = tot(lk, "TCC_HIT_sum"), tot(lk, "TCC_MISS_sum")
+    if hit is not None and miss is not None and hit + miss > 0:
+        out["l2_hit"] = hit / (hit + miss)
+    fetch, write = tot(lk, "FETCH_SIZE"), tot(lk, "WRITE_SIZE")
+    cal = {}
+    copy_bytes = float(1 << 31)
+    if cp:
+        n_copy = max(len(cp.get("FETCH_SIZE", [])), len(cp.get("WRITE_SIZE", [])), 1)
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            if c in cp and cp[c]:
+                cal[c] = copy_bytes / (max(cp[c]) * 1024.0)  # true bytes per counted byte, largest dispatch = the copy
+        rdc = {b: cp.get(f"TCC_EA0_RDREQ_{b}B_sum") for b in (32, 64, 128)}
+        if all(rdc.values()):
+            k = max(range(len(rdc[128])), key=lambda j: rdc[128][j])
+            cal["read_by_size"] = copy_bytes / (32 * rdc[32][k] + 64 * rdc[64][k] + 128 * rdc[128][k])
+        if cp.get("TCC_EA0_RDREQ_DRAM_32B_sum"):
+            cal["dram_read"] = copy_bytes / (32 * max(cp["TCC_EA0_RDREQ_DRAM_32B_sum"]))
+        if cp.get("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"):
+            cal["dram_write"] = copy_bytes / (32 * max(cp["TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]))
+        out["copy_dispatches"] = n_copy
+    out["copy_scale"] = cal
+    if dram is not None and dramw is not None:
+        # the DRAM-side bytes with the copy's ratio of true to counted bytes
+        out["dram_bytes_per_lookup_scaled"] = 32 * (dram * cal.get("dram_read", 1.0) +
+                                                    dramw * cal.get("dram_write", 1.0)) / n_lookups
+    if fetch is not None:
+        out["fetch_kib_per_launch"] = fetch / launches
+    if write is not None:
+        out["write_kib_per_launch"] = write / launches
+    if fetch is not None and write is not None and "FETCH_SIZE" in cal and "WRITE_SIZE" in cal:
+        out["traffic_bytes_per_lookup"] = (fetch * cal["FETCH_SIZE"] + write * cal["WRITE_SIZE"]) * 1024 / n_lookups
+    sq = {c: tot(lk, c) for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_SMEM",
+                                  "SQ_INSTS_VMEM_RD", "SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES",
+                                  "SQ_INST_CYCLES_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_BRANCH",
+                                  "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "SQ_INSTS_VALU_INT32",
+                                  "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                                  "SQ_INSTS_VALU_TRANS_F64", "GRBM_GUI_ACTIVE") if c in lk}
+    if sq:
+        wave_nuc = roof["nuclide_lookups"] / 64.0
+        out["per_wave_nuclide"] = {c: v / wave_nuc for c, v in sq.items()
+                                   if c.startswith("SQ_INSTS") or c.startswith("SQ_INST_")}
+        out["sq_totals"] = sq
+    out["source_runs"] = {"lookup": list(lookup_dirs), "copy": list(copy_dirs or []), "roofline_batch": roof_json}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -453,15 +558,26 @@ def main():
     ap.add_argument("--no-union", action="store_true", help="skip the hash-grid against union-grid comparison")
     ap.add_argument("--no-multipole", action="store_true", help="skip the windowed-multipole lookup benchmark")
     ap.add_argument("--loops", type=int, default=0, help="event loops of the timed steps (0: the tuned count)")
-    ap.add_argument("--mode", choices=("full", "c3", "lookup", "copy", "set", "fom", "c2", "union", "multipole"),
+    ap.add_argument("--pmc-dirs", nargs="*", default=[], help="traffic mode: rocprofv3 --pmc output directories "
+                                                              "of the roofline batch")
+    ap.add_argument("--copy-dirs", nargs="*", default=[], help="traffic mode: the same counters on --mode copy")
+    ap.add_argument("--roof-json", default="", help="traffic mode: the JSON line printed by --mode c3roof")
+    ap.add_argument("--traffic-out", default=TRAFFIC_FILE, help="traffic mode: where to write the summary")
+    ap.add_argument("--mode", choices=("full", "c3", "c3roof", "traffic", "lookup", "copy", "set", "fom", "c2", "union",
+                                       "multipole"),
                     default="full",
-                    help="c3: the headline steps only (no other benchmark, no CPU baseline); lookup: only the "
-                         "300-nuclide lookup benchmark; copy: only the copy calibration")
+                    help="c3: the headline steps only (no other benchmark, no CPU baseline); c3roof: only the "
+                         "roofline batch (one batch of the headline workload on one event loop, every lookup "
+                         "launch timed; for counter runs); lookup: only the 300-nuclide lookup benchmark; copy: "
+                         "only the copy calibration")
     args = ap.parse_args()
     if args.mode == "c3":
         for k in ("no_cpu_baseline", "no_inactive", "no_lookup_bench", "no_problem_set", "no_fom", "no_c2",
                   "no_channels", "no_union", "no_multipole"):
             setattr(args, k, True)
+    if args.mode == "traffic":  # host only: summarise counter runs
+        print(json.dumps(traffic_summary(args.pmc_dirs, args.copy_dirs, args.roof_json, args.traffic_out)))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X and has no multi-GPU path",
               file=sys.stderr)
@@ -503,6 +619,18 @@ def main():
     prob = mcsynth.c3_problem()
     n = prob.histories
     seed = prob.seed
+    if args.mode == "c3roof":
+        with Transport(prob, device=0) as t:
+            tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n, args.tuning_cache)
+            mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
+            t.run_batch(seed, 0, n, time_kernels=True)
+            one = t.stats()
+        print(json.dumps({"c3_roofline_batch": {
+            "histories": n, "tuning": {**tuning, "loops": 1}, "lookups": one["lookups"],
+            "nuclide_lookups": one["nuclide_lookups"], "lookup_launches": one["lookup_launches"],
+            "lookup_ms": one["lookup_ms"], "lookup_bytes": one["lookup_bytes"], "batch_ms": one["batch_ms"],
+            "kernel_digest": kernel_source_digest()}}), flush=True)
+        return
     t = Transport(prob, device=0)
     # launch shapes from the library's autotuner (from its cache when this
     # problem was tuned on this device kind, else timed on batches of other pids)
@@ -548,7 +676,8 @@ def main():
     alg_gbs = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     traffic = measured_traffic()
     if traffic is not None:
-        dram_per_launch = traffic["dram_bytes_per_lookup"] * lookups_per_launch
+        dram_per_launch = traffic.get("dram_bytes_per_lookup_scaled", traffic["dram_bytes_per_lookup"]) * \
+            lookups_per_launch
         achieved = dram_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
         roof_bytes = "DRAM bytes per lookup from the committed counter runs x lookups per launch"
     else:

@@ -544,8 +544,6 @@ __device__ __forceinline__ double surface_distance(const GeomDev &g, double x, d
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// Butterfly sum over the wave: every lane ends with the same bits, because at
-// each stage partners add the same two values (commutativity).
 // Lane j's value (j the same in every lane) in every lane.
 __device__ __forceinline__ double lane_f64(double v, int j)
 {
@@ -563,9 +561,11 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a converged wave, the same value in every lane: a
-// fixed tree of DPP steps (quad sums, rows, then rows 0+1 and 2+3 into lane
-// 63), read from lane 63.
+// Sum over the 64 lanes of a wave, the same value in every lane: a fixed tree
+// of DPP steps (quad sums, rows, then rows 0+1 and 2+3 into lane 63), read
+// from lane 63.  Precondition: all 64 lanes are active (an inactive lane's
+// value would be read as whatever its register holds), so callers pass 0.0
+// from the lanes that contribute nothing instead of masking them off.
 __device__ __forceinline__ double wave_sum(double v)
 {
     v = v + dpp_f64<0xb1, 0xf, 0xf>(v);   // quad_perm 1,0,3,2

@@ -165,14 +165,15 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
 // ---------------------------------------------------------------------------
 // Adds val into bin `bin` (< 0: nothing) of the workgroup's row.  Each wave
 // peels off one distinct bin at a time: the values of the lanes holding it
-// are added in lane order when they are few (cheaper than a butterfly over
-// all 64), by the butterfly when they are many, and the first of them adds
+// are added in lane order when they are few (cheaper than a reduction over
+// all 64), by the wave's DPP reduction tree when they are many, and the first of them adds
 // the sum into the wave's LDS slab;
 // the slabs are then added in wave order into the row.  Every thread of the
 // workgroup must call it.
 __device__ __forceinline__ double lanes_sum(double v, uint64_t lanes)
 {
-    // many lanes (a material's rates, one bin per wave): the butterfly
+    // many lanes (a material's rates, one bin per wave): the DPP tree over
+    // the whole wave (every lane of the wave is active here)
     if (__popcll(lanes) > 8) return wave_sum(((lanes >> lane_id()) & 1ull) ? v : 0.0);
     double s = 0.0;
     while (lanes) {

@@ -2,6 +2,7 @@
 against the oracle and the closed forms of a homogeneous reflected box:
 the pieces of every flight add up to the total track length, the flux is flat,
 and GPU and oracle cell tallies agree within 3 sigma (independent seeds)."""
+import os
 import sys
 
 import numpy as np
@@ -12,6 +13,9 @@ from paper_2403_12345_amd import mc
 from paper_2403_12345_amd.transport import Transport
 from tests.stats import three_sigma
 from tests.test_oracle_mesh import mesh_problem
+
+CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_12345_amd",
+                     "tuning_cache.txt")
 
 pytestmark = pytest.mark.gpu
 
@@ -108,3 +112,78 @@ def test_partial_mesh_same_histories_as_oracle(torch_cuda):
     r = oracle.run(oracle.OracleProblem(prob), 33, 0, 4000)
     np.testing.assert_allclose(gm, r.tl / 4000, rtol=1e-9, atol=1e-12)
     assert st["mesh_underflow"] == 0
+
+
+# --- the 100x100x10 mesh of the 300-nuclide 255x255 lattice -----------------
+
+def _c3_events_only(t):
+    # every event through the event kernels (sorted lookup queues, no
+    # one-launch tail), as in the large batches
+    mc.mc_set_tuning(t.ctx, tail_particles=-1, sort_min=1)
+
+
+@pytest.mark.timeout(300)
+def test_c3_mesh_cells_same_histories_as_oracle(torch_cuda):
+    """The 300-nuclide lattice's own mesh (100x100x10 over 321.3 x 321.3 x 1
+    cm): the first 20,000 pids through the event kernels against the
+    oracle's same pids, cell by cell.  Histories that are the same give
+    cell sums equal to the rounding of the fixed-point pieces (2^-33 each);
+    a history whose crossing moved by a last-ulp logarithm difference can
+    change the cells it visits, so at least 99.5 % of the touched cells must
+    agree to 1e-9 and the totals to 1e-9 relative."""
+    import mcsynth
+    prob = mcsynth.c3_problem()
+    n, seed = 20_000, prob.seed
+    print(f"c3 mesh per cell, pids [0, {n}) of seed {seed}", flush=True)
+    with Transport(prob) as t:
+        _c3_events_only(t)
+        t.run_batch(seed, 0, n)
+        gm, _, _ = t.tallies(mc.MC_T_FLUX_TRACK)
+        gc, _, _ = t.tallies(mc.MC_T_FLUX_COLLISION)
+        gl, _, _ = t.tallies(mc.MC_T_GLOBAL)
+        st = t.stats()
+    r = oracle.run(oracle.OracleProblem(prob), seed, 0, n)
+    om, oc = r.tl / n, r.coll / n
+    assert gm.shape == om.shape == (100_000,)
+    assert st["mesh_underflow"] == 0
+    np.testing.assert_allclose(gm.sum(), om.sum(), rtol=1e-9)
+    np.testing.assert_allclose(gm.sum(), gl[mc.MC_G_TRACK], rtol=1e-9)
+    np.testing.assert_allclose(gc.sum(), oc.sum(), rtol=1e-9)
+    for g, o in ((gm, om), (gc, oc)):
+        touched = (g != 0) | (o != 0)
+        close = np.abs(g - o) <= 1e-9 * np.abs(o) + 1e-12
+        frac = close[touched].mean()
+        print(f"cells touched {touched.sum()}, agreeing {frac:.5f}", flush=True)
+        assert touched.sum() > 90_000 and frac >= 0.995, frac
+
+
+@pytest.mark.timeout(300)
+def test_c3_mesh_is_flat_at_full_size(torch_cuda, tmp_path):
+    """Closed form at the benchmark's size: one material everywhere, a uniform
+    source and reflective faces make the flux flat, so each of the 10^5
+    equal cells expects 10^-5 of the total track length.  2e7 histories in 20
+    batches of 1e6 with the tuned launch shapes (several event loops, sorted
+    queues); per-cell 3 sigma with Student's t allowance (19 degrees of
+    freedom)."""
+    import shutil
+
+    import mcsynth
+    prob = mcsynth.c3_problem()
+    cache = tmp_path / "tuning_cache.txt"
+    shutil.copy(CACHE, cache)
+    per, batches = 1_000_000, 20
+    with Transport(prob) as t:
+        tuning = mc.mc_autotune(t.ctx, prob.seed, 1 << 40, prob.histories, str(cache))
+        print(f"c3 flat mesh, {batches} x {per} histories, tuning {tuning}", flush=True)
+        t.run_batches(prob.seed + 100, 0, per, batches)
+        gm, gs, meta = t.tallies(mc.MC_T_FLUX_TRACK)
+        gl, _, _ = t.tallies(mc.MC_T_GLOBAL)
+    assert meta.n_batches == batches
+    np.testing.assert_allclose(gm.sum(), gl[mc.MC_G_TRACK], rtol=1e-9)
+    truth = np.full(gm.size, gm.sum() / gm.size)
+    n_fail, allowed, z = three_sigma(gm, gs, truth=truth, dof=batches - 1)
+    print(f"cells outside 3 sigma {n_fail} (allowed {allowed}), worst z {z:.2f}", flush=True)
+    assert n_fail <= allowed, (n_fail, allowed, z)
+    # the cells' spread matches their standard errors (no cell systematically off)
+    zz = (gm - truth) / gs
+    assert abs(float(np.mean(zz))) < 0.05 and 0.9 < float(np.std(zz)) < 1.2
