@@ -149,12 +149,13 @@ def test_c3_mesh_cells_same_histories_as_oracle(torch_cuda):
     np.testing.assert_allclose(gm.sum(), om.sum(), rtol=1e-9)
     np.testing.assert_allclose(gm.sum(), gl[mc.MC_G_TRACK], rtol=1e-9)
     np.testing.assert_allclose(gc.sum(), oc.sum(), rtol=1e-9)
-    for g, o in ((gm, om), (gc, oc)):
+    # flights cross nearly every cell; collisions (points) reach fewer
+    for g, o, min_touched in ((gm, om, 95_000), (gc, oc, 80_000)):
         touched = (g != 0) | (o != 0)
         close = np.abs(g - o) <= 1e-9 * np.abs(o) + 1e-12
         frac = close[touched].mean()
         print(f"cells touched {touched.sum()}, agreeing {frac:.5f}", flush=True)
-        assert touched.sum() > 90_000 and frac >= 0.995, frac
+        assert touched.sum() > min_touched and frac >= 0.995, (touched.sum(), frac)
 
 
 @pytest.mark.timeout(300)
