@@ -467,6 +467,28 @@ int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, 
                     double *sig_s, int32_t sorted);
 
 /*
+ * mc_lookup_macro without any allocation, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results as mc_lookup_macro; the sort's scratch (keys, permutation, radix
+ * partials) lives in a static device array of the library, one per GPU,
+ * allocated when the library's code is loaded and held until the process
+ * ends (MC_NOALLOC_SCRATCH_BYTES).  The call allocates nothing (no hipMalloc,
+ * no caller allocator, no events) and does not honour mc_set_timing.
+ *   n        at most MC_NOALLOC_MAX_LOOKUPS; larger n is rejected
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several contexts, streams or threads) race and give wrong results;
+ * serialize them.  The array's device address is looked up once per GPU by
+ * mc_create (which fails with MC_EHIP if it cannot be had).  Errors:
+ * MC_ESTATE (no materials), MC_EINVAL (n above the maximum, null E or mat),
+ * MC_EHIP.
+ */
+#define MC_NOALLOC_MAX_LOOKUPS (1u << 20)
+#define MC_NOALLOC_SCRATCH_BYTES (30u << 20)
+int mc_lookup_macro_noalloc(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *sig_a,
+                            double *sig_s, int32_t sorted);
+
+/*
  * Per-nuclide results of the same lookup for n pairs that all use material
  * `mat` (n_k = its nuclide count):
  *   E        device, n fp64 energies

@@ -10,6 +10,7 @@
 #include <string>
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -30,6 +31,38 @@ constexpr uint64_t kSortNever = 1ull << 30;  // no queue is that long: never sor
 constexpr int64_t kDefaultMaxEvents = 100000;
 constexpr int64_t kDefaultTailParticles = 131072;
 
+}  // namespace
+
+// Scratch of the allocation-free lookup entry point (mc_lookup_macro_noalloc):
+// a static device array, one copy per GPU, placed when the code object loads
+// and held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: host code uses only the device address that
+// hipGetSymbolAddress returns for it (taken once per device when a context is
+// created on it, kept in noalloc_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[MC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `device`, looked up
+// on the first call for that device.
+hipError_t noalloc_scratch_ptr(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_noalloc_scratch[device] = p;
+    }
+    *out = g_noalloc_scratch[device];
+    return hipSuccess;
+}
 }  // namespace
 
 // Device buffers of one part of a context, released together; they come from
@@ -101,6 +134,7 @@ struct mc_ctx {
     uint32_t *s_perm = nullptr, *s_keys = nullptr;
     int32_t *s_mat = nullptr;
     SortBufs s_sort{};
+    void *noalloc_scratch = nullptr;  // this device's `scratch` (device address)
 
     std::vector<hipEvent_t> ev_a, ev_b;
     hipEvent_t ev_batch0 = nullptr, ev_batch1 = nullptr;
@@ -296,7 +330,8 @@ int mc_create(mc_ctx **out, int device, void *hip_stream, const mc_alloc *alloc)
     }
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     ctx->arch = prop.gcnArchName;
-    int rc = dalloc(ctx, ctx->misc_bufs, &ctx->ctr, 2);
+    int rc = noalloc_scratch_ptr(device, &ctx->noalloc_scratch) == hipSuccess ? MC_OK : MC_EHIP;
+    if (!rc) rc = dalloc(ctx, ctx->misc_bufs, &ctx->ctr, 2);
     if (!rc) rc = dalloc(ctx, ctx->misc_bufs, &ctx->dstat, 4);
     if (!rc && hipHostMalloc((void **)&ctx->ctr_host, 2 * sizeof(Counters), hipHostMallocDefault) != hipSuccess)
         rc = MC_ENOMEM;
@@ -2043,6 +2078,67 @@ int mc_lookup_macro(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, 
     s.sorted_lookups += sorted ? n : 0;
     s.lookup_bytes += 36ull * n + 56ull * nuc;
     s.lookup_ms += ms;
+    return MC_OK;
+}
+
+// The parts of the static scratch for a sorted lookup of up to n pairs,
+// each 256-byte aligned; returns the bytes they span.
+static size_t carve_noalloc(unsigned char *base, size_t n, uint32_t **perm, uint32_t **keys, SortBufs *sb)
+{
+    size_t off = 0;
+    auto take = [&](size_t words) {
+        uint32_t *p = reinterpret_cast<uint32_t *>(base + off);
+        off += (words * sizeof(uint32_t) + 255) & ~size_t(255);
+        return p;
+    };
+    *perm = take(n);
+    *keys = take(n);
+    sb->kA = take(n);
+    sb->kB = take(n);
+    sb->vA = take(n);
+    sb->vB = take(n);
+    const size_t tiles = sort_tile_count(n), chunks = sort_chunk_count(n);
+    sb->tile_hist = take(tiles * 256);
+    sb->chunk_total = take(chunks * 256);
+    sb->chunk_off = take((chunks + 1) * 256);
+    return off;
+}
+
+int mc_lookup_macro_noalloc(mc_ctx *ctx, size_t n, const double *E, const int32_t *mat, double *sig_a,
+                            double *sig_s, int32_t sorted)
+{
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->have_mat) return fail(ctx, MC_ESTATE, "mc_lookup_macro_noalloc: no materials");
+    if (n == 0) return MC_OK;
+    if (n > MC_NOALLOC_MAX_LOOKUPS)
+        return fail(ctx, MC_EINVAL, "mc_lookup_macro_noalloc: n = " + std::to_string(n) + " above the maximum of " +
+                                        std::to_string(MC_NOALLOC_MAX_LOOKUPS) + " lookups per call");
+    if (!E || !mat) return fail(ctx, MC_EINVAL, "mc_lookup_macro_noalloc: bad arguments");
+    if (!ctx->noalloc_scratch) return fail(ctx, MC_ESTATE, "mc_lookup_macro_noalloc: no scratch on this device");
+    HIPCHK(hipSetDevice(ctx->device));
+    LookupLaunch l;
+    l.xs = ctx->xs;
+    l.n_bound = (uint32_t)n;
+    l.E = E;
+    l.mat = mat;
+    l.Sa = sig_a;
+    l.Ss = sig_s;
+    l.ilp = lookup_ilp(ctx);
+    if (sorted) {
+        uint32_t *perm = nullptr, *keys = nullptr;
+        SortBufs sb;
+        const size_t used = carve_noalloc(static_cast<unsigned char *>(ctx->noalloc_scratch), n, &perm, &keys, &sb);
+        if (used > MC_NOALLOC_SCRATCH_BYTES)
+            return fail(ctx, MC_EINVAL, "mc_lookup_macro_noalloc: scratch too small for n");
+        // the radix counts add into chunk_total, which an earlier call (or an
+        // interrupted one) may have left non-zero: clear this call's part
+        HIPCHK(launch_fill_u32(sb.chunk_total, sort_chunk_count(n) * 256, 0u, ctx->stream));
+        HIPCHK(launch_sort(ctx->xs, nullptr, nullptr, (uint32_t)n, E, mat, sb, ctx->n_keys, perm, keys,
+                           ctx->stream));
+        l.list = perm;
+        l.keys = keys;
+    }
+    HIPCHK(launch_lookup(l, ctx->stream));
     return MC_OK;
 }
 

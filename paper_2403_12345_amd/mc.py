@@ -173,6 +173,7 @@ def load():
         "mc_reset_tallies": ([V], C.c_int),
         "mc_get_stats": ([V, P(mc_stats)], C.c_int),
         "mc_lookup_macro": ([V, SZ, V, V, V, V, I32], C.c_int),
+        "mc_lookup_macro_noalloc": ([V, SZ, V, V, V, V, I32], C.c_int),
         "mc_init_channels": ([V, I32, P(P(D))], C.c_int),
         "mc_set_union_grid": ([V, I32, P(U64)], C.c_int),
         "mc_init_multipole": ([V, I32, V, P(D), I32, P(I32), P(I32), P(D), P(D)], C.c_int),
@@ -250,14 +251,18 @@ def mc_version() -> str:
     return load().mc_version().decode()
 
 
-def mc_create(device: int = 0, stream=None, allocator: str | None = "torch"):
+def mc_create(device: int = 0, stream=None, allocator="torch"):
     """A context on `device` enqueuing on `stream` (torch's current stream by
     default); allocator "torch": its device memory comes from PyTorch's caching
-    allocator, None: from hipMalloc."""
+    allocator, None: from hipMalloc, an mc_alloc instance: from its callbacks
+    (the caller keeps it and its callbacks alive while the context lives)."""
     ctx = C.c_void_p()
-    if allocator not in ("torch", None):
-        raise ValueError(f"allocator must be 'torch' or None, not {allocator!r}")
-    al = C.byref(_TORCH_ALLOC) if allocator == "torch" else None
+    if isinstance(allocator, mc_alloc):
+        al = C.byref(allocator)
+    elif allocator in ("torch", None):
+        al = C.byref(_TORCH_ALLOC) if allocator == "torch" else None
+    else:
+        raise ValueError(f"allocator must be 'torch', None or an mc_alloc, not {allocator!r}")
     rc = load().mc_create(C.byref(ctx), device, _stream_handle(stream), al)
     _check(None, rc)
     return ctx
@@ -353,6 +358,17 @@ def mc_lookup_macro(ctx, E, mat, sig_a, sig_s, sorted_: bool = False):
     n = E.numel() if hasattr(E, "numel") else int(E)
     _check(ctx, load().mc_lookup_macro(ctx, n, _ptr(E), _ptr(mat), _ptr(sig_a), _ptr(sig_s),
                                        1 if sorted_ else 0))
+
+
+MC_NOALLOC_MAX_LOOKUPS = 1 << 20
+
+
+def mc_lookup_macro_noalloc(ctx, E, mat, sig_a, sig_s, sorted_: bool = False):
+    """mc_lookup_macro with the sort's scratch in the library's static device
+    array: allocates nothing; at most MC_NOALLOC_MAX_LOOKUPS pairs per call."""
+    n = E.numel() if hasattr(E, "numel") else int(E)
+    _check(ctx, load().mc_lookup_macro_noalloc(ctx, n, _ptr(E), _ptr(mat), _ptr(sig_a), _ptr(sig_s),
+                                               1 if sorted_ else 0))
 
 
 def mc_init_channels(ctx, channels):

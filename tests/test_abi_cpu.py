@@ -55,6 +55,8 @@ def test_binding_constants_match_header_and_oracle():
         assert getattr(mc, k) == _header_enum(k), k
     src = open(os.path.join(ROOT, "include", "mc.h")).read()
     assert mc.MC_MAX_CHANNELS == int(re.search(r"#define MC_MAX_CHANNELS (\d+)", src).group(1))
+    assert mc.MC_NOALLOC_MAX_LOOKUPS == 1 << int(re.search(r"#define MC_NOALLOC_MAX_LOOKUPS \(1u << (\d+)\)",
+                                                           src).group(1))
     assert mc.MC_N_GLOBAL == oracle.N_GLOBAL
     assert mc.MC_G_SPLIT == oracle.G_SPLIT and mc.MC_G_ROULETTE == oracle.G_ROULETTE
     from oracle import mlp
