@@ -496,7 +496,11 @@ __device__ __forceinline__ void wave_lds_sync()
 // window holds at most WIN_PTS points the wave reads it (energies and cross
 // sections) with one coalesced load each into LDS, and every lane bisects its
 // own bracket there and interpolates from there; a wider window falls back to
-// each lane searching global memory.  Per nuclide a wave then issues two
+// each lane searching global memory.  The search in LDS starts at a guess,
+// the bracket point at the lane's fractional position inside its hash bin
+// (points of a bin are roughly log-uniform), and walks from there to the
+// largest j of the bracket with E_j <= E: usually no step, so a nuclide costs
+// one round of LDS reads instead of a bisection's chain of dependent ones.  Per nuclide a wave then issues two
 // vector loads instead of one per bracket, probe and interval point.  Same
 // interval (with the one-off-bin walk), interpolation and sums in material
 // order as micro_group: the results bit for bit.  CHAN: the reaction
@@ -514,6 +518,21 @@ __device__ __forceinline__ void window_channels(const double *r0, int32_t K, dou
         if (xc < K) acc[xc] = acc[xc] + dens * (r0[xc] + f * (r1[xc] - r0[xc]));
 }
 
+// A wave-uniform read of a table that no kernel writes while it runs (the
+// material's nuclide rows), through the constant address space: the compiler
+// then issues a scalar load, and the vector loads in flight are not waited
+// for before it.
+template <class T>
+__device__ __forceinline__ T uniform_load(const T *p, int64_t i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const T __attribute__((address_space(4))) *const_ptr;
+    return ((const_ptr)p)[i];
+#else  // the host pass of the single-source compile never runs this
+    return p[i];
+#endif
+}
+
 template <bool CHAN>
 __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uint2 *sh, const int32_t *s_info,
                                                   uint32_t i, bool valid, double *we, double2 *wx, double *wc)
@@ -525,22 +544,24 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     const int32_t b0 = __builtin_amdgcn_readfirstlane(s_info[2]);
     const int32_t q0 = __builtin_amdgcn_readfirstlane(xs.mat_off[m]);
     const int32_t nk = __builtin_amdgcn_readfirstlane(xs.mat_off[m + 1]) - q0;
-    uint32_t p = 0;
-    double e = 0.0;
-    int32_t b = 0;
-    if (valid) {
-        p = a.list ? a.list[i] : i;
-        e = a.E[p];
-        b = (int32_t)(a.keys[i] % (uint32_t)xs.M);
-    }
+    // a lane past the end of the queue works on the wave's first particle
+    // (same values, never stored), so the nuclide loop needs no lane mask
+    const uint32_t i_own = valid ? i : i - (uint32_t)lane_id() + (uint32_t)(__ffsll((long long)vmask) - 1);
+    const uint32_t p = a.list ? a.list[i_own] : i_own;
+    const double e = a.E[p];
+    const int32_t b = (int32_t)(a.keys[i_own] % (uint32_t)xs.M);
     const int32_t bmin = __builtin_amdgcn_readfirstlane(__shfl(b, __ffsll((long long)vmask) - 1, 64));
     const int32_t bmax = __builtin_amdgcn_readfirstlane(__shfl(b, 63 - __clzll((long long)vmask), 64));
     const uint2 *hmin = sh + (bmin - b0) * nk, *hmax = sh + (bmax - b0) * nk, *hown = sh + (b - b0) * nk;
     const uint32_t lane = (uint32_t)lane_id();
-    double *E_w = we + (threadIdx.x & ~63u);
+    double *E_w = we + 1 + (threadIdx.x & ~63u);  // one pad point before and after the waves' rows
     double2 *X_w = wx + (threadIdx.x & ~63u);
     double *C_w = wc + (CHAN ? (threadIdx.x >> 6) * WIN_CHAN : 0);
     const int32_t K = CHAN ? xs.n_chan : 0;
+    // the lane's position inside its hash bin, in [0, 1): a guide only (the
+    // walk below decides the index), so single precision is enough
+    float tb = (__logf((float)e) - (float)xs.ln_emin) * (float)xs.inv_delta - (float)b;
+    tb = fminf(fmaxf(tb, 0.f), 1.f);
     const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
     const int32_t cp_mask = (1 << cp_sh) - 1;
     CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
@@ -553,7 +574,7 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     // nuclide q's window: first point and count (wave-uniform), and this
     // lane's point of it, loaded one nuclide ahead so that the loads of the
     // next window are in flight while the lanes search the current one
-    MatNuc mn_n = xs.mnuc[q0];
+    MatNuc mn_n = uniform_load(xs.mnuc, q0);
     uint32_t wlo_n = __builtin_amdgcn_readfirstlane(hmin[0].x);
     uint32_t wn_n = __builtin_amdgcn_readfirstlane(hmax[0].y) + 2u - wlo_n;  // points wlo .. wlo + wn - 1
     double pe = 0.0;
@@ -568,7 +589,7 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
         const double ce = pe;
         const double2 cx = px;
         if (q + 1 < nk) {
-            mn_n = xs.mnuc[q0 + q + 1];
+            mn_n = uniform_load(xs.mnuc, (int64_t)q0 + q + 1);
             wlo_n = __builtin_amdgcn_readfirstlane(hmin[q + 1].x);
             wn_n = __builtin_amdgcn_readfirstlane(hmax[q + 1].y) + 2u - wlo_n;
             if (wn_n <= (uint32_t)WIN_PTS && lane < wn_n) {
@@ -604,14 +625,36 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                 X_w[lane] = cx;
             }
             wave_lds_sync();
-            if (valid) {
-                uint32_t lo = hown[q].x, hi = hown[q].y;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1u) >> 1;
-                    if (E_w[mid - wlo] <= e) lo = mid; else hi = mid - 1u;
+            {
+                // largest k in the bracket [lo, hi] with E_k <= e (lo when
+                // none).  The guess j (nearest to the lane's position in the
+                // bin) and its neighbours are read at once: k is j - 1, j or
+                // j + 1 for all but ~0.05 % of lanes, which walk on.  The
+                // window holds lo .. hi + 1; E_w[j - 1] and E_w[j + 2] may
+                // lie one past it (padding or a neighbour's row: then unused).
+                const uint32_t lo = hown[q].x, hi = hown[q].y;
+                uint32_t j = lo + (uint32_t)(tb * (float)(hi - lo) + 0.5f);
+                j = j < hi ? j : hi;
+                const double *Ej = E_w + (int32_t)(j - wlo);
+                const double em = Ej[-1], eg = Ej[0], eg1 = Ej[1], ep = Ej[2];
+                const bool dn = j > lo && e < eg;
+                const bool up = !dn && j < hi && e >= eg1;
+                uint32_t k = dn ? j - 1u : (up ? j + 1u : j);
+                double e0 = dn ? em : (up ? eg1 : eg);
+                double e1 = dn ? eg : (up ? ep : eg1);
+                if ((k > lo && e < e0) || (k < hi && e >= e1)) {
+                    while (k > lo && e < e0) {
+                        --k;
+                        e1 = e0;
+                        e0 = E_w[k - wlo];
+                    }
+                    while (k < hi && e >= e1) {
+                        ++k;
+                        e0 = e1;
+                        e1 = E_w[k + 1u - wlo];
+                    }
                 }
-                ii = lo;
-                double e0 = E_w[ii - wlo], e1 = E_w[ii + 1u - wlo];
+                ii = k;
                 double2 x0 = X_w[ii - wlo], x1 = X_w[ii + 1u - wlo];
                 if ((e < e0 && ii > 0u) || (e >= e1 && ii + 2u < mn.len)) {
                     // hash bin computed one off: walk to the defined index
@@ -633,7 +676,7 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                 }
             }
             wave_lds_sync();
-        } else if (valid) {
+        } else {
             ii = grid_find(g, mn.len, hown[q].x, hown[q].y, e);
             const double e0 = g[ii], e1 = g[ii + 1u];
             const double2 x0 = x[ii], x1 = x[ii + 1u];
@@ -642,12 +685,10 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
             sg = x0.y + f * (x1.y - x0.y);
             if (CHAN) window_channels<CHAN>(xs.xc + (size_t)(mn.off + ii) * (size_t)K, K, mn.dens, f, acc);
         }
-        if (valid) {
-            sa = sa + mn.dens * c;
-            ss = ss + mn.dens * sg;
-            const int32_t done = q + 1;
-            if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
-        }
+        sa = sa + mn.dens * c;
+        ss = ss + mn.dens * sg;
+        const int32_t done = q + 1;
+        if ((done & cp_mask) == 0 && valid) cpw.put((done >> cp_sh) - 1, ss);
     }
     if (!valid) return 0;
     if (cp_sh != 30) cpw.finish(nk >> cp_sh);
@@ -672,7 +713,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
 {
     __shared__ uint2 sh[LDS_HASH_PAIRS];
     __shared__ int32_t s_info[4];
-    __shared__ double s_we[WIN ? WG : 1];
+    __shared__ double s_we[WIN ? WG + 2 : 1];
     __shared__ double2 s_wx[WIN ? WG : 1];
     __shared__ double s_wc[(WIN && CHAN) ? WAVES * WIN_CHAN : 1];
     const XsDev &xs = a.xs;
