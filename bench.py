@@ -33,6 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# particle state one event kernel streams per event (position, direction,
+# energy, weight, cross sections, ids, counters and flags: ~130 B per slot in
+# the bank, plus the queue index and the fields written back)
+STATE_BYTES_PER_EVENT = 150
 METRIC = "active particles/s and macro-XS lookups/s (HBM GB/s % peak); FOM learned vs analog"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lookup_traffic_c3.json")
 # launch shapes found by the library's autotuner on an MI355X (its cache format:
@@ -60,6 +64,31 @@ def measured_traffic():
     if d.get("kernel_digest") != kernel_source_digest():
         return None
     return d
+
+
+def streaming_rooflines(one, glob):
+    """HBM rooflines of the event kernels that stream particle state, from a
+    batch run with every launch timed: per event STATE_BYTES_PER_EVENT bytes;
+    events are flights (k_advance), surface crossings (queue split and
+    k_cross) and collisions (k_collide with its re-gathers), the last two as
+    the batch's shares of its flights."""
+    from paper_2403_12345_amd import mc
+    flights = one["flights"]
+    if not flights:
+        return None
+    ncoll, ncross = float(glob[mc.MC_G_NCOLL]), float(glob[mc.MC_G_NCROSS])
+    f_coll = ncoll / (ncoll + ncross) if ncoll + ncross > 0 else 0.0
+    out = {"bytes_per_event": STATE_BYTES_PER_EVENT, "flights": flights, "launches": one["iterations"],
+           "collision_share_of_flights": f_coll}
+    for name, ms, events in (("k_advance", one["advance_ms"], flights),
+                             ("k_split+k_cross", one["cross_ms"], flights * (1.0 - f_coll)),
+                             ("k_collide", one["collide_ms"], flights * f_coll)):
+        if ms <= 0:
+            continue
+        gbs = STATE_BYTES_PER_EVENT * events / (ms / 1e3) / 1e9
+        out[name] = {"ms": ms, "events": events, "ns_per_event": ms * 1e6 / events if events else None,
+                     "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
 
 
 def cpu_model() -> str:
@@ -458,7 +487,7 @@ def pmc_per_dispatch(dirs, kernel_regex: str):
     return {c: [v[k] for k in sorted(v)] for c, v in per.items()}
 
 
-def traffic_summary(lookup_dirs, copy_dirs, roof_json: str, out_path: str):
+def traffic_summary(lookup_dirs, copy_dirs, roof_json: str, out_path: str, stream_dirs=None):
     """Bytes the lookup kernel moves between L2 and memory, per macroscopic
     lookup, from rocprofv3 counter runs of the roofline batch (bench.py --mode
     c3roof, whose JSON line gives the batch's lookups), and the same counters
@@ -479,7 +508,8 @@ def traffic_summary(lookup_dirs, copy_dirs, roof_json: str, out_path: str):
 
     n_lookups = roof["lookups"]
     launches = roof["lookup_launches"]
-    out = {"kernel_digest": roof["kernel_digest"], "lookups": n_lookups, "launches": launches,
+    out = {"kernel_digest": roof["kernel_digest"], "source": "profiles/k_lookup_c3_transport.md",
+           "lookups": n_lookups, "launches": launches,
            "dispatches_counted": {c: len(v) for c, v in lk.items()}}
     rd = {b: tot(lk, f"TCC_EA0_RDREQ_{b}B_sum") for b in (32, 64, 128)}
     if all(v is not None for v in rd.values()):
@@ -536,7 +566,21 @@ def traffic_summary(lookup_dirs, copy_dirs, roof_json: str, out_path: str):
         out["per_wave_nuclide"] = {c: v / wave_nuc for c, v in sq.items()
                                    if c.startswith("SQ_INSTS") or c.startswith("SQ_INST_")}
         out["sq_totals"] = sq
-    out["source_runs"] = {"lookup": list(lookup_dirs), "copy": list(copy_dirs or []), "roofline_batch": roof_json}
+    # the event kernels that stream particle state: DRAM-side bytes per flight
+    if stream_dirs:
+        st_out = {}
+        for name, rx in (("k_advance", r"k_advance"), ("k_split", r"k_split_"), ("k_cross", r"k_cross"),
+                         ("k_collide", r"k_collide"), ("k_slots", r"k_slots_")):
+            d = pmc_per_dispatch(stream_dirs, rx)
+            r, w = tot(d, "TCC_EA0_RDREQ_DRAM_32B_sum"), tot(d, "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum")
+            if r is None or w is None or not roof.get("flights"):
+                continue
+            st_out[name] = {"dispatches": len(d["TCC_EA0_RDREQ_DRAM_32B_sum"]),
+                            "dram_read_bytes_per_flight": 32 * r / roof["flights"],
+                            "dram_write_bytes_per_flight": 32 * w / roof["flights"]}
+        out["streaming_per_flight"] = st_out
+    out["source_runs"] = {"lookup": list(lookup_dirs), "copy": list(copy_dirs or []), "roofline_batch": roof_json,
+                          "streaming": list(stream_dirs or [])}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     return out
@@ -562,6 +606,8 @@ def main():
                                                               "of the roofline batch")
     ap.add_argument("--copy-dirs", nargs="*", default=[], help="traffic mode: the same counters on --mode copy")
     ap.add_argument("--roof-json", default="", help="traffic mode: the JSON line printed by --mode c3roof")
+    ap.add_argument("--stream-dirs", nargs="*", default=[], help="traffic mode: DRAM counter runs of the event "
+                                                                 "kernels that stream particle state")
     ap.add_argument("--traffic-out", default=TRAFFIC_FILE, help="traffic mode: where to write the summary")
     ap.add_argument("--mode", choices=("full", "c3", "c3roof", "traffic", "lookup", "copy", "set", "fom", "c2", "union",
                                        "multipole"),
@@ -576,7 +622,8 @@ def main():
                   "no_channels", "no_union", "no_multipole"):
             setattr(args, k, True)
     if args.mode == "traffic":  # host only: summarise counter runs
-        print(json.dumps(traffic_summary(args.pmc_dirs, args.copy_dirs, args.roof_json, args.traffic_out)))
+        print(json.dumps(traffic_summary(args.pmc_dirs, args.copy_dirs, args.roof_json, args.traffic_out,
+                                         args.stream_dirs)))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X and has no multi-GPU path",
@@ -629,6 +676,8 @@ def main():
             "histories": n, "tuning": {**tuning, "loops": 1}, "lookups": one["lookups"],
             "nuclide_lookups": one["nuclide_lookups"], "lookup_launches": one["lookup_launches"],
             "lookup_ms": one["lookup_ms"], "lookup_bytes": one["lookup_bytes"], "batch_ms": one["batch_ms"],
+            "flights": one["flights"], "advance_ms": one["advance_ms"], "cross_ms": one["cross_ms"],
+            "collide_ms": one["collide_ms"], "iterations": one["iterations"],
             "kernel_digest": kernel_source_digest()}}), flush=True)
         return
     t = Transport(prob, device=0)
@@ -656,8 +705,10 @@ def main():
     # every lookup launch bracketed by HIP events on its stream (with several
     # loops a launch shares the GPU with the other loops' kernels)
     mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
+    t.reset()
     t.run_batch(seed, (args.warmup + args.steps) * n, n, time_kernels=True)
     one = t.stats()
+    glob_one, _, _ = t.tallies(mc.MC_T_GLOBAL)
     mc.mc_set_tuning(t.ctx, **tuning)
 
     inactive = None
@@ -669,6 +720,7 @@ def main():
         inactive = n / (time.perf_counter() - t1)
     t.close()
 
+    streaming = streaming_rooflines(one, glob_one)
     launches = max(one["lookup_launches"], 1)
     avg_launch_s = one["lookup_ms"] / 1e3 / launches
     lookups_per_launch = one["lookups"] / launches
@@ -741,6 +793,7 @@ def main():
         "total_track": float(glob[mc.MC_G_TRACK]),
         "mesh_underflow": steps_stats["mesh_underflow"],
         "inactive_particles_per_s": inactive,
+        "streaming_kernels": streaming,
     }
     c2 = mcsynth.c2_problem()
     if not args.no_c2:

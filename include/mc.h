@@ -185,6 +185,12 @@ typedef struct mc_stats {
                                    collision estimator) that were positive but
                                    below the fixed-point resolution 2^-33 weight*cm
                                    and so added nothing */
+    uint64_t flights;           /* particles the flight kernel advanced (one per
+                                   alive particle and iteration; the tail's are
+                                   not counted) */
+    double advance_ms;          /* summed flight-kernel time (time_kernels = 1), ms */
+    double cross_ms;            /* summed queue-split and surface-crossing time, ms */
+    double collide_ms;          /* summed collision time (with its queue sort), ms */
 } mc_stats;
 
 /* Batch statistics of one tally (mc_get_tallies).  s1 and s2 are set by the

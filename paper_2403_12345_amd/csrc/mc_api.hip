@@ -588,6 +588,24 @@ int mc_init_materials(mc_ctx *ctx, int32_t n_nuc, const int32_t *grid_len, const
     return MC_OK;
 }
 
+// Adds the counters of q (one batch or one loop) into a; the wall time, the
+// iteration count and the algorithmic lookup bytes are set by the caller.
+static void add_stats(mc_stats &a, const mc_stats &q)
+{
+    a.lookups += q.lookups;
+    a.nuclide_lookups += q.nuclide_lookups;
+    a.lookup_launches += q.lookup_launches;
+    a.sorted_lookups += q.sorted_lookups;
+    a.lost += q.lost;
+    a.lookup_ms += q.lookup_ms;
+    a.tail_particles += q.tail_particles;
+    a.mesh_underflow += q.mesh_underflow;
+    a.flights += q.flights;
+    a.advance_ms += q.advance_ms;
+    a.cross_ms += q.cross_ms;
+    a.collide_ms += q.collide_ms;
+}
+
 static int timing_event_pair(mc_ctx *ctx, size_t k);
 
 // Coefficients a_1 .. a_N of the rational Faddeeva series (Weideman 1994):
@@ -1006,6 +1024,7 @@ static int build_geometry(mc_ctx *ctx, const mc_geometry_desc *d, int32_t n_mat,
         g.mesh_dims[k] = d->mesh_dims[k];
         g.mesh_lo[k] = d->mesh_box[2 * k];
         g.mesh_hi[k] = d->mesh_box[2 * k + 1];
+        if (d->tally_kind == MC_TALLY_MESH) g.mesh_h[k] = (g.mesh_hi[k] - g.mesh_lo[k]) / (double)g.mesh_dims[k];
     }
     g.e_cut = d->energy_cutoff;
     int32_t *pm, *lm;
@@ -1355,6 +1374,37 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
 
     mc_stats s{};
     size_t n_timed = 0;
+    // with time_kernels: the kind of each timed launch (event pair n_timed)
+    enum { T_LOOKUP = 0, T_ADVANCE = 1, T_CROSS = 2, T_COLLIDE = 3 };
+    std::vector<int> timed_kind;
+    auto time_begin = [&](int kind) -> int {
+        if (!opts.time_kernels) return MC_OK;
+        int r = timing_event_pair(ctx, n_timed);
+        if (r) return r;
+        timed_kind.push_back(kind);
+        HIPCHK(hipEventRecord(ctx->ev_a[n_timed], st));
+        return MC_OK;
+    };
+    auto time_end = [&]() -> int {
+        if (!opts.time_kernels) return MC_OK;
+        HIPCHK(hipEventRecord(ctx->ev_b[n_timed], st));
+        ++n_timed;
+        return MC_OK;
+    };
+    // the timed launches' durations, summed per kind into s
+    auto sum_timed = [&]() -> int {
+        for (size_t k = 0; k < n_timed; ++k) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ctx->ev_a[k], ctx->ev_b[k]));
+            switch (timed_kind[k]) {
+            case T_LOOKUP: s.lookup_ms += t; break;
+            case T_ADVANCE: s.advance_ms += t; break;
+            case T_CROSS: s.cross_ms += t; break;
+            default: s.collide_ms += t; break;
+            }
+        }
+        return MC_OK;
+    };
     HIPCHK(hipEventRecord(ctx->ev_batch0, st));
     uint64_t it = 0;
     // every history ends within max_events + 1 iterations of its start, so the
@@ -1408,22 +1458,21 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
             } else {
                 l.list = b.L;
             }
-            if (opts.time_kernels) {
-                rc = timing_event_pair(ctx, n_timed);
-                if (rc) return rc;
-                HIPCHK(hipEventRecord(ctx->ev_a[n_timed], st));
-            }
+            if ((rc = time_begin(T_LOOKUP))) return rc;
             HIPCHK(launch_lookup(l, st));
-            if (opts.time_kernels) {
-                HIPCHK(hipEventRecord(ctx->ev_b[n_timed], st));
-                ++n_timed;
-            }
+            if ((rc = time_end())) return rc;
             s.lookups += c.nL;
             s.lookup_launches += 1;
         }
+        if ((rc = time_begin(T_ADVANCE))) return rc;
         HIPCHK(launch_advance(b, g, tal, W, dc, c.nA, seed, max_events, log ? 1 : 0, st));
+        if ((rc = time_end())) return rc;
+        s.flights += c.nA;
+        if ((rc = time_begin(T_CROSS))) return rc;
         HIPCHK(launch_split(b, dc, c.nA, st));
         HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
+        if ((rc = time_end())) return rc;
+        if ((rc = time_begin(T_COLLIDE))) return rc;
         // collisions re-gather sigma_s: in (material, energy) order when the
         // queues are long enough to sort (the sorted lookup queue is no longer
         // needed, its buffers take the sorted collide queue)
@@ -1434,6 +1483,7 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
             qc = b.Ls;
         }
         HIPCHK(launch_collide(b, qc, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
+        if ((rc = time_end())) return rc;
         if (W.kind != WW_OFF) HIPCHK(launch_ww_flush(b, W, dc, st));
     }
     if (!stats) {  // a worker of concurrent loops or batches: its caller forms the statistics
@@ -1441,11 +1491,7 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
         unsigned long long dstat[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(dstat, ctx->dstat, sizeof(dstat), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        for (size_t k = 0; k < n_timed; ++k) {
-            float t = 0.f;
-            HIPCHK(hipEventElapsedTime(&t, ctx->ev_a[k], ctx->ev_b[k]));
-            s.lookup_ms += t;
-        }
+        if ((rc = sum_timed())) return rc;
         s.iterations = it;
         s.nuclide_lookups = dstat[0];
         s.lost = dstat[1];
@@ -1481,11 +1527,7 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev_batch0, ctx->ev_batch1));
     s.batch_ms = ms;
-    for (size_t k = 0; k < n_timed; ++k) {
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, ctx->ev_a[k], ctx->ev_b[k]));
-        s.lookup_ms += t;
-    }
+    if ((rc = sum_timed())) return rc;
     s.iterations = it;
     s.nuclide_lookups = dstat[0];
     s.lost = dstat[1];
@@ -1682,13 +1724,8 @@ static int run_concurrent(mc_ctx *ctx, int L, uint64_t seed, uint64_t first_pid,
     mc_stats s{};
     for (int l = 0; l < L; ++l) {
         const mc_stats &q = ctx->workers[l]->stats;
-        s.lookups += q.lookups;
-        s.nuclide_lookups += q.nuclide_lookups;
-        s.lookup_launches += q.lookup_launches;
-        s.sorted_lookups += q.sorted_lookups;
-        s.lookup_ms += q.lookup_ms;
-        s.tail_particles += q.tail_particles;
-        s.lost += q.lost;
+        add_stats(s, q);
+        s.mesh_underflow = 0;  // counted once below from the shared mesh arrays
         s.iterations = std::max(s.iterations, q.iterations);
     }
     s.batch_ms = ms;
@@ -1755,15 +1792,8 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
             if (rc) return rc;
             const mc_stats &q = ctx->stats;
             tot.iterations += q.iterations;
-            tot.lookups += q.lookups;
-            tot.nuclide_lookups += q.nuclide_lookups;
-            tot.lookup_launches += q.lookup_launches;
-            tot.sorted_lookups += q.sorted_lookups;
-            tot.lost += q.lost;
             tot.lookup_bytes += q.lookup_bytes;
-            tot.lookup_ms += q.lookup_ms;
-            tot.tail_particles += q.tail_particles;
-            tot.mesh_underflow += q.mesh_underflow;
+            add_stats(tot, q);
         }
         tot.batch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         ctx->stats = tot;
@@ -1836,14 +1866,7 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
             const mc_stats &q = w->stats;
             mc_stats &a = tot[l];
             a.iterations += q.iterations;
-            a.lookups += q.lookups;
-            a.nuclide_lookups += q.nuclide_lookups;
-            a.lookup_launches += q.lookup_launches;
-            a.sorted_lookups += q.sorted_lookups;
-            a.lost += q.lost;
-            a.lookup_ms += q.lookup_ms;
-            a.tail_particles += q.tail_particles;
-            a.mesh_underflow += q.mesh_underflow;
+            add_stats(a, q);
         }
     };
     std::vector<std::thread> threads;
@@ -1878,14 +1901,7 @@ int mc_run_batches(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, u
     mc_stats s{};
     for (const mc_stats &a : tot) {
         s.iterations += a.iterations;
-        s.lookups += a.lookups;
-        s.nuclide_lookups += a.nuclide_lookups;
-        s.lookup_launches += a.lookup_launches;
-        s.sorted_lookups += a.sorted_lookups;
-        s.lost += a.lost;
-        s.lookup_ms += a.lookup_ms;
-        s.tail_particles += a.tail_particles;
-        s.mesh_underflow += a.mesh_underflow;
+        add_stats(s, a);
     }
     s.batch_ms = ms;
     s.lookup_bytes = (36ull + 8ull * (uint64_t)ctx->n_chan) * s.lookups +

@@ -560,8 +560,7 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     const int32_t K = CHAN ? xs.n_chan : 0;
     // the lane's position inside its hash bin, in [0, 1): a guide only (the
     // walk below decides the index), so single precision is enough
-    float tb = (__logf((float)e) - (float)xs.ln_emin) * (float)xs.inv_delta - (float)b;
-    tb = fminf(fmaxf(tb, 0.f), 1.f);
+    const float tb = bin_position(xs, e, b);
     const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
     const int32_t cp_mask = (1 << cp_sh) - 1;
     CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
@@ -633,8 +632,7 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                 // window holds lo .. hi + 1; E_w[j - 1] and E_w[j + 2] may
                 // lie one past it (padding or a neighbour's row: then unused).
                 const uint32_t lo = hown[q].x, hi = hown[q].y;
-                uint32_t j = lo + (uint32_t)(tb * (float)(hi - lo) + 0.5f);
-                j = j < hi ? j : hi;
+                const uint32_t j = bracket_guess(lo, hi, tb);
                 const double *Ej = E_w + (int32_t)(j - wlo);
                 const double em = Ej[-1], eg = Ej[0], eg1 = Ej[1], ep = Ej[2];
                 const bool dn = j > lo && e < eg;
@@ -773,6 +771,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     if (m >= 0) {
     const int32_t q0 = xs.mat_off[m];
     const int32_t nk = xs.mat_off[m + 1] - q0;
+    const float tb = bin_position(xs, e, b);
     double sa = 0.0, ss = 0.0;
     const MatNuc *mnuc = xs.mnuc + q0;
     const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
@@ -789,7 +788,7 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
             const int32_t cnt = nk - q < ILP ? nk - q : ILP;
             double dens[ILP], c[ILP], s[ILP], fr[ILP];
             uint32_t ix[ILP], pt[ILP];
-            micro_group<ILP>(xs, mnuc, h0, nk, q, cnt, e, dens, ix, c, s, fr, pt);
+            micro_group<ILP>(xs, mnuc, h0, nk, q, cnt, e, tb, dens, ix, c, s, fr, pt);
             if (CHAN) channel_group<ILP>(xs, cnt, dens, fr, pt, acc);
             // the sum runs in material order, one nuclide after the other
 #pragma unroll

@@ -100,7 +100,10 @@ __device__ __forceinline__ int32_t mesh_index(const GeomDev &g, double x, double
 // flight inside the mesh box (slab intersection: the entry and exit of the
 // flight through each pair of box planes), walked cell by cell by a 3-D
 // digital differential analyser, adding w * length per cell.  Track outside
-// the box scores nothing.
+// the box scores nothing.  Distances to planes are divided by the direction
+// component as written (a product with its reciprocal would cut the flight
+// into extra slivers of a few ulps where a plane's distance and the box's
+// clip round apart); cell sizes come precomputed with the geometry.
 __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, double y, double z, double u,
                                    double v, double w, double d, double wt)
 {
@@ -118,24 +121,25 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
         }
     }
     if (!(t_out > t_in)) return;
-    double h[3], tnext[3], tdelta[3];
+    double tnext[3], tdelta[3];
     int32_t c[3], step[3];
     // first cell: the one holding the clipped flight's first point (nudged
     // along the flight by a hair so a start on a mesh plane picks the cell ahead)
     const double tq = t_in + fmin(t_out - t_in, 1e-9) * 0.5;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        h[k] = (g.mesh_hi[k] - g.mesh_lo[k]) / g.mesh_dims[k];
+        const double h = g.mesh_h[k];
         const double q = r0[k] + dir[k] * tq;
-        int32_t v0 = (int32_t)floor((q - g.mesh_lo[k]) / h[k]);
+        int32_t v0 = (int32_t)floor((q - g.mesh_lo[k]) / h);
         c[k] = v0 < 0 ? 0 : (v0 > g.mesh_dims[k] - 1 ? g.mesh_dims[k] - 1 : v0);
         if (dir[k] > 0.0) {
             step[k] = 1;
-            tnext[k] = (g.mesh_lo[k] + (c[k] + 1) * h[k] - r0[k]) / dir[k];
-            tdelta[k] = h[k] / dir[k];
+            tnext[k] = (g.mesh_lo[k] + (c[k] + 1) * h - r0[k]) / dir[k];
+            tdelta[k] = h / dir[k];
         } else if (dir[k] < 0.0) {
             step[k] = -1;
-            tnext[k] = (g.mesh_lo[k] + c[k] * h[k] - r0[k]) / dir[k];
-            tdelta[k] = -h[k] / dir[k];
+            tnext[k] = (g.mesh_lo[k] + c[k] * h - r0[k]) / dir[k];
+            tdelta[k] = -h / dir[k];
         } else {
             step[k] = 0;
             tnext[k] = INFINITY;
@@ -273,7 +277,9 @@ template <int ILP, bool CHAN = false>
 __device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = nullptr, double *cp_row = nullptr)
 {
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
-    const uint2 *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
+    const int32_t bin = hash_bin(xs, p.E);
+    const float tb = bin_position(xs, p.E, bin);
+    const uint2 *h = hash_row(xs, p.mat, bin, nk);
     double sa = 0.0, ss = 0.0;
     const int32_t cp_sh = cp_row && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
     const int32_t cp_mask = (1 << cp_sh) - 1;
@@ -287,7 +293,7 @@ __device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = 
         const int32_t cnt = nk - q < ILP ? nk - q : ILP;
         double dens[ILP], c[ILP], s[ILP], fr[ILP];
         uint32_t ix[ILP], pt[ILP];
-        micro_group<ILP>(xs, xs.mnuc + q0, h, nk, q, cnt, p.E, dens, ix, c, s, fr, pt);
+        micro_group<ILP>(xs, xs.mnuc + q0, h, nk, q, cnt, p.E, tb, dens, ix, c, s, fr, pt);
         if (CHAN) channel_group<ILP>(xs, cnt, dens, fr, pt, acc);
 #pragma unroll
         for (int k = 0; k < ILP; ++k) {
@@ -450,21 +456,23 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
     }
     const double target = rng.next() * p.Ss;
     const int32_t q0 = xs.mat_off[p.mat], nk = xs.mat_off[p.mat + 1] - q0;
-    const uint2 *h = hash_row(xs, p.mat, hash_bin(xs, p.E), nk);
+    const int32_t bin = hash_bin(xs, p.E);
+    const float tb = bin_position(xs, p.E, bin);
+    const uint2 *h = hash_row(xs, p.mat, bin, nk);
     double cum = 0.0;
     int32_t pick = -1, qstart = 0;
     const int32_t ncp = cp ? cp_count(nk) : 0;
     if (ncp > 0) {
-        // the first checkpoint at or above the target bounds the segment
-        // (checkpoints never decrease: bisection for the first cp[j] >= target)
-        int32_t j = 0, len = ncp;
-        while (len > 0) {
-            const int32_t half = len >> 1;
-            if (cp[j + half] < target) {
-                j += half + 1;
-                len -= half + 1;
-            } else {
-                len = half;
+        // the first checkpoint at or above the target bounds the segment:
+        // checkpoints never decrease, so its index is the count of those below
+        // the target; the row (16-byte pairs) is read in one round of loads
+        int32_t j = 0;
+#pragma unroll
+        for (int32_t k = 0; k < CP_MAX; k += 2) {
+            if (k < ncp) {
+                const double2 v = *reinterpret_cast<const double2 *>(cp + k);
+                j += v.x < target ? 1 : 0;
+                j += (k + 1 < ncp && v.y < target) ? 1 : 0;
             }
         }
         if (j > 0) {
@@ -477,7 +485,7 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
         const int32_t cnt = nk - q < CILP ? nk - q : CILP;
         double dens[CILP], c[CILP], sg[CILP];
         uint32_t ix[CILP];
-        micro_group<CILP>(xs, xs.mnuc + q0, h, nk, q, cnt, p.E, dens, ix, c, sg);
+        micro_group<CILP>(xs, xs.mnuc + q0, h, nk, q, cnt, p.E, tb, dens, ix, c, sg);
 #pragma unroll
         for (int k = 0; k < CILP; ++k) {
             if (k < cnt && !done) {

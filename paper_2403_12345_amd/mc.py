@@ -61,7 +61,8 @@ class mc_stats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("lookups", C.c_uint64), ("nuclide_lookups", C.c_uint64),
                 ("lookup_launches", C.c_uint64), ("sorted_lookups", C.c_uint64), ("lost", C.c_uint64),
                 ("lookup_bytes", C.c_uint64), ("lookup_ms", C.c_double), ("batch_ms", C.c_double),
-                ("tail_particles", C.c_uint64), ("mesh_underflow", C.c_uint64)]
+                ("tail_particles", C.c_uint64), ("mesh_underflow", C.c_uint64), ("flights", C.c_uint64),
+                ("advance_ms", C.c_double), ("cross_ms", C.c_double), ("collide_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

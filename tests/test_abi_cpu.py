@@ -33,7 +33,7 @@ def test_struct_sizes_match_header_layout():
     # mc_history is 48 bytes (4 int32, 1 uint64, 3 double); the run options 48
     assert mc.HISTORY_DTYPE.itemsize == 48
     assert ctypes.sizeof(mc.mc_run_opts) == 48
-    assert ctypes.sizeof(mc.mc_stats) == 8 * 11
+    assert ctypes.sizeof(mc.mc_stats) == 8 * 15
     assert ctypes.sizeof(mc.mc_tally_meta) == 8 * 5
     assert ctypes.sizeof(mc.mc_alloc) == 8 * 3
     assert ctypes.sizeof(mc.mc_ww_desc) == 6 * 4 + 10 * 8

@@ -38,11 +38,14 @@ def test_committed_traffic_file_is_well_formed():
     with open(path) as fh:
         d = json.load(fh)
     assert len(d["kernel_digest"]) == 16
-    # DRAM bytes per lookup: read bytes by request size (from the DRAM side
-    # only) plus written bytes, over the lookups of the profiled launches
+    # DRAM-side bytes per lookup: read sectors plus written sectors (32 B each)
+    # over the lookups of the profiled batch, and the copy calibration's check
+    # that those counters count true bytes
     assert d["dram_bytes_per_lookup"] == pytest.approx(
-        (d["dram_read_bytes"] + d["write_bytes"]) / d["lookups"], rel=1e-6)
+        d["dram_read_bytes_per_lookup"] + d["dram_write_bytes_per_lookup"], rel=1e-9)
     assert 0 < d["dram_bytes_per_lookup"] < 36 + 56 * 300 * 8
+    for k in ("dram_read", "dram_write", "read_by_size"):
+        assert d["copy_scale"][k] == pytest.approx(1.0, abs=0.01)
     assert os.path.exists(os.path.join(ROOT, d["source"]))
 
 
