@@ -602,6 +602,8 @@ def main():
     ap.add_argument("--no-union", action="store_true", help="skip the hash-grid against union-grid comparison")
     ap.add_argument("--no-multipole", action="store_true", help="skip the windowed-multipole lookup benchmark")
     ap.add_argument("--loops", type=int, default=0, help="event loops of the timed steps (0: the tuned count)")
+    ap.add_argument("--tune", nargs="*", default=[], metavar="KEY=VALUE",
+                    help="override tuned launch shapes of the headline workload (mc_tuning fields)")
     ap.add_argument("--pmc-dirs", nargs="*", default=[], help="traffic mode: rocprofv3 --pmc output directories "
                                                               "of the roofline batch")
     ap.add_argument("--copy-dirs", nargs="*", default=[], help="traffic mode: the same counters on --mode copy")
@@ -669,6 +671,7 @@ def main():
     if args.mode == "c3roof":
         with Transport(prob, device=0) as t:
             tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n, args.tuning_cache)
+            tuning = {**tuning, **{k: int(v) for k, v in (kv.split("=", 1) for kv in args.tune)}}
             mc.mc_set_tuning(t.ctx, **{**tuning, "loops": 1})
             t.run_batch(seed, 0, n, time_kernels=True)
             one = t.stats()
@@ -684,8 +687,9 @@ def main():
     # launch shapes from the library's autotuner (from its cache when this
     # problem was tuned on this device kind, else timed on batches of other pids)
     tuning = mc.mc_autotune(t.ctx, seed, 1 << 40, n, args.tuning_cache)
-    if args.loops:
-        tuning = {**tuning, "loops": args.loops}
+    if args.loops or args.tune:
+        over = {k: int(v) for k, v in (kv.split("=", 1) for kv in args.tune)}
+        tuning = {**tuning, **over, **({"loops": args.loops} if args.loops else {})}
         mc.mc_set_tuning(t.ctx, **tuning)
     if args.warmup:
         t.run_batches(seed, 0, n, args.warmup)

@@ -2563,25 +2563,17 @@ int mc_autotune(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, cons
     const int32_t n_cap = (int32_t)std::min<uint64_t>(n, kMaxTunedInFlight);
     cur.in_flight = (int32_t)std::min<uint64_t>(n, kDefaultInFlight);
     cur.collide_sort_min = 0;  // follows sort_min unless the search turns it off
-    // each trial, timed per batch: 12 batches through mc_run_batches (whole
-    // rounds for 1 to 4 loops, so that loops > 1 shows its overlap of
-    // consecutive batches); batches of 2^22 histories or more are run one at
-    // a time, as mc_run_batch runs them (split over the loops), twice
-    const bool single = n >= (1ull << 22);
+    // each trial, timed per batch through mc_run_batches (consecutive batches,
+    // each event loop taking whole batches): 12 batches (whole rounds for 1
+    // to 4 loops, so that loops > 1 shows its overlap of consecutive
+    // batches); batches of 2^22 histories or more: one round, one batch per
+    // loop (at least two)
+    const bool large = n >= (1ull << 22);
     auto trial = [&](const mc_tuning &c, double &ms) -> int {
         ctx->tune = c;
-        if (single) {
-            double tot = 0.0;
-            for (int k = 0; k < 2; ++k) {
-                const int r = mc_run_batch(ctx, seed, first_pid, n, nullptr);
-                if (r) return r;
-                tot += ctx->stats.batch_ms;
-            }
-            ms = tot / 2.0;
-            return MC_OK;
-        }
-        const int r = mc_run_batches(ctx, seed, first_pid, n, 12, nullptr);
-        ms = ctx->stats.batch_ms / 12.0;
+        const uint64_t nb = large ? (uint64_t)std::max(2, (int)c.loops) : 12u;
+        const int r = mc_run_batches(ctx, seed, first_pid, n, nb, nullptr);
+        ms = ctx->stats.batch_ms / (double)nb;
         return r;
     };
     double best_ms = 0.0;
