@@ -399,24 +399,28 @@ def problem_set_bench(batches: int = 3):
 
 
 def fom_bench(analog_histories: int = 40_000_000, learned_histories: int = 4_000_000, analog_batches: int = 40,
-              batches: int = 20):
+              batches: int = 20, shield: bool = False, linear_histories: int = 0):
     """Deep-penetration slab: figure of merit 1/(R^2 T) of the far-face leakage
     with windows from the learned importance map (bootstrap, training, one
     refinement round) against analog transport, the two estimates checked for
     agreement within 3 sigma.  Also the linear bootstrap windows, and the
-    learned FOM with the generation and training time added to T."""
+    learned FOM with the generation and training time added to T.  shield:
+    the slab whose attenuation sits in a thin dense shield deep inside, where
+    the importance is far from linear in depth."""
     import math
 
     import mcsynth
     from paper_2403_12345_amd import importance
     from paper_2403_12345_amd.transport import Transport
 
-    prob = mcsynth.c5_problem()
+    prob = mcsynth.c5_shield_problem() if shield else mcsynth.c5_problem()
     seed = prob.seed
-    out = {"workload": "3-layer slab 100/10/90 cm, Sigma_t(2 MeV) 0.2/1.5/0.2 per cm, synthetic "
-                       "absorber/scatterers (10 nuclides), normal 2 MeV beam, detector = leakage through x = 200",
+    linear_histories = linear_histories or learned_histories
+    layers = "160/12/28 cm, Sigma_t(2 MeV) 0.05/3.0/0.05" if shield else "100/10/90 cm, Sigma_t(2 MeV) 0.2/1.5/0.2"
+    out = {"workload": f"3-layer slab {layers} per cm, synthetic absorber/scatterers (10 nuclides), normal "
+                       f"2 MeV beam, detector = leakage through x = 200",
            "analog_histories": analog_histories, "learned_histories": learned_histories,
-           "analog_batches": analog_batches, "batches": batches}
+           "linear_histories": linear_histories, "analog_batches": analog_batches, "batches": batches}
     with Transport(prob) as t:
         t.run_batch(seed, 0, 100_000)  # warm-up (allocation, first launches)
         tic = time.perf_counter()
@@ -424,7 +428,7 @@ def fom_bench(analog_histories: int = 40_000_000, learned_histories: int = 4_000
         t_learn = time.perf_counter() - tic
         an = importance.production(t, seed=seed + 1, histories=analog_histories, batches=analog_batches,
                                    windows="analog")
-        lin = importance.production(t, seed=seed + 2, histories=learned_histories, batches=batches,
+        lin = importance.production(t, seed=seed + 2, histories=linear_histories, batches=batches,
                                     windows="linear", lin=(0.0, li.slope, 0.0))
         ml = importance.production(t, seed=seed + 3, histories=learned_histories, batches=batches,
                                    windows="mlp", ln_range=li.ln_range)
@@ -442,6 +446,7 @@ def fom_bench(analog_histories: int = 40_000_000, learned_histories: int = 4_000
     out["final_loss"] = float(li.loss_curves[-1][-1])
     out["ln_importance_span"] = li.ln_range
     out["gain_vs_analog"] = ml.fom / an.fom if an.fom > 0 else None
+    out["gain_vs_linear"] = ml.fom / lin.fom if lin.fom > 0 else None
     rel = ml.rel
     out["learned_fom_incl_training"] = 1.0 / (rel * rel * (ml.seconds + t_learn)) if ml.mean > 0 else 0.0
     out["agree_3sigma"] = bool(abs(ml.mean - an.mean) <= 3 * math.hypot(ml.stderr, an.stderr))
@@ -648,7 +653,9 @@ def main():
         print(json.dumps({"problem_set": problem_set_bench()}), flush=True)
         return
     if args.mode == "fom":
-        print(json.dumps({"fom": fom_bench()}), flush=True)
+        print(json.dumps({"fom": fom_bench(),
+                          "fom_shield": fom_bench(shield=True, learned_histories=4_000_000,
+                                                  linear_histories=400_000)}), flush=True)
         return
     if args.mode == "multipole":
         print(json.dumps({"multipole": multipole_microbench()}), flush=True)
@@ -824,6 +831,9 @@ def main():
         line["problem_set"] = problem_set_bench()
     if not args.no_fom:
         line["fom"] = fom_bench()
+        # linear windows split ~500 times per history in the shielded slab:
+        # fewer histories for them
+        line["fom_shield"] = fom_bench(shield=True, learned_histories=4_000_000, linear_histories=400_000)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, seed)
         line["cpu_oracle"] = cpu_oracle_extra(c2, prob)

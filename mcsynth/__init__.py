@@ -560,6 +560,19 @@ def c5_problem(data_seed: int = 5005, seed: int = 5, histories: int = 10_000_000
                    tally=Tally(TALLY_SLAB), histories=histories, batches=batches, seed=seed)
 
 
+def c5_shield_problem(data_seed: int = 5005, seed: int = 6, histories: int = 4_000_000,
+                      batches: int = 20) -> Problem:
+    """The deep-penetration slab's recipe with the attenuation concentrated in a
+    thin dense shield deep inside: 160 / 12 / 28 cm with Sigma_t(2 MeV) = 0.05 /
+    3.0 / 0.05 per cm (8 + 36 + 1.4 mean free paths).  The importance then is
+    nearly flat in the first layer and falls steeply across the shield, a shape
+    a map linear in depth cannot follow.  Analog transmission about 8e-5."""
+    prob = c5_problem(data_seed=data_seed, seed=seed, histories=histories, batches=batches,
+                      thickness=(160.0, 12.0, 28.0), sigma_t=(0.05, 3.0, 0.05))
+    prob.name = "c5_shielded_slab"
+    return prob
+
+
 def lookup_energies(rng, n: int) -> np.ndarray:
     """Energies log-uniform over [EMIN, EMAX] (the lookup benchmark's input)."""
     return _log_uniform(rng, EMIN, EMAX, n).astype(np.float64)

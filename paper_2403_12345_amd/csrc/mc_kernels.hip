@@ -685,8 +685,10 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
         }
         sa = sa + mn.dens * c;
         ss = ss + mn.dens * sg;
+        // (a lane past the queue's end writes the same values as the lane
+        // whose particle it repeats, into that particle's row)
         const int32_t done = q + 1;
-        if ((done & cp_mask) == 0 && valid) cpw.put((done >> cp_sh) - 1, ss);
+        if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
     }
     if (!valid) return 0;
     if (cp_sh != 30) cpw.finish(nk >> cp_sh);

@@ -220,7 +220,10 @@ __device__ inline void wg_glob_add(const double (&val)[N_GLOBAL], double *lds, d
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N_GLOBAL; ++k) {
-        const double s = wave_sum(val[k]);
+        // a wave whose lanes all hold zero for this sum skips the reduction
+        // (its slot is zero either way): each event kernel scores only a few
+        // of the sums, and those it never touches are dropped when compiled
+        const double s = __ballot(val[k] != 0.0) ? wave_sum(val[k]) : 0.0;
         if (lane_id() == 0) lds[k * WAVES + wave] = s;
     }
     __syncthreads();
