@@ -640,29 +640,42 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
                 uint32_t k = dn ? j - 1u : (up ? j + 1u : j);
                 double e0 = dn ? em : (up ? eg1 : eg);
                 double e1 = dn ? eg : (up ? ep : eg1);
-                if ((k > lo && e < e0) || (k < hi && e >= e1)) {
-                    while (k > lo && e < e0) {
-                        --k;
-                        e1 = e0;
-                        e0 = E_w[k - wlo];
+                // rare: the interval lies further than one step from the
+                // guess, or outside the bracket (the hash bin computed one off
+                // at a bin edge).  A wave-uniform test, so the common case
+                // skips the walks without any lane masking.
+                const bool rare = (k > 0u && e < e0) || (k + 2u < mn.len && e >= e1);
+                bool glob = false;
+                if (__ballot(rare)) {
+                    if (rare) {
+                        while (k > lo && e < e0) {
+                            --k;
+                            e1 = e0;
+                            e0 = E_w[k - wlo];
+                        }
+                        while (k < hi && e >= e1) {
+                            ++k;
+                            e0 = e1;
+                            e1 = E_w[k + 1u - wlo];
+                        }
+                        glob = (e < e0 && k > 0u) || (e >= e1 && k + 2u < mn.len);
                     }
-                    while (k < hi && e >= e1) {
-                        ++k;
-                        e0 = e1;
-                        e1 = E_w[k + 1u - wlo];
+                }
+                // k lies in the bracket, inside the window: the cross sections
+                // from LDS; a lane whose hash bin was computed one off then
+                // walks to the defined index in global memory and reloads
+                double2 x0 = X_w[k - wlo], x1 = X_w[k + 1u - wlo];
+                if (__ballot(glob)) {
+                    if (glob) {
+                        while (k > 0u && e < g[k]) --k;
+                        while (k + 2u < mn.len && e >= g[k + 1u]) ++k;
+                        e0 = g[k];
+                        e1 = g[k + 1u];
+                        x0 = x[k];
+                        x1 = x[k + 1u];
                     }
                 }
                 ii = k;
-                double2 x0 = X_w[ii - wlo], x1 = X_w[ii + 1u - wlo];
-                if ((e < e0 && ii > 0u) || (e >= e1 && ii + 2u < mn.len)) {
-                    // hash bin computed one off: walk to the defined index
-                    while (ii > 0u && e < g[ii]) --ii;
-                    while (ii + 2u < mn.len && e >= g[ii + 1u]) ++ii;
-                    e0 = g[ii];
-                    e1 = g[ii + 1u];
-                    x0 = x[ii];
-                    x1 = x[ii + 1u];
-                }
                 f = (e - e0) / (e1 - e0);
                 c = x0.x + f * (x1.x - x0.x);
                 sg = x0.y + f * (x1.y - x0.y);
