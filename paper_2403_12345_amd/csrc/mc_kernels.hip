@@ -716,6 +716,222 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     return nk;
 }
 
+// Interval of E inside the bracket [lo, hi] of one nuclide whose grid window
+// (points wlo ..) is staged at Ew / Xw (the window holds lo .. hi + 1; Ew[-1]
+// and one point past the window may be read, unused), g / x its tables in
+// global memory, len its grid length: the defined index i(E) and the
+// interval's energies and cross sections.  The first probe is the guess
+// nearest to the lane's position tb in its hash bin; the interval is the
+// guess or a neighbour for nearly every lane, the rest walk (behind
+// wave-uniform tests, so the common case runs without lane masks).
+__device__ __forceinline__ uint32_t window_search(const double *Ew, const double2 *Xw, uint32_t wlo, uint32_t lo,
+                                                  uint32_t hi, float tb, double e, const double *g,
+                                                  const double2 *x, uint32_t len, double &e0, double &e1,
+                                                  double2 &x0, double2 &x1)
+{
+    const uint32_t j = bracket_guess(lo, hi, tb);
+    const double *Ej = Ew + (int32_t)(j - wlo);
+    const double em = Ej[-1], eg = Ej[0], eg1 = Ej[1], ep = Ej[2];
+    const bool dn = j > lo && e < eg;
+    const bool up = !dn && j < hi && e >= eg1;
+    uint32_t k = dn ? j - 1u : (up ? j + 1u : j);
+    e0 = dn ? em : (up ? eg1 : eg);
+    e1 = dn ? eg : (up ? ep : eg1);
+    const bool rare = (k > 0u && e < e0) || (k + 2u < len && e >= e1);
+    bool glob = false;
+    if (__ballot(rare)) {
+        if (rare) {
+            while (k > lo && e < e0) {
+                --k;
+                e1 = e0;
+                e0 = Ew[k - wlo];
+            }
+            while (k < hi && e >= e1) {
+                ++k;
+                e0 = e1;
+                e1 = Ew[k + 1u - wlo];
+            }
+            glob = (e < e0 && k > 0u) || (e >= e1 && k + 2u < len);
+        }
+    }
+    // k lies in the bracket, inside the window: the cross sections from LDS;
+    // a lane whose hash bin was computed one off then walks to the defined
+    // index in global memory and reloads
+    x0 = Xw[k - wlo];
+    x1 = Xw[k + 1u - wlo];
+    if (__ballot(glob)) {
+        if (glob) {
+            while (k > 0u && e < g[k]) --k;
+            while (k + 2u < len && e >= g[k + 1u]) ++k;
+            e0 = g[k];
+            e1 = g[k + 1u];
+            x0 = x[k];
+            x1 = x[k + 1u];
+        }
+    }
+    return k;
+}
+
+// One nuclide on its own (the odd last one, or one of a pair whose windows do
+// not fit half a wave each): its window loaded now into E_w / X_w when it
+// holds at most WIN_PTS points, else a search of global memory.  Returns the
+// micro cross sections in c, sg.
+__device__ __forceinline__ void window_single(const XsDev &xs, const MatNuc &mn, uint32_t wlo, uint32_t wn,
+                                              uint2 br, float tb, double e, double *E_w, double2 *X_w,
+                                              uint32_t lane, double &c, double &sg)
+{
+    const double *g = xs.Eg + mn.off;
+    const double2 *x = xs.xs + mn.off;
+    double e0, e1;
+    double2 x0, x1;
+    if (wn <= (uint32_t)WIN_PTS) {
+        double pe = 0.0;
+        double2 px = make_double2(0.0, 0.0);
+        if (lane < wn) {
+            pe = g[wlo + lane];
+            px = x[wlo + lane];
+        }
+        E_w[lane] = pe;
+        X_w[lane] = px;
+        wave_lds_sync();
+        (void)window_search(E_w, X_w, wlo, br.x, br.y, tb, e, g, x, mn.len, e0, e1, x0, x1);
+        wave_lds_sync();
+    } else {
+        const uint32_t k = grid_find(g, mn.len, br.x, br.y, e);
+        e0 = g[k];
+        e1 = g[k + 1u];
+        x0 = x[k];
+        x1 = x[k + 1u];
+    }
+    const double f = (e - e0) / (e1 - e0);
+    c = x0.x + f * (x1.x - x0.x);
+    sg = x0.y + f * (x1.y - x0.y);
+}
+
+// window_lookups without reaction channels, two nuclides at a time: when the
+// windows of nuclides q and q + 1 hold at most half a wave's points each (all
+// but ~1e-4 of the pairs of the 300-nuclide tables), one load per lane brings
+// both (lanes 0-31 nuclide q's window, lanes 32-63 the other's), one LDS
+// store and one wave sync stage them, and the two searches run side by side;
+// the next pair's windows are loaded meanwhile.  A pair that does not fit,
+// and an odd last nuclide, go one at a time.  The same intervals,
+// interpolation, sums in material order and checkpoints as window_lookups:
+// the results bit for bit.
+__device__ __forceinline__ int32_t window_lookups_pairs(const LookupArgs &a, const uint2 *sh, const int32_t *s_info,
+                                                        uint32_t i, bool valid, double *we, double2 *wx)
+{
+    constexpr uint32_t HALF = WIN_PTS / 2;
+    const XsDev &xs = a.xs;
+    const uint64_t vmask = __ballot(valid);
+    if (!vmask) return 0;
+    const int32_t m = __builtin_amdgcn_readfirstlane(s_info[1]);
+    const int32_t b0 = __builtin_amdgcn_readfirstlane(s_info[2]);
+    const int32_t q0 = __builtin_amdgcn_readfirstlane(xs.mat_off[m]);
+    const int32_t nk = __builtin_amdgcn_readfirstlane(xs.mat_off[m + 1]) - q0;
+    // a lane past the end of the queue works on the wave's first particle
+    // (same values, never stored), so the nuclide loop needs no lane mask
+    const uint32_t i_own = valid ? i : i - (uint32_t)lane_id() + (uint32_t)(__ffsll((long long)vmask) - 1);
+    const uint32_t p = a.list ? a.list[i_own] : i_own;
+    const double e = a.E[p];
+    const int32_t b = (int32_t)(a.keys[i_own] % (uint32_t)xs.M);
+    const int32_t bmin = __builtin_amdgcn_readfirstlane(__shfl(b, __ffsll((long long)vmask) - 1, 64));
+    const int32_t bmax = __builtin_amdgcn_readfirstlane(__shfl(b, 63 - __clzll((long long)vmask), 64));
+    const uint2 *hmin = sh + (bmin - b0) * nk, *hmax = sh + (bmax - b0) * nk, *hown = sh + (b - b0) * nk;
+    const uint32_t lane = (uint32_t)lane_id();
+    double *E_w = we + 1 + (threadIdx.x & ~63u);  // one pad point before and after the waves' rows
+    double2 *X_w = wx + (threadIdx.x & ~63u);
+    const float tb = bin_position(xs, e, b);
+    const int32_t cp_sh = a.cp && nk > CP_MIN_NUC ? cp_shift(nk) : 30;  // 30: never a checkpoint
+    const int32_t cp_mask = (1 << cp_sh) - 1;
+    CpPairs cpw{a.cp ? a.cp + (size_t)p * CP_MAX : nullptr, 0.0};
+    double sa = 0.0, ss = 0.0;
+    // the pair starting at nuclide q: its rows, windows (first point and
+    // count, wave-uniform) and this lane's point, loaded one pair ahead
+    struct Pair {
+        MatNuc ma, mb;
+        uint32_t wla, wna, wlb, wnb;
+        bool fits;
+    };
+    auto load_pair = [&](int32_t q, Pair &r, double &pe, double2 &px) {
+        r.ma = uniform_load(xs.mnuc, (int64_t)q0 + q);
+        r.mb = uniform_load(xs.mnuc, (int64_t)q0 + q + 1);
+        r.wla = __builtin_amdgcn_readfirstlane(hmin[q].x);
+        r.wna = __builtin_amdgcn_readfirstlane(hmax[q].y) + 2u - r.wla;
+        r.wlb = __builtin_amdgcn_readfirstlane(hmin[q + 1].x);
+        r.wnb = __builtin_amdgcn_readfirstlane(hmax[q + 1].y) + 2u - r.wlb;
+        r.fits = r.wna <= HALF && r.wnb <= HALF;
+        pe = 0.0;
+        px = make_double2(0.0, 0.0);
+        if (r.fits) {
+            const bool lo_half = lane < HALF;
+            const uint32_t t = lo_half ? lane : lane - HALF;
+            if (t < (lo_half ? r.wna : r.wnb)) {
+                const uint32_t pt = lo_half ? r.ma.off + r.wla + t : r.mb.off + r.wlb + t;
+                pe = xs.Eg[pt];
+                px = xs.xs[pt];
+            }
+        }
+    };
+    auto accumulate = [&](int32_t q, const MatNuc &mn, double c, double sg) {
+        sa = sa + mn.dens * c;
+        ss = ss + mn.dens * sg;
+        // (a lane past the queue's end writes the same values as the lane
+        // whose particle it repeats, into that particle's row)
+        const int32_t done = q + 1;
+        if ((done & cp_mask) == 0) cpw.put((done >> cp_sh) - 1, ss);
+    };
+    Pair nxt{};
+    double pe = 0.0;
+    double2 px = make_double2(0.0, 0.0);
+    if (nk >= 2) load_pair(0, nxt, pe, px);
+    int32_t q = 0;
+    for (; q + 1 < nk; q += 2) {
+        const Pair cur = nxt;
+        const double ce = pe;
+        const double2 cx = px;
+        if (q + 3 < nk) load_pair(q + 2, nxt, pe, px);
+        const uint2 bra = hown[q], brb = hown[q + 1];  // this lane's brackets of q, q + 1
+        double ca, sga, cb, sgb;
+        if (cur.fits) {
+            E_w[lane] = ce;
+            X_w[lane] = cx;
+            wave_lds_sync();
+            double e0a, e1a, e0b, e1b;
+            double2 x0a, x1a, x0b, x1b;
+            (void)window_search(E_w, X_w, cur.wla, bra.x, bra.y, tb, e, xs.Eg + cur.ma.off, xs.xs + cur.ma.off,
+                                cur.ma.len, e0a, e1a, x0a, x1a);
+            (void)window_search(E_w + HALF, X_w + HALF, cur.wlb, brb.x, brb.y, tb, e, xs.Eg + cur.mb.off,
+                                xs.xs + cur.mb.off, cur.mb.len, e0b, e1b, x0b, x1b);
+            wave_lds_sync();
+            const double fa = (e - e0a) / (e1a - e0a);
+            const double fb = (e - e0b) / (e1b - e0b);
+            ca = x0a.x + fa * (x1a.x - x0a.x);
+            sga = x0a.y + fa * (x1a.y - x0a.y);
+            cb = x0b.x + fb * (x1b.x - x0b.x);
+            sgb = x0b.y + fb * (x1b.y - x0b.y);
+        } else {
+            window_single(xs, cur.ma, cur.wla, cur.wna, bra, tb, e, E_w, X_w, lane, ca, sga);
+            window_single(xs, cur.mb, cur.wlb, cur.wnb, brb, tb, e, E_w, X_w, lane, cb, sgb);
+        }
+        accumulate(q, cur.ma, ca, sga);
+        accumulate(q + 1, cur.mb, cb, sgb);
+    }
+    if (q < nk) {  // the odd last nuclide
+        const MatNuc mn = uniform_load(xs.mnuc, (int64_t)q0 + q);
+        const uint32_t wlo = __builtin_amdgcn_readfirstlane(hmin[q].x);
+        const uint32_t wn = __builtin_amdgcn_readfirstlane(hmax[q].y) + 2u - wlo;
+        double c, sg;
+        window_single(xs, mn, wlo, wn, hown[q], tb, e, E_w, X_w, lane, c, sg);
+        accumulate(q, mn, c, sg);
+    }
+    if (!valid) return 0;
+    if (cp_sh != 30) cpw.finish(nk >> cp_sh);
+    if (a.Sa) a.Sa[p] = sa;
+    if (a.Ss) a.Ss[p] = ss;
+    if (a.flags) a.flags[p] = F_ALIVE;
+    return nk;
+}
+
 // DIAG: the per-nuclide outputs (idx_out, sc_out, ss_out) may be set; the
 // transport's lookups run without them, in fewer registers.  CHAN: the
 // reaction channels are assembled in the same pass (same index and fraction
@@ -763,7 +979,8 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     }
     int32_t nk_done = 0;
     if (WIN && staged) {
-        nk_done = window_lookups<CHAN>(a, sh, s_info, i, valid, s_we, s_wx, s_wc);
+        if constexpr (CHAN) nk_done = window_lookups<CHAN>(a, sh, s_info, i, valid, s_we, s_wx, s_wc);
+        else nk_done = window_lookups_pairs(a, sh, s_info, i, valid, s_we, s_wx);
     } else if (valid) {
     const uint32_t p = a.list ? a.list[i] : i;
     const double e = a.E[p];
