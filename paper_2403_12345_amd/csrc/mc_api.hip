@@ -1464,13 +1464,17 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
             s.lookups += c.nL;
             s.lookup_launches += 1;
         }
+        // analog runs without an importance grid cross surfaces in the flight
+        // kernel (the split then queues only collisions)
+        const bool fuse_cross = W.kind == WW_OFF && W.imp_nx == 0;
         if ((rc = time_begin(T_ADVANCE))) return rc;
-        HIPCHK(launch_advance(b, g, tal, W, dc, c.nA, seed, max_events, log ? 1 : 0, st));
+        HIPCHK(launch_advance(b, g, tal, W, dc, c.nA, seed, max_events, log ? 1 : 0, fuse_cross, log, first_pid,
+                              ctx->dstat + 1, st));
         if ((rc = time_end())) return rc;
         s.flights += c.nA;
         if ((rc = time_begin(T_CROSS))) return rc;
         HIPCHK(launch_split(b, dc, c.nA, st));
-        HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
+        if (!fuse_cross) HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
         if ((rc = time_end())) return rc;
         if ((rc = time_begin(T_COLLIDE))) return rc;
         // collisions re-gather sigma_s: in (material, energy) order when the

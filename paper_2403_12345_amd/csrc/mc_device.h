@@ -22,7 +22,8 @@ constexpr int MAX_LDS_BINS = 1024;  // tallies with more bins use the mesh path
 constexpr uint8_t F_ALIVE = 1, F_LOOKUP = 2;
 // event codes written by the advance kernel
 enum : uint8_t { EV_COLLIDE = 0, EV_CYL = 1, EV_XLO = 2, EV_XHI = 3, EV_YLO = 4, EV_YHI = 5,
-                 EV_ZLO = 6, EV_ZHI = 7 };
+                 EV_ZLO = 6, EV_ZHI = 7,
+                 EV_DONE = 0xFE };  // the crossing was done by the flight kernel
 enum { GEOM_INFINITE = 0, GEOM_LATTICE = 1, GEOM_SLAB = 2 };
 enum { BC_REFLECT = 0, BC_VACUUM = 1 };
 enum { SRC_POINT = 0, SRC_BOX = 1, SRC_BEAM = 2 };

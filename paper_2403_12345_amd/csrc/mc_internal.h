@@ -53,8 +53,8 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
                        uint32_t *out_list, uint32_t *out_keys, hipStream_t st);
 hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st);
 hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
-                          uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on,
-                          hipStream_t st);
+                          uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on, bool cross,
+                          HistLog *log, uint64_t first_pid, unsigned long long *lost, hipStream_t st);
 hipError_t launch_split(const BankDev &b, Counters *ctr, uint32_t n_bound, hipStream_t st);
 hipError_t launch_cross(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
                         uint32_t n_bound, uint64_t seed, HistLog *log, uint64_t first_pid, unsigned long long *lost,

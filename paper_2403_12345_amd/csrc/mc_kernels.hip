@@ -1212,8 +1212,19 @@ __global__ void __launch_bounds__(WG) k_lookup_mp(MpDev mp, uint32_t n, const do
 // ---------------------------------------------------------------------------
 // advance: sample the flight, move, score track length
 // ---------------------------------------------------------------------------
+template <int WWK>
+__device__ __forceinline__ void end_copy(const BankDev &b, const WwDev &W, uint32_t s, Particle &p, int32_t fate,
+                                         HistLog *log, uint64_t first_pid);
+
+// Flight of every alive particle.  CROSS (analog runs without an importance
+// grid): a particle whose flight ends on a surface crosses it here, from the
+// state the flight has in registers, instead of in k_cross (one pass over the
+// bank fewer); it is marked EV_DONE, and the split queues only collisions.
+// A particle at the event cap then ends here as lost too.
+template <bool CROSS>
 __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev tal, WwDev W, const Counters *ctr,
-                                                uint64_t seed, int64_t max_events, int32_t log_on)
+                                                uint64_t seed, int64_t max_events, int32_t log_on, HistLog *log,
+                                                uint64_t first_pid, unsigned long long *lost)
 {
     extern __shared__ double slab[];
     __shared__ double gl[N_GLOBAL * WAVES];
@@ -1228,18 +1239,42 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
     if (i < n) {
         const uint32_t s = b.A[i];
         if ((int64_t)b.ncoll[s] + b.ncross[s] >= max_events) {
-            b.event[s] = 0xFF;  // event cap reached: the cross kernel ends it as lost
+            if constexpr (CROSS) {  // event cap reached: the history ends here as lost
+                Particle p = load_particle(b, s);
+                atomicAdd(lost, 1ull);
+                end_copy<WW_OFF>(b, W, s, p, FATE_LOST, log, first_pid);
+                b.event[s] = EV_DONE;
+            } else {
+                b.event[s] = 0xFF;  // the cross kernel ends it as lost
+            }
         } else {
             Particle p = load_particle(b, s);
             const double x0 = p.x;
             flight_mat = p.mat;
             if (tal.chan) sx_row = b.sx + (size_t)s * tal.n_chan;
             do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on != 0, sc);
-            if (W.imp_nx) imp_enter(W, s, x0, p.x, p.E, p.wt);
-            b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+            if (!CROSS && W.imp_nx) imp_enter(W, s, x0, p.x, p.E, p.wt);
             b.ndraw[s] = p.ndraw;
-            b.event[s] = p.ev;
             if (log_on) b.track[s] = p.track;
+            if (CROSS && p.ev != EV_COLLIDE) {
+                bool need_lookup, leak_xhi;
+                const int32_t fate = do_cross(p, g, sc, need_lookup, leak_xhi);
+                b.ncross[s] = p.ncross;
+                if (fate) {
+                    end_copy<WW_OFF>(b, W, s, p, fate, log, first_pid);
+                } else {
+                    b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+                    b.u[s] = p.u; b.v[s] = p.v; b.w[s] = p.w;
+                    b.cell[s] = p.cell;
+                    b.inside[s] = p.inside ? 1 : 0;
+                    b.mat[s] = p.mat;
+                    if (need_lookup) b.flags[s] = F_ALIVE | F_LOOKUP;
+                }
+                b.event[s] = EV_DONE;
+            } else {
+                b.x[s] = p.x; b.y[s] = p.y; b.z[s] = p.z;
+                b.event[s] = p.ev;
+            }
         }
     }
     if (tal.enabled && g.tally_kind != TALLY_MESH)
@@ -1265,7 +1300,7 @@ __global__ void __launch_bounds__(WG) k_split_count(BankDev b, const Counters *c
             if (i < n) {
                 const uint8_t ev = b.event[b.A[i]];
                 cc += ev == EV_COLLIDE ? 1u : 0u;
-                cx += ev != EV_COLLIDE ? 1u : 0u;
+                cx += ev != EV_COLLIDE && ev != EV_DONE ? 1u : 0u;
             }
         }
     }
@@ -1288,7 +1323,7 @@ __global__ void __launch_bounds__(WG) k_split_scatter(BankDev b, Counters *ctr)
         const uint32_t s = valid ? b.A[i] : 0u;
         const uint8_t ev = valid ? b.event[s] : 0;
         const bool pc = valid && ev == EV_COLLIDE;
-        const bool px = valid && ev != EV_COLLIDE;
+        const bool px = valid && ev != EV_COLLIDE && ev != EV_DONE;
         const Rank3 rk = block_rank3(pc, px, false, lds);
         if (pc) b.Qc[pre[0] + run[0] + rk.rank[0]] = s;
         if (px) b.Qx[pre[1] + run[1] + rk.rank[1]] = s;
@@ -1879,13 +1914,17 @@ hipError_t launch_lookup(const LookupLaunch &l, hipStream_t st)
 }
 
 hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t, const WwDev &W, const Counters *ctr,
-                          uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on,
-                          hipStream_t st)
+                          uint32_t n_bound, uint64_t seed, int64_t max_events, int32_t log_on, bool cross,
+                          HistLog *log, uint64_t first_pid, unsigned long long *lost, hipStream_t st)
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    hipLaunchKernelGGL(k_advance, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, W, ctr, seed,
-                       max_events, log_on);
+    if (cross)
+        hipLaunchKernelGGL(k_advance<true>, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, W, ctr, seed,
+                           max_events, log_on, log, first_pid, lost);
+    else
+        hipLaunchKernelGGL(k_advance<false>, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, W, ctr,
+                           seed, max_events, log_on, log, first_pid, lost);
     return hipGetLastError();
 }
 
