@@ -589,6 +589,28 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// The GPU hands consecutive workgroups of a launch to its 8 XCDs in turn, and
+// each XCD has its own L2.  For a queue whose neighbouring entries read the
+// same table lines (a sorted lookup queue), this maps workgroup b to the
+// block of work it takes so that XCD_CHUNK neighbouring blocks run on one
+// XCD: the launch is cut into runs of 8 XCD_CHUNK blocks, and within a run
+// XCD x (b mod 8) takes blocks x XCD_CHUNK .. x XCD_CHUNK + XCD_CHUNK - 1 in
+// order.  The XCDs still move through the queue together (the grid is sized
+// for the longest queue, and only its first blocks have work), and blocks
+// past the last whole run keep their own index.  A bijection of [0, G)
+// whatever the placement; only the L2 sharing depends on it.
+#ifndef MC_XCD_CHUNK
+#define MC_XCD_CHUNK 4u
+#endif
+constexpr uint32_t XCD_CHUNK = MC_XCD_CHUNK;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
+{
+    constexpr uint32_t RUN = 8u * XCD_CHUNK;
+    if (b >= G / RUN * RUN) return b;
+    const uint32_t run = b / RUN, k = b % RUN;
+    return run * RUN + (k & 7u) * XCD_CHUNK + (k >> 3);
+}
+
 }  // namespace mc
 
 namespace mc {

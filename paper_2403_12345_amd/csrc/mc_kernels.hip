@@ -947,7 +947,10 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     __shared__ double s_wc[(WIN && CHAN) ? WAVES * WIN_CHAN : 1];
     const XsDev &xs = a.xs;
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
-    const uint32_t i0 = blockIdx.x * WG;
+    // a sorted queue: runs of XCD_CHUNK neighbouring blocks on one XCD, so
+    // that workgroups sharing hash bins (and so grid windows) share one L2
+    const uint32_t blk = a.keys ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t i0 = blk * WG;
     if (i0 >= n) return;
     const uint32_t i = i0 + threadIdx.x;
     const bool valid = i < n;
