@@ -716,60 +716,110 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
     return nk;
 }
 
-// Interval of E inside the bracket [lo, hi] of one nuclide whose grid window
-// (points wlo ..) is staged at Ew / Xw (the window holds lo .. hi + 1; Ew[-1]
-// and one point past the window may be read, unused), g / x its tables in
-// global memory, len its grid length: the defined index i(E) and the
-// interval's energies and cross sections.  The first probe is the guess
-// nearest to the lane's position tb in its hash bin; the interval is the
-// guess or a neighbour for nearly every lane, the rest walk (behind
-// wave-uniform tests, so the common case runs without lane masks).
-__device__ __forceinline__ uint32_t window_search(const double *Ew, const double2 *Xw, uint32_t wlo, uint32_t lo,
-                                                  uint32_t hi, float tb, double e, const double *g,
-                                                  const double2 *x, uint32_t len, double &e0, double &e1,
-                                                  double2 &x0, double2 &x1)
+// One nuclide's search in window_search: its grid window (points wlo ..,
+// staged at Ew / Xw; the window holds lo .. hi + 1, and Ew[-1] and one point
+// past the window may be read, unused), this lane's hash bracket [lo, hi],
+// its tables g / x in global memory and its grid length.
+struct WinQ {
+    const double *Ew;
+    const double2 *Xw;
+    uint32_t wlo, lo, hi, len;
+    const double *g;
+    const double2 *x;
+};
+
+// The interval's energies and cross sections.
+struct WinHit {
+    double e0, e1;
+    double2 x0, x1;
+};
+
+// Interval i(E) of each of N nuclides (side by side, so that their LDS reads
+// are in flight together): the first probe is the guess nearest to the
+// lane's position tb in its hash bin; the interval is the guess or a
+// neighbour for nearly every lane, the rest walk (behind wave-uniform tests,
+// one for all N, so the common case runs without lane masks).
+template <int N>
+__device__ __forceinline__ void window_search(const WinQ (&w)[N], float tb, double e, WinHit (&h)[N])
 {
-    const uint32_t j = bracket_guess(lo, hi, tb);
-    const double *Ej = Ew + (int32_t)(j - wlo);
-    const double em = Ej[-1], eg = Ej[0], eg1 = Ej[1], ep = Ej[2];
-    const bool dn = j > lo && e < eg;
-    const bool up = !dn && j < hi && e >= eg1;
-    uint32_t k = dn ? j - 1u : (up ? j + 1u : j);
-    e0 = dn ? em : (up ? eg1 : eg);
-    e1 = dn ? eg : (up ? ep : eg1);
-    const bool rare = (k > 0u && e < e0) || (k + 2u < len && e >= e1);
-    bool glob = false;
-    if (__ballot(rare)) {
-        if (rare) {
-            while (k > lo && e < e0) {
-                --k;
-                e1 = e0;
-                e0 = Ew[k - wlo];
+    uint32_t k[N];
+    bool rare[N], glob[N];
+    double em[N], eg[N], eg1[N], ep[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const uint32_t j = bracket_guess(w[n].lo, w[n].hi, tb);
+        const double *Ej = w[n].Ew + (int32_t)(j - w[n].wlo);
+        em[n] = Ej[-1];
+        eg[n] = Ej[0];
+        eg1[n] = Ej[1];
+        ep[n] = Ej[2];
+        k[n] = j;
+    }
+    bool any_rare = false;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const uint32_t j = k[n];
+        const bool dn = j > w[n].lo && e < eg[n];
+        const bool up = !dn && j < w[n].hi && e >= eg1[n];
+        k[n] = dn ? j - 1u : (up ? j + 1u : j);
+        h[n].e0 = dn ? em[n] : (up ? eg1[n] : eg[n]);
+        h[n].e1 = dn ? eg[n] : (up ? ep[n] : eg1[n]);
+        rare[n] = (k[n] > 0u && e < h[n].e0) || (k[n] + 2u < w[n].len && e >= h[n].e1);
+        glob[n] = false;
+        any_rare = any_rare || rare[n];
+    }
+    if (__ballot(any_rare)) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            if (rare[n]) {
+                uint32_t kk = k[n];
+                double e0 = h[n].e0, e1 = h[n].e1;
+                while (kk > w[n].lo && e < e0) {
+                    --kk;
+                    e1 = e0;
+                    e0 = w[n].Ew[kk - w[n].wlo];
+                }
+                while (kk < w[n].hi && e >= e1) {
+                    ++kk;
+                    e0 = e1;
+                    e1 = w[n].Ew[kk + 1u - w[n].wlo];
+                }
+                glob[n] = (e < e0 && kk > 0u) || (e >= e1 && kk + 2u < w[n].len);
+                k[n] = kk;
+                h[n].e0 = e0;
+                h[n].e1 = e1;
             }
-            while (k < hi && e >= e1) {
-                ++k;
-                e0 = e1;
-                e1 = Ew[k + 1u - wlo];
-            }
-            glob = (e < e0 && k > 0u) || (e >= e1 && k + 2u < len);
         }
     }
     // k lies in the bracket, inside the window: the cross sections from LDS;
     // a lane whose hash bin was computed one off then walks to the defined
     // index in global memory and reloads
-    x0 = Xw[k - wlo];
-    x1 = Xw[k + 1u - wlo];
-    if (__ballot(glob)) {
-        if (glob) {
-            while (k > 0u && e < g[k]) --k;
-            while (k + 2u < len && e >= g[k + 1u]) ++k;
-            e0 = g[k];
-            e1 = g[k + 1u];
-            x0 = x[k];
-            x1 = x[k + 1u];
-        }
+    bool any_glob = false;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        h[n].x0 = w[n].Xw[k[n] - w[n].wlo];
+        h[n].x1 = w[n].Xw[k[n] + 1u - w[n].wlo];
+        any_glob = any_glob || glob[n];
     }
-    return k;
+    if (__ballot(any_glob)) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            if (glob[n]) {
+                uint32_t kk = k[n];
+                const double *g = w[n].g;
+                while (kk > 0u && e < g[kk]) --kk;
+                while (kk + 2u < w[n].len && e >= g[kk + 1u]) ++kk;
+                h[n].e0 = g[kk];
+                h[n].e1 = g[kk + 1u];
+                h[n].x0 = w[n].x[kk];
+                h[n].x1 = w[n].x[kk + 1u];
+            }
+        }
+        // these loads complete here (vmcnt 0), so that the common path,
+        // which joins below, waits on none of them, and so not on the next
+        // windows' loads issued before them either
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
 }
 
 // One nuclide on its own (the odd last one, or one of a pair whose windows do
@@ -794,7 +844,13 @@ __device__ __forceinline__ void window_single(const XsDev &xs, const MatNuc &mn,
         E_w[lane] = pe;
         X_w[lane] = px;
         wave_lds_sync();
-        (void)window_search(E_w, X_w, wlo, br.x, br.y, tb, e, g, x, mn.len, e0, e1, x0, x1);
+        const WinQ w[1] = {{E_w, X_w, wlo, br.x, br.y, mn.len, g, x}};
+        WinHit hit[1];
+        window_search(w, tb, e, hit);
+        e0 = hit[0].e0;
+        e1 = hit[0].e1;
+        x0 = hit[0].x0;
+        x1 = hit[0].x1;
         wave_lds_sync();
     } else {
         const uint32_t k = grid_find(g, mn.len, br.x, br.y, e);
@@ -896,19 +952,18 @@ __device__ __forceinline__ int32_t window_lookups_pairs(const LookupArgs &a, con
             E_w[lane] = ce;
             X_w[lane] = cx;
             wave_lds_sync();
-            double e0a, e1a, e0b, e1b;
-            double2 x0a, x1a, x0b, x1b;
-            (void)window_search(E_w, X_w, cur.wla, bra.x, bra.y, tb, e, xs.Eg + cur.ma.off, xs.xs + cur.ma.off,
-                                cur.ma.len, e0a, e1a, x0a, x1a);
-            (void)window_search(E_w + HALF, X_w + HALF, cur.wlb, brb.x, brb.y, tb, e, xs.Eg + cur.mb.off,
-                                xs.xs + cur.mb.off, cur.mb.len, e0b, e1b, x0b, x1b);
+            const WinQ w[2] = {{E_w, X_w, cur.wla, bra.x, bra.y, cur.ma.len, xs.Eg + cur.ma.off, xs.xs + cur.ma.off},
+                               {E_w + HALF, X_w + HALF, cur.wlb, brb.x, brb.y, cur.mb.len, xs.Eg + cur.mb.off,
+                                xs.xs + cur.mb.off}};
+            WinHit hit[2];
+            window_search(w, tb, e, hit);
             wave_lds_sync();
-            const double fa = (e - e0a) / (e1a - e0a);
-            const double fb = (e - e0b) / (e1b - e0b);
-            ca = x0a.x + fa * (x1a.x - x0a.x);
-            sga = x0a.y + fa * (x1a.y - x0a.y);
-            cb = x0b.x + fb * (x1b.x - x0b.x);
-            sgb = x0b.y + fb * (x1b.y - x0b.y);
+            const double fa = (e - hit[0].e0) / (hit[0].e1 - hit[0].e0);
+            const double fb = (e - hit[1].e0) / (hit[1].e1 - hit[1].e0);
+            ca = hit[0].x0.x + fa * (hit[0].x1.x - hit[0].x0.x);
+            sga = hit[0].x0.y + fa * (hit[0].x1.y - hit[0].x0.y);
+            cb = hit[1].x0.x + fb * (hit[1].x1.x - hit[1].x0.x);
+            sgb = hit[1].x0.y + fb * (hit[1].x1.y - hit[1].x0.y);
         } else {
             window_single(xs, cur.ma, cur.wla, cur.wna, bra, tb, e, E_w, X_w, lane, ca, sga);
             window_single(xs, cur.mb, cur.wlb, cur.wnb, brb, tb, e, E_w, X_w, lane, cb, sgb);
