@@ -717,9 +717,8 @@ __device__ __forceinline__ int32_t window_lookups(const LookupArgs &a, const uin
 }
 
 // One nuclide's search in window_search: its grid window (points wlo ..,
-// staged at Ew / Xw; the window holds lo .. hi + 1, and Ew[-1] and one point
-// past the window may be read, unused), this lane's hash bracket [lo, hi],
-// its tables g / x in global memory and its grid length.
+// staged at Ew / Xw; the window holds lo .. hi + 1), this lane's hash
+// bracket [lo, hi], its tables g / x in global memory and its grid length.
 struct WinQ {
     const double *Ew;
     const double2 *Xw;
@@ -736,35 +735,43 @@ struct WinHit {
 
 // Interval i(E) of each of N nuclides (side by side, so that their LDS reads
 // are in flight together): the first probe is the guess nearest to the
-// lane's position tb in its hash bin; the interval is the guess or a
-// neighbour for nearly every lane, the rest walk (behind wave-uniform tests,
-// one for all N, so the common case runs without lane masks).
+// lane's position tb in its hash bin, whose two energies say whether the
+// interval is the guess or a neighbour; the interval's energies and cross
+// sections are then read at that index.  Nearly every lane is done there;
+// the rest walk (behind wave-uniform tests, one for all N, so the common
+// case runs without lane masks).
 template <int N>
 __device__ __forceinline__ void window_search(const WinQ (&w)[N], float tb, double e, WinHit (&h)[N])
 {
     uint32_t k[N];
     bool rare[N], glob[N];
-    double em[N], eg[N], eg1[N], ep[N];
+    double eg[N], eg1[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
         const uint32_t j = bracket_guess(w[n].lo, w[n].hi, tb);
         const double *Ej = w[n].Ew + (int32_t)(j - w[n].wlo);
-        em[n] = Ej[-1];
         eg[n] = Ej[0];
         eg1[n] = Ej[1];
-        ep[n] = Ej[2];
         k[n] = j;
     }
     bool any_rare = false;
 #pragma unroll
     for (int n = 0; n < N; ++n) {
+        // (bitwise, not short-circuit, so that no load or compare waits
+        // behind a branch)
         const uint32_t j = k[n];
-        const bool dn = j > w[n].lo && e < eg[n];
-        const bool up = !dn && j < w[n].hi && e >= eg1[n];
-        k[n] = dn ? j - 1u : (up ? j + 1u : j);
-        h[n].e0 = dn ? em[n] : (up ? eg1[n] : eg[n]);
-        h[n].e1 = dn ? eg[n] : (up ? ep[n] : eg1[n]);
-        rare[n] = (k[n] > 0u && e < h[n].e0) || (k[n] + 2u < w[n].len && e >= h[n].e1);
+        const bool dn = (j > w[n].lo) & (e < eg[n]);
+        const bool up = !dn & (j < w[n].hi) & (e >= eg1[n]);
+        k[n] = j + (up ? 1u : 0u) - (dn ? 1u : 0u);
+        const uint32_t t = k[n] - w[n].wlo;
+        h[n].e0 = w[n].Ew[t];
+        h[n].e1 = w[n].Ew[t + 1u];
+        h[n].x0 = w[n].Xw[t];
+        h[n].x1 = w[n].Xw[t + 1u];
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        rare[n] = ((k[n] > 0u) & (e < h[n].e0)) | ((k[n] + 2u < w[n].len) & (e >= h[n].e1));
         glob[n] = false;
         any_rare = any_rare || rare[n];
     }
@@ -788,19 +795,17 @@ __device__ __forceinline__ void window_search(const WinQ (&w)[N], float tb, doub
                 k[n] = kk;
                 h[n].e0 = e0;
                 h[n].e1 = e1;
+                h[n].x0 = w[n].Xw[kk - w[n].wlo];
+                h[n].x1 = w[n].Xw[kk + 1u - w[n].wlo];
             }
         }
     }
-    // k lies in the bracket, inside the window: the cross sections from LDS;
-    // a lane whose hash bin was computed one off then walks to the defined
-    // index in global memory and reloads
+    // k lies in the bracket, inside the window, and the cross sections came
+    // from LDS; a lane whose hash bin was computed one off then walks to the
+    // defined index in global memory and reloads
     bool any_glob = false;
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
-        h[n].x0 = w[n].Xw[k[n] - w[n].wlo];
-        h[n].x1 = w[n].Xw[k[n] + 1u - w[n].wlo];
-        any_glob = any_glob || glob[n];
-    }
+    for (int n = 0; n < N; ++n) any_glob = any_glob || glob[n];
     if (__ballot(any_glob)) {
 #pragma unroll
         for (int n = 0; n < N; ++n) {
