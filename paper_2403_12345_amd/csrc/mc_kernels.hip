@@ -1284,11 +1284,17 @@ __device__ __forceinline__ void end_copy(const BankDev &b, const WwDev &W, uint3
 // state the flight has in registers, instead of in k_cross (one pass over the
 // bank fewer); it is marked EV_DONE, and the split queues only collisions.
 // A particle at the event cap then ends here as lost too.
-template <bool CROSS>
+// LOG: the history log may be on; without it (the transport's runs) the
+// fields only the log reads are never loaded or kept, in fewer registers.
+template <bool CROSS, bool LOG>
 __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev tal, WwDev W, const Counters *ctr,
                                                 uint64_t seed, int64_t max_events, int32_t log_on, HistLog *log,
                                                 uint64_t first_pid, unsigned long long *lost)
 {
+    if constexpr (!LOG) {
+        log = nullptr;
+        log_on = 0;
+    }
     extern __shared__ double slab[];
     __shared__ double gl[N_GLOBAL * WAVES];
     const uint32_t n = ctr->nA;
@@ -1491,11 +1497,12 @@ __global__ void __launch_bounds__(WG) k_cross(BankDev b, GeomDev g, TallyDev tal
 // ---------------------------------------------------------------------------
 // `list` is the collide queue, in split order or sorted by (material, hash
 // bin of E) so that the gathers of neighbouring lanes share cache lines.
-template <int WWK>
+template <int WWK, bool LOG>
 __global__ void __launch_bounds__(WG) k_collide(BankDev b, const uint32_t *list, XsDev xs, GeomDev g, TallyDev tal,
                                                 WwDev W, const Counters *ctr, uint64_t seed, HistLog *log,
                                                 uint64_t first_pid)
 {
+    if constexpr (!LOG) log = nullptr;  // (as in k_advance)
     extern __shared__ double slab[];
     __shared__ double gl[N_GLOBAL * WAVES];
     const uint32_t n = ctr->nC;
@@ -1982,12 +1989,20 @@ hipError_t launch_advance(const BankDev &b, const GeomDev &g, const TallyDev &t,
 {
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
-    if (cross)
-        hipLaunchKernelGGL(k_advance<true>, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, W, ctr, seed,
-                           max_events, log_on, log, first_pid, lost);
+    const dim3 grid(blocks_for(n_bound, WG));
+    const bool lg = log != nullptr || log_on != 0;
+    if (cross && lg)
+        hipLaunchKernelGGL((k_advance<true, true>), grid, dim3(WG), lds, st, b, g, t, W, ctr, seed, max_events, log_on,
+                           log, first_pid, lost);
+    else if (cross)
+        hipLaunchKernelGGL((k_advance<true, false>), grid, dim3(WG), lds, st, b, g, t, W, ctr, seed, max_events,
+                           log_on, log, first_pid, lost);
+    else if (lg)
+        hipLaunchKernelGGL((k_advance<false, true>), grid, dim3(WG), lds, st, b, g, t, W, ctr, seed, max_events,
+                           log_on, log, first_pid, lost);
     else
-        hipLaunchKernelGGL(k_advance<false>, dim3(blocks_for(n_bound, WG)), dim3(WG), lds, st, b, g, t, W, ctr,
-                           seed, max_events, log_on, log, first_pid, lost);
+        hipLaunchKernelGGL((k_advance<false, false>), grid, dim3(WG), lds, st, b, g, t, W, ctr, seed, max_events,
+                           log_on, log, first_pid, lost);
     return hipGetLastError();
 }
 
@@ -2026,18 +2041,31 @@ hipError_t launch_collide(const BankDev &b, const uint32_t *list, const XsDev &x
     if (n_bound == 0) return hipSuccess;
     const size_t lds = slab_bytes(g, t);
     const dim3 grid(blocks_for(n_bound, WG));
+    const bool lg = log != nullptr;
     switch (W.kind) {
     case WW_LINEAR:
-        hipLaunchKernelGGL(k_collide<WW_LINEAR>, grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
-                           first_pid);
+        if (lg)
+            hipLaunchKernelGGL((k_collide<WW_LINEAR, true>), grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed,
+                               log, first_pid);
+        else
+            hipLaunchKernelGGL((k_collide<WW_LINEAR, false>), grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr,
+                               seed, log, first_pid);
         break;
     case WW_MLP:
-        hipLaunchKernelGGL(k_collide<WW_MLP>, grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
-                           first_pid);
+        if (lg)
+            hipLaunchKernelGGL((k_collide<WW_MLP, true>), grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
+                               first_pid);
+        else
+            hipLaunchKernelGGL((k_collide<WW_MLP, false>), grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed,
+                               log, first_pid);
         break;
     default:
-        hipLaunchKernelGGL(k_collide<WW_OFF>, grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
-                           first_pid);
+        if (lg)
+            hipLaunchKernelGGL((k_collide<WW_OFF, true>), grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed, log,
+                               first_pid);
+        else
+            hipLaunchKernelGGL((k_collide<WW_OFF, false>), grid, dim3(WG), lds, st, b, list, xs, g, t, W, ctr, seed,
+                               log, first_pid);
         break;
     }
     return hipGetLastError();
