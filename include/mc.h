@@ -91,7 +91,11 @@ enum { MC_FATE_ABSORBED = 1, MC_FATE_CUTOFF = 2, MC_FATE_LEAKED = 3, MC_FATE_LOS
  *   of radius `radius` (< pitch/2) about its centre filled with
  *   pin_material[j*nx + i] (-1: no cylinder), and moderator_material outside.
  *   A 2-level assembly lattice whose assembly pitch is a whole number of pin
- *   pitches is described as the equivalent flat lattice.
+ *   pitches is described as the equivalent flat lattice: each assembly's
+ *   pin layout (its pin materials and its positions without a cylinder,
+ *   such as water holes and guide tubes) fills pin_material at its cells.
+ *   One pin radius and pitch hold for the whole lattice (no gaps between
+ *   assemblies).
  * MC_GEOM_SLAB    : layers along x with edges x_edges[0..n_layers], infinite in
  *   y and z; layer l holds layer_material[l].
  * bc[6]           : boundary condition of the x-, x+, y-, y+, z-, z+ faces.

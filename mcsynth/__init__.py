@@ -442,6 +442,68 @@ def c2_problem(data_seed: int = 2002, seed: int = 2, histories: int = 1_000_000,
                    tally=Tally(TALLY_PIN), histories=histories, batches=batches, seed=seed)
 
 
+def assembly_pin_map(core, layouts, pins: int = 17) -> np.ndarray:
+    """Pin-cell material map of a core of assemblies, as the flat lattice
+    describes it: core[J][I] is the type of the assembly in column I and row
+    J (I along x, J along y), layouts[type] a pins x pins array (row j along
+    y, column i along x) of pin materials, -1 for a position without a
+    cylinder (a water hole or guide tube).  Cell (I*pins + i, J*pins + j)
+    of the (NA*pins)^2 lattice takes layouts[core[J][I]][j][i]; the result
+    is row-major in y (index y*nx + x), the order of pin_material."""
+    core = np.asarray(core, np.int32)
+    na_y, na_x = core.shape
+    out = np.empty((na_y * pins, na_x * pins), np.int32)
+    for J in range(na_y):
+        for I in range(na_x):
+            lay = np.asarray(layouts[int(core[J, I])], np.int32)
+            assert lay.shape == (pins, pins)
+            out[J * pins:(J + 1) * pins, I * pins:(I + 1) * pins] = lay
+    return out.ravel()
+
+
+# 17x17 positions of the 24 guide tubes and the central instrument tube of a
+# PWR-style assembly (five rows of the symmetric pattern)
+GUIDE_TUBES_17 = [(2, 5), (2, 8), (2, 11), (3, 3), (3, 13), (5, 2), (5, 5), (5, 8), (5, 11), (5, 14),
+                  (8, 2), (8, 5), (8, 8), (8, 11), (8, 14), (11, 2), (11, 5), (11, 8), (11, 11), (11, 14),
+                  (13, 3), (13, 13), (14, 5), (14, 8), (14, 11)]
+
+
+def core_problem(data_seed: int = 3103, seed: int = 31, histories: int = 200_000,
+                 batches: int = 10) -> Problem:
+    """A 3x3 core of 17x17-pin assemblies of three types, the flat 51x51
+    lattice of the same pins (r 0.41, pitch 1.26, 1 cm high, reflective):
+    type 0 fuel (material 0, 20 nuclides) with its 25 guide-tube positions
+    empty (water), type 1 the same with absorber rods (material 1, 3
+    nuclides) in the guide tubes, type 2 a water assembly (no cylinders).
+    Core map (rows along y): [[0, 1, 0], [1, 2, 1], [0, 1, 0]]; moderator
+    material 2 (5 nuclides, the first with A = 1); uniform 2 MeV source over
+    the box; a 51x51x1 mesh flux tally whose cells are the pin cells."""
+    rng = np.random.default_rng(data_seed)
+    n_f, n_a, n_m = 20, 3, 5
+    awr = np.concatenate([rng.uniform(2.0, 240.0, n_f + n_a), [1.0], rng.uniform(2.0, 30.0, n_m - 1)])
+    sizes = rng.integers(5_000, 20_001, awr.size)
+    nucs = [make_nuclide(rng, a, int(s), "clustered") for a, s in zip(awr, sizes)]
+    fuel = make_material(rng, nucs, np.arange(0, n_f), 0.6)
+    absorber = make_material(rng, nucs, np.arange(n_f, n_f + n_a), 0.9)
+    moder = make_material(rng, nucs, np.arange(n_f + n_a, n_f + n_a + n_m), 0.5, fixed_fraction=(0, 0.6))
+    pins = 17
+    t0 = np.zeros((pins, pins), np.int32)
+    for j, i in GUIDE_TUBES_17:
+        t0[j, i] = -1
+    t1 = t0.copy()
+    for j, i in GUIDE_TUBES_17:
+        t1[j, i] = 1
+    t2 = np.full((pins, pins), -1, np.int32)
+    core = [[0, 1, 0], [1, 2, 1], [0, 1, 0]]
+    n = 3 * pins
+    geom = _lattice_geometry(n, assembly_pin_map(core, [t0, t1, t2], pins), 2)
+    L = n * PIN_PITCH
+    return Problem(name="core_3x3_assemblies", nuclides=nucs, materials=[fuel, absorber, moder],
+                   geometry=geom, source=Source(kind=SRC_BOX, box=(0.0, L, 0.0, L, 0.0, 1.0)),
+                   tally=Tally(TALLY_MESH, mesh_dims=(n, n, 1), mesh_box=(0.0, L, 0.0, L, 0.0, 1.0)),
+                   histories=histories, batches=batches, seed=seed)
+
+
 def lattice_homogeneous_problem(nuclides: List[Nuclide], material: Material, n: int = 17,
                                 seed: int = 21, histories: int = 20_000, batches: int = 10,
                                 height: float = 1.0) -> Problem:

@@ -270,3 +270,31 @@ def test_invalid_inputs_rejected(torch_cuda):
         assert e.value.code == mc.MC_EINVAL
     finally:
         mc.mc_destroy(ctx)
+
+
+def test_core_of_assemblies_matches_oracle(torch_cuda):
+    """A 3x3 core of three assembly types (open guide tubes, absorber rods,
+    a water assembly) on the flat 51x51 lattice: same-seed histories mostly
+    identical to the oracle's (device and host logarithms may differ in the
+    last ulp), and the flux of every pin cell (a 51x51x1 mesh) within 3
+    sigma of the oracle's on independent batches."""
+    torch = torch_cuda
+    prob = mcsynth.core_problem()
+    n = 20_000
+    _say("3x3 core of assemblies")
+    with Transport(prob) as t:
+        g = _gpu_histories(torch, t, 31, 0, n)
+        t.reset()
+        for b in range(20):
+            t.run_batch(310, b * n, n)
+        gm, gs, _ = t.tallies(mc.MC_T_FLUX_TRACK)
+    o = oracle.run(oracle.OracleProblem(prob), 31, 0, n, history=True).history
+    same = (g["n_draws"] == o["n_draws"]) & (g["E_final"] == o["E_final"]) & (g["fate"] == o["fate"])
+    _say(f"core identical histories: {same.mean():.4f}")
+    assert same.mean() > 0.9 and np.all(g["fate"] > 0)
+    assert np.all(gm > 0.0)
+    st = oracle.run_batches(oracle.OracleProblem(prob), 311, 20, n)
+    # 2601 bins, each side's standard error from 20 batches: Student's t
+    # allowance (2 x 19 degrees of freedom)
+    n_fail, allowed, z = three_sigma(gm, gs, st.mean["tl"], st.stderr["tl"], dof=38)
+    assert n_fail <= allowed, (n_fail, allowed, z)
