@@ -138,6 +138,7 @@ struct mc_ctx {
 
     std::vector<hipEvent_t> ev_a, ev_b;
     hipEvent_t ev_batch0 = nullptr, ev_batch1 = nullptr;
+    hipEvent_t ev_ctr[2] = {nullptr, nullptr};  // an iteration's queue lengths are on the host
 
     // concurrent event loops (tuning field loops > 1): each a worker context
     // with its own stream, bank and counters, sharing this context's tables;
@@ -337,6 +338,8 @@ int mc_create(mc_ctx **out, int device, void *hip_stream, const mc_alloc *alloc)
         rc = MC_ENOMEM;
     if (!rc && (hipEventCreate(&ctx->ev_batch0) != hipSuccess || hipEventCreate(&ctx->ev_batch1) != hipSuccess))
         rc = MC_EHIP;
+    for (int k = 0; k < 2 && !rc; ++k)
+        if (hipEventCreateWithFlags(&ctx->ev_ctr[k], hipEventDisableTiming) != hipSuccess) rc = MC_EHIP;
     if (rc) {
         mc_destroy(ctx);
         return rc;
@@ -378,6 +381,8 @@ void mc_destroy(mc_ctx *ctx)
     for (hipEvent_t e : ctx->ev_b) (void)hipEventDestroy(e);
     if (ctx->ev_batch0) (void)hipEventDestroy(ctx->ev_batch0);
     if (ctx->ev_batch1) (void)hipEventDestroy(ctx->ev_batch1);
+    for (hipEvent_t e : ctx->ev_ctr)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -1412,33 +1417,61 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
     // (with weight windows a history also runs its pending copies one by one)
     uint64_t max_iter = (n / cap + 2) * ((uint64_t)max_events + 2);
     if (W.kind != WW_OFF) max_iter *= 1ull + (uint64_t)W.depth * (uint64_t)W.nmax;
+    // The host runs one iteration behind the GPU: after the first iteration
+    // (whose queue lengths it waits for) it queues iteration `it` while the
+    // GPU still works on iteration it - 1, knowing the queue lengths of
+    // it - 1 only (copied to the host as soon as that iteration's queues were
+    // built).  Every kernel reads its exact length from the device counters;
+    // the host sizes grids by bounds: with no histories left to start and no
+    // weight-window copies, no queue grows, so iteration it's queues are no
+    // longer than it - 1's alive queue, and otherwise the bank capacity
+    // bounds them.  Its choices (sort or not, the one-launch tail) follow
+    // it - 1's lengths, which changes no result: a sorted queue only reorders
+    // the lookups, and the tail runs the same histories.  The loop ends when
+    // it - 1 had no particle alive (one empty iteration queued).
+    Counters p{};                 // lengths of iteration it - 1 (of it itself when it = 0)
+    bool sorted_prev = false;     // iteration it - 1 sorted its lookup queue
+    bool tail_run = false;
+    const bool analog = W.kind == WW_OFF;
     for (;; ++it) {
         if (it >= max_iter) return fail(ctx, MC_EHIP, "event loop did not terminate");
         const int cur = (int)(it & 1);
         HIPCHK(launch_slots_count(b, st));
         HIPCHK(launch_slots_queue(b, g, W, ctx->ctr, cur, first_pid, n, seed, st));
         HIPCHK(hipMemcpyAsync(ctx->ctr_host + cur, ctx->ctr + cur, sizeof(Counters), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        const Counters c = ctx->ctr_host[cur];
-        if (c.nA == 0) {
-            if (c.issued != n || c.top != 0)
+        HIPCHK(hipEventRecord(ctx->ev_ctr[cur], st));
+        const bool exact = it == 0;
+        if (exact) {
+            HIPCHK(hipEventSynchronize(ctx->ev_ctr[cur]));
+            p = ctx->ctr_host[cur];
+        } else {
+            HIPCHK(hipEventSynchronize(ctx->ev_ctr[cur ^ 1]));
+            p = ctx->ctr_host[cur ^ 1];
+            s.lookups += p.nL;
+            if (sorted_prev) s.sorted_lookups += p.nL;
+            s.flights += p.nA;
+        }
+        if (p.nA == 0) {
+            if (p.issued != n || p.top != 0)
                 return fail(ctx, MC_EHIP, "event loop ended before every history (and copy) was run");
+            if (!exact) --it;  // iterations with particles: 0 .. it - 2
             break;
         }
         Counters *dc = ctx->ctr + cur;
+        const uint32_t bound = (exact || (analog && p.issued == n)) ? p.nA : cap;
         const int64_t tail = tail_particles(ctx);
-        if (tail > 0 && W.kind == WW_OFF && W.imp_nx == 0 && c.issued == n && (int64_t)c.nA <= tail) {
+        if (tail > 0 && analog && W.imp_nx == 0 && p.issued == n && (int64_t)p.nA <= tail) {
             // every history has started and few remain: finish them in one launch
-            HIPCHK(launch_tail(b, ctx->xs, g, tal, dc, c.nA, seed, max_events, log, first_pid, ctx->dstat + 1, st));
-            s.tail_particles = c.nA;
+            HIPCHK(launch_tail(b, ctx->xs, g, tal, dc, bound, seed, max_events, log, first_pid, ctx->dstat + 1, st));
+            tail_run = true;
             ++it;
             break;
         }
-        if (c.nL > 0) {
+        {
             LookupLaunch l;
             l.xs = ctx->xs;
             l.n_ptr = &dc->nL;
-            l.n_bound = c.nL;
+            l.n_bound = bound;
             l.E = b.E;
             l.mat = b.mat;
             l.Sa = b.Sa;
@@ -1448,47 +1481,48 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
             l.ilp = lookup_ilp(ctx);
             l.cp = b.cp;
             l.sx = b.sx;
-            const bool sort = (uint64_t)c.nL >= sort_min && sort_min != UINT64_MAX;
-            if (sort) {
-                HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, c.nL, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls,
+            sorted_prev = (uint64_t)p.nL >= sort_min && sort_min != UINT64_MAX;
+            if (sorted_prev) {
+                HIPCHK(launch_sort(ctx->xs, b.L, &dc->nL, bound, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls,
                                    b.Lkey, st));
                 l.list = b.Ls;
                 l.keys = b.Lkey;
-                s.sorted_lookups += c.nL;
             } else {
                 l.list = b.L;
             }
             if ((rc = time_begin(T_LOOKUP))) return rc;
             HIPCHK(launch_lookup(l, st));
             if ((rc = time_end())) return rc;
-            s.lookups += c.nL;
             s.lookup_launches += 1;
         }
         // analog runs without an importance grid cross surfaces in the flight
         // kernel (the split then queues only collisions)
-        const bool fuse_cross = W.kind == WW_OFF && W.imp_nx == 0;
+        const bool fuse_cross = analog && W.imp_nx == 0;
         if ((rc = time_begin(T_ADVANCE))) return rc;
-        HIPCHK(launch_advance(b, g, tal, W, dc, c.nA, seed, max_events, log ? 1 : 0, fuse_cross, log, first_pid,
+        HIPCHK(launch_advance(b, g, tal, W, dc, bound, seed, max_events, log ? 1 : 0, fuse_cross, log, first_pid,
                               ctx->dstat + 1, st));
         if ((rc = time_end())) return rc;
-        s.flights += c.nA;
         if ((rc = time_begin(T_CROSS))) return rc;
-        HIPCHK(launch_split(b, dc, c.nA, st));
-        if (!fuse_cross) HIPCHK(launch_cross(b, g, tal, W, dc, c.nA, seed, log, first_pid, ctx->dstat + 1, st));
+        HIPCHK(launch_split(b, dc, bound, st));
+        if (!fuse_cross) HIPCHK(launch_cross(b, g, tal, W, dc, bound, seed, log, first_pid, ctx->dstat + 1, st));
         if ((rc = time_end())) return rc;
         if ((rc = time_begin(T_COLLIDE))) return rc;
         // collisions re-gather sigma_s: in (material, energy) order when the
         // queues are long enough to sort (the sorted lookup queue is no longer
         // needed, its buffers take the sorted collide queue)
         const uint32_t *qc = b.Qc;
-        if ((uint64_t)c.nA >= collide_sort_min && collide_sort_min != UINT64_MAX) {
-            HIPCHK(launch_sort(ctx->xs, b.Qc, &dc->nC, c.nA, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls, b.Lkey,
+        if ((uint64_t)p.nA >= collide_sort_min && collide_sort_min != UINT64_MAX) {
+            HIPCHK(launch_sort(ctx->xs, b.Qc, &dc->nC, bound, b.E, b.mat, ctx->bank_sort, ctx->n_keys, b.Ls, b.Lkey,
                                st));
             qc = b.Ls;
         }
-        HIPCHK(launch_collide(b, qc, ctx->xs, g, tal, W, dc, c.nA, seed, log, first_pid, st));
+        HIPCHK(launch_collide(b, qc, ctx->xs, g, tal, W, dc, bound, seed, log, first_pid, st));
         if ((rc = time_end())) return rc;
         if (W.kind != WW_OFF) HIPCHK(launch_ww_flush(b, W, dc, st));
+    }
+    if (tail_run) {  // the tail's particle count: the lengths of its iteration
+        HIPCHK(hipStreamSynchronize(st));
+        s.tail_particles = ctx->ctr_host[(it - 1) & 1].nA;
     }
     if (!stats) {  // a worker of concurrent loops or batches: its caller forms the statistics
         HIPCHK(hipEventRecord(ctx->ev_batch1, st));

@@ -276,11 +276,14 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
 // Tiles of WG * items keys, items in [1, 16] chosen per sort so that a
 // queue of a few hundred thousand keys still spreads over ~1024 workgroups;
 // chunks of at least 16 tiles, at most 128 chunks for the one-workgroup scan.
+// The kernels take the shape from the queue's length as they read it on the
+// device, so a launch sized for a bound sorts a shorter queue as if it had
+// been sized for it.
 struct SortShape {
     uint32_t items, tiles, chunk, chunks;
 };
 
-static SortShape sort_shape(uint32_t n)
+__host__ __device__ inline SortShape sort_shape(uint32_t n)
 {
     SortShape s;
     const uint32_t per = 1024u * WG;
@@ -321,7 +324,6 @@ struct SortPassArgs {
     const uint32_t *n_ptr;
     uint32_t n_fixed;
     int32_t shift;
-    uint32_t items, chunk;     // keys per thread of a tile, tiles per chunk
     const uint32_t *keys_in;   // null on the first pass: keys computed from (E, mat) of vals_in
     uint32_t *keys_first;      // first pass: where the computed keys go
     const uint32_t *vals_in;   // null: identity
@@ -335,11 +337,12 @@ __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
 {
     __shared__ uint32_t h[256];
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
-    const uint32_t base = blockIdx.x * a.items * (uint32_t)WG;
+    const SortShape sh = sort_shape(n);
+    const uint32_t base = blockIdx.x * sh.items * (uint32_t)WG;
     if (base >= n) return;
     h[threadIdx.x] = 0u;
     __syncthreads();
-    for (uint32_t r = 0; r < a.items; ++r) {
+    for (uint32_t r = 0; r < sh.items; ++r) {
         const uint32_t i = base + r * WG + threadIdx.x;
         const bool valid = i < n;
         uint32_t key = 0;
@@ -358,16 +361,18 @@ __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
     __syncthreads();
     const uint32_t c = h[threadIdx.x];
     a.tile_hist[blockIdx.x * 256 + threadIdx.x] = c;
-    if (c) atomicAdd(&a.chunk_total[(blockIdx.x / a.chunk) * 256 + threadIdx.x], c);
+    if (c) atomicAdd(&a.chunk_total[(blockIdx.x / sh.chunk) * 256 + threadIdx.x], c);
 }
 
 // chunk_off[c][d] = items of digit d in chunks < c, and in the row after the
 // last chunk, chunk_off[n_chunks][d] = items with digit < d (the scatter adds
 // the two); resets chunk_total for the next pass.  One workgroup, thread =
 // digit, one pass over the chunk totals.
-__global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32_t *chunk_off, uint32_t n_chunks)
+__global__ void __launch_bounds__(WG) k_radix_scan(uint32_t *chunk_total, uint32_t *chunk_off,
+                                                   const uint32_t *n_ptr, uint32_t n_fixed)
 {
     __shared__ uint32_t tot[256];
+    const uint32_t n_chunks = sort_shape(n_ptr ? *n_ptr : n_fixed).chunks;
     const uint32_t d = threadIdx.x;
     constexpr uint32_t B = 16;  // chunk totals loaded together (independent loads in flight)
     uint32_t run = 0;
@@ -401,12 +406,12 @@ __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
     __shared__ uint32_t off[256];
     __shared__ uint32_t wc[WAVES * 256];
     const uint32_t n = a.n_ptr ? *a.n_ptr : a.n_fixed;
-    const uint32_t base = blockIdx.x * a.items * (uint32_t)WG;
+    const SortShape sh = sort_shape(n);
+    const uint32_t base = blockIdx.x * sh.items * (uint32_t)WG;
     if (base >= n) return;
-    const uint32_t t = blockIdx.x, c0 = (t / a.chunk) * a.chunk;
+    const uint32_t t = blockIdx.x, c0 = (t / sh.chunk) * sh.chunk;
     {
-        const uint32_t n_chunks = (gridDim.x + a.chunk - 1) / a.chunk;
-        uint32_t o = a.chunk_off[(t / a.chunk) * 256 + threadIdx.x] + a.chunk_off[n_chunks * 256 + threadIdx.x];
+        uint32_t o = a.chunk_off[(t / sh.chunk) * 256 + threadIdx.x] + a.chunk_off[sh.chunks * 256 + threadIdx.x];
         // the chunk's earlier tiles, their histograms loaded 8 at a time
         for (uint32_t u0 = c0; u0 < t; u0 += 8) {
             uint32_t v[8];
@@ -420,7 +425,7 @@ __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
     const int wave = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
     const uint32_t *keys_in = a.keys_in ? a.keys_in : a.keys_first;
-    for (uint32_t r = 0; r < a.items; ++r) {
+    for (uint32_t r = 0; r < sh.items; ++r) {
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) wc[w * 256 + threadIdx.x] = 0u;
         __syncthreads();
@@ -1881,12 +1886,12 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
     uint32_t bits = 1;
     while (bits < 32 && (1ull << bits) < (uint64_t)n_keys) ++bits;
     const int passes = (int)((bits + 7) / 8);
-    const SortShape sh = sort_shape(n_bound);
-    const unsigned tiles = sh.tiles;
-    const uint32_t chunks = sh.chunks;
+    // tiles of the longest queue up to n_bound: at most 1024 up to 16 tiles
+    // of 16 keys per thread (the shape's cap), one per 4096 keys beyond
+    const uint32_t per16 = 16u * 1024u * WG;
+    const unsigned tiles = n_bound <= 1024u * WG ? (n_bound + WG - 1) / WG
+                           : (n_bound <= per16 ? 1024u : (n_bound + 16u * WG - 1) / (16u * WG));
     SortPassArgs a{};
-    a.items = sh.items;
-    a.chunk = sh.chunk;
     a.xs = xs;
     a.E = E;
     a.mat = mat;
@@ -1914,7 +1919,7 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
             a.vals_out = (p & 1) ? sb.vA : sb.vB;
         }
         hipLaunchKernelGGL(k_radix_count, dim3(tiles), dim3(WG), 0, st, a);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(WG), 0, st, sb.chunk_total, sb.chunk_off, chunks);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(WG), 0, st, sb.chunk_total, sb.chunk_off, n_ptr, n_bound);
         hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(WG), 0, st, a);
     }
     return hipGetLastError();
