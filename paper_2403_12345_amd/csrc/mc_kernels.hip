@@ -223,6 +223,7 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
     const uint32_t n_free = tot[2] - n_copy;
     const uint32_t n_new = (uint32_t)((uint64_t)n_free < remaining ? (uint64_t)n_free : remaining);
     const uint32_t base = blockIdx.x * (uint32_t)TILE;
+    const uint32_t n_refill = n_copy + n_new;  // the first n_refill free slots are refilled
     uint32_t run[3] = {0, 0, 0};
     for (int r = 0; r < TILE_ITEMS; ++r) {
         const uint32_t s = base + r * WG + threadIdx.x;
@@ -232,19 +233,19 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
         const bool look = valid && (f & F_LOOKUP);
         const bool fr = valid && !(f & F_ALIVE);
         const Rank3 rk = block_rank3(alive, look, fr, lds);
-        if (alive) bank.A[pre[0] + run[0] + rk.rank[0]] = s;
-        if (look) bank.L[pre[1] + run[1] + rk.rank[1]] = s;
-        if (fr) {
-            const uint32_t k = pre[2] + run[2] + rk.rank[2];
-            if (k < n_copy) {
-                load_copy(bank, W, s, qtop - 1u - k);
-                bank.A[tot[0] + k] = s;
-                bank.L[tot[1] + k] = s;
-            } else if (k - n_copy < n_new) {
-                init_particle(bank, geom, W, s, first_pid + prev.issued + (k - n_copy), seed);
-                bank.A[tot[0] + k] = s;
-                bank.L[tot[1] + k] = s;
-            }
+        // the queues hold their slots in slot order, refilled ones included:
+        // slot s follows the alive (lookup) slots and the refilled slots
+        // before it, so with every slot alive the alive queue is the identity
+        const uint32_t k = pre[2] + run[2] + rk.rank[2];  // free slots before s
+        const uint32_t ref = k < n_refill ? k : n_refill;  // refilled slots before s
+        const uint32_t ia = pre[0] + run[0] + rk.rank[0] + ref, il = pre[1] + run[1] + rk.rank[1] + ref;
+        if (alive) bank.A[ia] = s;
+        if (look) bank.L[il] = s;
+        if (fr && k < n_refill) {
+            if (k < n_copy) load_copy(bank, W, s, qtop - 1u - k);
+            else init_particle(bank, geom, W, s, first_pid + prev.issued + (k - n_copy), seed);
+            bank.A[ia] = s;
+            bank.L[il] = s;
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) run[q] += rk.total[q];
@@ -1311,7 +1312,7 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
     int32_t flight_mat = -1;              // material of this lane's flight (-1: none)
     const double *sx_row = b.sx;
     if (i < n) {
-        const uint32_t s = b.A[i];
+        const uint32_t s = n == b.C ? i : b.A[i];  // every slot alive: the queue is the identity
         if ((int64_t)b.ncoll[s] + b.ncross[s] >= max_events) {
             if constexpr (CROSS) {  // event cap reached: the history ends here as lost
                 Particle p = load_particle(b, s);
@@ -1372,7 +1373,7 @@ __global__ void __launch_bounds__(WG) k_split_count(BankDev b, const Counters *c
         for (int r = 0; r < TILE_ITEMS; ++r) {
             const uint32_t i = base + r * WG + threadIdx.x;
             if (i < n) {
-                const uint8_t ev = b.event[b.A[i]];
+                const uint8_t ev = b.event[n == b.C ? i : b.A[i]];
                 cc += ev == EV_COLLIDE ? 1u : 0u;
                 cx += ev != EV_COLLIDE && ev != EV_DONE ? 1u : 0u;
             }
@@ -1394,7 +1395,7 @@ __global__ void __launch_bounds__(WG) k_split_scatter(BankDev b, Counters *ctr)
     for (int r = 0; r < TILE_ITEMS; ++r) {
         const uint32_t i = base + r * WG + threadIdx.x;
         const bool valid = i < n;
-        const uint32_t s = valid ? b.A[i] : 0u;
+        const uint32_t s = valid ? (n == b.C ? i : b.A[i]) : 0u;
         const uint8_t ev = valid ? b.event[s] : 0;
         const bool pc = valid && ev == EV_COLLIDE;
         const bool px = valid && ev != EV_COLLIDE && ev != EV_DONE;
