@@ -242,8 +242,10 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
         if (alive) bank.A[ia] = s;
         if (look) bank.L[il] = s;
         if (fr && k < n_refill) {
+            // copies load here; new histories start in k_slots_init, from the
+            // list of their slots (the cross queue is free until the split)
             if (k < n_copy) load_copy(bank, W, s, qtop - 1u - k);
-            else init_particle(bank, geom, W, s, first_pid + prev.issued + (k - n_copy), seed);
+            else bank.Qx[k - n_copy] = s;
             bank.A[ia] = s;
             bank.L[il] = s;
         }
@@ -263,6 +265,18 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
         c.pad = 0;
         ctr[cur] = c;
     }
+}
+
+// The source particles the refill started: the j-th new history of this
+// iteration (pid first_pid + issued - n_new + j) in slot Qx[j].  Its own
+// kernel, so that the queue scan runs without the source sampling's registers.
+__global__ void __launch_bounds__(WG) k_slots_init(BankDev bank, GeomDev geom, WwDev W, const Counters *ctr, int cur,
+                                                   uint64_t first_pid, uint64_t seed)
+{
+    const Counters c = ctr[cur];
+    const uint32_t j = blockIdx.x * WG + threadIdx.x;
+    if (j >= c.n_new) return;
+    init_particle(bank, geom, W, bank.Qx[j], first_pid + (c.issued - c.n_new) + j, seed);
 }
 
 // ---------------------------------------------------------------------------
@@ -1876,6 +1890,8 @@ hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, const WwDev &W
 {
     hipLaunchKernelGGL(k_slots_queue, dim3(blocks_for(b.C, TILE)), dim3(WG), 0, st, b, g, W, ctr, cur,
                        first_pid, n_hist, seed);
+    // new histories: at most one per slot
+    hipLaunchKernelGGL(k_slots_init, dim3(blocks_for(b.C, WG)), dim3(WG), 0, st, b, g, W, ctr, cur, first_pid, seed);
     return hipGetLastError();
 }
 
