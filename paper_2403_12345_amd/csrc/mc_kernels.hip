@@ -1325,6 +1325,13 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
     clear_score(sc);
     int32_t flight_mat = -1;              // material of this lane's flight (-1: none)
     const double *sx_row = b.sx;
+    // a mesh tally scores last, after the crossing, the stores and the
+    // workgroup's tally rows: on this GPU a load waits for every earlier
+    // store and atomic of its wave, so no load may follow the mesh's atomic
+    // adds; the flight's start, direction, length and weight wait here
+    const bool mesh = tal.enabled && g.tally_kind == TALLY_MESH;
+    bool mesh_on = false;
+    double fx = 0.0, fy = 0.0, fz = 0.0, fu = 0.0, fv = 0.0, fw = 0.0, fd = 0.0, fwt = 0.0;
     if (i < n) {
         const uint32_t s = n == b.C ? i : b.A[i];  // every slot alive: the queue is the identity
         if ((int64_t)b.ncoll[s] + b.ncross[s] >= max_events) {
@@ -1339,9 +1346,11 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
         } else {
             Particle p = load_particle(b, s);
             const double x0 = p.x;
+            fx = p.x; fy = p.y; fz = p.z; fu = p.u; fv = p.v; fw = p.w; fwt = p.wt;
             flight_mat = p.mat;
             if (tal.chan) sx_row = b.sx + (size_t)s * tal.n_chan;
-            do_advance(p, g, seed, tal.enabled != 0, tal.mesh_tl, log_on != 0, sc);
+            fd = do_advance(p, g, seed, tal.enabled != 0, mesh ? nullptr : tal.mesh_tl, log_on != 0, sc);
+            mesh_on = mesh;
             if (!CROSS && W.imp_nx) imp_enter(W, s, x0, p.x, p.E, p.wt);
             b.ndraw[s] = p.ndraw;
             if (log_on) b.track[s] = p.track;
@@ -1372,6 +1381,7 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
         wg_chan_add(flight_mat, sc.g[G_TRACK], sx_row, tal.n_chan, slab, tal.chan_bins,
                     tal.chan + (size_t)blockIdx.x * tal.chan_bins);
     wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
+    if (mesh_on) mesh_flight(g, tal.mesh_tl, fx, fy, fz, fu, fv, fw, fd, fwt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1535,10 +1545,20 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, const uint32_t *list,
     Particle p{};
     uint32_t s = 0;
     int32_t fate = 0;
+    // the collision estimator's mesh cell scores last (no load may follow an
+    // atomic add of the wave: it would wait for it)
+    const bool mesh = tal.enabled && g.tally_kind == TALLY_MESH;
+    int32_t mesh_cell = -1;
+    double mesh_val = 0.0;
     if (act) {
         s = list[i];
         p = load_particle(b, s);
-        fate = do_collide(p, xs, g, seed, tal.enabled != 0, tal.mesh_coll, sc, b.cp ? b.cp + (size_t)s * CP_MAX : nullptr);
+        if (mesh) {
+            mesh_cell = mesh_index(g, p.x, p.y, p.z);
+            mesh_val = p.wt / (p.Sa + p.Ss);
+        }
+        fate = do_collide(p, xs, g, seed, tal.enabled != 0, mesh ? nullptr : tal.mesh_coll, sc,
+                          b.cp ? b.cp + (size_t)s * CP_MAX : nullptr);
         if (fate == 0 && W.imp_nx) imp_enter(W, s, p.x, p.x, p.E, p.wt);
     }
     if constexpr (WWK != WW_OFF) {
@@ -1561,6 +1581,7 @@ __global__ void __launch_bounds__(WG) k_collide(BankDev b, const uint32_t *list,
     if (tal.enabled && g.tally_kind != TALLY_MESH)
         wg_bin_add(sc.c_bin, sc.c_val, slab, tal.n_bins, tal.coll + (size_t)blockIdx.x * tal.n_bins);
     wg_glob_add(sc.g, gl, tal.glob + (size_t)blockIdx.x * N_GLOBAL);
+    if (mesh_cell >= 0) mesh_add(tal.mesh_coll, mesh_cell, mesh_val, g.n_bins);
 }
 
 // ---------------------------------------------------------------------------

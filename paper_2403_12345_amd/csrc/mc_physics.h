@@ -146,6 +146,10 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
             tdelta[k] = INFINITY;
         }
     }
+    // the mesh sizes in registers: indexed by the axis of the step, the
+    // argument array would be read from memory each step, and that read
+    // would wait for the step's atomic add to complete
+    const int32_t nx = g.mesh_dims[0], ny = g.mesh_dims[1], nz = g.mesh_dims[2];
     double t = t_in;
     for (int guard = 0; guard < 100000 && t < t_out; ++guard) {
         int k = 0;
@@ -153,13 +157,14 @@ __device__ inline void mesh_flight(const GeomDev &g, double *acc, double x, doub
         if (tnext[2] < tnext[k]) k = 2;
         const double t1 = fmin(fmax(tnext[k], t), t_out);
         if (t1 > t) {
-            const int32_t idx = (c[2] * g.mesh_dims[1] + c[1]) * g.mesh_dims[0] + c[0];
+            const int32_t idx = (c[2] * ny + c[1]) * nx + c[0];
             mesh_add(acc, idx, wt * (t1 - t), g.n_bins);
         }
         t = t1;
         if (t >= t_out) break;
         c[k] += step[k];
-        if (c[k] < 0 || c[k] >= g.mesh_dims[k]) break;
+        const int32_t nk = k == 0 ? nx : (k == 1 ? ny : nz);
+        if (c[k] < 0 || c[k] >= nk) break;
         tnext[k] += tdelta[k];
     }
 }
@@ -319,9 +324,11 @@ __device__ inline void do_lookup(Particle &p, const XsDev &xs, double *sx_row = 
 }
 
 // Flight: distance to collision -ln(xi)/Sigma_t (one draw), distance to the
-// nearest surface, move by the smaller, score the track length.  Sets p.ev.
-__device__ inline void do_advance(Particle &p, const GeomDev &g, uint64_t seed, bool tally_on, double *mesh_tl,
-                                  bool log_on, StepScore &sc)
+// nearest surface, move by the smaller, score the track length.  Sets p.ev
+// and returns the flight's length.  A mesh tally with mesh_tl null is left to
+// the caller (mesh_flight from the flight's start).
+__device__ inline double do_advance(Particle &p, const GeomDev &g, uint64_t seed, bool tally_on, double *mesh_tl,
+                                    bool log_on, StepScore &sc)
 {
     Rng rng(seed, p.pid, p.lineage, p.ndraw);
     const double st = p.Sa + p.Ss;
@@ -344,10 +351,13 @@ __device__ inline void do_advance(Particle &p, const GeomDev &g, uint64_t seed, 
         case TALLY_ENERGY: sc.tl_bin = energy_bin(g, p.E); break;
         case TALLY_PIN: sc.tl_bin = p.inside ? p.cell : -1; break;
         case TALLY_SLAB: sc.tl_bin = p.cell; break;
-        case TALLY_MESH: mesh_flight(g, mesh_tl, x0, y0, z0, p.u, p.v, p.w, d, p.wt); break;
+        case TALLY_MESH:
+            if (mesh_tl) mesh_flight(g, mesh_tl, x0, y0, z0, p.u, p.v, p.w, d, p.wt);
+            break;
         }
         sc.tl_val = p.wt * d;
     }
+    return d;
 }
 
 // Surface crossing p.ev: lattice step (the coordinate snaps onto the plane),
@@ -399,7 +409,12 @@ __device__ inline int32_t do_cross(Particle &p, const GeomDev &g, StepScore &sc,
         }
     }
     if (face >= 0) {
-        if (g.bc[face] == BC_VACUUM) {
+        // (the face's condition picked from the six, not indexed: an indexed
+        // read of the argument array would go to memory)
+        int32_t bcf = g.bc[0];
+#pragma unroll
+        for (int f = 1; f < 6; ++f) bcf = face == f ? g.bc[f] : bcf;
+        if (bcf == BC_VACUUM) {
             sc.g[G_LEAK] += p.wt;
             if (face == 1) {
                 leak_xhi = true;
@@ -444,8 +459,8 @@ __device__ inline int32_t do_collide(Particle &p, const XsDev &xs, const GeomDev
         case TALLY_ENERGY: sc.c_bin = energy_bin(g, p.E); break;
         case TALLY_PIN: sc.c_bin = p.inside ? p.cell : -1; break;
         case TALLY_SLAB: sc.c_bin = p.cell; break;
-        case TALLY_MESH: {
-            const int32_t c = mesh_index(g, p.x, p.y, p.z);
+        case TALLY_MESH: {  // (mesh_coll null: the caller scores it)
+            const int32_t c = mesh_coll ? mesh_index(g, p.x, p.y, p.z) : -1;
             if (c >= 0) mesh_add(mesh_coll, c, p.wt / st, g.n_bins);
         } break;
         }
