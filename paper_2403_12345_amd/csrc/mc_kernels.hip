@@ -225,10 +225,18 @@ __global__ void __launch_bounds__(WG) k_slots_queue(BankDev bank, GeomDev geom, 
     const uint32_t base = blockIdx.x * (uint32_t)TILE;
     const uint32_t n_refill = n_copy + n_new;  // the first n_refill free slots are refilled
     uint32_t run[3] = {0, 0, 0};
+    // every item's flags loaded before any queue entry is stored (a load
+    // waits for the earlier stores of its wave)
+    uint8_t fl[TILE_ITEMS];
+#pragma unroll
+    for (int r = 0; r < TILE_ITEMS; ++r) {
+        const uint32_t s = base + r * WG + threadIdx.x;
+        fl[r] = s < bank.C ? bank.flags[s] : 0;
+    }
     for (int r = 0; r < TILE_ITEMS; ++r) {
         const uint32_t s = base + r * WG + threadIdx.x;
         const bool valid = s < bank.C;
-        const uint8_t f = valid ? bank.flags[s] : 0;
+        const uint8_t f = fl[r];
         const bool alive = valid && (f & F_ALIVE);
         const bool look = valid && (f & F_LOOKUP);
         const bool fr = valid && !(f & F_ALIVE);
@@ -297,6 +305,7 @@ __global__ void __launch_bounds__(WG) k_slots_init(BankDev bank, GeomDev geom, W
 struct SortShape {
     uint32_t items, tiles, chunk, chunks;
 };
+constexpr uint32_t SORT_BATCH = 4;  // items of a thread loaded together
 
 __host__ __device__ inline SortShape sort_shape(uint32_t n)
 {
@@ -357,21 +366,26 @@ __global__ void __launch_bounds__(WG) k_radix_count(SortPassArgs a)
     if (base >= n) return;
     h[threadIdx.x] = 0u;
     __syncthreads();
-    for (uint32_t r = 0; r < sh.items; ++r) {
-        const uint32_t i = base + r * WG + threadIdx.x;
-        const bool valid = i < n;
-        uint32_t key = 0;
-        if (valid) {
-            if (a.keys_in) {
-                key = a.keys_in[i];
-            } else {
-                key = sort_key(a.xs, a.E, a.mat, a.vals_in ? a.vals_in[i] : i);
-                a.keys_first[i] = key;
-            }
+    // keys SORT_BATCH items at a time, all loaded before any is stored (a
+    // load waits for the earlier stores of its wave)
+    for (uint32_t r0 = 0; r0 < sh.items; r0 += SORT_BATCH) {
+        uint32_t key[SORT_BATCH];
+        bool valid[SORT_BATCH];
+#pragma unroll
+        for (uint32_t j = 0; j < SORT_BATCH; ++j) {
+            const uint32_t i = base + (r0 + j) * WG + threadIdx.x;
+            valid[j] = r0 + j < sh.items && i < n;
+            key[j] = 0u;
+            if (valid[j]) key[j] = a.keys_in ? a.keys_in[i] : sort_key(a.xs, a.E, a.mat, a.vals_in ? a.vals_in[i] : i);
         }
-        const uint32_t d = (key >> a.shift) & 255u;
-        const uint64_t peers = digit_peers(d, valid);
-        if (valid && lane_id() == __ffsll((long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+#pragma unroll
+        for (uint32_t j = 0; j < SORT_BATCH; ++j) {
+            if (r0 + j >= sh.items) break;  // (uniform)
+            if (valid[j] && !a.keys_in) a.keys_first[base + (r0 + j) * WG + threadIdx.x] = key[j];
+            const uint32_t d = (key[j] >> a.shift) & 255u;
+            const uint64_t peers = digit_peers(d, valid[j]);
+            if (valid[j] && lane_id() == __ffsll((long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     const uint32_t c = h[threadIdx.x];
@@ -440,30 +454,42 @@ __global__ void __launch_bounds__(WG) k_radix_scatter(SortPassArgs a)
     const int wave = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
     const uint32_t *keys_in = a.keys_in ? a.keys_in : a.keys_first;
-    for (uint32_t r = 0; r < sh.items; ++r) {
+    // SORT_BATCH items' keys and values loaded before any is scattered (a
+    // load waits for the earlier stores of its wave)
+    for (uint32_t r0 = 0; r0 < sh.items; r0 += SORT_BATCH) {
+        uint32_t kb[SORT_BATCH], vb[SORT_BATCH];
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) wc[w * 256 + threadIdx.x] = 0u;
-        __syncthreads();
-        const uint32_t i = base + r * WG + threadIdx.x;
-        const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const uint32_t val = valid ? (a.vals_in ? a.vals_in[i] : i) : 0u;
-        const uint32_t d = (key >> a.shift) & 255u;
-        const uint64_t peers = digit_peers(d, valid);
-        if (valid && lane_id() == __ffsll((long long)peers) - 1) wc[wave * 256 + d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = off[d] + (uint32_t)__popcll(peers & lt);
-            for (int w = 0; w < wave; ++w) pos += wc[w * 256 + d];
-            a.keys_out[pos] = key;
-            a.vals_out[pos] = val;
+        for (uint32_t j = 0; j < SORT_BATCH; ++j) {
+            const uint32_t i = base + (r0 + j) * WG + threadIdx.x;
+            const bool valid = r0 + j < sh.items && i < n;
+            kb[j] = valid ? keys_in[i] : 0u;
+            vb[j] = valid ? (a.vals_in ? a.vals_in[i] : i) : 0u;
         }
-        __syncthreads();
-        uint32_t add = 0;
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) add += wc[w * 256 + threadIdx.x];
-        off[threadIdx.x] += add;
-        __syncthreads();
+        for (uint32_t j = 0; j < SORT_BATCH; ++j) {
+            if (r0 + j >= sh.items) break;  // (uniform)
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) wc[w * 256 + threadIdx.x] = 0u;
+            __syncthreads();
+            const bool valid = base + (r0 + j) * WG + threadIdx.x < n;
+            const uint32_t key = kb[j];
+            const uint32_t d = (key >> a.shift) & 255u;
+            const uint64_t peers = digit_peers(d, valid);
+            if (valid && lane_id() == __ffsll((long long)peers) - 1) wc[wave * 256 + d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = off[d] + (uint32_t)__popcll(peers & lt);
+                for (int w = 0; w < wave; ++w) pos += wc[w * 256 + d];
+                a.keys_out[pos] = key;
+                a.vals_out[pos] = vb[j];
+            }
+            __syncthreads();
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) add += wc[w * 256 + threadIdx.x];
+            off[threadIdx.x] += add;
+            __syncthreads();
+        }
     }
 }
 
@@ -1416,11 +1442,22 @@ __global__ void __launch_bounds__(WG) k_split_scatter(BankDev b, Counters *ctr)
     tile_prefix3(b.tile_cnt, n_tiles, blockIdx.x, lds, pre, tot);
     const uint32_t base = blockIdx.x * (uint32_t)TILE;
     uint32_t run[3] = {0, 0, 0};
+    // every item's slot and event loaded before any queue entry is stored (a
+    // load waits for the earlier stores of its wave)
+    uint32_t sl[TILE_ITEMS];
+    uint8_t evs[TILE_ITEMS];
+#pragma unroll
+    for (int r = 0; r < TILE_ITEMS; ++r) {
+        const uint32_t i = base + r * WG + threadIdx.x;
+        sl[r] = i < n ? (n == b.C ? i : b.A[i]) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < TILE_ITEMS; ++r) evs[r] = base + r * WG + threadIdx.x < n ? b.event[sl[r]] : 0;
     for (int r = 0; r < TILE_ITEMS; ++r) {
         const uint32_t i = base + r * WG + threadIdx.x;
         const bool valid = i < n;
-        const uint32_t s = valid ? (n == b.C ? i : b.A[i]) : 0u;
-        const uint8_t ev = valid ? b.event[s] : 0;
+        const uint32_t s = sl[r];
+        const uint8_t ev = evs[r];
         const bool pc = valid && ev == EV_COLLIDE;
         const bool px = valid && ev != EV_COLLIDE && ev != EV_DONE;
         const Rank3 rk = block_rank3(pc, px, false, lds);
