@@ -1352,7 +1352,7 @@ __global__ void __launch_bounds__(WG) k_advance(BankDev b, GeomDev g, TallyDev t
     int32_t flight_mat = -1;              // material of this lane's flight (-1: none)
     const double *sx_row = b.sx;
     // a mesh tally scores last, after the crossing, the stores and the
-    // workgroup's tally rows: on this GPU a load waits for every earlier
+    // workgroup's tally rows: on gfx950 a load waits for every earlier
     // store and atomic of its wave, so no load may follow the mesh's atomic
     // adds; the flight's start, direction, length and weight wait here
     const bool mesh = tal.enabled && g.tally_kind == TALLY_MESH;
@@ -1961,8 +1961,9 @@ hipError_t launch_sort(const XsDev &xs, const uint32_t *list, const uint32_t *n_
     uint32_t bits = 1;
     while (bits < 32 && (1ull << bits) < (uint64_t)n_keys) ++bits;
     const int passes = (int)((bits + 7) / 8);
-    // tiles of the longest queue up to n_bound: at most 1024 up to 16 tiles
-    // of 16 keys per thread (the shape's cap), one per 4096 keys beyond
+    // the most tiles a queue of up to n_bound keys takes: one per 256 keys
+    // up to 2^18 keys, then at most 1024 (a tile holds up to 16 keys per
+    // thread) up to 2^22, then one per 4096 keys
     const uint32_t per16 = 16u * 1024u * WG;
     const unsigned tiles = n_bound <= 1024u * WG ? (n_bound + WG - 1) / WG
                            : (n_bound <= per16 ? 1024u : (n_bound + 16u * WG - 1) / (16u * WG));
