@@ -1436,26 +1436,33 @@ static int run_loop(mc_ctx *ctx, uint64_t seed, uint64_t first_pid, uint64_t n, 
     for (;; ++it) {
         if (it >= max_iter) return fail(ctx, MC_EHIP, "event loop did not terminate");
         const int cur = (int)(it & 1);
-        HIPCHK(launch_slots_count(b, st));
-        HIPCHK(launch_slots_queue(b, g, W, ctx->ctr, cur, first_pid, n, seed, st));
-        HIPCHK(hipMemcpyAsync(ctx->ctr_host + cur, ctx->ctr + cur, sizeof(Counters), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(ctx->ev_ctr[cur], st));
         const bool exact = it == 0;
-        if (exact) {
-            HIPCHK(hipEventSynchronize(ctx->ev_ctr[cur]));
-            p = ctx->ctr_host[cur];
-        } else {
+        if (!exact) {  // the lengths of iteration it - 1 (its queues were built long ago)
             HIPCHK(hipEventSynchronize(ctx->ev_ctr[cur ^ 1]));
             p = ctx->ctr_host[cur ^ 1];
             s.lookups += p.nL;
             if (sorted_prev) s.sorted_lookups += p.nL;
             s.flights += p.nA;
+            if (p.nA == 0) {  // iteration it - 1 was empty: every history ended before it
+                if (p.issued != n || p.top != 0)
+                    return fail(ctx, MC_EHIP, "event loop ended before every history (and copy) was run");
+                --it;  // iterations with particles: 0 .. it - 2
+                break;
+            }
         }
-        if (p.nA == 0) {
-            if (p.issued != n || p.top != 0)
-                return fail(ctx, MC_EHIP, "event loop ended before every history (and copy) was run");
-            if (!exact) --it;  // iterations with particles: 0 .. it - 2
-            break;
+        HIPCHK(launch_slots_count(b, st));
+        const uint32_t new_bound = (uint32_t)std::min<uint64_t>(cap, n - p.issued);  // histories not yet started
+        HIPCHK(launch_slots_queue(b, g, W, ctx->ctr, cur, first_pid, n, seed, new_bound, st));
+        HIPCHK(hipMemcpyAsync(ctx->ctr_host + cur, ctx->ctr + cur, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ctx->ev_ctr[cur], st));
+        if (exact) {
+            HIPCHK(hipEventSynchronize(ctx->ev_ctr[cur]));
+            p = ctx->ctr_host[cur];
+            if (p.nA == 0) {
+                if (p.issued != n || p.top != 0)
+                    return fail(ctx, MC_EHIP, "event loop ended before every history (and copy) was run");
+                break;
+            }
         }
         Counters *dc = ctx->ctr + cur;
         const uint32_t bound = (exact || (analog && p.issued == n)) ? p.nA : cap;

@@ -33,7 +33,8 @@ hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 hipError_t launch_slots_count(const BankDev &b, hipStream_t st);
 hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, const WwDev &W, Counters *ctr, int cur,
-                              uint64_t first_pid, uint64_t n_hist, uint64_t seed, hipStream_t st);
+                              uint64_t first_pid, uint64_t n_hist, uint64_t seed, uint32_t new_bound,
+                              hipStream_t st);
 // Scratch of the radix sort of up to `cap` items.
 struct SortBufs {
     uint32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr;

@@ -1944,12 +1944,16 @@ hipError_t launch_slots_count(const BankDev &b, hipStream_t st)
 }
 
 hipError_t launch_slots_queue(const BankDev &b, const GeomDev &g, const WwDev &W, Counters *ctr, int cur,
-                              uint64_t first_pid, uint64_t n_hist, uint64_t seed, hipStream_t st)
+                              uint64_t first_pid, uint64_t n_hist, uint64_t seed, uint32_t new_bound,
+                              hipStream_t st)
 {
     hipLaunchKernelGGL(k_slots_queue, dim3(blocks_for(b.C, TILE)), dim3(WG), 0, st, b, g, W, ctr, cur,
                        first_pid, n_hist, seed);
-    // new histories: at most one per slot
-    hipLaunchKernelGGL(k_slots_init, dim3(blocks_for(b.C, WG)), dim3(WG), 0, st, b, g, W, ctr, cur, first_pid, seed);
+    // new histories: at most one per slot, and at most new_bound (the
+    // histories not yet started)
+    const uint32_t nb = new_bound < b.C ? new_bound : b.C;
+    if (nb)
+        hipLaunchKernelGGL(k_slots_init, dim3(blocks_for(nb, WG)), dim3(WG), 0, st, b, g, W, ctr, cur, first_pid, seed);
     return hipGetLastError();
 }
 
