@@ -298,3 +298,35 @@ def test_core_of_assemblies_matches_oracle(torch_cuda):
     # allowance (2 x 19 degrees of freedom)
     n_fail, allowed, z = three_sigma(gm, gs, st.mean["tl"], st.stderr["tl"], dof=38)
     assert n_fail <= allowed, (n_fail, allowed, z)
+
+
+def test_event_loop_counts_do_not_depend_on_launch_choices(torch_cuda):
+    """The host runs the event loop one iteration behind the GPU and takes
+    its choices (sort or not, bank size) from the previous iteration's queue
+    lengths; the histories, and so the numbers of lookups, flights and
+    iterations it reports, must not depend on them: every iteration counted
+    once, sorted or not."""
+    torch = torch_cuda
+    prob = mcsynth.c2_problem()
+    n = 60_000
+    out = {}
+    for name, tune in (("sorted", dict(sort_min=1)), ("unsorted", dict(sort_min=1 << 30)),
+                       ("ragged", dict(sort_min=1, in_flight=7_777))):
+        with Transport(prob) as t:
+            mc.mc_set_tuning(t.ctx, tail_particles=-1, **tune)
+            h = _gpu_histories(torch, t, 2, 0, n)
+            out[name] = (h, t.stats())
+    hs, ss = out["sorted"]
+    hu, su = out["unsorted"]
+    hr, sr = out["ragged"]
+    for f in ("fate", "n_coll", "n_cross", "n_draws", "E_final"):
+        assert np.array_equal(hs[f], hu[f]) and np.array_equal(hs[f], hr[f]), f
+    # every history's lookups: one at its start and one after each collision
+    # that leaves it alive (C2's materials change at crossings too)
+    assert ss["lookups"] == su["lookups"] == sr["lookups"] > n
+    assert ss["flights"] == su["flights"] == sr["flights"] == int(hs["n_coll"].sum() + hs["n_cross"].sum())
+    # (an iteration whose predecessor had no lookups is not sorted: the
+    # choice follows the previous lengths)
+    assert 0.99 * ss["lookups"] <= ss["sorted_lookups"] <= ss["lookups"] and su["sorted_lookups"] == 0
+    assert ss["iterations"] == su["iterations"] and sr["iterations"] > ss["iterations"]
+    assert ss["tail_particles"] == su["tail_particles"] == sr["tail_particles"] == 0
