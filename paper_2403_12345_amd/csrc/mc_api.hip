@@ -545,6 +545,7 @@ static int upload_xs(mc_ctx *ctx, const HostXs &H, int32_t M, Buffers &B, XsDev 
     x.M = M;
     x.ln_emin = std::log(H.emin);
     x.inv_delta = (double)M / std::log(H.emax / H.emin);
+    x.div_safe = H.emin >= 0x1p-100 && H.emax <= 0x1p100 ? 1 : 0;
     return MC_OK;
 }
 

@@ -60,6 +60,7 @@ struct XsDev {
     int32_t n_mat;
     int32_t M;                 // hash bins
     double ln_emin, inv_delta; // bin b = floor((ln E - ln emin) * inv_delta)
+    int32_t div_safe;          // every grid energy in [2^-100, 2^100] (the interval fraction's short division)
     // reaction channels: n_chan values per grid point, point p's at xc[p * n_chan]
     int32_t n_chan;
     const double *xc;

@@ -794,7 +794,10 @@ __device__ __forceinline__ void window_search(const WinQ (&w)[N], float tb, doub
     double eg[N], eg1[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        const uint32_t j = bracket_guess(w[n].lo, w[n].hi, tb);
+        // (bracket_guess in one fused multiply-add: a window holds at most
+        // 64 points, so hi - lo is exact in float and the guess stays <= hi;
+        // any guess in the bracket ends at the same interval)
+        const uint32_t j = w[n].lo + (uint32_t)__builtin_fmaf(tb, (float)(w[n].hi - w[n].lo), 0.5f);
         const double *Ej = w[n].Ew + (int32_t)(j - w[n].wlo);
         eg[n] = Ej[0];
         eg1[n] = Ej[1];
@@ -817,7 +820,9 @@ __device__ __forceinline__ void window_search(const WinQ (&w)[N], float tb, doub
     }
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        rare[n] = ((k[n] > 0u) & (e < h[n].e0)) | ((k[n] + 2u < w[n].len) & (e >= h[n].e1));
+        // (at the grid's ends, k = 0 or k = len - 2, E outside [e0, e1) is
+        // the clamped interval itself: the walks below then leave it as is)
+        rare[n] = (e < h[n].e0) | (e >= h[n].e1);
         glob[n] = false;
         any_rare = any_rare || rare[n];
     }
@@ -915,6 +920,37 @@ __device__ __forceinline__ void window_single(const XsDev &xs, const MatNuc &mn,
     sg = x0.y + f * (x1.y - x0.y);
 }
 
+// The interval fraction (E - E_i) / (E_(i+1) - E_i), correctly rounded, in
+// the form the division's own instruction sequence takes when neither
+// operand needs the scaling that sequence applies near the ends of the
+// exponent range: the reciprocal refined by two Newton steps, the quotient
+// and one fused correction (Markstein's theorem: correctly rounded).  With
+// every grid energy and E in [2^-100, 2^100] the difference and the spacing
+// lie in [2^-152, 2^101] (or the difference is 0), nothing is scaled and the
+// special-case fix-up returns the quotient unchanged, so this is the same
+// value as the division, in three instructions fewer.
+__device__ __forceinline__ double frac_div(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    const double q = n * r;
+    return __builtin_fma(__builtin_fma(-d, q, n), r, q);
+}
+
+// frac_div may serve the wave: the tables' energies lie in its range (a
+// flag set with the tables) and so do the energies of all the wave's lanes.
+__device__ __forceinline__ bool frac_div_wave(const LookupArgs &a, uint32_t i, bool valid)
+{
+    if (!a.xs.div_safe) return false;
+    bool in = true;
+    if (valid) {
+        const double e = a.E[a.list ? a.list[i] : i];
+        in = e >= 0x1p-100 && e <= 0x1p100;
+    }
+    return __ballot(!in) == 0;
+}
+
 // window_lookups without reaction channels, two nuclides at a time: when the
 // windows of nuclides q and q + 1 hold at most half a wave's points each (all
 // but ~1e-4 of the pairs of the 300-nuclide tables), one load per lane brings
@@ -924,6 +960,7 @@ __device__ __forceinline__ void window_single(const XsDev &xs, const MatNuc &mn,
 // and an odd last nuclide, go one at a time.  The same intervals,
 // interpolation, sums in material order and checkpoints as window_lookups:
 // the results bit for bit.
+template <bool FAST_DIV>
 __device__ __forceinline__ int32_t window_lookups_pairs(const LookupArgs &a, const uint2 *sh, const int32_t *s_info,
                                                         uint32_t i, bool valid, double *we, double2 *wx)
 {
@@ -1009,8 +1046,10 @@ __device__ __forceinline__ int32_t window_lookups_pairs(const LookupArgs &a, con
             WinHit hit[2];
             window_search(w, tb, e, hit);
             wave_lds_sync();
-            const double fa = (e - hit[0].e0) / (hit[0].e1 - hit[0].e0);
-            const double fb = (e - hit[1].e0) / (hit[1].e1 - hit[1].e0);
+            const double fa = FAST_DIV ? frac_div(e - hit[0].e0, hit[0].e1 - hit[0].e0)
+                                       : (e - hit[0].e0) / (hit[0].e1 - hit[0].e0);
+            const double fb = FAST_DIV ? frac_div(e - hit[1].e0, hit[1].e1 - hit[1].e0)
+                                       : (e - hit[1].e0) / (hit[1].e1 - hit[1].e0);
             ca = hit[0].x0.x + fa * (hit[0].x1.x - hit[0].x0.x);
             sga = hit[0].x0.y + fa * (hit[0].x1.y - hit[0].x0.y);
             cb = hit[1].x0.x + fb * (hit[1].x1.x - hit[1].x0.x);
@@ -1089,7 +1128,10 @@ __global__ void __launch_bounds__(WG) k_lookup(LookupArgs a)
     int32_t nk_done = 0;
     if (WIN && staged) {
         if constexpr (CHAN) nk_done = window_lookups<CHAN>(a, sh, s_info, i, valid, s_we, s_wx, s_wc);
-        else nk_done = window_lookups_pairs(a, sh, s_info, i, valid, s_we, s_wx);
+        else if (frac_div_wave(a, i, valid))
+            nk_done = window_lookups_pairs<true>(a, sh, s_info, i, valid, s_we, s_wx);
+        else
+            nk_done = window_lookups_pairs<false>(a, sh, s_info, i, valid, s_we, s_wx);
     } else if (valid) {
     const uint32_t p = a.list ? a.list[i] : i;
     const double e = a.E[p];
